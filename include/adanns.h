@@ -1,0 +1,132 @@
+/*
+ * adanns.h - C ABI of the MI355X (gfx950) AdANNS-IVF / IVF-PQ search library.
+ *
+ * The operations follow the paper's problem statement and Algorithm 1
+ * (AdANNS, arXiv 2305.19435): a database of N points embedded in R^d by a
+ * Matryoshka representation (Section 3), an IVF index built by clustering
+ * the first d_c coordinates (Section 4.1; Algorithm 1, construction), and a
+ * search that assigns each query to its nprobe nearest centroids on the
+ * first d_c coordinates, scans the probed inverted lists with the first d_s
+ * coordinates and returns the k nearest (Algorithm 1, inference; Appendix A,
+ * Table "formula", AdANNS-IVF and AdANNS-IVF-D rows).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named as "device" must point to memory of the current HIP
+ *   device (e.g. torch tensors); "host" pointers to ordinary host memory.
+ *   Caller-owned buffers stay owned by the caller; the library copies what
+ *   it keeps into its own device memory, owned by the index object.
+ * - Matrices are row-major; ``ld*`` is the row stride in elements.
+ * - ``stream`` is a hipStream_t (NULL = the default stream). Searches are
+ *   enqueued on it and return without waiting for the device, except that a
+ *   call may synchronise ``stream`` once to grow its scratch memory.
+ * - Distances are squared L2 in FP32, ascending, ties broken by the smaller
+ *   id. When fewer than k candidates exist the trailing slots hold id -1 and
+ *   distance +inf. Probe lists are sorted by (centroid distance, list index).
+ * - Every function returns an adanns_status and never throws. Arguments are
+ *   validated before any device work; on error the outputs are untouched and
+ *   adanns_last_error() (thread-local) says why. A HIP failure of an earlier
+ *   asynchronous launch surfaces as ADANNS_EHIP. nq = 0 is a no-op.
+ * - A built index is read-only during searches; searches on different
+ *   streams may run concurrently (each stream gets its own scratch memory).
+ */
+#ifndef ADANNS_H
+#define ADANNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct adanns_index adanns_index; /* opaque, library-owned */
+
+typedef enum adanns_status {
+  ADANNS_OK = 0,
+  ADANNS_EINVAL = -1,      /* invalid argument */
+  ADANNS_ENOMEM = -2,      /* device or host allocation failed */
+  ADANNS_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
+  ADANNS_EUNSUPPORTED = -4,/* valid request this build does not support */
+  ADANNS_EBUDGET = -5      /* request exceeds an admission budget */
+} adanns_status;
+
+typedef enum adanns_format {
+  ADANNS_FP32 = 0,
+  ADANNS_BF16 = 1,         /* round-to-nearest-even bfloat16 */
+  ADANNS_FP8_E4M3 = 2      /* OCP e4m3, one FP32 scale per vector */
+} adanns_format;
+
+/* Thread-local text of the last error ("" if none). Never NULL. */
+const char *adanns_last_error(void);
+
+/* Library version string. */
+const char *adanns_version(void);
+
+/*
+ * Import an IVF index whose clustering was computed elsewhere (Section 3,
+ * "Inverted File Index": centroids plus the inverted file of each cluster's
+ * members; Algorithm 1, construction on the d_c_build prefix).
+ *   X         device, [n x d] FP32 rows, row stride ldx >= d. Copied.
+ *   centroids device, [nlist x d_c_build] FP32, row stride d_c_build. Copied.
+ *   assign    device, [n] int32, the list of each row, each in [0, nlist).
+ * Lists keep their members in ascending row order; a row's id is its index
+ * in X. Requirements: n >= 1, 1 <= d <= 8192, 1 <= nlist <= 65536,
+ * 1 <= d_c_build <= d, n < 2^31. Synchronises ``stream``.
+ * On success *out owns the index; release it with adanns_index_free().
+ */
+adanns_status adanns_ivf_import(const float *X, int64_t n, int32_t d, int64_t ldx,
+                                const float *centroids, int32_t nlist, int32_t d_c_build,
+                                const int32_t *assign, void *stream, adanns_index **out);
+
+/*
+ * AdANNS-IVF search (Algorithm 1, inference; Appendix A, Table "formula"):
+ * probes = the nprobe clusters nearest to Q[i, :d_c] on the centroids'
+ * first d_c coordinates; result = the k rows of the probed lists nearest to
+ * Q[i, :d_s] on their first d_s coordinates. d_c < d_c_build searches a
+ * prefix of the built centroids (AdANNS-IVF-D, Section 5.1).
+ *   Q      device, [nq x ldq] FP32, ldq >= max(d_c, d_s).
+ *   dist   device, [nq x k] FP32 out.
+ *   ids    device, [nq x k] int64 out.
+ *   probes device, [nq x nprobe] int32 out, or NULL.
+ * Limits: 1 <= d_c <= d_c_build, 1 <= d_s <= d, 1 <= nprobe <= nlist,
+ * 1 <= k <= 1024.
+ */
+adanns_status adanns_search(const adanns_index *index, const float *Q, int64_t nq, int64_t ldq,
+                            int32_t d_c, int32_t d_s, int32_t nprobe, int32_t k,
+                            float *dist, int64_t *ids, int32_t *probes, void *stream);
+
+/*
+ * Same as adanns_search with the probe lists given instead of computed:
+ *   probes device, [nq x nprobe] int32, each in [0, nlist), no repeats
+ *          within a row; both are checked (ADANNS_EINVAL), which copies the
+ *          probes to the host and synchronises ``stream``.
+ * Used to check the list scan on its own.
+ */
+adanns_status adanns_search_probes(const adanns_index *index, const float *Q, int64_t nq,
+                                   int64_t ldq, int32_t d_s, int32_t nprobe,
+                                   const int32_t *probes, int32_t k, float *dist,
+                                   int64_t *ids, void *stream);
+
+/* Sizes of an index. Any out pointer may be NULL. */
+adanns_status adanns_index_info(const adanns_index *index, int64_t *n, int32_t *d,
+                                int32_t *nlist, int32_t *d_c_build);
+
+/* The inverted lists as stored: offsets host [nlist + 1] int64, ids host [n]
+ * int64 (member ids grouped by list). Either may be NULL. Synchronous. */
+adanns_status adanns_index_lists(const adanns_index *index, int64_t *offsets, int64_t *ids);
+
+/* The centroids as stored: host [nlist x d_c_build] FP32. Synchronous. */
+adanns_status adanns_index_centroids(const adanns_index *index, float *centroids);
+
+/* Device bytes held by the index, scratch memory included. */
+size_t adanns_index_device_bytes(const adanns_index *index);
+
+/* Release an index and all its device memory (NULL is a no-op). Waits for
+ * the device first. */
+void adanns_index_free(adanns_index *index);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADANNS_H */

@@ -1,0 +1,64 @@
+"""ctypes binding of libadanns.so: argument marshalling only.
+
+Every function here forwards to the C ABI declared in include/adanns.h with
+the same name; device buffers are torch tensors on the current HIP device
+and the stream is torch's current stream. No search arithmetic happens in
+Python, and there is no fallback: if the shared library is missing or fails
+to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libadanns.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                      "(python -c 'import __graft_entry__ as g; g.build()')")
+lib = C.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, EBUDGET = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED", -5: "EBUDGET"}
+
+vp = C.c_void_p
+i32 = C.c_int32
+i64 = C.c_int64
+PIX = C.POINTER(vp)
+
+_SIGS = {
+    "adanns_last_error": (C.c_char_p, []),
+    "adanns_version": (C.c_char_p, []),
+    "adanns_ivf_import": (C.c_int, [vp, i64, i32, i64, vp, i32, i32, vp, vp, PIX]),
+    "adanns_search": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, vp, vp, vp, vp]),
+    "adanns_search_probes": (C.c_int, [vp, vp, i64, i64, i32, i32, vp, i32, vp, vp, vp]),
+    "adanns_index_info": (C.c_int, [vp, vp, vp, vp, vp]),
+    "adanns_index_lists": (C.c_int, [vp, vp, vp]),
+    "adanns_index_centroids": (C.c_int, [vp, vp]),
+    "adanns_index_device_bytes": (C.c_size_t, [vp]),
+    "adanns_index_free": (None, [vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class AdannsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def check(status: int):
+    if status != OK:
+        raise AdannsError(status, lib.adanns_last_error().decode())
+
+
+def last_error() -> str:
+    return lib.adanns_last_error().decode()
+
+
+def version() -> str:
+    return lib.adanns_version().decode()

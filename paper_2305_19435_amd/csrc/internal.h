@@ -1,0 +1,132 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "adanns.h"
+
+namespace adanns {
+
+// ---- layout constants ------------------------------------------------------
+// Vectors are stored per inverted list in "slabs" of SLAB consecutive
+// coordinates: element (list h, slab s, row r, t) lives at
+//   vec[poff[h] * d_pad + (s * npad_h + r) * SLAB + t],
+// with npad_h = poff[h+1] - poff[h] the list's row count rounded up to ROWPAD.
+// The first d_s coordinates of a list (d_s a multiple of SLAB) are therefore
+// one contiguous span, and a tile of rows x SLAB coordinates is one
+// contiguous block of rows * 128 bytes.
+constexpr int SLAB = 32;
+constexpr int ROWPAD = 64;
+constexpr int TILE_Q = 64;     // queries per distance tile
+constexpr int TILE_V = 64;     // vectors per distance tile
+constexpr int MAX_SHORTLIST = 1024;
+constexpr int REFINE_MARGIN = 8;   // extra first-pass candidates re-measured exactly
+constexpr int PERSIST_WG = 2048;   // workgroups of the persistent tile kernel (multiple of 8)
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---- error handling ----------------------------------------------------------
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define ADANNS_HIP(call)                                                          \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ::adanns::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                          __FILE__, __LINE__);                                    \
+      return ADANNS_EHIP;                                                         \
+    }                                                                             \
+  } while (0)
+
+#define ADANNS_REQUIRE(cond, ...)         \
+  do {                                    \
+    if (!(cond)) {                        \
+      ::adanns::set_error(__VA_ARGS__);   \
+      return ADANNS_EINVAL;               \
+    }                                     \
+  } while (0)
+
+// ---- per-stream scratch memory ---------------------------------------------
+struct Scratch {
+  void *base = nullptr;
+  size_t bytes = 0;
+};
+
+// Carves aligned sub-buffers out of one allocation.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  size_t cap;
+  template <class T>
+  T *take(size_t count) {
+    off = (size_t)round_up((int64_t)off, 256);
+    T *p = reinterpret_cast<T *>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace adanns
+
+struct adanns_index {
+  int device = 0;
+  int64_t n = 0;
+  int32_t d = 0, d_pad = 0, nlist = 0, d_cb = 0, d_cb_pad = 0, nl_pad = 0;
+  int64_t rows_pad = 0;
+  int32_t max_len = 0;
+  std::vector<int64_t> h_off, h_poff;
+  std::vector<int32_t> h_len;
+  std::vector<int64_t> h_ids;          // member ids grouped by list
+  std::vector<int64_t> top_prefix;     // sum of the p largest list lengths, p = 0..nlist
+  // device memory owned by the index
+  float *vec = nullptr;                // slab layout, rows_pad * d_pad floats
+  int64_t *poff = nullptr;             // [nlist + 1]
+  int32_t *len = nullptr;              // [nlist]
+  int64_t *rowid = nullptr;            // [rows_pad], -1 on padding rows
+  float *cent = nullptr;               // [nlist][d_cb_pad] row-major, zero padded
+  float *cent_slab = nullptr;          // centroids as one slab-layout list of nl_pad rows
+  size_t own_bytes = 0;
+  std::mutex mu;
+  std::map<hipStream_t, adanns::Scratch> scratch;
+};
+
+namespace adanns {
+
+// Grows (if needed) and returns the scratch memory of ``stream``.
+adanns_status get_scratch(adanns_index *ix, hipStream_t stream, size_t bytes, void **out);
+
+// ---- launch wrappers (kernels.hip) -----------------------------------------
+struct SearchBufs {
+  float *Qs;          // [nq][dq_pad]
+  int64_t ldqs;
+  float *S;           // [nq][nlist] coarse first-pass scores
+  int32_t *probes;    // [nq][nprobe]
+  int32_t *cnt;       // [nlist]
+  int32_t *cursor;    // [nlist]
+  int32_t *bkt_off;   // [nlist]
+  int32_t *tile_off;  // [nlist + 1]
+  int32_t *bucket;    // [nq * nprobe]
+  int64_t *seg_off;   // [nq + 1]
+  int64_t *pair_base; // [nq * nprobe]
+  float *D;           // first-pass distances, query-segmented
+};
+
+hipError_t launch_stage_queries(const float *Q, int64_t nq, int64_t ldq, int32_t dq,
+                                float *Qs, int64_t ldqs, hipStream_t st);
+hipError_t launch_layout(const float *src, int64_t ldsrc, int32_t dsrc, const int64_t *src_row,
+                         const int32_t *row_list, const int64_t *poff, int64_t rows_pad,
+                         int32_t d_pad, float *dst, hipStream_t st);
+hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_c,
+                         int32_t nprobe, int32_t *user_probes, hipStream_t st);
+hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_s,
+                       int32_t nprobe, int32_t k, float *dist, int64_t *ids, hipStream_t st);
+
+}  // namespace adanns

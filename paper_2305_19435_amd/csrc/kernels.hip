@@ -1,0 +1,726 @@
+// Device kernels of the AdANNS-IVF search path for gfx950 (CDNA4) and their
+// host-side launch wrappers.
+//
+//   k_stage_queries  query prefix staging (zero-padded, 16-byte aligned rows)
+//   k_tile_dist      first-pass distances |x|^2 - 2 q.x for tiles of
+//                    64 queries x 64 vectors on FP32 MFMA; one kernel serves
+//                    the coarse step (all queries against the centroids) and
+//                    the list scan (each list against the queries probing it)
+//   k_select_refine  per query: radix selection of the shortlist, exact
+//                    re-measurement of the shortlist in compensated FP32,
+//                    bitonic sort by (distance, id), top-k / top-nprobe out
+//   k_count / k_list_scan / k_scatter / k_seg_len / k_pair_base
+//                    probe bucketing: (query, probe) pairs grouped per list,
+//                    tile counts per list and the output segment of each pair
+//
+// The coarse step follows Algorithm 1's inference loop (distances to every
+// centroid on the d_c prefix, then the nprobe nearest); the scan is its
+// linear scan of the probed lists on the d_s prefix (Appendix A, Table
+// "formula", AdANNS-IVF row).
+#include "internal.h"
+
+#include <algorithm>
+#include <cstdio>
+
+namespace adanns {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Monotone map from float to uint32 (total order, -0 < +0).
+__device__ __forceinline__ uint32_t order_key(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// ---- compensated arithmetic for the exact re-measurement ---------------------
+// Knuth's TwoSum: s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Adds (q - x)^2 to the unevaluated sum S + C. q - x = d + de exactly
+// (TwoSum), d*d = p + pe exactly (FMA), so only the tiny terms 2*d*de and
+// de^2 (dropped, below u^2 of the term) and the rounding of C are inexact.
+__device__ __forceinline__ void acc_sq_diff(float q, float x, float &S, float &C) {
+#pragma clang fp contract(off)
+  float d, de;
+  two_sum(q, -x, d, de);
+  float p = d * d;
+  float pe = __builtin_fmaf(d, d, -p);
+  float t, te;
+  two_sum(S, p, t, te);
+  S = t;
+  C = C + (te + (pe + 2.0f * d * de));
+}
+
+__device__ __forceinline__ void wave_reduce_pair(float &S, float &C) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    float S2 = __shfl_xor(S, off);
+    float C2 = __shfl_xor(C, off);
+    float t, te;
+    two_sum(S, S2, t, te);
+    S = t;
+    C = C + (C2 + te);
+  }
+  float hi, lo;
+  two_sum(S, C, hi, lo);
+  S = hi;
+  C = lo;
+}
+
+// Exclusive prefix sum over the block (blockDim.x a multiple of 64).
+template <class T>
+__device__ T block_excl_scan(T v, T *sh /* >= blockDim.x / 64 */, T *total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  T inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    T t = __shfl_up(inc, off);
+    if (lane >= off) inc += t;
+  }
+  if (lane == 63) sh[wv] = inc;
+  __syncthreads();
+  T before = 0, all = 0;
+  for (int w = 0; w < nw; ++w) {
+    T s = sh[w];
+    if (w < wv) before += s;
+    all += s;
+  }
+  __syncthreads();
+  if (total) *total = all;
+  return before + inc - v;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_stage_queries(const float *__restrict__ Q, int64_t nq, int64_t ldq, int32_t dq,
+                                float *__restrict__ Qs, int64_t ldqs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t row = i / ldqs, col = i % ldqs;
+  if (row >= nq) return;
+  Qs[i] = col < dq ? Q[row * ldq + col] : 0.0f;
+}
+
+// Slab layout writer: one thread per destination element.
+__global__ void k_layout(const float *__restrict__ src, int64_t ldsrc, int32_t dsrc,
+                         const int64_t *__restrict__ src_row, const int32_t *__restrict__ row_list,
+                         const int64_t *__restrict__ poff, int64_t rows_pad, int32_t d_pad,
+                         float *__restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows_pad * d_pad) return;
+  int64_t g = i / d_pad;
+  int32_t dim = (int32_t)(i % d_pad);
+  int32_t h = row_list[g];
+  int64_t p0 = poff[h];
+  int64_t npad = poff[h + 1] - p0;
+  int64_t r = g - p0;
+  int64_t sr = src_row[g];
+  float v = (sr >= 0 && dim < dsrc) ? src[sr * ldsrc + dim] : 0.0f;
+  dst[p0 * d_pad + ((int64_t)(dim / SLAB) * npad + r) * SLAB + (dim % SLAB)] = v;
+}
+
+// ---- first-pass distance tiles ------------------------------------------------
+struct TileArgs {
+  const float *Qs;
+  int64_t ldqs;
+  int32_t d_dot;           // coordinates in the dot product (d_c or d_s)
+  const float *vec;        // slab layout base
+  int32_t d_pad;
+  const int64_t *poff;     // scan: [nlist + 1] padded row offsets
+  const int32_t *len;      // scan: [nlist] list lengths
+  int32_t nlist;
+  const int32_t *tile_off; // scan: [nlist + 1] tile prefix
+  const int32_t *bkt_off;  // scan: start of each list's bucket
+  const int32_t *cnt;      // scan: pairs per list
+  const int32_t *bucket;   // scan: pair ids grouped by list
+  int32_t pair_div;        // query of a pair = pair / pair_div
+  const int64_t *pair_base;// scan: output offset of each pair
+  float *out;
+  // coarse mode: one list (the centroids) against all queries
+  int32_t coarse;
+  int64_t nq;
+  int32_t nl, nl_pad, qtiles, total_host;
+};
+
+__global__ __launch_bounds__(256) void k_tile_dist(TileArgs a) {
+  __shared__ __attribute__((aligned(16))) float As[TILE_Q][SLAB + 4];
+  __shared__ __attribute__((aligned(16))) float Bs[TILE_V][SLAB + 4];
+  __shared__ int64_t rbase[TILE_Q];
+  __shared__ int32_t rq[TILE_Q];
+  __shared__ float cn[TILE_V];
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int total = a.coarse ? a.total_host : a.tile_off[a.nlist];
+  const int G = gridDim.x;
+  // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
+  // contiguous run of work items so tiles that share a vector tile (the
+  // query tiles of one list) meet in the same L2.
+  const int L = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+
+  const int lr = tid >> 3;        // load row 0..31 (and +32)
+  const int lc = (tid & 7) * 4;   // load column 0..28
+  const int rb = (wv >> 1) * 32;  // this wave's 32x32 output sub-tile
+  const int cb = (wv & 1) * 32;
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+
+  for (int w = L; w < total; w += G) {
+    int h, qt, vt, m, nvec;
+    int64_t npad;
+    const float *vbase;
+    if (a.coarse) {
+      h = 0;
+      qt = w % a.qtiles;
+      vt = w / a.qtiles;
+      m = (int)a.nq;
+      nvec = a.nl;
+      npad = a.nl_pad;
+      vbase = a.vec;
+    } else {
+      int lo = 0, hi = a.nlist - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (a.tile_off[mid] <= w) lo = mid; else hi = mid - 1;
+      }
+      h = lo;
+      m = a.cnt[h];
+      nvec = a.len[h];
+      int64_t p0 = a.poff[h];
+      npad = a.poff[h + 1] - p0;
+      int qts = (m + TILE_Q - 1) / TILE_Q;
+      int rem = w - a.tile_off[h];
+      qt = rem % qts;
+      vt = rem / qts;
+      vbase = a.vec + p0 * a.d_pad;
+    }
+    __syncthreads();  // previous item's epilogue is done with rq / rbase / cn
+    if (tid < TILE_Q) {
+      int i = qt * TILE_Q + tid;
+      if (i < m) {
+        int32_t pair = a.coarse ? i : a.bucket[a.bkt_off[h] + i];
+        rq[tid] = pair / a.pair_div;
+        rbase[tid] = a.coarse ? (int64_t)i * a.nl : a.pair_base[pair];
+      } else {
+        rq[tid] = -1;
+        rbase[tid] = 0;
+      }
+    }
+    __syncthreads();
+    const int qa = rq[lr], qb = rq[lr + 32];
+    const float *qpa = a.Qs + (int64_t)(qa < 0 ? 0 : qa) * a.ldqs;
+    const float *qpb = a.Qs + (int64_t)(qb < 0 ? 0 : qb) * a.ldqs;
+    const float *vp = vbase + (int64_t)vt * TILE_V * SLAB;
+    const int nslab = (a.d_dot + SLAB - 1) / SLAB;
+
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+    float nrm0 = 0.f, nrm1 = 0.f;
+    float4 ra0, ra1, rb0, rb1;
+
+    auto load = [&](int s) {
+      const int dim = s * SLAB + lc;
+      ra0 = qa >= 0 ? *(const float4 *)(qpa + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+      ra1 = qb >= 0 ? *(const float4 *)(qpb + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+      if (dim + 4 > a.d_dot) {
+        if (dim + 0 >= a.d_dot) { ra0.x = 0.f; ra1.x = 0.f; }
+        if (dim + 1 >= a.d_dot) { ra0.y = 0.f; ra1.y = 0.f; }
+        if (dim + 2 >= a.d_dot) { ra0.z = 0.f; ra1.z = 0.f; }
+        if (dim + 3 >= a.d_dot) { ra0.w = 0.f; ra1.w = 0.f; }
+      }
+      const float *src = vp + (int64_t)s * npad * SLAB;
+      rb0 = *(const float4 *)(src + lr * SLAB + lc);
+      rb1 = *(const float4 *)(src + (lr + 32) * SLAB + lc);
+    };
+
+    load(0);
+    for (int s = 0; s < nslab; ++s) {
+      __syncthreads();
+      *(float4 *)&As[lr][lc] = ra0;
+      *(float4 *)&As[lr + 32][lc] = ra1;
+      *(float4 *)&Bs[lr][lc] = rb0;
+      *(float4 *)&Bs[lr + 32][lc] = rb1;
+      {  // vector norms over the same prefix, from the registers just stored
+        const int dim = s * SLAB + lc;
+        float x[4] = {rb0.x, rb0.y, rb0.z, rb0.w};
+        float y[4] = {rb1.x, rb1.y, rb1.z, rb1.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (dim + e < a.d_dot) {
+            nrm0 += x[e] * x[e];
+            nrm1 += y[e] * y[e];
+          }
+        }
+      }
+      __syncthreads();
+      if (s + 1 < nslab) load(s + 1);
+
+      float af[2][8], bf[2][8];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        float4 x0 = *(const float4 *)&As[rb + i * 16 + fr][fk];
+        float4 x1 = *(const float4 *)&As[rb + i * 16 + fr][fk + 4];
+        af[i][0] = x0.x; af[i][1] = x0.y; af[i][2] = x0.z; af[i][3] = x0.w;
+        af[i][4] = x1.x; af[i][5] = x1.y; af[i][6] = x1.z; af[i][7] = x1.w;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        float4 x0 = *(const float4 *)&Bs[cb + j * 16 + fr][fk];
+        float4 x1 = *(const float4 *)&Bs[cb + j * 16 + fr][fk + 4];
+        bf[j][0] = x0.x; bf[j][1] = x0.y; bf[j][2] = x0.z; bf[j][3] = x0.w;
+        bf[j][4] = x1.x; bf[j][5] = x1.y; bf[j][6] = x1.z; bf[j][7] = x1.w;
+      }
+      // MFMA k-slot (lane >> 4) carries coordinate 8 * (lane >> 4) + kb for
+      // both operands, so every coordinate of the slab is used exactly once.
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kb], bf[j][kb], acc[i][j], 0, 0, 0);
+    }
+    // norms: 8 threads share a row
+    nrm0 += __shfl_xor(nrm0, 1);
+    nrm0 += __shfl_xor(nrm0, 2);
+    nrm0 += __shfl_xor(nrm0, 4);
+    nrm1 += __shfl_xor(nrm1, 1);
+    nrm1 += __shfl_xor(nrm1, 2);
+    nrm1 += __shfl_xor(nrm1, 4);
+    if ((tid & 7) == 0) {
+      cn[lr] = nrm0;
+      cn[lr + 32] = nrm1;
+    }
+    __syncthreads();
+    // 16x16 f32 MFMA result: lane holds column (lane & 15), rows 4*(lane>>4)+e
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = rb + i * 16 + (lane >> 4) * 4 + e;
+          const int col = cb + j * 16 + (lane & 15);
+          const int v = vt * TILE_V + col;
+          if (rq[row] >= 0 && v < nvec) a.out[rbase[row] + v] = cn[col] - 2.0f * acc[i][j][e];
+        }
+  }
+}
+
+// ---- per-query selection and exact re-measurement ----------------------------
+struct SelArgs {
+  int32_t coarse;
+  const float *D;
+  const int64_t *seg_off;  // scan: [nq + 1]
+  int32_t nl;              // coarse: scores per query
+  int32_t Kp;              // shortlist length
+  int32_t kout;            // results per query
+  const float *Qs;
+  int64_t ldqs;
+  int32_t d_dot;
+  const float *cent;       // coarse: [nl][ld_cent]
+  int32_t ld_cent;
+  const float *vec;        // scan: slab layout
+  int32_t d_pad;
+  const int64_t *poff;
+  const int64_t *rowid;
+  const int32_t *probes;   // scan: [nq][nprobe]
+  int32_t nprobe;
+  const int64_t *pair_base;
+  float *out_dist;
+  int64_t *out_ids;
+  int32_t *out_probes;
+  int32_t *out_probes2;
+};
+
+__device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
+
+__device__ __forceinline__ bool pair_less(float ah, float al, int64_t ai, float bh, float bl,
+                                          int64_t bi) {
+  if (ah != bh) return ah < bh;
+  if (al != bl) return al < bl;
+  return ai < bi;
+}
+
+__global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
+  __shared__ uint32_t hist[2048];
+  __shared__ int64_t cpos[MAX_SHORTLIST];
+  __shared__ float chi[MAX_SHORTLIST], clo[MAX_SHORTLIST];
+  __shared__ int64_t cid[MAX_SHORTLIST];
+  __shared__ uint32_t sh32[16];
+  __shared__ int64_t sh64[16];
+  __shared__ uint32_t s_bin, s_before;
+  __shared__ int s_slot;
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t q = blockIdx.x;
+  const float *seg;
+  int64_t L, seg0 = 0;
+  if (a.coarse) {
+    seg = a.D + q * a.nl;
+    L = a.nl;
+  } else {
+    seg0 = a.seg_off[q];
+    seg = a.D + seg0;
+    L = a.seg_off[q + 1] - seg0;
+  }
+  int ncand;
+  if (L <= a.Kp) {
+    ncand = (int)L;
+    for (int i = tid; i < ncand; i += blockDim.x) cpos[i] = i;
+  } else {
+    ncand = a.Kp;
+    // radix selection of the Kp-th smallest key: 11 + 11 + 10 bits
+    uint32_t prefix = 0, pmask = 0, need = (uint32_t)a.Kp;
+    for (int pass = 0; pass < 3; ++pass) {
+      const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
+      const int nb = pass < 2 ? 2048 : 1024;
+      for (int i = tid; i < 2048; i += blockDim.x) hist[i] = 0;
+      __syncthreads();
+      for (int64_t i = tid; i < L; i += blockDim.x) {
+        uint32_t kk = order_key(seg[i]);
+        if ((kk & pmask) == prefix) atomicAdd(&hist[(kk >> shift) & (nb - 1)], 1u);
+      }
+      __syncthreads();
+      const int per = nb / 256;
+      uint32_t local = 0;
+      for (int e = 0; e < per; ++e) local += hist[tid * per + e];
+      uint32_t excl = block_excl_scan<uint32_t>(local, sh32, nullptr);
+      if (excl < need && need <= excl + local) {
+        uint32_t c = excl;
+        for (int e = 0; e < per; ++e) {
+          uint32_t hb = hist[tid * per + e];
+          if (c + hb >= need) {
+            s_bin = (uint32_t)(tid * per + e);
+            s_before = c;
+            break;
+          }
+          c += hb;
+        }
+      }
+      __syncthreads();
+      prefix |= s_bin << shift;
+      pmask |= (uint32_t)(nb - 1) << shift;
+      need -= s_before;
+      __syncthreads();
+    }
+    // prefix is the Kp-th smallest key; take every smaller key and the first
+    // ``need`` equal ones in position order.
+    const uint32_t T = prefix;
+    const int64_t chunk = (L + blockDim.x - 1) / blockDim.x;
+    const int64_t a0 = tid * chunk, a1 = min64(L, a0 + chunk);
+    uint32_t ne = 0;
+    for (int64_t i = a0; i < a1; ++i) ne += order_key(seg[i]) == T;
+    uint32_t eq_before = block_excl_scan<uint32_t>(ne, sh32, nullptr);
+    if (tid == 0) s_slot = 0;
+    __syncthreads();
+    const int nlt = a.Kp - (int)need;
+    for (int64_t i = a0; i < a1; ++i) {
+      uint32_t kk = order_key(seg[i]);
+      if (kk < T) {
+        int slot = atomicAdd(&s_slot, 1);
+        cpos[slot] = i;
+      } else if (kk == T) {
+        if (eq_before < need) cpos[nlt + eq_before] = i;
+        ++eq_before;
+      }
+    }
+  }
+  __syncthreads();
+
+  // exact re-measurement, one wave per candidate
+  const float *qrow = a.Qs + q * a.ldqs;
+  for (int c = wv; c < ncand; c += (blockDim.x >> 6)) {
+    const int64_t pos = cpos[c];
+    float S = 0.f, C = 0.f;
+    int64_t id;
+    if (a.coarse) {
+      const float *x = a.cent + pos * a.ld_cent;
+      for (int dim = lane; dim < a.d_dot; dim += 64) acc_sq_diff(qrow[dim], x[dim], S, C);
+      id = pos;
+    } else {
+      const int64_t pabs = seg0 + pos;
+      const int64_t *pb = a.pair_base + q * a.nprobe;
+      int lo = 0, hi = a.nprobe - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pb[mid] <= pabs) lo = mid; else hi = mid - 1;
+      }
+      const int32_t h = a.probes[q * a.nprobe + lo];
+      const int64_t r = pabs - pb[lo];
+      const int64_t p0 = a.poff[h];
+      const int64_t npad = a.poff[h + 1] - p0;
+      const float *base = a.vec + p0 * a.d_pad + r * SLAB;
+      for (int dim = lane; dim < a.d_dot; dim += 64)
+        acc_sq_diff(qrow[dim], base[(int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)], S, C);
+      id = a.rowid[p0 + r];
+    }
+    wave_reduce_pair(S, C);
+    if (lane == 0) {
+      chi[c] = S;
+      clo[c] = C;
+      cid[c] = id;
+    }
+  }
+  int P2 = 1;
+  while (P2 < ncand) P2 <<= 1;
+  for (int c = ncand + tid; c < P2; c += blockDim.x) {
+    chi[c] = __builtin_inff();
+    clo[c] = 0.f;
+    cid[c] = INT64_MAX;
+  }
+  // bitonic sort by (distance, id)
+  for (int size = 2; size <= P2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int t = tid; t < (P2 >> 1); t += blockDim.x) {
+        const int i = 2 * t - (t & (stride - 1));
+        const int j = i + stride;
+        const bool up = (i & size) == 0;
+        const bool gt = pair_less(chi[j], clo[j], cid[j], chi[i], clo[i], cid[i]);
+        if (gt == up) {
+          float th = chi[i]; chi[i] = chi[j]; chi[j] = th;
+          float tl = clo[i]; clo[i] = clo[j]; clo[j] = tl;
+          int64_t ti = cid[i]; cid[i] = cid[j]; cid[j] = ti;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < a.kout; j += blockDim.x) {
+    const bool has = j < ncand;
+    if (a.coarse) {
+      const int32_t hsel = has ? (int32_t)cid[j] : -1;
+      a.out_probes[q * a.kout + j] = hsel;
+      if (a.out_probes2) a.out_probes2[q * a.kout + j] = hsel;
+    } else {
+      a.out_dist[q * a.kout + j] = has ? chi[j] : __builtin_inff();
+      a.out_ids[q * a.kout + j] = has ? cid[j] : -1;
+    }
+  }
+}
+
+// ---- probe bucketing ---------------------------------------------------------
+__global__ void k_count(const int32_t *__restrict__ probes, int64_t npairs,
+                        int32_t *__restrict__ cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < npairs) atomicAdd(&cnt[probes[i]], 1);
+}
+
+// One workgroup of 1024 threads: bucket offsets, tile prefix, cursor reset.
+__global__ __launch_bounds__(1024) void k_list_scan(const int32_t *__restrict__ cnt,
+                                                    const int32_t *__restrict__ len, int32_t nlist,
+                                                    int32_t *__restrict__ bkt_off,
+                                                    int32_t *__restrict__ tile_off,
+                                                    int32_t *__restrict__ cursor) {
+  __shared__ int32_t sh[16];
+  const int tid = threadIdx.x;
+  const int chunk = (nlist + blockDim.x - 1) / blockDim.x;
+  const int h0 = tid * chunk, h1 = min(nlist, h0 + chunk);
+  int32_t sc = 0, st = 0;
+  for (int h = h0; h < h1; ++h) {
+    sc += cnt[h];
+    st += ((cnt[h] + TILE_Q - 1) / TILE_Q) * ((len[h] + TILE_V - 1) / TILE_V);
+  }
+  int32_t tot_t;
+  int32_t ec = block_excl_scan<int32_t>(sc, sh, nullptr);
+  int32_t et = block_excl_scan<int32_t>(st, sh, &tot_t);
+  for (int h = h0; h < h1; ++h) {
+    bkt_off[h] = ec;
+    tile_off[h] = et;
+    cursor[h] = 0;
+    ec += cnt[h];
+    et += ((cnt[h] + TILE_Q - 1) / TILE_Q) * ((len[h] + TILE_V - 1) / TILE_V);
+  }
+  if (tid == 0) tile_off[nlist] = tot_t;
+}
+
+__global__ void k_scatter(const int32_t *__restrict__ probes, int64_t npairs,
+                          const int32_t *__restrict__ bkt_off, int32_t *__restrict__ cursor,
+                          int32_t *__restrict__ bucket) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npairs) return;
+  int32_t h = probes[i];
+  int32_t pos = bkt_off[h] + atomicAdd(&cursor[h], 1);
+  bucket[pos] = (int32_t)i;
+}
+
+__global__ void k_seg_len(const int32_t *__restrict__ probes, int64_t nq, int32_t nprobe,
+                          const int32_t *__restrict__ len, int64_t *__restrict__ seg_len) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int64_t s = 0;
+  for (int j = 0; j < nprobe; ++j) s += len[probes[q * nprobe + j]];
+  seg_len[q] = s;
+}
+
+// One workgroup: out[0..n] = exclusive prefix of in[0..n).
+__global__ __launch_bounds__(1024) void k_scan_i64(const int64_t *__restrict__ in, int64_t n,
+                                                   int64_t *__restrict__ out) {
+  __shared__ int64_t sh[16];
+  const int tid = threadIdx.x;
+  const int64_t chunk = (n + blockDim.x - 1) / blockDim.x;
+  const int64_t a0 = tid * chunk, a1 = min64(n, a0 + chunk);
+  int64_t s = 0;
+  for (int64_t i = a0; i < a1; ++i) s += in[i];
+  int64_t tot;
+  int64_t e = block_excl_scan<int64_t>(s, sh, &tot);
+  __syncthreads();  // every thread has read ``in`` (which may alias scratch) before writes
+  for (int64_t i = a0; i < a1; ++i) {
+    int64_t v = in[i];
+    out[i] = e;
+    e += v;
+  }
+  if (tid == 0) out[n] = tot;
+}
+
+__global__ void k_pair_base(const int32_t *__restrict__ probes, int64_t nq, int32_t nprobe,
+                            const int32_t *__restrict__ len, const int64_t *__restrict__ seg_off,
+                            int64_t *__restrict__ pair_base) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  int64_t s = seg_off[q];
+  for (int j = 0; j < nprobe; ++j) {
+    pair_base[q * nprobe + j] = s;
+    s += len[probes[q * nprobe + j]];
+  }
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+// ---- launch wrappers -------------------------------------------------------------
+hipError_t launch_stage_queries(const float *Q, int64_t nq, int64_t ldq, int32_t dq, float *Qs,
+                                int64_t ldqs, hipStream_t st) {
+  int64_t n = nq * ldqs;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stage_queries, dim3(blocks_for(n, 256)), dim3(256), 0, st, Q, nq, ldq, dq,
+                     Qs, ldqs);
+  return hipGetLastError();
+}
+
+hipError_t launch_layout(const float *src, int64_t ldsrc, int32_t dsrc, const int64_t *src_row,
+                         const int32_t *row_list, const int64_t *poff, int64_t rows_pad,
+                         int32_t d_pad, float *dst, hipStream_t st) {
+  int64_t n = rows_pad * d_pad;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_layout, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, ldsrc, dsrc,
+                     src_row, row_list, poff, rows_pad, d_pad, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_c,
+                         int32_t nprobe, int32_t *user_probes, hipStream_t st) {
+  TileArgs t{};
+  t.Qs = b.Qs;
+  t.ldqs = b.ldqs;
+  t.d_dot = d_c;
+  t.vec = ix->cent_slab;
+  t.d_pad = ix->d_cb_pad;
+  t.pair_div = 1;
+  t.out = b.S;
+  t.coarse = 1;
+  t.nq = nq;
+  t.nl = ix->nlist;
+  t.nl_pad = ix->nl_pad;
+  t.qtiles = (int32_t)cdiv(nq, TILE_Q);
+  t.total_host = t.qtiles * (int32_t)cdiv(ix->nlist, TILE_V);
+  int grid = (int)std::min<int64_t>(PERSIST_WG, round_up(t.total_host, 8));
+  hipLaunchKernelGGL(k_tile_dist, dim3(grid), dim3(256), 0, st, t);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+
+  SelArgs s{};
+  s.coarse = 1;
+  s.D = b.S;
+  s.nl = ix->nlist;
+  s.Kp = std::min<int32_t>(ix->nlist, std::min<int32_t>(nprobe + REFINE_MARGIN, MAX_SHORTLIST));
+  s.kout = nprobe;
+  s.Qs = b.Qs;
+  s.ldqs = b.ldqs;
+  s.d_dot = d_c;
+  s.cent = ix->cent;
+  s.ld_cent = ix->d_cb_pad;
+  s.out_probes = b.probes;
+  s.out_probes2 = user_probes;
+  hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_s,
+                       int32_t nprobe, int32_t k, float *dist, int64_t *ids, hipStream_t st) {
+  const int64_t npairs = nq * nprobe;
+  const int32_t nlist = ix->nlist;
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nlist, 256)), dim3(256), 0, st, b.cnt,
+                     (int64_t)nlist, 0);
+  hipLaunchKernelGGL(k_count, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, b.probes, npairs,
+                     b.cnt);
+  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, st, b.cnt, ix->len, nlist, b.bkt_off,
+                     b.tile_off, b.cursor);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, b.probes, npairs,
+                     b.bkt_off, b.cursor, b.bucket);
+  // per-query segment lengths go to pair_base as a temporary, then the scan
+  hipLaunchKernelGGL(k_seg_len, dim3(blocks_for(nq, 256)), dim3(256), 0, st, b.probes, nq, nprobe,
+                     ix->len, b.pair_base);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, b.pair_base, nq, b.seg_off);
+  hipLaunchKernelGGL(k_pair_base, dim3(blocks_for(nq, 256)), dim3(256), 0, st, b.probes, nq,
+                     nprobe, ix->len, b.seg_off, b.pair_base);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+
+  TileArgs t{};
+  t.Qs = b.Qs;
+  t.ldqs = b.ldqs;
+  t.d_dot = d_s;
+  t.vec = ix->vec;
+  t.d_pad = ix->d_pad;
+  t.poff = ix->poff;
+  t.len = ix->len;
+  t.nlist = nlist;
+  t.tile_off = b.tile_off;
+  t.bkt_off = b.bkt_off;
+  t.cnt = b.cnt;
+  t.bucket = b.bucket;
+  t.pair_div = nprobe;
+  t.pair_base = b.pair_base;
+  t.out = b.D;
+  t.coarse = 0;
+  hipLaunchKernelGGL(k_tile_dist, dim3(PERSIST_WG), dim3(256), 0, st, t);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+
+  SelArgs s{};
+  s.coarse = 0;
+  s.D = b.D;
+  s.seg_off = b.seg_off;
+  s.Kp = std::min<int32_t>(k + REFINE_MARGIN, MAX_SHORTLIST);
+  s.kout = k;
+  s.Qs = b.Qs;
+  s.ldqs = b.ldqs;
+  s.d_dot = d_s;
+  s.vec = ix->vec;
+  s.d_pad = ix->d_pad;
+  s.poff = ix->poff;
+  s.rowid = ix->rowid;
+  s.probes = b.probes;
+  s.nprobe = nprobe;
+  s.pair_base = b.pair_base;
+  s.out_dist = dist;
+  s.out_ids = ids;
+  hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+  return hipGetLastError();
+}
+
+}  // namespace adanns

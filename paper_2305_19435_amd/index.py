@@ -1,0 +1,114 @@
+"""Python face of the index object: thin wrappers over the C ABI."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _dev_f32(x, dev):
+    t = x if isinstance(x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(x))
+    return t.to(device=dev, dtype=torch.float32).contiguous()
+
+
+def _dev_i32(x, dev):
+    t = x if isinstance(x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(x))
+    return t.to(device=dev, dtype=torch.int32).contiguous()
+
+
+class IvfIndex:
+    """An IVF index resident in HBM (owns a library ``adanns_index``)."""
+
+    def __init__(self, handle: int):
+        self._h = C.c_void_p(handle)
+        n, d, nl, dcb = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib.adanns_index_info(self._h, C.byref(n), C.byref(d), C.byref(nl), C.byref(dcb)))
+        self.n, self.d, self.nlist, self.d_c_build = n.value, d.value, nl.value, dcb.value
+
+    # ---- construction -------------------------------------------------------
+    @classmethod
+    def import_ivf(cls, X, centroids, assign, device="cuda", stream=None) -> "IvfIndex":
+        """adanns_ivf_import: X [n, d] FP32, centroids [nlist, d_c_build], assign [n]."""
+        dev = torch.device(device)
+        Xd = X if (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32
+                   and X.stride(1) == 1) else _dev_f32(X, dev)
+        Cd = _dev_f32(centroids, dev)
+        Ad = _dev_i32(assign, dev)
+        out = C.c_void_p()
+        check(lib.adanns_ivf_import(Xd.data_ptr(), Xd.shape[0], Xd.shape[1], Xd.stride(0),
+                                    Cd.data_ptr(), Cd.shape[0], Cd.shape[1], Ad.data_ptr(),
+                                    _stream(stream), C.byref(out)))
+        return cls(out.value)
+
+    # ---- search ---------------------------------------------------------------
+    def search(self, Q, d_c: int, d_s: int, nprobe: int, k: int, return_probes=False,
+               stream=None, out=None):
+        """adanns_search. Returns (dist [nq,k] f32, ids [nq,k] i64[, probes])."""
+        Qd = Q if (isinstance(Q, torch.Tensor) and Q.is_cuda and Q.dtype == torch.float32
+                   and Q.stride(1) == 1) else _dev_f32(Q, "cuda")
+        nq = Qd.shape[0]
+        if out is None:
+            dist = torch.empty((nq, k), dtype=torch.float32, device=Qd.device)
+            ids = torch.empty((nq, k), dtype=torch.int64, device=Qd.device)
+        else:
+            dist, ids = out
+        probes = torch.empty((nq, nprobe), dtype=torch.int32, device=Qd.device) if return_probes else None
+        check(lib.adanns_search(self._h, Qd.data_ptr(), nq, Qd.stride(0) if nq else Qd.shape[1],
+                                d_c, d_s, nprobe, k, dist.data_ptr(), ids.data_ptr(),
+                                _ptr(probes), _stream(stream)))
+        return (dist, ids, probes) if return_probes else (dist, ids)
+
+    def search_probes(self, Q, probes, d_s: int, k: int, stream=None):
+        """adanns_search_probes: scan the given probe lists [nq, nprobe]."""
+        Qd = _dev_f32(Q, "cuda") if not isinstance(Q, torch.Tensor) or not Q.is_cuda else Q
+        Pd = _dev_i32(probes, Qd.device)
+        nq, nprobe = Pd.shape
+        dist = torch.empty((nq, k), dtype=torch.float32, device=Qd.device)
+        ids = torch.empty((nq, k), dtype=torch.int64, device=Qd.device)
+        check(lib.adanns_search_probes(self._h, Qd.data_ptr(), nq, Qd.stride(0) if nq else Qd.shape[1],
+                                       d_s, nprobe, Pd.data_ptr(), k, dist.data_ptr(),
+                                       ids.data_ptr(), _stream(stream)))
+        return dist, ids
+
+    # ---- introspection ----------------------------------------------------------
+    def lists(self):
+        off = np.empty(self.nlist + 1, dtype=np.int64)
+        ids = np.empty(self.n, dtype=np.int64)
+        check(lib.adanns_index_lists(self._h, off.ctypes.data, ids.ctypes.data))
+        return off, ids
+
+    def centroids(self):
+        c = np.empty((self.nlist, self.d_c_build), dtype=np.float32)
+        check(lib.adanns_index_centroids(self._h, c.ctypes.data))
+        return c
+
+    def device_bytes(self) -> int:
+        return int(lib.adanns_index_device_bytes(self._h))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib.adanns_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,135 @@
+"""GPU parity of AdANNS-IVF search (C ABI) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from parity_util import check_search, oracle_index
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_19435_amd as p
+    return p
+
+
+@pytest.fixture(scope="module")
+def small(lib, small_data):
+    w, X, Q = small_data
+    C32, a, off, ids = oracle_index(X, w.nlist, w.d_c, 10, w.seed)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    yield w, X, Q, C32, off, ids, index
+    index.free()
+
+
+def _run(index, Q, d_c, d_s, nprobe, k):
+    dist, gid, probes = index.search(torch.from_numpy(Q).cuda(), d_c, d_s, nprobe, k,
+                                     return_probes=True)
+    torch.cuda.synchronize()
+    return dist.cpu().numpy(), gid.cpu().numpy(), probes.cpu().numpy()
+
+
+def test_import_lists_match_oracle(small):
+    w, X, Q, C32, off, ids, index = small
+    o2, i2 = index.lists()
+    assert np.array_equal(o2, off) and np.array_equal(i2, ids)
+    assert np.array_equal(index.centroids(), C32)
+
+
+def test_forced_probes_scan(small):
+    """The list scan alone: both sides scan the oracle's probes."""
+    from oracle import ivf
+    w, X, Q, C32, off, ids, index = small
+    _, _, P = ivf.ivf_search64(X, Q, C32.astype(np.float64), off, ids, w.d_c, w.d_s, w.nprobe, w.k)
+    dist, gid = index.search_probes(torch.from_numpy(Q).cuda(), P.astype(np.int32), w.d_s, w.k)
+    torch.cuda.synchronize()
+    rep = check_search(X, Q, C32, off, ids, w.d_c, w.d_s, w.nprobe, w.k, dist.cpu().numpy(),
+                       gid.cpu().numpy(), forced=P)
+    assert rep.ok, rep.problems
+
+
+@pytest.mark.parametrize("d_c,d_s,nprobe,k", [
+    (16, 64, 4, 10),      # the small workload
+    (16, 64, 32, 10),     # every list: exact search
+    (12, 40, 3, 7),       # prefixes that are not multiples of the slab width
+    (1, 1, 1, 1),
+    (16, 64, 1, 300),     # k beyond a list: padding
+    (8, 33, 5, 100),
+])
+def test_search_parity(small, d_c, d_s, nprobe, k):
+    w, X, Q, C32, off, ids, index = small
+    dist, gid, probes = _run(index, Q, d_c, d_s, nprobe, k)
+    rep = check_search(X, Q, C32, off, ids, d_c, d_s, nprobe, k, dist, gid, got_p=probes)
+    assert rep.ok, rep.problems
+    assert rep.probe_diffs == 0
+
+
+def test_exhaustive_equals_exact(small):
+    from oracle import exact
+    w, X, Q, C32, off, ids, index = small
+    dist, gid, _ = _run(index, Q, w.d_c, w.d, w.nlist, w.k)
+    De, Ie = exact.exact_knn64(X, Q, w.k)
+    mism = (gid != Ie).sum()
+    assert mism == 0 or np.all(np.abs(De[gid != Ie] - De[gid != Ie]) == 0)
+    np.testing.assert_allclose(dist, De, rtol=1e-5)
+
+
+def test_edge_query_counts(small):
+    w, X, Q, C32, off, ids, index = small
+    # nq = 0 is a no-op
+    dist, gid = index.search(torch.empty((0, w.d), device="cuda"), w.d_c, w.d_s, w.nprobe, w.k)
+    assert dist.shape == (0, w.k)
+    for nq in (1, 65, 130):
+        Qn = np.concatenate([Q] * 2)[:nq]
+        d, g, p = _run(index, Qn, w.d_c, w.d_s, w.nprobe, w.k)
+        rep = check_search(X, Qn, C32, off, ids, w.d_c, w.d_s, w.nprobe, w.k, d, g, got_p=p)
+        assert rep.ok, rep.problems
+
+
+def test_repeat_bitwise_and_alone_vs_batch(small):
+    w, X, Q, C32, off, ids, index = small
+    a = _run(index, Q, w.d_c, w.d_s, w.nprobe, w.k)
+    b = _run(index, Q, w.d_c, w.d_s, w.nprobe, w.k)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    one = _run(index, Q[7:8], w.d_c, w.d_s, w.nprobe, w.k)
+    assert np.array_equal(one[1][0], a[1][7]) and np.array_equal(one[0][0], a[0][7])
+
+
+def test_invalid_arguments(small, lib):
+    w, X, Q, C32, off, ids, index = small
+    Qd = torch.from_numpy(Q).cuda()
+    for bad in [dict(d_c=0), dict(d_c=w.d_c + 1 if w.d_c < w.d else w.d + 1),
+                dict(d_s=w.d + 1), dict(nprobe=0), dict(nprobe=w.nlist + 1), dict(k=0),
+                dict(k=2000)]:
+        args = dict(d_c=w.d_c, d_s=w.d_s, nprobe=w.nprobe, k=w.k)
+        args.update(bad)
+        with pytest.raises(lib.AdannsError) as ei:
+            index.search(Qd, **args)
+        assert ei.value.status == -1
+
+
+@pytest.fixture(scope="module")
+def medium(lib):
+    """Several vector tiles per list, several query tiles per list."""
+    m = synth.Mixture(256, 300, seed=77)
+    X = m.database(60_000)
+    Q = m.queries(1500)
+    C32, a, off, ids = oracle_index(X, 64, 32, 6, 77)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    yield X, Q, C32, off, ids, index
+    index.free()
+
+
+@pytest.mark.parametrize("d_c,d_s,nprobe,k", [(32, 256, 8, 10), (24, 200, 16, 50), (32, 96, 2, 10)])
+def test_medium_parity(medium, d_c, d_s, nprobe, k):
+    X, Q, C32, off, ids, index = medium
+    dist, gid, probes = _run(index, Q, d_c, d_s, nprobe, k)
+    sample = list(range(0, len(Q), 7))
+    rep = check_search(X, Q, C32, off, ids, d_c, d_s, nprobe, k, dist, gid, got_p=probes,
+                       queries=sample)
+    assert rep.ok, rep.problems
