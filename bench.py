@@ -1,0 +1,287 @@
+#!/usr/bin/env python
+"""Benchmark of the AdANNS-IVF search hot path on one MI355X.
+
+One step = one ``adanns_search`` over the whole query batch: coarse
+assignment on the d_c prefix (MFMA tile kernel + selection), probe
+bucketing, the list scan on the d_s prefix (MFMA tile kernel) and the
+per-query top-k merge with exact re-measurement (Algorithm 1, inference).
+
+Workload (default): the ImageNet-1K shape of the paper's retrieval
+experiments (Section 3 "Datasets", Appendix C): N = 1,281,167 vectors of
+d = 2048, 50,000 queries, nlist = 1024, d_s = 2048, k = 10, searched at
+d_c = 64, nprobe = 8 (one point of the d_c x nprobe grid). Inputs are
+seeded synthetic mixtures (``synth``), resident in HBM before timing. The
+index is built by the library on the GPU (adanns_build_ivf: 10 Lloyd
+iterations on 64 * nlist seeded training rows, then one assignment of every
+row).
+
+The CPU-baseline leg times the FP64 oracle's IVF search on a bounded sample
+of the same queries against an index the oracle builds itself from the same
+training rows and initial centroids, reports recall@10 of both against exact
+FP64 search, and checks the library's search on the oracle-built index
+against the oracle query by query (tie-aware ids, distances to 1e-5).
+
+Prints one JSON line (rank 0, N = 1 only).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "QPS at recall@10 parity with FP64 oracle; p50/p99 latency; % HBM roofline"
+MFMA_FP32_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="imagenet1k")
+    ap.add_argument("--n", type=int, default=None, help="database rows (default: workload)")
+    ap.add_argument("--nq", type=int, default=None)
+    ap.add_argument("--dc", type=int, default=None)
+    ap.add_argument("--nprobe", type=int, default=None)
+    ap.add_argument("--iters", type=int, default=10)
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2305_19435_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, per_launch_units: float):
+    """HBM bytes per launch from committed counter summaries, if they were
+    taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
+                                   "design (see DESIGN.md), --gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    import paper_2305_19435_amd as lib
+
+    torch.cuda.set_device(0)
+    w = synth.WORKLOADS[args.workload]
+    n = args.n or w.n
+    nq = args.nq or w.nq
+    d_c = args.dc or w.d_c
+    nprobe = args.nprobe or w.nprobe
+    d_s, k, nlist = w.d_s, w.k, w.nlist
+    mix = w.mixture()
+
+    t0 = time.time()
+    X = mix.database(n)
+    Q = mix.queries(nq)
+    log(f"generated X {X.shape} Q {Q.shape} in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    Xd = torch.from_numpy(X).cuda()
+    Qd = torch.from_numpy(Q).cuda()
+    torch.cuda.synchronize()
+    log(f"uploaded in {time.time() - t0:.1f}s")
+
+    n_train = min(n, 64 * nlist)
+    train_rows = synth.subsample_rows(n, n_train, w.seed)
+    init = synth.init_rows(n_train, nlist, w.seed)
+    t0 = time.time()
+    index, obj = lib.IvfIndex.build_ivf(Xd, nlist, d_c, args.iters, init, train_rows=train_rows,
+                                         return_objective=True)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    log(f"GPU index built in {build_s:.1f}s; objective {obj[0]:.1f} -> {obj[-1]:.1f}")
+    del Xd
+    torch.cuda.empty_cache()
+
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy: 1 GiB read, 1 GiB written")
+
+    stream = torch.cuda.current_stream()
+    dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+    ids = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+    for _ in range(args.warmup):
+        index.search(Qd, d_c, d_s, nprobe, k, out=(dist, ids))
+    torch.cuda.synchronize()
+
+    lib.timing_reset()
+    lib.timing_enable(True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        index.search(Qd, d_c, d_s, nprobe, k, out=(dist, ids))
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    lib.timing_enable(False)
+    step_ms = np.array([a.elapsed_time(b) for a, b in evs])
+    kern = {}
+    for name in ("tile_dist_coarse", "select_coarse", "bucketing", "tile_dist_scan", "select_scan"):
+        cnt, ms = lib.timing_read(name)
+        if cnt:
+            kern[name] = ms / cnt
+    ms_per_step = wall * 1000.0 / args.steps
+    qps = nq * args.steps / wall
+    log(f"{args.steps} steps: {ms_per_step:.3f} ms/step, {qps:,.0f} QPS; kernels {kern}")
+
+    # algorithmic work of one launch of each kernel
+    _, _, probes = index.search(Qd, d_c, d_s, nprobe, k, return_probes=True)
+    torch.cuda.synchronize()
+    off, _ = index.lists()
+    lens = np.diff(off)
+    cand = int(lens[probes.cpu().numpy().astype(np.int64)].sum())
+    flops = {
+        "tile_dist_scan": 2.0 * cand * d_s,
+        "tile_dist_coarse": 2.0 * nq * nlist * d_c,
+    }
+    dominant = max(kern, key=kern.get)
+    if dominant in flops:
+        ach = flops[dominant] / (kern[dominant] * 1e-3) / 1e12
+        roof = {"kernel": dominant, "bound": "mfma", "achieved": round(ach, 2),
+                "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / MFMA_FP32_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(dominant, w.name, 1.0),
+                "algorithmic_flops_per_launch": flops[dominant],
+                "avg_launch_ms": round(kern[dominant], 4)}
+    else:
+        roof = {"kernel": dominant, "bound": "alu", "achieved": None, "peak": None,
+                "unit": None, "frac": None, "traffic": None}
+    scan_bytes = 4.0 * n * d_s  # one read of the d_s prefix of every vector
+    roof["scan_hbm_floor_frac"] = round(scan_bytes / (kern.get("tile_dist_scan", 1e9) * 1e-3)
+                                        / 1e9 / HBM_PEAK_GBS, 4)
+
+    out = {
+        "metric": METRIC,
+        "value": round(qps, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded Gaussian mixture, decaying spectrum, L2-normalised",
+        "config": {"workload": f"{w.name}: N={n} d={w.d} nq={nq} nlist={nlist} d_c={d_c} "
+                               f"d_s={d_s} nprobe={nprobe} k={k}",
+                   "n": n, "d": w.d, "nq": nq, "nlist": nlist, "d_c": d_c, "d_s": d_s,
+                   "nprobe": nprobe, "k": k, "candidates_per_query": cand / nq,
+                   "index": f"GPU Lloyd, {args.iters} iters on {n_train} seeded rows",
+                   "index_build_s": round(build_s, 2)},
+        "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
+                       "p99": round(float(np.percentile(step_ms, 99)), 4),
+                       "note": "whole-batch latency per step"},
+        "kernels_avg_ms": {k_: round(v, 4) for k_, v in kern.items()},
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["recall_at_10"], out["oracle_parity"] = cpu_baseline_leg(
+            lib, torch, X, Q, ids.cpu().numpy(), train_rows, init, nlist, d_c, d_s, nprobe, k,
+            args.iters, args.cpu_sample)
+    index.free()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_leg(lib, torch, X, Q, gpu_ids, train_rows, init, nlist, d_c, d_s, nprobe, k,
+                     iters, sample):
+    """The FP64 oracle as it stands, on a bounded sample of the same workload."""
+    from oracle import check, exact, ivf, kmeans, metrics
+
+    t0 = time.time()
+    C64, _, _ = kmeans.kmeans64(X[train_rows, :d_c], nlist, iters, init)
+    C32 = C64.astype(np.float32)
+    a = kmeans.assign64(X[:, :d_c], C32.astype(np.float64))
+    off, ids = kmeans.build_lists(a, nlist)
+    log(f"oracle index built in {time.time() - t0:.1f}s")
+    qs = np.arange(min(sample, len(Q)))
+    t0 = time.perf_counter()
+    rd, ri, rp, cands = ivf.ivf_search64(X, Q[qs], C32.astype(np.float64), off, ids, d_c, d_s,
+                                         nprobe, k, return_candidates=True)
+    cpu_s = time.perf_counter() - t0
+    log(f"oracle search of {len(qs)} queries in {cpu_s:.1f}s")
+    t0 = time.time()
+    De, Ie = exact.exact_knn64(X, Q[qs], k)
+    log(f"exact ground truth in {time.time() - t0:.1f}s")
+    rec = {"gpu_index_gpu_search": metrics.k_recall_at_n(gpu_ids[qs], Ie, k),
+           "oracle_index_oracle_search": metrics.k_recall_at_n(ri, Ie, k),
+           "queries": int(len(qs)), "ground_truth": "exact FP64 k-NN at full d"}
+    # the library's search on the oracle-built index, checked query by query
+    t0 = time.time()
+    index = lib.IvfIndex.import_ivf(X, C32, a.astype(np.int32))
+    gd, gi, gp = index.search(torch.from_numpy(Q[qs]).cuda(), d_c, d_s, nprobe, k,
+                              return_probes=True)
+    torch.cuda.synchronize()
+    gd, gi, gp = gd.cpu().numpy(), gi.cpu().numpy(), gp.cpu().numpy()
+    index.free()
+    rep = check.Report()
+    Cf = C32.astype(np.float64)
+    probe_ok = all(check.probes_valid(ivf.coarse64(Q[q], Cf, d_c), gp[j], nprobe)
+                   for j, q in enumerate(qs))
+    same_probes = bool(np.array_equal(gp, rp))
+    if probe_ok:
+        if not same_probes:
+            rd, ri, _, cands = ivf.ivf_search64(X, Q[qs], Cf, off, ids, d_c, d_s, nprobe, k,
+                                                forced_probes=gp, return_candidates=True)
+        for j, q in enumerate(qs):
+            check.compare_knn(Q[q], X, cands[j], gd[j], gi[j], rd[j], ri[j], d_s, report=rep,
+                              tag=f"q{q}")
+    parity = {"queries": int(len(qs)), "probes_valid": bool(probe_ok), "ok": bool(rep.ok and probe_ok),
+              "id_ties": rep.id_mismatch_ties, "max_rel_dist_err": rep.max_rel_dist_err,
+              "problems": rep.problems[:3]}
+    log(f"oracle parity {parity} in {time.time() - t0:.1f}s")
+    base = {"value": round(len(qs) / cpu_s, 3), "unit": "queries/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {len(qs)} queries of the same workload, FP64 IVF search "
+                      f"(single-threaded NumPy) on the oracle's own index"}
+    return base, rec, parity
+
+
+if __name__ == "__main__":
+    main()

@@ -80,6 +80,30 @@ adanns_status adanns_ivf_import(const float *X, int64_t n, int32_t d, int64_t ld
                                 const int32_t *assign, void *stream, adanns_index **out);
 
 /*
+ * Build an IVF index on the GPU: Lloyd's k-means on X[:, :d_c] (Section 3,
+ * "Inverted File Index"; Section 4.1; Algorithm 1, construction), then one
+ * final assignment of every row, which defines the inverted lists.
+ *   X          device, [n x d] FP32, row stride ldx >= d. Copied.
+ *   train_rows host, [n_train] int64 rows of X the iterations run on, or
+ *              NULL for all rows (then n_train is ignored).
+ *   init_rows  host, [nlist] int32 indices into the training rows: the
+ *              initial centroids (the caller draws them, e.g. the first
+ *              nlist entries of a seeded permutation).
+ *   iters      assign/update rounds, 0..1000. Assignment ties go to the
+ *              smaller centroid index; an empty cluster keeps its centroid.
+ *   objective  host, [iters + 1] doubles or NULL: the k-means objective on
+ *              the training rows after each assignment, the last entry after
+ *              the final assignment.
+ * Centroids are FP32 (each update is a compensated-sum mean rounded to
+ * FP32). Limits as adanns_ivf_import; the training set must hold at least
+ * nlist rows. Synchronises ``stream``; allocates temporary device memory.
+ */
+adanns_status adanns_build_ivf(const float *X, int64_t n, int32_t d, int64_t ldx, int32_t nlist,
+                               int32_t d_c, int32_t iters, const int32_t *init_rows,
+                               const int64_t *train_rows, int64_t n_train, double *objective,
+                               void *stream, adanns_index **out);
+
+/*
  * AdANNS-IVF search (Algorithm 1, inference; Appendix A, Table "formula"):
  * probes = the nprobe clusters nearest to Q[i, :d_c] on the centroids'
  * first d_c coordinates; result = the k rows of the probed lists nearest to
@@ -107,6 +131,19 @@ adanns_status adanns_search_probes(const adanns_index *index, const float *Q, in
                                    int64_t ldq, int32_t d_s, int32_t nprobe,
                                    const int32_t *probes, int32_t k, float *dist,
                                    int64_t *ids, void *stream);
+
+/*
+ * Kernel timing with HIP events, for measurement tools. While enabled, every
+ * search records an event pair around each of its kernel groups on its
+ * stream ("tile_dist_coarse", "select_coarse", "bucketing",
+ * "tile_dist_scan", "select_scan", and the variants of the other search
+ * forms). adanns_timing_read() waits for the recorded events and returns the
+ * number of timed launches and their total milliseconds since the last
+ * reset; unknown names read as 0 launches. Process-wide; thread-safe.
+ */
+adanns_status adanns_timing_enable(int32_t enable);
+adanns_status adanns_timing_reset(void);
+adanns_status adanns_timing_read(const char *kernel, int64_t *launches, double *total_ms);
 
 /* Sizes of an index. Any out pointer may be NULL. */
 adanns_status adanns_index_info(const adanns_index *index, int64_t *n, int32_t *d,

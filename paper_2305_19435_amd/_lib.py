@@ -31,6 +31,10 @@ _SIGS = {
     "adanns_last_error": (C.c_char_p, []),
     "adanns_version": (C.c_char_p, []),
     "adanns_ivf_import": (C.c_int, [vp, i64, i32, i64, vp, i32, i32, vp, vp, PIX]),
+    "adanns_build_ivf": (C.c_int, [vp, i64, i32, i64, i32, i32, i32, vp, vp, i64, vp, vp, PIX]),
+    "adanns_timing_enable": (C.c_int, [i32]),
+    "adanns_timing_reset": (C.c_int, []),
+    "adanns_timing_read": (C.c_int, [C.c_char_p, vp, vp]),
     "adanns_search": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, vp, vp, vp, vp]),
     "adanns_search_probes": (C.c_int, [vp, vp, i64, i64, i32, i32, vp, i32, vp, vp, vp]),
     "adanns_index_info": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -62,3 +66,19 @@ def last_error() -> str:
 
 def version() -> str:
     return lib.adanns_version().decode()
+
+
+def timing_enable(on: bool = True):
+    check(lib.adanns_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    check(lib.adanns_timing_reset())
+
+
+def timing_read(kernel: str):
+    """(launches, total_ms) of a kernel group since the last reset."""
+    n = C.c_int64()
+    ms = C.c_double()
+    check(lib.adanns_timing_read(kernel.encode(), C.addressof(n), C.addressof(ms)))
+    return n.value, ms.value

@@ -1,6 +1,7 @@
 // C ABI of the library: argument validation, index import and layout,
 // per-stream scratch memory and the search driver. See include/adanns.h.
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -42,6 +43,53 @@ adanns_status get_scratch(adanns_index *ix, hipStream_t stream, size_t bytes, vo
     s.bytes = want;
   }
   *out = s.base;
+  return ADANNS_OK;
+}
+
+// ---- kernel timing -------------------------------------------------------------
+static std::atomic<bool> g_timing{false};
+static std::mutex g_tmu;
+struct PendingTimer {
+  std::string name;
+  hipEvent_t a, b;
+};
+static std::vector<PendingTimer> g_pending;
+static std::map<std::string, std::pair<int64_t, double>> g_totals;
+
+bool timing_on() { return g_timing.load(std::memory_order_relaxed); }
+
+KernelTimer::KernelTimer(const char *n, hipStream_t s) : name(n), st(s) {
+  if (!timing_on()) return;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    (void)hipGetLastError();
+    if (a) (void)hipEventDestroy(a);
+    a = b = nullptr;
+    return;
+  }
+  (void)hipEventRecord(a, st);
+}
+
+void KernelTimer::stop() {
+  if (!a) return;
+  (void)hipEventRecord(b, st);
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_pending.push_back({name, a, b});
+  a = b = nullptr;
+}
+
+static adanns_status resolve_timers() {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (auto &p : g_pending) {
+    float ms = 0.f;
+    ADANNS_HIP(hipEventSynchronize(p.b));
+    ADANNS_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+    auto &t = g_totals[p.name];
+    t.first += 1;
+    t.second += ms;
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  g_pending.clear();
   return ADANNS_OK;
 }
 
@@ -134,7 +182,8 @@ adanns_status build_layout(adanns_index *ix, const float *X, int64_t ldx,
 }
 
 // Centroids: a zero-padded row-major copy and a one-list slab layout.
-adanns_status build_centroids(adanns_index *ix, const float *centroids, hipStream_t st) {
+adanns_status build_centroids(adanns_index *ix, const float *centroids, int64_t ldc,
+                              hipStream_t st) {
   const int32_t nlist = ix->nlist;
   adanns_status s;
   if ((s = dmalloc(ix, (void **)&ix->cent, (size_t)nlist * ix->d_cb_pad * sizeof(float)))) return s;
@@ -142,7 +191,7 @@ adanns_status build_centroids(adanns_index *ix, const float *centroids, hipStrea
     return s;
   ADANNS_HIP(hipMemsetAsync(ix->cent, 0, (size_t)nlist * ix->d_cb_pad * sizeof(float), st));
   ADANNS_HIP(hipMemcpy2DAsync(ix->cent, ix->d_cb_pad * sizeof(float), centroids,
-                              ix->d_cb * sizeof(float), ix->d_cb * sizeof(float), nlist,
+                              ldc * sizeof(float), ix->d_cb * sizeof(float), nlist,
                               hipMemcpyDeviceToDevice, st));
   std::vector<int64_t> src_row(ix->nl_pad, -1), poff = {0, ix->nl_pad};
   for (int32_t r = 0; r < nlist; ++r) src_row[r] = r;
@@ -202,6 +251,150 @@ adanns_status check_async() {
 
 using namespace adanns;
 
+static adanns_status init_index_shape(adanns_index *ix, int64_t n, int32_t d, int32_t nlist,
+                                      int32_t d_cb) {
+  (void)hipGetDevice(&ix->device);
+  ix->n = n;
+  ix->d = d;
+  ix->d_pad = (int32_t)round_up(d, SLAB);
+  ix->nlist = nlist;
+  ix->d_cb = d_cb;
+  ix->d_cb_pad = (int32_t)round_up(d_cb, SLAB);
+  ix->nl_pad = (int32_t)round_up(nlist, ROWPAD);
+  return ADANNS_OK;
+}
+
+// Lloyd's k-means on the GPU. Assignment = the coarse step with one probe
+// (first-pass MFMA scores, exact re-measurement of the best few, ties to the
+// smaller index); update = per-centroid mean in a fixed summation order.
+static adanns_status kmeans_gpu(const float *X, int64_t n, int64_t ldx, int32_t nlist, int32_t d_c,
+                                int32_t iters, const int32_t *init_rows, const int64_t *train_rows,
+                                int64_t n_train, double *objective, hipStream_t st,
+                                std::vector<int32_t> &assign_all, float **C_out) {
+  const int32_t dcp = (int32_t)round_up(d_c, SLAB);
+  const int64_t nt = train_rows ? n_train : n;
+  DevFree tmp;
+  // centroid-only index used by the coarse kernels
+  adanns_index cix;
+  init_index_shape(&cix, nlist, d_c, nlist, d_c);
+  float *C = nullptr, *Xt = nullptr, *S = nullptr, *mind = nullptr;
+  int32_t *asg = nullptr, *perm = nullptr, *d_init = nullptr;
+  int64_t *d_rows = nullptr, *d_off = nullptr;
+  const int64_t chunk = std::max<int64_t>(4096, std::min<int64_t>(262144, (int64_t(1) << 28) / nlist));
+  ADANNS_HIP(hipMalloc(&C, (size_t)nlist * dcp * sizeof(float)));
+  ADANNS_HIP(hipMalloc(&cix.cent_slab, (size_t)cix.nl_pad * dcp * sizeof(float)));
+  tmp.ptrs.push_back(cix.cent_slab);
+  ADANNS_HIP(hipMalloc(&Xt, (size_t)nt * dcp * sizeof(float)));
+  tmp.ptrs.push_back(Xt);
+  ADANNS_HIP(hipMalloc(&S, (size_t)chunk * nlist * sizeof(float)));
+  tmp.ptrs.push_back(S);
+  ADANNS_HIP(hipMalloc(&mind, (size_t)std::max(nt, std::min(n, chunk)) * sizeof(float)));
+  tmp.ptrs.push_back(mind);
+  ADANNS_HIP(hipMalloc(&asg, (size_t)std::max(nt, n) * sizeof(int32_t)));
+  tmp.ptrs.push_back(asg);
+  ADANNS_HIP(hipMalloc(&perm, (size_t)nt * sizeof(int32_t)));
+  tmp.ptrs.push_back(perm);
+  ADANNS_HIP(hipMalloc(&d_init, (size_t)nlist * sizeof(int32_t)));
+  tmp.ptrs.push_back(d_init);
+  ADANNS_HIP(hipMalloc(&d_off, (size_t)(nlist + 1) * sizeof(int64_t)));
+  tmp.ptrs.push_back(d_off);
+  float *Xc = nullptr;  // staged chunk for the final assignment of all rows
+  ADANNS_HIP(hipMalloc(&Xc, (size_t)std::min(n, chunk) * dcp * sizeof(float)));
+  tmp.ptrs.push_back(Xc);
+  if (train_rows) {
+    ADANNS_HIP(hipMalloc(&d_rows, (size_t)nt * sizeof(int64_t)));
+    tmp.ptrs.push_back(d_rows);
+    ADANNS_HIP(hipMemcpyAsync(d_rows, train_rows, nt * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  }
+  ADANNS_HIP(launch_stage_rows(X, ldx, d_rows, nullptr, nt, d_c, Xt, dcp, st));
+  ADANNS_HIP(hipMemcpyAsync(d_init, init_rows, nlist * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  ADANNS_HIP(launch_stage_rows(Xt, dcp, nullptr, d_init, nlist, d_c, C, dcp, st));
+  cix.cent = C;
+
+  std::vector<int32_t> h_asg(nt);
+  std::vector<float> h_mind(std::max(nt, n));
+  std::vector<int32_t> h_perm(nt);
+  std::vector<int64_t> h_off(nlist + 1);
+  std::vector<int64_t> src_row(cix.nl_pad, -1), poff = {0, cix.nl_pad};
+  for (int32_t r = 0; r < nlist; ++r) src_row[r] = r;
+  std::vector<int32_t> row_list(cix.nl_pad, 0);
+  int64_t *d_src = nullptr, *d_poff1 = nullptr;
+  int32_t *d_rl = nullptr;
+  ADANNS_HIP(hipMalloc(&d_src, cix.nl_pad * sizeof(int64_t)));
+  tmp.ptrs.push_back(d_src);
+  ADANNS_HIP(hipMalloc(&d_poff1, 2 * sizeof(int64_t)));
+  tmp.ptrs.push_back(d_poff1);
+  ADANNS_HIP(hipMalloc(&d_rl, cix.nl_pad * sizeof(int32_t)));
+  tmp.ptrs.push_back(d_rl);
+  ADANNS_HIP(hipMemcpyAsync(d_src, src_row.data(), cix.nl_pad * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  ADANNS_HIP(hipMemcpyAsync(d_poff1, poff.data(), 2 * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  ADANNS_HIP(hipMemcpyAsync(d_rl, row_list.data(), cix.nl_pad * sizeof(int32_t), hipMemcpyHostToDevice, st));
+
+  auto assign_rows = [&](const float *rows, int64_t ldr, int64_t count, int32_t *out_asg,
+                         float *out_min) -> adanns_status {
+    ADANNS_HIP(launch_layout(C, dcp, d_c, d_src, d_rl, d_poff1, cix.nl_pad, dcp, cix.cent_slab, st));
+    for (int64_t a0 = 0; a0 < count; a0 += chunk) {
+      const int64_t m = std::min(chunk, count - a0);
+      SearchBufs b{};
+      b.Qs = const_cast<float *>(rows) + a0 * ldr;
+      b.ldqs = ldr;
+      b.S = S;
+      b.probes = out_asg + a0;
+      ADANNS_HIP(launch_coarse(&cix, b, m, d_c, 1, nullptr, st, out_min + a0));
+    }
+    return ADANNS_OK;
+  };
+  adanns_status s;
+  for (int32_t it = 0; it < iters; ++it) {
+    if ((s = assign_rows(Xt, dcp, nt, asg, mind))) return s;
+    ADANNS_HIP(hipMemcpyAsync(h_asg.data(), asg, nt * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    ADANNS_HIP(hipMemcpyAsync(h_mind.data(), mind, nt * sizeof(float), hipMemcpyDeviceToHost, st));
+    ADANNS_HIP(hipStreamSynchronize(st));
+    if (objective) {
+      double J = 0.0;
+      for (int64_t j = 0; j < nt; ++j) J += h_mind[j];
+      objective[it] = J;
+    }
+    // stable counting sort of the training rows by cluster
+    std::fill(h_off.begin(), h_off.end(), 0);
+    for (int64_t j = 0; j < nt; ++j) h_off[h_asg[j] + 1]++;
+    for (int32_t h = 0; h < nlist; ++h) h_off[h + 1] += h_off[h];
+    std::vector<int64_t> cur(h_off.begin(), h_off.end() - 1);
+    for (int64_t j = 0; j < nt; ++j) h_perm[cur[h_asg[j]]++] = (int32_t)j;
+    ADANNS_HIP(hipMemcpyAsync(perm, h_perm.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    ADANNS_HIP(hipMemcpyAsync(d_off, h_off.data(), (nlist + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    ADANNS_HIP(launch_centroid_update(Xt, dcp, perm, d_off, nlist, d_c, C, dcp, st));
+  }
+  // final assignment of every row against the final centroids
+  assign_all.assign(n, 0);
+  ADANNS_HIP(launch_layout(C, dcp, d_c, d_src, d_rl, d_poff1, cix.nl_pad, dcp, cix.cent_slab, st));
+  for (int64_t a0 = 0; a0 < n; a0 += chunk) {
+    const int64_t m = std::min(chunk, n - a0);
+    ADANNS_HIP(launch_stage_rows(X + a0 * ldx, ldx, nullptr, nullptr, m, d_c, Xc, dcp, st));
+    SearchBufs b{};
+    b.Qs = Xc;
+    b.ldqs = dcp;
+    b.S = S;
+    b.probes = asg + a0;
+    ADANNS_HIP(launch_coarse(&cix, b, m, d_c, 1, nullptr, st, mind));
+    ADANNS_HIP(hipMemcpyAsync(h_mind.data() + a0, mind, m * sizeof(float), hipMemcpyDeviceToHost, st));
+  }
+  ADANNS_HIP(hipMemcpyAsync(assign_all.data(), asg, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  ADANNS_HIP(hipStreamSynchronize(st));
+  if (objective) {
+    double J = 0.0;
+    if (train_rows)
+      for (int64_t j = 0; j < nt; ++j) J += h_mind[train_rows[j]];
+    else
+      for (int64_t j = 0; j < n; ++j) J += h_mind[j];
+    objective[iters] = J;
+  }
+  cix.cent = nullptr;
+  cix.cent_slab = nullptr;  // freed by tmp
+  *C_out = C;
+  return ADANNS_OK;
+}
+
 extern "C" {
 
 const char *adanns_last_error(void) { return g_err; }
@@ -235,15 +428,8 @@ adanns_status adanns_ivf_import(const float *X, int64_t n, int32_t d, int64_t ld
     set_error("out of host memory");
     return ADANNS_ENOMEM;
   }
-  (void)hipGetDevice(&ix->device);
-  ix->n = n;
-  ix->d = d;
-  ix->d_pad = (int32_t)round_up(d, SLAB);
-  ix->nlist = nlist;
-  ix->d_cb = d_c_build;
-  ix->d_cb_pad = (int32_t)round_up(d_c_build, SLAB);
-  ix->nl_pad = (int32_t)round_up(nlist, ROWPAD);
-  if ((s = build_layout(ix, X, ldx, h_assign, st)) || (s = build_centroids(ix, centroids, st))) {
+  init_index_shape(ix, n, d, nlist, d_c_build);
+  if ((s = build_layout(ix, X, ldx, h_assign, st)) || (s = build_centroids(ix, centroids, d_c_build, st))) {
     free_index_memory(ix);
     delete ix;
     return s;
@@ -323,6 +509,85 @@ adanns_status adanns_search_probes(const adanns_index *index, const float *Q, in
       }
   }
   return search_common(index, Q, nq, ldq, 0, d_s, nprobe, probes, k, dist, ids, nullptr, stream);
+}
+
+adanns_status adanns_build_ivf(const float *X, int64_t n, int32_t d, int64_t ldx, int32_t nlist,
+                               int32_t d_c, int32_t iters, const int32_t *init_rows,
+                               const int64_t *train_rows, int64_t n_train, double *objective,
+                               void *stream, adanns_index **out) {
+  clear_error();
+  ADANNS_REQUIRE(out != nullptr, "out is NULL");
+  ADANNS_REQUIRE(X != nullptr && init_rows != nullptr, "X and init_rows must be non-NULL");
+  ADANNS_REQUIRE(n >= 1 && n < (int64_t(1) << 31), "n must be in [1, 2^31), got %lld",
+                 (long long)n);
+  ADANNS_REQUIRE(d >= 1 && d <= 8192, "d must be in [1, 8192], got %d", d);
+  ADANNS_REQUIRE(ldx >= d, "ldx (%lld) must be >= d (%d)", (long long)ldx, d);
+  ADANNS_REQUIRE(nlist >= 1 && nlist <= 65536, "nlist must be in [1, 65536], got %d", nlist);
+  ADANNS_REQUIRE(d_c >= 1 && d_c <= d, "d_c must be in [1, d], got %d", d_c);
+  ADANNS_REQUIRE(iters >= 0 && iters <= 1000, "iters must be in [0, 1000], got %d", iters);
+  const int64_t nt = train_rows ? n_train : n;
+  ADANNS_REQUIRE(nt >= nlist, "the training set (%lld rows) must hold at least nlist rows",
+                 (long long)nt);
+  if (train_rows)
+    for (int64_t j = 0; j < nt; ++j)
+      ADANNS_REQUIRE(train_rows[j] >= 0 && train_rows[j] < n, "train_rows[%lld] out of range",
+                     (long long)j);
+  for (int32_t h = 0; h < nlist; ++h)
+    ADANNS_REQUIRE(init_rows[h] >= 0 && init_rows[h] < nt, "init_rows[%d] = %d out of range", h,
+                   init_rows[h]);
+  adanns_status s = check_async();
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int32_t> assign;
+  float *C = nullptr;
+  if ((s = kmeans_gpu(X, n, ldx, nlist, d_c, iters, init_rows, train_rows, nt, objective, st,
+                      assign, &C))) {
+    if (C) (void)hipFree(C);
+    return s;
+  }
+  adanns_index *ix = new (std::nothrow) adanns_index();
+  if (!ix) {
+    (void)hipFree(C);
+    set_error("out of host memory");
+    return ADANNS_ENOMEM;
+  }
+  init_index_shape(ix, n, d, nlist, d_c);
+  if ((s = build_layout(ix, X, ldx, assign, st)) ||
+      (s = build_centroids(ix, C, round_up(d_c, SLAB), st))) {
+    (void)hipFree(C);
+    free_index_memory(ix);
+    delete ix;
+    return s;
+  }
+  (void)hipFree(C);
+  *out = ix;
+  return ADANNS_OK;
+}
+
+adanns_status adanns_timing_enable(int32_t enable) {
+  clear_error();
+  g_timing.store(enable != 0);
+  return ADANNS_OK;
+}
+
+adanns_status adanns_timing_reset(void) {
+  clear_error();
+  adanns_status s = resolve_timers();
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_totals.clear();
+  return s;
+}
+
+adanns_status adanns_timing_read(const char *kernel, int64_t *launches, double *total_ms) {
+  clear_error();
+  ADANNS_REQUIRE(kernel != nullptr, "kernel name is NULL");
+  adanns_status s = resolve_timers();
+  if (s) return s;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  auto it = g_totals.find(kernel);
+  if (launches) *launches = it == g_totals.end() ? 0 : it->second.first;
+  if (total_ms) *total_ms = it == g_totals.end() ? 0.0 : it->second.second;
+  return ADANNS_OK;
 }
 
 adanns_status adanns_index_info(const adanns_index *ix, int64_t *n, int32_t *d, int32_t *nlist,

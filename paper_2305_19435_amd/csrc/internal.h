@@ -103,6 +103,19 @@ namespace adanns {
 // Grows (if needed) and returns the scratch memory of ``stream``.
 adanns_status get_scratch(adanns_index *ix, hipStream_t stream, size_t bytes, void **out);
 
+// ---- kernel timing with HIP events ------------------------------------------
+// When timing is on, a KernelTimer records an event pair around the launches
+// in its scope on ``stream``; adanns_timing_read() resolves them.
+bool timing_on();
+struct KernelTimer {
+  const char *name;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  KernelTimer(const char *name, hipStream_t st);
+  void stop();
+  ~KernelTimer() { stop(); }
+};
+
 // ---- launch wrappers (kernels.hip) -----------------------------------------
 struct SearchBufs {
   float *Qs;          // [nq][dq_pad]
@@ -125,7 +138,14 @@ hipError_t launch_layout(const float *src, int64_t ldsrc, int32_t dsrc, const in
                          const int32_t *row_list, const int64_t *poff, int64_t rows_pad,
                          int32_t d_pad, float *dst, hipStream_t st);
 hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_c,
-                         int32_t nprobe, int32_t *user_probes, hipStream_t st);
+                         int32_t nprobe, int32_t *user_probes, hipStream_t st,
+                         float *out_min_dist = nullptr);
+hipError_t launch_stage_rows(const float *X, int64_t ldx, const int64_t *rows,
+                             const int32_t *rows32, int64_t nrows, int32_t dcols, float *out,
+                             int64_t ldo, hipStream_t st);
+hipError_t launch_centroid_update(const float *X, int64_t ldx, const int32_t *perm,
+                                  const int64_t *off, int32_t nlist, int32_t dcols, float *C,
+                                  int64_t ldc, hipStream_t st);
 hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_s,
                        int32_t nprobe, int32_t k, float *dist, int64_t *ids, hipStream_t st);
 

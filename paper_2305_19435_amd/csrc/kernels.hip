@@ -111,6 +111,47 @@ __global__ void k_stage_queries(const float *__restrict__ Q, int64_t nq, int64_t
   Qs[i] = col < dq ? Q[row * ldq + col] : 0.0f;
 }
 
+// Rows (optionally gathered through ``rows``) copied to a zero-padded buffer.
+__global__ void k_stage_rows(const float *__restrict__ X, int64_t ldx, const int64_t *__restrict__ rows,
+                             const int32_t *__restrict__ rows32, int64_t nrows, int32_t dcols,
+                             float *__restrict__ out, int64_t ldo) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t r = i / ldo, c = i % ldo;
+  if (r >= nrows) return;
+  int64_t src = rows ? rows[r] : (rows32 ? (int64_t)rows32[r] : r);
+  out[i] = c < dcols ? X[src * ldx + c] : 0.0f;
+}
+
+// Lloyd update: centroid h becomes the mean of its members (perm[off[h] ..
+// off[h+1]) rows of X), summed in a fixed order in compensated FP32; a
+// centroid without members keeps its value.
+__global__ __launch_bounds__(256) void k_centroid_update(const float *__restrict__ X, int64_t ldx,
+                                                         const int32_t *__restrict__ perm,
+                                                         const int64_t *__restrict__ off,
+                                                         int32_t dcols, float *__restrict__ C,
+                                                         int64_t ldc) {
+#pragma clang fp contract(off)
+  const int32_t h = blockIdx.x;
+  const int32_t dim = blockIdx.y * blockDim.x + threadIdx.x;
+  if (dim >= dcols) return;
+  const int64_t a0 = off[h], a1 = off[h + 1];
+  if (a1 == a0) return;
+  float S = 0.f, E = 0.f;
+  for (int64_t i = a0; i < a1; ++i) {
+    float t, te;
+    two_sum(S, X[(int64_t)perm[i] * ldx + dim], t, te);
+    S = t;
+    E = E + te;
+  }
+  float hi, lo;
+  two_sum(S, E, hi, lo);
+  const float cnt = (float)(a1 - a0);
+  float m = hi / cnt;
+  // one correction step: (hi + lo - m * cnt) / cnt
+  float r = __builtin_fmaf(-m, cnt, hi) + lo;
+  C[(int64_t)h * ldc + dim] = m + r / cnt;
+}
+
 // Slab layout writer: one thread per destination element.
 __global__ void k_layout(const float *__restrict__ src, int64_t ldsrc, int32_t dsrc,
                          const int64_t *__restrict__ src_row, const int32_t *__restrict__ row_list,
@@ -504,6 +545,7 @@ __global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
       const int32_t hsel = has ? (int32_t)cid[j] : -1;
       a.out_probes[q * a.kout + j] = hsel;
       if (a.out_probes2) a.out_probes2[q * a.kout + j] = hsel;
+      if (a.out_dist) a.out_dist[q * a.kout + j] = has ? chi[j] : __builtin_inff();
     } else {
       a.out_dist[q * a.kout + j] = has ? chi[j] : __builtin_inff();
       a.out_ids[q * a.kout + j] = has ? cid[j] : -1;
@@ -621,8 +663,28 @@ hipError_t launch_layout(const float *src, int64_t ldsrc, int32_t dsrc, const in
   return hipGetLastError();
 }
 
+hipError_t launch_stage_rows(const float *X, int64_t ldx, const int64_t *rows,
+                             const int32_t *rows32, int64_t nrows, int32_t dcols, float *out,
+                             int64_t ldo, hipStream_t st) {
+  int64_t n = nrows * ldo;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stage_rows, dim3(blocks_for(n, 256)), dim3(256), 0, st, X, ldx, rows, rows32,
+                     nrows, dcols, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_centroid_update(const float *X, int64_t ldx, const int32_t *perm,
+                                  const int64_t *off, int32_t nlist, int32_t dcols, float *C,
+                                  int64_t ldc, hipStream_t st) {
+  KernelTimer tm("kmeans_update", st);
+  hipLaunchKernelGGL(k_centroid_update, dim3(nlist, blocks_for(dcols, 256)), dim3(256), 0, st, X,
+                     ldx, perm, off, dcols, C, ldc);
+  return hipGetLastError();
+}
+
 hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_c,
-                         int32_t nprobe, int32_t *user_probes, hipStream_t st) {
+                         int32_t nprobe, int32_t *user_probes, hipStream_t st,
+                         float *out_min_dist) {
   TileArgs t{};
   t.Qs = b.Qs;
   t.ldqs = b.ldqs;
@@ -638,7 +700,10 @@ hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq
   t.qtiles = (int32_t)cdiv(nq, TILE_Q);
   t.total_host = t.qtiles * (int32_t)cdiv(ix->nlist, TILE_V);
   int grid = (int)std::min<int64_t>(PERSIST_WG, round_up(t.total_host, 8));
-  hipLaunchKernelGGL(k_tile_dist, dim3(grid), dim3(256), 0, st, t);
+  {
+    KernelTimer tm("tile_dist_coarse", st);
+    hipLaunchKernelGGL(k_tile_dist, dim3(grid), dim3(256), 0, st, t);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 
@@ -655,7 +720,11 @@ hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq
   s.ld_cent = ix->d_cb_pad;
   s.out_probes = b.probes;
   s.out_probes2 = user_probes;
-  hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+  s.out_dist = out_min_dist;
+  {
+    KernelTimer tm("select_coarse", st);
+    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+  }
   return hipGetLastError();
 }
 
@@ -663,6 +732,7 @@ hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, 
                        int32_t nprobe, int32_t k, float *dist, int64_t *ids, hipStream_t st) {
   const int64_t npairs = nq * nprobe;
   const int32_t nlist = ix->nlist;
+  KernelTimer tmb("bucketing", st);
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nlist, 256)), dim3(256), 0, st, b.cnt,
                      (int64_t)nlist, 0);
   hipLaunchKernelGGL(k_count, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, b.probes, npairs,
@@ -677,6 +747,7 @@ hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, 
   hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, b.pair_base, nq, b.seg_off);
   hipLaunchKernelGGL(k_pair_base, dim3(blocks_for(nq, 256)), dim3(256), 0, st, b.probes, nq,
                      nprobe, ix->len, b.seg_off, b.pair_base);
+  tmb.stop();
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
 
@@ -697,7 +768,10 @@ hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, 
   t.pair_base = b.pair_base;
   t.out = b.D;
   t.coarse = 0;
-  hipLaunchKernelGGL(k_tile_dist, dim3(PERSIST_WG), dim3(256), 0, st, t);
+  {
+    KernelTimer tm("tile_dist_scan", st);
+    hipLaunchKernelGGL(k_tile_dist, dim3(PERSIST_WG), dim3(256), 0, st, t);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
@@ -719,7 +793,10 @@ hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, 
   s.pair_base = b.pair_base;
   s.out_dist = dist;
   s.out_ids = ids;
-  hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+  {
+    KernelTimer tm("select_scan", st);
+    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+  }
   return hipGetLastError();
 }
 

@@ -53,6 +53,24 @@ class IvfIndex:
                                     _stream(stream), C.byref(out)))
         return cls(out.value)
 
+    @classmethod
+    def build_ivf(cls, X, nlist: int, d_c: int, iters: int, init_rows, train_rows=None,
+                  stream=None, return_objective=False):
+        """adanns_build_ivf: GPU Lloyd k-means on X[:, :d_c] (X a CUDA FP32 tensor)."""
+        Xd = X if (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32
+                   and X.stride(1) == 1) else _dev_f32(X, "cuda")
+        init = np.ascontiguousarray(init_rows, dtype=np.int32)
+        tr = None if train_rows is None else np.ascontiguousarray(train_rows, dtype=np.int64)
+        obj = np.zeros(iters + 1, dtype=np.float64)
+        out = C.c_void_p()
+        check(lib.adanns_build_ivf(Xd.data_ptr(), Xd.shape[0], Xd.shape[1], Xd.stride(0), nlist,
+                                   d_c, iters, init.ctypes.data,
+                                   None if tr is None else tr.ctypes.data,
+                                   0 if tr is None else len(tr), obj.ctypes.data,
+                                   _stream(stream), C.byref(out)))
+        ix = cls(out.value)
+        return (ix, obj) if return_objective else ix
+
     # ---- search ---------------------------------------------------------------
     def search(self, Q, d_c: int, d_s: int, nprobe: int, k: int, return_probes=False,
                stream=None, out=None):
