@@ -360,16 +360,29 @@ __global__ __launch_bounds__(256) void k_tile_dist(TileArgs a) {
 }
 
 // ---- per-query selection and exact re-measurement ----------------------------
+// Candidate measures used after the first-pass selection. Each returns the
+// exact value of a distance the method defines, as an unevaluated FP32 pair.
+enum SelMode : int32_t {
+  SEL_COARSE = 0,        // centroid distance on d_c, FP32 centroids
+  SEL_L2 = 1,            // vector distance on d_s, FP32 slab layout
+  SEL_ADC = 2,           // asymmetric PQ distance (rotated query vs codebooks)
+  SEL_QUANT = 3,         // distance between quantised query and quantised vector
+  SEL_COARSE_QUANT = 4,  // distance between quantised query and quantised centroid
+};
+
 struct SelArgs {
-  int32_t coarse;
+  int32_t mode;
   const float *D;
-  const int64_t *seg_off;  // scan: [nq + 1]
-  int32_t nl;              // coarse: scores per query
-  int32_t Kp;              // shortlist length
+  const int64_t *seg_off;  // scan modes: [nq + 1]
+  int32_t nl;              // coarse modes: scores per query
+  int32_t K1;              // first-pass shortlist length
+  int32_t K2;              // kept after the first exact measure
   int32_t kout;            // results per query
+  int32_t stageB;          // re-measure the K2 kept with exact FP32 L2, keep kout
   const float *Qs;
   int64_t ldqs;
-  int32_t d_dot;
+  int32_t d_dot;           // coordinates of the first measure
+  int32_t d_B;             // coordinates of the second measure
   const float *cent;       // coarse: [nl][ld_cent]
   int32_t ld_cent;
   const float *vec;        // scan: slab layout
@@ -379,6 +392,21 @@ struct SelArgs {
   const int32_t *probes;   // scan: [nq][nprobe]
   int32_t nprobe;
   const int64_t *pair_base;
+  // ADC
+  const uint8_t *codes;    // [rows_pad][M]
+  int32_t M, dsub;
+  const float *cb;         // [M][256][dsub]
+  const float *qr_hi, *qr_lo;  // rotated queries as pairs, [nq][ldqr]
+  int64_t ldqr;
+  // quantised operands (precision form)
+  int32_t qfmt;            // 1 = bf16, 2 = fp8 e4m3
+  const void *qvec;        // slab layout of the quantised vectors (or centroids)
+  const float *qscale;     // per layout row (fp8)
+  int32_t qd_pad;          // padded width of the quantised layout
+  const void *qQ;          // quantised queries [nq][ldqq]
+  const float *qQscale;    // per query (fp8)
+  int64_t ldqq;
+  int64_t qnpad;           // coarse-quant: rows of the one-list layout
   float *out_dist;
   int64_t *out_ids;
   int32_t *out_probes;
@@ -394,21 +422,89 @@ __device__ __forceinline__ bool pair_less(float ah, float al, int64_t ai, float 
   return ai < bi;
 }
 
+// Adds ((qh + ql) - x)^2 for a query coordinate given as a pair.
+__device__ __forceinline__ void acc_sq_diff2(float qh, float ql, float x, float &S, float &C) {
+#pragma clang fp contract(off)
+  float d, de;
+  two_sum(qh, -x, d, de);
+  de = de + ql;
+  float p = d * d;
+  float pe = __builtin_fmaf(d, d, -p);
+  float t, te;
+  two_sum(S, p, t, te);
+  S = t;
+  C = C + (te + (pe + 2.0f * d * de));
+}
+
+// Exact product a*b as a pair.
+__device__ __forceinline__ void two_prod(float a, float b, float &p, float &e) {
+#pragma clang fp contract(off)
+  p = a * b;
+  e = __builtin_fmaf(a, b, -p);
+}
+
+// Value of an OCP e4m3 byte (finite codes only; 0x7F/0xFF never stored).
+__device__ __forceinline__ float e4m3_to_float(uint32_t c) {
+  const uint32_t s = c & 0x80u, e = (c >> 3) & 0xFu, f = c & 7u;
+  float v = e == 0 ? (float)f * 0.001953125f
+                   : __uint_as_float(((e + 120u) << 23) | (f << 20));
+  return s ? -v : v;
+}
+
+__device__ __forceinline__ float bf16_to_float(uint16_t b) {
+  return __uint_as_float((uint32_t)b << 16);
+}
+
+// Quantised value (as an exact pair) of coordinate ``i`` of a quantised row.
+__device__ __forceinline__ void quant_value(int32_t fmt, const void *base, int64_t idx, float scale,
+                                            float &hi, float &lo) {
+  if (fmt == 1) {
+    hi = bf16_to_float(((const uint16_t *)base)[idx]);
+    lo = 0.f;
+  } else {
+    two_prod(scale, e4m3_to_float(((const uint8_t *)base)[idx]), hi, lo);
+  }
+}
+
+__device__ __forceinline__ void bitonic_sort(float *chi, float *clo, int64_t *cid, int64_t *cg,
+                                             int P2) {
+  const int tid = threadIdx.x;
+  for (int size = 2; size <= P2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int t = tid; t < (P2 >> 1); t += blockDim.x) {
+        const int i = 2 * t - (t & (stride - 1));
+        const int j = i + stride;
+        const bool up = (i & size) == 0;
+        const bool gt = pair_less(chi[j], clo[j], cid[j], chi[i], clo[i], cid[i]);
+        if (gt == up) {
+          float th = chi[i]; chi[i] = chi[j]; chi[j] = th;
+          float tl = clo[i]; clo[i] = clo[j]; clo[j] = tl;
+          int64_t ti = cid[i]; cid[i] = cid[j]; cid[j] = ti;
+          int64_t tg = cg[i]; cg[i] = cg[j]; cg[j] = tg;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
   __shared__ uint32_t hist[2048];
   __shared__ int64_t cpos[MAX_SHORTLIST];
   __shared__ float chi[MAX_SHORTLIST], clo[MAX_SHORTLIST];
   __shared__ int64_t cid[MAX_SHORTLIST];
+  __shared__ int64_t cg[MAX_SHORTLIST];   // coarse: h; scan: (h << 32) | row in list
   __shared__ uint32_t sh32[16];
-  __shared__ int64_t sh64[16];
   __shared__ uint32_t s_bin, s_before;
   __shared__ int s_slot;
 
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
   const int64_t q = blockIdx.x;
+  const bool coarse = a.mode == SEL_COARSE || a.mode == SEL_COARSE_QUANT;
   const float *seg;
   int64_t L, seg0 = 0;
-  if (a.coarse) {
+  if (coarse) {
     seg = a.D + q * a.nl;
     L = a.nl;
   } else {
@@ -417,13 +513,13 @@ __global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
     L = a.seg_off[q + 1] - seg0;
   }
   int ncand;
-  if (L <= a.Kp) {
+  if (L <= a.K1) {
     ncand = (int)L;
     for (int i = tid; i < ncand; i += blockDim.x) cpos[i] = i;
   } else {
-    ncand = a.Kp;
-    // radix selection of the Kp-th smallest key: 11 + 11 + 10 bits
-    uint32_t prefix = 0, pmask = 0, need = (uint32_t)a.Kp;
+    ncand = a.K1;
+    // radix selection of the K1-th smallest key: 11 + 11 + 10 bits
+    uint32_t prefix = 0, pmask = 0, need = (uint32_t)a.K1;
     for (int pass = 0; pass < 3; ++pass) {
       const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
       const int nb = pass < 2 ? 2048 : 1024;
@@ -456,7 +552,7 @@ __global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
       need -= s_before;
       __syncthreads();
     }
-    // prefix is the Kp-th smallest key; take every smaller key and the first
+    // prefix is the K1-th smallest key; take every smaller key and the first
     // ``need`` equal ones in position order.
     const uint32_t T = prefix;
     const int64_t chunk = (L + blockDim.x - 1) / blockDim.x;
@@ -466,7 +562,7 @@ __global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
     uint32_t eq_before = block_excl_scan<uint32_t>(ne, sh32, nullptr);
     if (tid == 0) s_slot = 0;
     __syncthreads();
-    const int nlt = a.Kp - (int)need;
+    const int nlt = a.K1 - (int)need;
     for (int64_t i = a0; i < a1; ++i) {
       uint32_t kk = order_key(seg[i]);
       if (kk < T) {
@@ -480,16 +576,30 @@ __global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
   }
   __syncthreads();
 
-  // exact re-measurement, one wave per candidate
+  // first exact measure, one wave per candidate
   const float *qrow = a.Qs + q * a.ldqs;
-  for (int c = wv; c < ncand; c += (blockDim.x >> 6)) {
+  for (int c = wv; c < ncand; c += nwv) {
     const int64_t pos = cpos[c];
     float S = 0.f, C = 0.f;
-    int64_t id;
-    if (a.coarse) {
-      const float *x = a.cent + pos * a.ld_cent;
-      for (int dim = lane; dim < a.d_dot; dim += 64) acc_sq_diff(qrow[dim], x[dim], S, C);
+    int64_t id, gpack;
+    if (coarse) {
       id = pos;
+      gpack = pos;
+      if (a.mode == SEL_COARSE) {
+        const float *x = a.cent + pos * a.ld_cent;
+        for (int dim = lane; dim < a.d_dot; dim += 64) acc_sq_diff(qrow[dim], x[dim], S, C);
+      } else {
+        const float xs = a.qfmt == 2 ? a.qscale[pos] : 1.f;
+        const float qs = a.qfmt == 2 ? a.qQscale[q] : 1.f;
+        for (int dim = lane; dim < a.d_dot; dim += 64) {
+          float qh, ql, xh, xl;
+          quant_value(a.qfmt, a.qQ, q * a.ldqq + dim, qs, qh, ql);
+          quant_value(a.qfmt, a.qvec,
+                      ((int64_t)(dim / SLAB) * a.qnpad + pos) * SLAB + (dim % SLAB), xs, xh, xl);
+          // (qh + ql) - (xh + xl)
+          acc_sq_diff2(qh, ql - xl, xh, S, C);
+        }
+      }
     } else {
       const int64_t pabs = seg0 + pos;
       const int64_t *pb = a.pair_base + q * a.nprobe;
@@ -502,16 +612,39 @@ __global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
       const int64_t r = pabs - pb[lo];
       const int64_t p0 = a.poff[h];
       const int64_t npad = a.poff[h + 1] - p0;
-      const float *base = a.vec + p0 * a.d_pad + r * SLAB;
-      for (int dim = lane; dim < a.d_dot; dim += 64)
-        acc_sq_diff(qrow[dim], base[(int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)], S, C);
       id = a.rowid[p0 + r];
+      gpack = ((int64_t)h << 32) | r;
+      if (a.mode == SEL_L2) {
+        const float *base = a.vec + p0 * a.d_pad + r * SLAB;
+        for (int dim = lane; dim < a.d_dot; dim += 64)
+          acc_sq_diff(qrow[dim], base[(int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)], S, C);
+      } else if (a.mode == SEL_ADC) {
+        const uint8_t *code = a.codes + (p0 + r) * a.M;
+        const float *qh = a.qr_hi + q * a.ldqr, *ql = a.qr_lo + q * a.ldqr;
+        for (int dim = lane; dim < a.d_dot; dim += 64) {
+          const int m = dim / a.dsub, t = dim - m * a.dsub;
+          const float x = a.cb[((int64_t)m * 256 + code[m]) * a.dsub + t];
+          acc_sq_diff2(qh[dim], ql[dim], x, S, C);
+        }
+      } else {  // SEL_QUANT
+        const float xs = a.qfmt == 2 ? a.qscale[p0 + r] : 1.f;
+        const float qs = a.qfmt == 2 ? a.qQscale[q] : 1.f;
+        for (int dim = lane; dim < a.d_dot; dim += 64) {
+          float qh, ql, xh, xl;
+          quant_value(a.qfmt, a.qQ, q * a.ldqq + dim, qs, qh, ql);
+          quant_value(a.qfmt, a.qvec,
+                      p0 * a.qd_pad + ((int64_t)(dim / SLAB) * npad + r) * SLAB + (dim % SLAB), xs,
+                      xh, xl);
+          acc_sq_diff2(qh, ql - xl, xh, S, C);
+        }
+      }
     }
     wave_reduce_pair(S, C);
     if (lane == 0) {
       chi[c] = S;
       clo[c] = C;
       cid[c] = id;
+      cg[c] = gpack;
     }
   }
   int P2 = 1;
@@ -520,28 +653,48 @@ __global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
     chi[c] = __builtin_inff();
     clo[c] = 0.f;
     cid[c] = INT64_MAX;
+    cg[c] = -1;
   }
-  // bitonic sort by (distance, id)
-  for (int size = 2; size <= P2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      __syncthreads();
-      for (int t = tid; t < (P2 >> 1); t += blockDim.x) {
-        const int i = 2 * t - (t & (stride - 1));
-        const int j = i + stride;
-        const bool up = (i & size) == 0;
-        const bool gt = pair_less(chi[j], clo[j], cid[j], chi[i], clo[i], cid[i]);
-        if (gt == up) {
-          float th = chi[i]; chi[i] = chi[j]; chi[j] = th;
-          float tl = clo[i]; clo[i] = clo[j]; clo[j] = tl;
-          int64_t ti = cid[i]; cid[i] = cid[j]; cid[j] = ti;
-        }
+  bitonic_sort(chi, clo, cid, cg, P2);
+
+  int nres = ncand;
+  if (a.stageB) {
+    // second exact measure (FP32 L2 on d_B coordinates) of the K2 best
+    nres = ncand < a.K2 ? ncand : a.K2;
+    for (int c = wv; c < nres; c += nwv) {
+      float S = 0.f, C = 0.f;
+      if (coarse) {
+        const float *x = a.cent + cg[c] * a.ld_cent;
+        for (int dim = lane; dim < a.d_B; dim += 64) acc_sq_diff(qrow[dim], x[dim], S, C);
+      } else {
+        const int32_t h = (int32_t)(cg[c] >> 32);
+        const int64_t r = cg[c] & 0xffffffffll;
+        const int64_t p0 = a.poff[h];
+        const int64_t npad = a.poff[h + 1] - p0;
+        const float *base = a.vec + p0 * a.d_pad + r * SLAB;
+        for (int dim = lane; dim < a.d_B; dim += 64)
+          acc_sq_diff(qrow[dim], base[(int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)], S, C);
+      }
+      wave_reduce_pair(S, C);
+      if (lane == 0) {
+        chi[c] = S;
+        clo[c] = C;
       }
     }
+    __syncthreads();
+    int P3 = 1;
+    while (P3 < nres) P3 <<= 1;
+    for (int c = nres + tid; c < P3; c += blockDim.x) {
+      chi[c] = __builtin_inff();
+      clo[c] = 0.f;
+      cid[c] = INT64_MAX;
+      cg[c] = -1;
+    }
+    bitonic_sort(chi, clo, cid, cg, P3);
   }
-  __syncthreads();
   for (int j = tid; j < a.kout; j += blockDim.x) {
-    const bool has = j < ncand;
-    if (a.coarse) {
+    const bool has = j < nres;
+    if (coarse) {
       const int32_t hsel = has ? (int32_t)cid[j] : -1;
       a.out_probes[q * a.kout + j] = hsel;
       if (a.out_probes2) a.out_probes2[q * a.kout + j] = hsel;
@@ -708,10 +861,11 @@ hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq
   if (e != hipSuccess) return e;
 
   SelArgs s{};
-  s.coarse = 1;
+  s.mode = SEL_COARSE;
   s.D = b.S;
   s.nl = ix->nlist;
-  s.Kp = std::min<int32_t>(ix->nlist, std::min<int32_t>(nprobe + REFINE_MARGIN, MAX_SHORTLIST));
+  s.K1 = std::min<int32_t>(ix->nlist, std::min<int32_t>(nprobe + REFINE_MARGIN, MAX_SHORTLIST));
+  s.K2 = nprobe;
   s.kout = nprobe;
   s.Qs = b.Qs;
   s.ldqs = b.ldqs;
@@ -776,10 +930,11 @@ hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, 
   if (e != hipSuccess) return e;
 
   SelArgs s{};
-  s.coarse = 0;
+  s.mode = SEL_L2;
   s.D = b.D;
   s.seg_off = b.seg_off;
-  s.Kp = std::min<int32_t>(k + REFINE_MARGIN, MAX_SHORTLIST);
+  s.K1 = std::min<int32_t>(k + REFINE_MARGIN, MAX_SHORTLIST);
+  s.K2 = k;
   s.kout = k;
   s.Qs = b.Qs;
   s.ldqs = b.ldqs;
