@@ -133,6 +133,40 @@ adanns_status adanns_search_probes(const adanns_index *index, const float *Q, in
                                    int64_t *ids, void *stream);
 
 /*
+ * Attach a product-quantisation codec to an index (Section 3, "Optimized
+ * Product Quantization"; Section 4.2 AdANNS-OPQ; Section 4.3 AdANNS-IVFOPQ):
+ * the first d_s coordinates of a vector, rotated by R, are split into M
+ * blocks of d_s/M coordinates and each block is replaced by the index of
+ * its nearest codeword (256 per block, one byte).
+ *   R         device, [d_s x d_s] FP32 row-major (q' = q[:d_s] R), or NULL
+ *             for the identity (plain PQ). Copied.
+ *   codebooks device, [M x 256 x d_s/M] FP32. Copied.
+ *   codes     device, [n x M] uint8, row j = database row j. Copied into
+ *             list order.
+ * Limits: M a multiple of 4 in [4, 64], M divides d_s, d_s <= min(d, 2048),
+ * one codec per M. Synchronises ``stream``.
+ */
+adanns_status adanns_pq_import(adanns_index *index, int32_t M, int32_t d_s, const float *R,
+                               const float *codebooks, const uint8_t *codes, void *stream);
+
+/*
+ * AdANNS-IVF-PQ search (Section 4.3; Appendix A, Table "formula", IVFOPQ
+ * row, read with an unquantised query): probes from the unrotated d_c
+ * prefix as in adanns_search; the probed lists are scanned with the
+ * asymmetric distance D(x) = sum_m |q'_m - C_m[code_m(x)]|^2 (tables held
+ * in LDS); with rerank_k > 0 the rerank_k best by that distance are
+ * re-ranked by the exact squared L2 distance on the first d_rerank
+ * coordinates of the index's FP32 vectors (shortlist, then re-rank with the
+ * high-dimensional representation) and dist holds those exact distances.
+ *   M      selects the codec. k in [1, 1016]; rerank_k 0 or in [k, 1016].
+ * Other arguments and conventions as adanns_search.
+ */
+adanns_status adanns_search_pq(const adanns_index *index, const float *Q, int64_t nq, int64_t ldq,
+                               int32_t d_c, int32_t nprobe, int32_t M, int32_t k,
+                               int32_t rerank_k, int32_t d_rerank, float *dist, int64_t *ids,
+                               int32_t *probes, void *stream);
+
+/*
  * Kernel timing with HIP events, for measurement tools. While enabled, every
  * search records an event pair around each of its kernel groups on its
  * stream ("tile_dist_coarse", "select_coarse", "bucketing",

@@ -54,14 +54,20 @@ def probes_valid(c: np.ndarray, probes, nprobe: int, tol: float = 1e-6) -> bool:
 
 def compare_knn(q, X, cand_ids, got_d, got_i, ref_d, ref_i, d_s: int,
                 tol: float = 1e-6, dist_tol: float = 1e-5, report: Report | None = None,
-                tag: str = "") -> Report:
+                tag: str = "", dist64=None) -> Report:
     """Compare one query's result (got) with the oracle's (ref).
 
-    ``cand_ids`` are the ids the method scanned (union of probed lists),
-    ``X`` the database (any float dtype), ``q`` the query.
+    ``cand_ids`` are the ids the method ranked (union of probed lists, or the
+    shortlist that was re-ranked), ``X`` the database (any float dtype), ``q``
+    the query. ``dist64`` maps an id array to the oracle's float64 distances
+    of the method being checked (default: squared L2 on the first d_s
+    coordinates of X).
     """
     rep = report or Report()
     q = np.asarray(q, dtype=np.float64)
+    if dist64 is None:
+        def dist64(idx):
+            return sqdist64(q[:d_s], np.asarray(X)[np.asarray(idx), :d_s])
     got_i = np.asarray(got_i, dtype=np.int64)
     ref_i = np.asarray(ref_i, dtype=np.int64)
     k = len(ref_i)
@@ -82,7 +88,7 @@ def compare_knn(q, X, cand_ids, got_d, got_i, ref_d, ref_i, d_s: int,
         return rep
     if len(gi) == 0:
         return rep
-    d64_got = sqdist64(q[:d_s], np.asarray(X)[gi, :d_s])
+    d64_got = dist64(gi)
     d64_ref = np.asarray(ref_d)[valid_r]
     # positions
     for pos in range(len(gi)):
@@ -97,14 +103,14 @@ def compare_knn(q, X, cand_ids, got_d, got_i, ref_d, ref_i, d_s: int,
     if len(cand) > len(gi):
         rest = np.array(sorted(cand - set(gi.tolist())), dtype=np.int64)
         if len(rest) and len(gi) == k:
-            dr = sqdist64(q[:d_s], np.asarray(X)[rest, :d_s])
+            dr = dist64(rest)
             if np.any(dr < kth * (1 - tol)):
                 j = rest[np.argmin(dr)]
                 rep.fail(f"{tag} left out a nearer candidate {j} ({dr.min()!r} < {kth!r})")
                 return rep
     # distances
     gd = np.asarray(got_d, dtype=np.float64)[valid_g]
-    floor = dist_tol * float(q[:d_s] @ q[:d_s])
+    floor = dist_tol * float(q[:d_s] @ q[:d_s]) if X is not None else 0.0
     err = np.abs(gd - d64_got)
     rel = err / np.maximum(d64_got, 1e-300)
     bad = err > np.maximum(dist_tol * d64_got, floor)

@@ -128,14 +128,19 @@ def adc_dist64(lut, codes) -> np.ndarray:
 
 def ivfpq_search64(Q, centroids, offsets, list_ids, codes, R, codebooks, d_c: int,
                    nprobe: int, k: int, rerank_k: int = 0, X=None, d_rerank=None,
-                   forced_probes=None):
+                   forced_probes=None, return_candidates=False):
     """AdANNS-IVFOPQ: coarse on the unrotated d_c prefix, ADC scan of the probed
     lists, optional exact re-rank of the best ``rerank_k`` on X[:, :d_rerank].
 
     ``codes`` are indexed by database id. R is [d_s, d_s] (identity for plain
     PQ); the query's first d_s = R.shape[0] coordinates are rotated.
     Returns (dist, ids, probes); with re-ranking the distances are exact.
+    With ``return_candidates`` also the ids each query's final order was
+    chosen from (the probed members, or the re-ranked shortlist) and the
+    query's table.
     """
+    cands = []
+    luts = []
     Q = np.asarray(Q)
     nq = Q.shape[0]
     d_s = R.shape[0]
@@ -152,6 +157,7 @@ def ivfpq_search64(Q, centroids, offsets, list_ids, codes, R, codebooks, d_c: in
         members = np.concatenate([list_ids[offsets[h]:offsets[h + 1]] for h in probes])
         members = np.asarray(members, dtype=np.int64)
         lut = adc_lut64(q[:d_s] @ R, codebooks)
+        luts.append(lut)
         approx = adc_dist64(lut, codes[members]) if len(members) else np.zeros(0)
         if rerank_k:
             sd, si = topk_by_dist_then_id(approx, members, rerank_k)
@@ -159,6 +165,10 @@ def ivfpq_search64(Q, centroids, offsets, list_ids, codes, R, codebooks, d_c: in
             dr = d_rerank if d_rerank is not None else X.shape[1]
             exact = sqdist64(q[:dr], np.asarray(X)[si, :dr]) if len(si) else np.zeros(0)
             D[qi], I[qi] = topk_by_dist_then_id(exact, si, k)
+            cands.append(si)
         else:
             D[qi], I[qi] = topk_by_dist_then_id(approx, members, k)
+            cands.append(members)
+    if return_candidates:
+        return D, I, P, cands, luts
     return D, I, P

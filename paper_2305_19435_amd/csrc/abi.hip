@@ -118,6 +118,12 @@ void free_index_memory(adanns_index *ix) {
   void *ptrs[] = {ix->vec, ix->poff, ix->len, ix->rowid, ix->cent, ix->cent_slab};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  for (auto &kv : ix->pq) {
+    void *pp[] = {kv.second.R, kv.second.cb, kv.second.codes};
+    for (void *p : pp)
+      if (p) (void)hipFree(p);
+  }
+  ix->pq.clear();
   for (auto &kv : ix->scratch)
     if (kv.second.base) (void)hipFree(kv.second.base);
   ix->scratch.clear();
@@ -561,6 +567,103 @@ adanns_status adanns_build_ivf(const float *X, int64_t n, int32_t d, int64_t ldx
   }
   (void)hipFree(C);
   *out = ix;
+  return ADANNS_OK;
+}
+
+adanns_status adanns_pq_import(adanns_index *ix, int32_t M, int32_t d_s, const float *R,
+                               const float *codebooks, const uint8_t *codes, void *stream) {
+  clear_error();
+  ADANNS_REQUIRE(ix != nullptr, "index is NULL");
+  ADANNS_REQUIRE(codebooks != nullptr && codes != nullptr, "codebooks and codes must be non-NULL");
+  ADANNS_REQUIRE(d_s >= 1 && d_s <= ix->d && d_s <= 2048, "d_s must be in [1, min(d, 2048)], got %d",
+                 d_s);
+  ADANNS_REQUIRE(M >= 4 && M <= 64 && M % 4 == 0, "M must be a multiple of 4 in [4, 64], got %d", M);
+  ADANNS_REQUIRE(d_s % M == 0, "M (%d) must divide d_s (%d)", M, d_s);
+  ADANNS_REQUIRE(ix->pq.find(M) == ix->pq.end(), "the index already holds a codec with M = %d", M);
+  adanns_status s = check_async();
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  PqCodec c;
+  c.M = M;
+  c.d_s = d_s;
+  c.dsub = d_s / M;
+  auto fail = [&](adanns_status e) {
+    void *pp[] = {c.R, c.cb, c.codes};
+    for (void *p : pp)
+      if (p) (void)hipFree(p);
+    return e;
+  };
+  if ((s = dmalloc(ix, (void **)&c.R, (size_t)d_s * d_s * sizeof(float)))) return fail(s);
+  if ((s = dmalloc(ix, (void **)&c.cb, (size_t)M * 256 * c.dsub * sizeof(float)))) return fail(s);
+  if ((s = dmalloc(ix, (void **)&c.codes, (size_t)ix->rows_pad * M))) return fail(s);
+  if (R) {
+    if (hipMemcpyAsync(c.R, R, (size_t)d_s * d_s * sizeof(float), hipMemcpyDeviceToDevice, st))
+      return fail(ADANNS_EHIP);
+  } else {
+    std::vector<float> eye((size_t)d_s * d_s, 0.f);
+    for (int32_t i = 0; i < d_s; ++i) eye[(size_t)i * d_s + i] = 1.f;
+    if (hipMemcpyAsync(c.R, eye.data(), eye.size() * sizeof(float), hipMemcpyHostToDevice, st) ||
+        hipStreamSynchronize(st))
+      return fail(ADANNS_EHIP);
+  }
+  if (hipMemcpyAsync(c.cb, codebooks, (size_t)M * 256 * c.dsub * sizeof(float),
+                     hipMemcpyDeviceToDevice, st) ||
+      launch_gather_codes(codes, M, ix->rowid, ix->rows_pad, c.codes, st) ||
+      hipStreamSynchronize(st)) {
+    set_error("HIP error while importing the PQ codec");
+    return fail(ADANNS_EHIP);
+  }
+  ix->pq[M] = c;
+  return ADANNS_OK;
+}
+
+adanns_status adanns_search_pq(const adanns_index *cix, const float *Q, int64_t nq, int64_t ldq,
+                               int32_t d_c, int32_t nprobe, int32_t M, int32_t k,
+                               int32_t rerank_k, int32_t d_rerank, float *dist, int64_t *ids,
+                               int32_t *probes, void *stream) {
+  clear_error();
+  adanns_index *ix = const_cast<adanns_index *>(cix);
+  ADANNS_REQUIRE(ix != nullptr, "index is NULL");
+  auto it = ix->pq.find(M);
+  ADANNS_REQUIRE(it != ix->pq.end(), "the index holds no PQ codec with M = %d", M);
+  const PqCodec &pq = it->second;
+  ADANNS_REQUIRE(nq >= 0, "nq must be >= 0");
+  ADANNS_REQUIRE(d_c >= 1 && d_c <= ix->d_cb, "d_c must be in [1, %d], got %d", ix->d_cb, d_c);
+  ADANNS_REQUIRE(nprobe >= 1 && nprobe <= ix->nlist, "nprobe must be in [1, %d], got %d",
+                 ix->nlist, nprobe);
+  ADANNS_REQUIRE(k >= 1 && k <= MAX_SHORTLIST - REFINE_MARGIN, "k must be in [1, %d], got %d",
+                 MAX_SHORTLIST - REFINE_MARGIN, k);
+  ADANNS_REQUIRE(rerank_k == 0 || (rerank_k >= k && rerank_k <= MAX_SHORTLIST - REFINE_MARGIN),
+                 "rerank_k must be 0 or in [k, %d], got %d", MAX_SHORTLIST - REFINE_MARGIN,
+                 rerank_k);
+  if (rerank_k > 0)
+    ADANNS_REQUIRE(d_rerank >= 1 && d_rerank <= ix->d, "d_rerank must be in [1, %d], got %d",
+                   ix->d, d_rerank);
+  ADANNS_REQUIRE(nq < (int64_t(1) << 31) / nprobe, "nq * nprobe must be below 2^31");
+  const int32_t dq = std::max(std::max(d_c, pq.d_s), rerank_k > 0 ? d_rerank : 0);
+  ADANNS_REQUIRE(ldq >= dq, "ldq (%lld) is smaller than the prefix (%d)", (long long)ldq, dq);
+  if (nq == 0) return ADANNS_OK;
+  ADANNS_REQUIRE(Q && dist && ids, "Q, dist and ids must be non-NULL");
+  adanns_status s = check_async();
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int32_t dq_pad = (int32_t)round_up(dq, SLAB);
+  size_t total = 0;
+  SearchBufs b0 = carve(nullptr, ix, nq, dq_pad, nprobe, true, &total);
+  (void)b0;
+  const size_t extra = (size_t)round_up((size_t)nq * pq.d_s * 4, 256) * 2 +
+                       (size_t)round_up((size_t)nq * M * 256 * 4, 256) + 1024;
+  void *base = nullptr;
+  if ((s = get_scratch(ix, st, total + extra, &base))) return s;
+  SearchBufs b = carve((char *)base, ix, nq, dq_pad, nprobe, true, &total);
+  Carver c{(char *)base, total, 0};
+  float *qr_hi = c.take<float>((size_t)nq * pq.d_s);
+  float *qr_lo = c.take<float>((size_t)nq * pq.d_s);
+  float *lut = c.take<float>((size_t)nq * M * 256);
+  ADANNS_HIP(launch_stage_queries(Q, nq, ldq, dq, b.Qs, b.ldqs, st));
+  ADANNS_HIP(launch_coarse(ix, b, nq, d_c, nprobe, probes, st));
+  ADANNS_HIP(launch_pq_search(ix, pq, b, nq, nprobe, k, rerank_k, d_rerank, qr_hi, qr_lo, lut,
+                              dist, ids, st));
   return ADANNS_OK;
 }
 

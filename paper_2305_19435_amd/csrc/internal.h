@@ -76,6 +76,16 @@ struct Carver {
 
 }  // namespace adanns
 
+namespace adanns {
+// Product-quantisation codec attached to an index (one per M).
+struct PqCodec {
+  int32_t M = 0, d_s = 0, dsub = 0;
+  float *R = nullptr;        // [d_s][d_s] row-major, q' = q[:d_s] R
+  float *cb = nullptr;       // [M][256][dsub]
+  uint8_t *codes = nullptr;  // [rows_pad][M], layout-row order, zero on padding rows
+};
+}  // namespace adanns
+
 struct adanns_index {
   int device = 0;
   int64_t n = 0;
@@ -93,6 +103,7 @@ struct adanns_index {
   int64_t *rowid = nullptr;            // [rows_pad], -1 on padding rows
   float *cent = nullptr;               // [nlist][d_cb_pad] row-major, zero padded
   float *cent_slab = nullptr;          // centroids as one slab-layout list of nl_pad rows
+  std::map<int32_t, adanns::PqCodec> pq;   // keyed by M
   size_t own_bytes = 0;
   std::mutex mu;
   std::map<hipStream_t, adanns::Scratch> scratch;
@@ -148,5 +159,14 @@ hipError_t launch_centroid_update(const float *X, int64_t ldx, const int32_t *pe
                                   int64_t ldc, hipStream_t st);
 hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_s,
                        int32_t nprobe, int32_t k, float *dist, int64_t *ids, hipStream_t st);
+hipError_t launch_bucketing(const adanns_index *ix, const SearchBufs &b, int64_t nq,
+                            int32_t nprobe, hipStream_t st);
+hipError_t launch_gather_codes(const uint8_t *codes, int32_t M, const int64_t *rowid,
+                               int64_t rows_pad, uint8_t *out, hipStream_t st);
+// IVF-PQ: rotation (compensated), tables, ADC scan and selection.
+hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const SearchBufs &b,
+                            int64_t nq, int32_t nprobe, int32_t k, int32_t rerank_k,
+                            int32_t d_rerank, float *qr_hi, float *qr_lo, float *lut, float *dist,
+                            int64_t *ids, hipStream_t st);
 
 }  // namespace adanns

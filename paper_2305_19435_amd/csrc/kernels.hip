@@ -706,6 +706,128 @@ __global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
   }
 }
 
+// ---- IVF-PQ ----------------------------------------------------------------------
+// Codes of database row rowid[g] copied to layout row g (zero on padding rows).
+__global__ void k_gather_codes(const uint8_t *__restrict__ codes, int32_t M,
+                               const int64_t *__restrict__ rowid, int64_t rows_pad,
+                               uint8_t *__restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows_pad * M) return;
+  int64_t g = i / M, m = i % M;
+  int64_t src = rowid[g];
+  out[i] = src >= 0 ? codes[src * M + m] : 0;
+}
+
+// q' = q[:d_s] R in compensated FP32 (TwoProd + TwoSum), stored as a pair
+// (hi, lo). ROT_Q queries per workgroup share each read of R.
+constexpr int ROT_Q = 4;
+constexpr int ROT_MAXC = 8;  // output columns per thread: d_s <= 2048
+__global__ __launch_bounds__(256) void k_rotate(const float *__restrict__ Qs, int64_t ldqs,
+                                                int64_t nq, const float *__restrict__ R,
+                                                int32_t d_s, float *__restrict__ qh,
+                                                float *__restrict__ ql, int64_t ldqr) {
+#pragma clang fp contract(off)
+  extern __shared__ float qsh[];  // [ROT_Q][d_s]
+  const int tid = threadIdx.x;
+  const int64_t q0 = (int64_t)blockIdx.x * ROT_Q;
+  for (int i = tid; i < ROT_Q * d_s; i += blockDim.x) {
+    const int qq = i / d_s, c = i % d_s;
+    qsh[i] = q0 + qq < nq ? Qs[(q0 + qq) * ldqs + c] : 0.f;
+  }
+  __syncthreads();
+  float S[ROT_Q][ROT_MAXC], C[ROT_Q][ROT_MAXC];
+#pragma unroll
+  for (int a = 0; a < ROT_Q; ++a)
+#pragma unroll
+    for (int b = 0; b < ROT_MAXC; ++b) S[a][b] = C[a][b] = 0.f;
+  for (int i = 0; i < d_s; ++i) {
+#pragma unroll
+    for (int b = 0; b < ROT_MAXC; ++b) {
+      const int j = tid + b * 256;
+      if (j < d_s) {
+        const float r = R[(int64_t)i * d_s + j];
+#pragma unroll
+        for (int a = 0; a < ROT_Q; ++a) {
+          float p, pe, t, te;
+          two_prod(qsh[a * d_s + i], r, p, pe);
+          two_sum(S[a][b], p, t, te);
+          S[a][b] = t;
+          C[a][b] = C[a][b] + (te + pe);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < ROT_Q; ++a) {
+    if (q0 + a >= nq) continue;
+#pragma unroll
+    for (int b = 0; b < ROT_MAXC; ++b) {
+      const int j = tid + b * 256;
+      if (j < d_s) {
+        float hi, lo;
+        two_sum(S[a][b], C[a][b], hi, lo);
+        qh[(q0 + a) * ldqr + j] = hi;
+        ql[(q0 + a) * ldqr + j] = lo;
+      }
+    }
+  }
+}
+
+// LUT[q][m][c] = |q'_m - C_m[c]|^2 in FP32 from the rotated query's high part.
+__global__ __launch_bounds__(256) void k_pq_lut(const float *__restrict__ qh, int64_t ldqr,
+                                                const float *__restrict__ cb, int32_t M,
+                                                int32_t dsub, float *__restrict__ lut) {
+  extern __shared__ float qrow[];
+  const int64_t q = blockIdx.x;
+  const int d_s = M * dsub;
+  for (int i = threadIdx.x; i < d_s; i += blockDim.x) qrow[i] = qh[q * ldqr + i];
+  __syncthreads();
+  const int c = threadIdx.x;  // blockDim.x == 256 codewords
+  for (int m = 0; m < M; ++m) {
+    const float *cw = cb + ((int64_t)m * 256 + c) * dsub;
+    float acc = 0.f;
+    for (int t = 0; t < dsub; ++t) {
+      const float dd = qrow[m * dsub + t] - cw[t];
+      acc += dd * dd;
+    }
+    lut[(q * M + m) * 256 + c] = acc;
+  }
+}
+
+// ADC scan of one (query, probe) pair: the query's table is held in LDS and
+// every vector of the probed list sums M table entries picked by its codes.
+__global__ __launch_bounds__(256) void k_adc_scan(const float *__restrict__ lut, int32_t M,
+                                                  const uint8_t *__restrict__ codes,
+                                                  const int32_t *__restrict__ probes,
+                                                  int32_t nprobe, const int64_t *__restrict__ poff,
+                                                  const int32_t *__restrict__ len,
+                                                  const int64_t *__restrict__ pair_base,
+                                                  float *__restrict__ D) {
+  extern __shared__ float tab[];  // [M][256]
+  const int64_t pair = blockIdx.x;
+  const int64_t q = pair / nprobe;
+  const float4 *src = (const float4 *)(lut + q * M * 256);
+  for (int i = threadIdx.x; i < M * 64; i += blockDim.x) ((float4 *)tab)[i] = src[i];
+  __syncthreads();
+  const int32_t h = probes[pair];
+  const int32_t n = len[h];
+  const uint8_t *cbase = codes + poff[h] * M;
+  float *out = D + pair_base[pair];
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    const uint32_t *row = (const uint32_t *)(cbase + (int64_t)r * M);
+    float acc = 0.f;
+    for (int w = 0; w < (M >> 2); ++w) {
+      const uint32_t c4 = row[w];
+      const int m = w * 4;
+      acc += tab[(m + 0) * 256 + (c4 & 0xff)];
+      acc += tab[(m + 1) * 256 + ((c4 >> 8) & 0xff)];
+      acc += tab[(m + 2) * 256 + ((c4 >> 16) & 0xff)];
+      acc += tab[(m + 3) * 256 + (c4 >> 24)];
+    }
+    out[r] = acc;
+  }
+}
+
 // ---- probe bucketing ---------------------------------------------------------
 __global__ void k_count(const int32_t *__restrict__ probes, int64_t npairs,
                         int32_t *__restrict__ cnt) {
@@ -882,8 +1004,8 @@ hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_s,
-                       int32_t nprobe, int32_t k, float *dist, int64_t *ids, hipStream_t st) {
+hipError_t launch_bucketing(const adanns_index *ix, const SearchBufs &b, int64_t nq,
+                            int32_t nprobe, hipStream_t st) {
   const int64_t npairs = nq * nprobe;
   const int32_t nlist = ix->nlist;
   KernelTimer tmb("bucketing", st);
@@ -902,7 +1024,13 @@ hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, 
   hipLaunchKernelGGL(k_pair_base, dim3(blocks_for(nq, 256)), dim3(256), 0, st, b.probes, nq,
                      nprobe, ix->len, b.seg_off, b.pair_base);
   tmb.stop();
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_s,
+                       int32_t nprobe, int32_t k, float *dist, int64_t *ids, hipStream_t st) {
+  const int32_t nlist = ix->nlist;
+  hipError_t e = launch_bucketing(ix, b, nq, nprobe, st);
   if (e != hipSuccess) return e;
 
   TileArgs t{};
@@ -950,6 +1078,76 @@ hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, 
   s.out_ids = ids;
   {
     KernelTimer tm("select_scan", st);
+    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_codes(const uint8_t *codes, int32_t M, const int64_t *rowid,
+                               int64_t rows_pad, uint8_t *out, hipStream_t st) {
+  int64_t n = rows_pad * M;
+  hipLaunchKernelGGL(k_gather_codes, dim3(blocks_for(n, 256)), dim3(256), 0, st, codes, M, rowid,
+                     rows_pad, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const SearchBufs &b,
+                            int64_t nq, int32_t nprobe, int32_t k, int32_t rerank_k,
+                            int32_t d_rerank, float *qr_hi, float *qr_lo, float *lut, float *dist,
+                            int64_t *ids, hipStream_t st) {
+  hipError_t e = launch_bucketing(ix, b, nq, nprobe, st);
+  if (e != hipSuccess) return e;
+  const int64_t ldqr = pq.d_s;
+  {
+    KernelTimer tm("pq_rotate", st);
+    hipLaunchKernelGGL(k_rotate, dim3((unsigned)cdiv(nq, ROT_Q)), dim3(256),
+                       ROT_Q * pq.d_s * sizeof(float), st, b.Qs, b.ldqs, nq, pq.R, pq.d_s, qr_hi,
+                       qr_lo, ldqr);
+  }
+  {
+    KernelTimer tm("pq_lut", st);
+    hipLaunchKernelGGL(k_pq_lut, dim3((unsigned)nq), dim3(256), pq.d_s * sizeof(float), st, qr_hi,
+                       ldqr, pq.cb, pq.M, pq.dsub, lut);
+  }
+  {
+    KernelTimer tm("adc_scan", st);
+    hipLaunchKernelGGL(k_adc_scan, dim3((unsigned)(nq * nprobe)), dim3(256),
+                       pq.M * 256 * sizeof(float), st, lut, pq.M, pq.codes, b.probes, nprobe,
+                       ix->poff, ix->len, b.pair_base, b.D);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  SelArgs s{};
+  s.mode = SEL_ADC;
+  s.D = b.D;
+  s.seg_off = b.seg_off;
+  const int32_t keep = rerank_k > 0 ? rerank_k : k;
+  s.K1 = std::min<int32_t>(keep + REFINE_MARGIN, MAX_SHORTLIST);
+  s.K2 = keep;
+  s.kout = k;
+  s.stageB = rerank_k > 0;
+  s.Qs = b.Qs;
+  s.ldqs = b.ldqs;
+  s.d_dot = pq.d_s;
+  s.d_B = d_rerank;
+  s.vec = ix->vec;
+  s.d_pad = ix->d_pad;
+  s.poff = ix->poff;
+  s.rowid = ix->rowid;
+  s.probes = b.probes;
+  s.nprobe = nprobe;
+  s.pair_base = b.pair_base;
+  s.codes = pq.codes;
+  s.M = pq.M;
+  s.dsub = pq.dsub;
+  s.cb = pq.cb;
+  s.qr_hi = qr_hi;
+  s.qr_lo = qr_lo;
+  s.ldqr = ldqr;
+  s.out_dist = dist;
+  s.out_ids = ids;
+  {
+    KernelTimer tm("select_adc", st);
     hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
   }
   return hipGetLastError();

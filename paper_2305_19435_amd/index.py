@@ -101,6 +101,35 @@ class IvfIndex:
                                        ids.data_ptr(), _stream(stream)))
         return dist, ids
 
+    # ---- IVF-PQ -------------------------------------------------------------------
+    def pq_import(self, M: int, d_s: int, R, codebooks, codes, stream=None):
+        """adanns_pq_import: R [d_s, d_s] or None, codebooks [M, 256, d_s/M], codes [n, M]."""
+        dev = torch.device("cuda")
+        Rd = None if R is None else _dev_f32(R, dev)
+        Cd = _dev_f32(codebooks, dev)
+        codes_t = codes if isinstance(codes, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(codes, dtype=np.uint8))
+        Kd = codes_t.to(device=dev, dtype=torch.uint8).contiguous()
+        check(lib.adanns_pq_import(self._h, M, d_s, _ptr(Rd), Cd.data_ptr(), Kd.data_ptr(),
+                                   _stream(stream)))
+
+    def search_pq(self, Q, d_c: int, nprobe: int, M: int, k: int, rerank_k: int = 0,
+                  d_rerank: int = 0, return_probes=False, stream=None, out=None):
+        """adanns_search_pq. Returns (dist, ids[, probes])."""
+        Qd = Q if (isinstance(Q, torch.Tensor) and Q.is_cuda and Q.dtype == torch.float32
+                   and Q.stride(1) == 1) else _dev_f32(Q, "cuda")
+        nq = Qd.shape[0]
+        if out is None:
+            dist = torch.empty((nq, k), dtype=torch.float32, device=Qd.device)
+            ids = torch.empty((nq, k), dtype=torch.int64, device=Qd.device)
+        else:
+            dist, ids = out
+        probes = torch.empty((nq, nprobe), dtype=torch.int32, device=Qd.device) if return_probes else None
+        check(lib.adanns_search_pq(self._h, Qd.data_ptr(), nq, Qd.stride(0) if nq else Qd.shape[1],
+                                   d_c, nprobe, M, k, rerank_k, d_rerank, dist.data_ptr(),
+                                   ids.data_ptr(), _ptr(probes), _stream(stream)))
+        return (dist, ids, probes) if return_probes else (dist, ids)
+
     # ---- introspection ----------------------------------------------------------
     def lists(self):
         off = np.empty(self.nlist + 1, dtype=np.int64)

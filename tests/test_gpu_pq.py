@@ -1,0 +1,84 @@
+"""GPU parity of AdANNS-IVF-PQ search (adanns_search_pq) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import check, ivf, pq
+from parity_util import oracle_index
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_19435_amd as p
+    return p
+
+
+def make_codec(X, M, d_s, opq, seed):
+    """Oracle-trained codec, rounded to the FP32 values the library holds."""
+    X64 = X[:, :d_s].astype(np.float64)
+    init = synth.init_rows(len(X), 256, seed, synth.STREAM_PQ)
+    if opq:
+        R, cbs, _ = pq.opq_train64(X64[:4000], M, 3, 3, synth.init_rows(4000, 256, seed, synth.STREAM_PQ))
+    else:
+        R, cbs = np.eye(d_s), pq.pq_train64(X64, M, 4, init_rows=init)
+    R32, cb32 = R.astype(np.float32), cbs.astype(np.float32)
+    codes = pq.pq_encode64(X64 @ R32.astype(np.float64), cb32.astype(np.float64))
+    return R32, cb32, codes
+
+
+@pytest.fixture(scope="module")
+def pq_small(lib, small_data):
+    w, X, Q = small_data
+    C32, a, off, ids = oracle_index(X, w.nlist, w.d_c, 10, w.seed)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    codecs = {}
+    for M, opq in ((16, True), (8, False)):
+        R32, cb32, codes = make_codec(X, M, w.d, opq, w.seed + M)
+        index.pq_import(M, w.d, R32 if opq else None, cb32, codes)
+        codecs[M] = (R32, cb32, codes)
+    yield w, X, Q, C32, off, ids, index, codecs
+    index.free()
+
+
+@pytest.mark.parametrize("M,nprobe,k,rerank", [(16, 4, 10, 0), (8, 4, 10, 0), (16, 4, 10, 40),
+                                               (16, 32, 5, 0), (8, 2, 50, 60)])
+def test_pq_parity(pq_small, M, nprobe, k, rerank):
+    w, X, Q, C32, off, ids, index, codecs = pq_small
+    R32, cb32, codes = codecs[M]
+    d_c = w.d_c
+    dist, gid, probes = index.search_pq(torch.from_numpy(Q).cuda(), d_c, nprobe, M, k,
+                                        rerank_k=rerank, d_rerank=w.d, return_probes=True)
+    torch.cuda.synchronize()
+    dist, gid, probes = dist.cpu().numpy(), gid.cpu().numpy(), probes.cpu().numpy()
+    Cf = C32.astype(np.float64)
+    for qi in range(len(Q)):
+        assert check.probes_valid(ivf.coarse64(Q[qi], Cf, d_c), probes[qi], nprobe)
+    rd, ri, _, cands, luts = pq.ivfpq_search64(
+        Q, Cf, off, ids, codes, R32.astype(np.float64), cb32.astype(np.float64), d_c, nprobe, k,
+        rerank_k=rerank, X=X, d_rerank=w.d, forced_probes=probes, return_candidates=True)
+    rep = check.Report()
+    for qi in range(len(Q)):
+        if rerank:
+            fn = None
+        else:
+            lut = luts[qi]
+            fn = (lambda lut: (lambda idx: pq.adc_dist64(lut, codes[np.asarray(idx)])))(lut)
+        check.compare_knn(Q[qi], X, cands[qi], dist[qi], gid[qi], rd[qi], ri[qi], w.d,
+                          report=rep, tag=f"q{qi}", dist64=fn)
+    assert rep.ok, rep.problems
+
+
+def test_pq_invalid(pq_small, lib):
+    w, X, Q, C32, off, ids, index, codecs = pq_small
+    Qd = torch.from_numpy(Q).cuda()
+    with pytest.raises(lib.AdannsError):
+        index.search_pq(Qd, w.d_c, 4, 12, 10)           # no codec with M = 12
+    with pytest.raises(lib.AdannsError):
+        index.search_pq(Qd, w.d_c, 4, 16, 10, rerank_k=5, d_rerank=w.d)   # rerank_k < k
+    with pytest.raises(lib.AdannsError):
+        index.pq_import(16, w.d, None, codecs[16][1], codecs[16][2])      # duplicate M
