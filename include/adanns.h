@@ -167,6 +167,44 @@ adanns_status adanns_search_pq(const adanns_index *index, const float *Q, int64_
                                int32_t *probes, void *stream);
 
 /*
+ * Precision form (Section 4.3: a cheap first pass builds a shortlist that is
+ * re-ranked with the full-precision representation). Builds a low-precision
+ * copy of the index's vectors and centroids: fmt ADANNS_BF16 (round to
+ * nearest even) or ADANNS_FP8_E4M3 (OCP e4m3, one FP32 scale per vector,
+ * scale = max|x| / 448 over the vector's d coordinates, codes of
+ * x * (448 / max|x|) rounded to nearest even, saturating). Idempotent.
+ * Synchronises ``stream``.
+ */
+adanns_status adanns_set_precision(adanns_index *index, int32_t fmt, void *stream);
+
+/*
+ * Precision-form search. Queries are quantised the same way (one scale per
+ * query over its first d coordinates, so ldq >= d). Coarse: first-pass
+ * scores of quantised query and centroid prefixes on BF16 / FP8 MFMA with
+ * FP32 accumulation; the nprobe + coarse_margin best by the exact distance
+ * between the quantised values, then the nprobe nearest by exact FP32
+ * centroid distance. Scan: first-pass distances of quantised query and
+ * vectors on MFMA; the rerank_k best by the exact distance between the
+ * quantised values; those re-ranked by the exact squared L2 distance on the
+ * FP32 vectors' first d_s coordinates; dist holds those exact distances.
+ * Needs adanns_set_precision(fmt) first. 1 <= k <= rerank_k <= 1016,
+ * nprobe + coarse_margin <= 1016. Other conventions as adanns_search.
+ */
+adanns_status adanns_search_precision(const adanns_index *index, const float *Q, int64_t nq,
+                                      int64_t ldq, int32_t d_c, int32_t d_s, int32_t nprobe,
+                                      int32_t k, int32_t fmt, int32_t rerank_k,
+                                      int32_t coarse_margin, float *dist, int64_t *ids,
+                                      int32_t *probes, void *stream);
+
+/*
+ * The low-precision copy as stored, in database-id order: values host
+ * [n x d] (uint16 bf16 bits, or e4m3 bytes), scales host [n] FP32 (1 for
+ * bf16). Either may be NULL. Synchronous; for tests and tools.
+ */
+adanns_status adanns_index_quantized(const adanns_index *index, int32_t fmt, void *values,
+                                     float *scales);
+
+/*
  * Kernel timing with HIP events, for measurement tools. While enabled, every
  * search records an event pair around each of its kernel groups on its
  * stream ("tile_dist_coarse", "select_coarse", "bucketing",

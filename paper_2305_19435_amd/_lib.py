@@ -34,6 +34,10 @@ _SIGS = {
     "adanns_build_ivf": (C.c_int, [vp, i64, i32, i64, i32, i32, i32, vp, vp, i64, vp, vp, PIX]),
     "adanns_pq_import": (C.c_int, [vp, i32, i32, vp, vp, vp, vp]),
     "adanns_search_pq": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp]),
+    "adanns_set_precision": (C.c_int, [vp, i32, vp]),
+    "adanns_index_quantized": (C.c_int, [vp, i32, vp, vp]),
+    "adanns_search_precision": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, i32, i32, i32,
+                                          vp, vp, vp, vp]),
     "adanns_timing_enable": (C.c_int, [i32]),
     "adanns_timing_reset": (C.c_int, []),
     "adanns_timing_read": (C.c_int, [C.c_char_p, vp, vp]),

@@ -118,6 +118,12 @@ void free_index_memory(adanns_index *ix) {
   void *ptrs[] = {ix->vec, ix->poff, ix->len, ix->rowid, ix->cent, ix->cent_slab};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  for (auto &qsv : ix->quant) {
+    void *pp[] = {qsv.vec, qsv.scale, qsv.cent, qsv.cent_scale};
+    for (void *p : pp)
+      if (p) (void)hipFree(p);
+    qsv = QuantStore{};
+  }
   for (auto &kv : ix->pq) {
     void *pp[] = {kv.second.R, kv.second.cb, kv.second.codes};
     for (void *p : pp)
@@ -664,6 +670,136 @@ adanns_status adanns_search_pq(const adanns_index *cix, const float *Q, int64_t 
   ADANNS_HIP(launch_coarse(ix, b, nq, d_c, nprobe, probes, st));
   ADANNS_HIP(launch_pq_search(ix, pq, b, nq, nprobe, k, rerank_k, d_rerank, qr_hi, qr_lo, lut,
                               dist, ids, st));
+  return ADANNS_OK;
+}
+
+adanns_status adanns_set_precision(adanns_index *ix, int32_t fmt, void *stream) {
+  clear_error();
+  ADANNS_REQUIRE(ix != nullptr, "index is NULL");
+  ADANNS_REQUIRE(fmt == ADANNS_BF16 || fmt == ADANNS_FP8_E4M3,
+                 "fmt must be ADANNS_BF16 (1) or ADANNS_FP8_E4M3 (2), got %d", fmt);
+  ADANNS_REQUIRE(ix->vec != nullptr, "the index holds no FP32 vectors to quantise");
+  if (ix->quant[fmt].vec) return ADANNS_OK;
+  adanns_status s = check_async();
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  QuantStore q;
+  const size_t eb = fmt == ADANNS_BF16 ? 2 : 1;
+  auto fail = [&](adanns_status e) {
+    void *pp[] = {q.vec, q.scale, q.cent, q.cent_scale};
+    for (void *p : pp)
+      if (p) (void)hipFree(p);
+    return e;
+  };
+  if ((s = dmalloc(ix, &q.vec, (size_t)ix->rows_pad * ix->d_pad * eb))) return fail(s);
+  if ((s = dmalloc(ix, &q.cent, (size_t)ix->nl_pad * ix->d_cb_pad * eb))) return fail(s);
+  if (fmt == ADANNS_FP8_E4M3) {
+    if ((s = dmalloc(ix, (void **)&q.scale, (size_t)ix->rows_pad * sizeof(float)))) return fail(s);
+    if ((s = dmalloc(ix, (void **)&q.cent_scale, (size_t)ix->nl_pad * sizeof(float))))
+      return fail(s);
+  }
+  if (launch_quantize_store(ix, fmt, q, st)) {
+    set_error("HIP error while quantising the vectors");
+    return fail(ADANNS_EHIP);
+  }
+  if (fmt == ADANNS_FP8_E4M3) {
+    int64_t *d_poff2 = nullptr;
+    const int64_t h_poff2[2] = {0, ix->nl_pad};
+    if (hipMalloc(&d_poff2, 2 * sizeof(int64_t)) ||
+        hipMemcpyAsync(d_poff2, h_poff2, 2 * sizeof(int64_t), hipMemcpyHostToDevice, st) ||
+        launch_quantize_cent_fp8(ix, d_poff2, q, st) || hipStreamSynchronize(st)) {
+      if (d_poff2) (void)hipFree(d_poff2);
+      set_error("HIP error while quantising the centroids");
+      return fail(ADANNS_EHIP);
+    }
+    (void)hipFree(d_poff2);
+  }
+  if (hipStreamSynchronize(st)) {
+    set_error("HIP error while quantising");
+    return fail(ADANNS_EHIP);
+  }
+  ix->quant[fmt] = q;
+  return ADANNS_OK;
+}
+
+adanns_status adanns_search_precision(const adanns_index *cix, const float *Q, int64_t nq,
+                                      int64_t ldq, int32_t d_c, int32_t d_s, int32_t nprobe,
+                                      int32_t k, int32_t fmt, int32_t rerank_k,
+                                      int32_t coarse_margin, float *dist, int64_t *ids,
+                                      int32_t *probes, void *stream) {
+  clear_error();
+  adanns_index *ix = const_cast<adanns_index *>(cix);
+  ADANNS_REQUIRE(ix != nullptr, "index is NULL");
+  ADANNS_REQUIRE(fmt == ADANNS_BF16 || fmt == ADANNS_FP8_E4M3, "fmt must be 1 or 2, got %d", fmt);
+  ADANNS_REQUIRE(ix->quant[fmt].vec != nullptr,
+                 "no quantised copy in this format: call adanns_set_precision first");
+  ADANNS_REQUIRE(nq >= 0, "nq must be >= 0");
+  ADANNS_REQUIRE(d_c >= 1 && d_c <= ix->d_cb, "d_c must be in [1, %d], got %d", ix->d_cb, d_c);
+  ADANNS_REQUIRE(d_s >= 1 && d_s <= ix->d, "d_s must be in [1, %d], got %d", ix->d, d_s);
+  ADANNS_REQUIRE(nprobe >= 1 && nprobe <= ix->nlist, "nprobe must be in [1, %d], got %d",
+                 ix->nlist, nprobe);
+  ADANNS_REQUIRE(k >= 1 && rerank_k >= k && rerank_k <= MAX_SHORTLIST - REFINE_MARGIN,
+                 "need 1 <= k <= rerank_k <= %d (k %d, rerank_k %d)",
+                 MAX_SHORTLIST - REFINE_MARGIN, k, rerank_k);
+  ADANNS_REQUIRE(coarse_margin >= 0 && nprobe + coarse_margin <= MAX_SHORTLIST - REFINE_MARGIN,
+                 "coarse_margin must be >= 0 with nprobe + coarse_margin <= %d",
+                 MAX_SHORTLIST - REFINE_MARGIN);
+  ADANNS_REQUIRE(ldq >= ix->d, "ldq (%lld) must be >= d (%d): queries are quantised over d",
+                 (long long)ldq, ix->d);
+  ADANNS_REQUIRE(nq < (int64_t(1) << 31) / nprobe, "nq * nprobe must be below 2^31");
+  if (nq == 0) return ADANNS_OK;
+  ADANNS_REQUIRE(Q && dist && ids, "Q, dist and ids must be non-NULL");
+  adanns_status s = check_async();
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int32_t dq = std::max(d_c, d_s);
+  const int32_t dq_pad = (int32_t)round_up(dq, SLAB);
+  const size_t eb = fmt == ADANNS_BF16 ? 2 : 1;
+  size_t total = 0;
+  carve(nullptr, ix, nq, dq_pad, nprobe, true, &total);
+  const size_t extra = (size_t)round_up((size_t)nq * ix->d_pad * eb, 256) +
+                       (size_t)round_up((size_t)nq * 4, 256) + 1024;
+  void *base = nullptr;
+  if ((s = get_scratch(ix, st, total + extra, &base))) return s;
+  SearchBufs b = carve((char *)base, ix, nq, dq_pad, nprobe, true, &total);
+  Carver c{(char *)base, total, 0};
+  void *Qq = c.take<uint8_t>((size_t)nq * ix->d_pad * eb);
+  float *qscale = c.take<float>((size_t)nq);
+  ADANNS_HIP(launch_stage_queries(Q, nq, ldq, dq, b.Qs, b.ldqs, st));
+  ADANNS_HIP(launch_quantize_queries(Q, nq, ldq, ix->d, fmt, Qq, ix->d_pad, qscale, st));
+  ADANNS_HIP(launch_precision_search(ix, fmt, b, Qq, ix->d_pad, qscale, nq, d_c, d_s, nprobe, k,
+                                     rerank_k, coarse_margin, dist, ids, probes, st));
+  return ADANNS_OK;
+}
+
+adanns_status adanns_index_quantized(const adanns_index *ix, int32_t fmt, void *values,
+                                     float *scales) {
+  clear_error();
+  ADANNS_REQUIRE(ix != nullptr, "index is NULL");
+  ADANNS_REQUIRE(fmt == ADANNS_BF16 || fmt == ADANNS_FP8_E4M3, "fmt must be 1 or 2, got %d", fmt);
+  ADANNS_REQUIRE(ix->quant[fmt].vec != nullptr, "no quantised copy in this format");
+  const size_t eb = fmt == ADANNS_BF16 ? 2 : 1;
+  std::vector<uint8_t> lay((size_t)ix->rows_pad * ix->d_pad * eb);
+  ADANNS_HIP(hipMemcpy(lay.data(), ix->quant[fmt].vec, lay.size(), hipMemcpyDeviceToHost));
+  std::vector<float> sc;
+  if (fmt == ADANNS_FP8_E4M3) {
+    sc.resize(ix->rows_pad);
+    ADANNS_HIP(hipMemcpy(sc.data(), ix->quant[fmt].scale, sc.size() * 4, hipMemcpyDeviceToHost));
+  }
+  for (int32_t h = 0; h < ix->nlist; ++h) {
+    const int64_t p0 = ix->h_poff[h], npad = ix->h_poff[h + 1] - p0;
+    for (int64_t r = 0; r < ix->h_len[h]; ++r) {
+      const int64_t id = ix->h_ids[ix->h_off[h] + r];
+      if (values) {
+        for (int32_t dim = 0; dim < ix->d; ++dim) {
+          const size_t src = (size_t)(p0 * ix->d_pad + ((int64_t)(dim / SLAB) * npad + r) * SLAB +
+                                      dim % SLAB) * eb;
+          std::memcpy((uint8_t *)values + ((size_t)id * ix->d + dim) * eb, &lay[src], eb);
+        }
+      }
+      if (scales) scales[id] = fmt == ADANNS_FP8_E4M3 ? sc[p0 + r] : 1.0f;
+    }
+  }
   return ADANNS_OK;
 }
 

@@ -84,6 +84,15 @@ struct PqCodec {
   float *cb = nullptr;       // [M][256][dsub]
   uint8_t *codes = nullptr;  // [rows_pad][M], layout-row order, zero on padding rows
 };
+// Low-precision copies of the vectors and centroids (precision form): same
+// slab indexing as the FP32 layout, 2-byte (bf16) or 1-byte (e4m3) elements,
+// one FP32 scale per stored row for e4m3.
+struct QuantStore {
+  void *vec = nullptr;
+  float *scale = nullptr;       // [rows_pad] (e4m3 only)
+  void *cent = nullptr;         // one-list slab layout of nl_pad rows
+  float *cent_scale = nullptr;  // [nl_pad] (e4m3 only)
+};
 }  // namespace adanns
 
 struct adanns_index {
@@ -104,6 +113,7 @@ struct adanns_index {
   float *cent = nullptr;               // [nlist][d_cb_pad] row-major, zero padded
   float *cent_slab = nullptr;          // centroids as one slab-layout list of nl_pad rows
   std::map<int32_t, adanns::PqCodec> pq;   // keyed by M
+  adanns::QuantStore quant[3];             // indexed by adanns_format (1 bf16, 2 e4m3)
   size_t own_bytes = 0;
   std::mutex mu;
   std::map<hipStream_t, adanns::Scratch> scratch;
@@ -163,6 +173,19 @@ hipError_t launch_bucketing(const adanns_index *ix, const SearchBufs &b, int64_t
                             int32_t nprobe, hipStream_t st);
 hipError_t launch_gather_codes(const uint8_t *codes, int32_t M, const int64_t *rowid,
                                int64_t rows_pad, uint8_t *out, hipStream_t st);
+// Precision form: quantised copies, quantised queries, first passes, selection.
+hipError_t launch_quantize_store(const adanns_index *ix, int32_t fmt, QuantStore &qs,
+                                 hipStream_t st);
+hipError_t launch_quantize_cent_fp8(const adanns_index *ix, const int64_t *poff2, QuantStore &qs,
+                                    hipStream_t st);
+hipError_t launch_quantize_queries(const float *Q, int64_t nq, int64_t ldq, int32_t d,
+                                   int32_t fmt, void *Qq, int64_t ldqq, float *qscale,
+                                   hipStream_t st);
+hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const SearchBufs &b,
+                                   const void *Qq, int64_t ldqq, const float *qscale, int64_t nq,
+                                   int32_t d_c, int32_t d_s, int32_t nprobe, int32_t k,
+                                   int32_t rerank_k, int32_t coarse_margin, float *dist,
+                                   int64_t *ids, int32_t *user_probes, hipStream_t st);
 // IVF-PQ: rotation (compensated), tables, ADC scan and selection.
 hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const SearchBufs &b,
                             int64_t nq, int32_t nprobe, int32_t k, int32_t rerank_k,

@@ -828,6 +828,324 @@ __global__ __launch_bounds__(256) void k_adc_scan(const float *__restrict__ lut,
   }
 }
 
+// ---- precision form ------------------------------------------------------------
+// BF16: upper half of the FP32 encoding after round-to-nearest-even.
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// OCP e4m3: nearest value, ties to the even code, saturating at +-448; the
+// scaling by powers of two is exact, so the only rounding is rint().
+__device__ __forceinline__ uint8_t e4m3_encode(float y) {
+  const float a = fabsf(y);
+  uint32_t code;
+  if (!(a < 448.f)) {
+    code = 0x7Eu;
+  } else if (a < 0.015625f) {
+    code = (uint32_t)__builtin_rintf(a * 512.f);
+  } else {
+    int e = (int)((__float_as_uint(a) >> 23) & 0xFFu) - 127;
+    uint32_t m = (uint32_t)__builtin_rintf(a * __uint_as_float((uint32_t)(130 - e) << 23));
+    if (m == 16u) {
+      m = 8u;
+      e += 1;
+    }
+    code = ((uint32_t)(e + 7) << 3) | (m - 8u);
+    if (code > 0x7Eu) code = 0x7Eu;
+  }
+  const uint32_t sign = (code != 0u && (__float_as_uint(y) >> 31)) ? 0x80u : 0u;
+  return (uint8_t)(sign | code);
+}
+
+__global__ void k_quant_bf16(const float *__restrict__ src, int64_t n, uint16_t *__restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = bf16_rne(src[i]);
+}
+
+// One wave per slab-layout row: scale = amax / 448 over the row's first
+// d_used coordinates, codes of x * (448 / amax).
+__global__ __launch_bounds__(256) void k_quant_fp8_slab(const float *__restrict__ src,
+                                                        const int64_t *__restrict__ poff,
+                                                        int32_t nlist, int64_t rows, int32_t d_pad,
+                                                        int32_t d_used, uint8_t *__restrict__ dst,
+                                                        float *__restrict__ scale) {
+  const int lane = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (g >= rows) return;
+  int lo = 0, hi = nlist - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (poff[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  const int64_t p0 = poff[lo], npad = poff[lo + 1] - p0, r = g - p0;
+  const int64_t base = p0 * d_pad + r * SLAB;
+  float amax = 0.f;
+  for (int dim = lane; dim < d_used; dim += 64)
+    amax = fmaxf(amax, fabsf(src[base + (int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+  const float inv = amax > 0.f ? 448.f / amax : 0.f;
+  if (lane == 0) scale[g] = amax / 448.f;
+  for (int dim = lane; dim < d_pad; dim += 64) {
+    const int64_t idx = base + (int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB);
+    dst[idx] = dim < d_used ? e4m3_encode(src[idx] * inv) : (uint8_t)0;
+  }
+}
+
+// Row-major query quantisation (one wave per row), zero beyond d_used.
+__global__ __launch_bounds__(256) void k_quant_rows(const float *__restrict__ Q, int64_t nq,
+                                                    int64_t ldq, int32_t d_used, int32_t fmt,
+                                                    void *__restrict__ out, int64_t ldo,
+                                                    float *__restrict__ scale) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (q >= nq) return;
+  const float *row = Q + q * ldq;
+  if (fmt == 1) {
+    uint16_t *o = (uint16_t *)out + q * ldo;
+    for (int dim = lane; dim < ldo; dim += 64) o[dim] = dim < d_used ? bf16_rne(row[dim]) : 0;
+    if (lane == 0 && scale) scale[q] = 1.f;
+    return;
+  }
+  float amax = 0.f;
+  for (int dim = lane; dim < d_used; dim += 64) amax = fmaxf(amax, fabsf(row[dim]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+  const float inv = amax > 0.f ? 448.f / amax : 0.f;
+  if (lane == 0) scale[q] = amax / 448.f;
+  uint8_t *o = (uint8_t *)out + q * ldo;
+  for (int dim = lane; dim < ldo; dim += 64) o[dim] = dim < d_used ? e4m3_encode(row[dim] * inv) : 0;
+}
+
+__device__ __forceinline__ float qdecode(int FMT, uint32_t bits) {
+  return FMT == 1 ? __uint_as_float(bits << 16) : e4m3_to_float(bits);
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct TileQArgs {
+  const uint8_t *Qq;       // quantised queries, row-major, ldqq elements per row
+  int64_t ldqq;
+  const float *qscale;     // per query (e4m3), else unused
+  int32_t d_dot;
+  const uint8_t *vec;      // quantised slab layout
+  const float *vscale;     // per layout row (e4m3)
+  int32_t d_pad;
+  const int64_t *poff;
+  const int32_t *len;
+  int32_t nlist;
+  const int32_t *tile_off;
+  const int32_t *bkt_off;
+  const int32_t *cnt;
+  const int32_t *bucket;
+  int32_t pair_div;
+  const int64_t *pair_base;
+  float *out;
+  int32_t coarse;
+  int64_t nq;
+  int32_t nl, nl_pad, qtiles, total_host;
+};
+
+// First pass of the precision form: s_x^2 |x_hat|^2 - 2 s_q s_x (q_hat . x_hat)
+// on BF16 (FMT 1) or e4m3 (FMT 2) MFMA with FP32 accumulation; products of
+// these formats are exact in FP32. Tiles of 64 queries x 64 vectors, K steps
+// of 4 slabs (128 coordinates).
+template <int FMT>
+__global__ __launch_bounds__(256) void k_tile_dist_q(TileQArgs a) {
+  constexpr int EB = FMT == 1 ? 2 : 1;
+  constexpr int KS = 4;
+  constexpr int ROWB = SLAB * EB;
+  constexpr int STEPB = KS * ROWB;
+  constexpr int CPR = STEPB / 16;          // 16-byte chunks per row per step
+  constexpr int NU = TILE_Q * CPR / 256;   // chunks per thread per operand
+  __shared__ __attribute__((aligned(16))) uint8_t As[TILE_Q][STEPB + 16];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[TILE_V][STEPB + 16];
+  __shared__ int64_t rbase[TILE_Q];
+  __shared__ int32_t rq[TILE_Q];
+  __shared__ float rsc[TILE_Q], csc[TILE_V], cn[TILE_V];
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int total = a.coarse ? a.total_host : a.tile_off[a.nlist];
+  const int G = gridDim.x;
+  const int L = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  const int rb = (wv >> 1) * 32, cb = (wv & 1) * 32;
+  const int fr = lane & 15, fg = lane >> 4;
+  const int nslab_dot = (a.d_dot + SLAB - 1) / SLAB;
+  const int nsteps = (nslab_dot + KS - 1) / KS;
+
+  for (int w = L; w < total; w += G) {
+    int h, qt, vt, m, nvec;
+    int64_t npad, p0;
+    if (a.coarse) {
+      h = 0;
+      qt = w % a.qtiles;
+      vt = w / a.qtiles;
+      m = (int)a.nq;
+      nvec = a.nl;
+      npad = a.nl_pad;
+      p0 = 0;
+    } else {
+      int lo = 0, hi = a.nlist - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (a.tile_off[mid] <= w) lo = mid; else hi = mid - 1;
+      }
+      h = lo;
+      m = a.cnt[h];
+      nvec = a.len[h];
+      p0 = a.poff[h];
+      npad = a.poff[h + 1] - p0;
+      const int qts = (m + TILE_Q - 1) / TILE_Q;
+      const int rem = w - a.tile_off[h];
+      qt = rem % qts;
+      vt = rem / qts;
+    }
+    __syncthreads();
+    if (tid < TILE_Q) {
+      const int i = qt * TILE_Q + tid;
+      if (i < m) {
+        const int32_t pair = a.coarse ? i : a.bucket[a.bkt_off[h] + i];
+        const int32_t qq = pair / a.pair_div;
+        rq[tid] = qq;
+        rbase[tid] = a.coarse ? (int64_t)i * a.nl : a.pair_base[pair];
+        rsc[tid] = FMT == 2 ? a.qscale[qq] : 1.f;
+      } else {
+        rq[tid] = -1;
+        rbase[tid] = 0;
+        rsc[tid] = 0.f;
+      }
+    } else if (tid < TILE_Q + TILE_V) {
+      const int col = tid - TILE_Q;
+      csc[col] = FMT == 2 ? a.vscale[p0 + vt * TILE_V + col] : 1.f;
+    }
+    __syncthreads();
+    const uint8_t *vbase = a.vec + (p0 * a.d_pad + (int64_t)vt * TILE_V * SLAB) * EB;
+
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+    float nrm[NU];
+#pragma unroll
+    for (int u = 0; u < NU; ++u) nrm[u] = 0.f;
+    uint4 ra[NU], rbv[NU];
+
+    auto load = [&](int step) {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int idx = tid + 256 * u;
+        const int row = idx / CPR, ch = idx % CPR;
+        const int byte = ch * 16;
+        const int slab = step * KS + byte / ROWB;
+        const int inb = byte % ROWB;
+        const int e0 = slab * SLAB + inb / EB;  // first coordinate of the chunk
+        uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+        if (slab < nslab_dot) {
+          const int qq = rq[row];
+          if (qq >= 0) va = *(const uint4 *)(a.Qq + ((int64_t)qq * a.ldqq + e0) * EB);
+          vb = *(const uint4 *)(vbase + ((int64_t)slab * npad * SLAB + (int64_t)row * SLAB) * EB + inb);
+          if (e0 + 16 / EB > a.d_dot) {  // zero query coordinates past d_dot
+            uint32_t wds[4] = {va.x, va.y, va.z, va.w};
+#pragma unroll
+            for (int e = 0; e < 16 / EB; ++e) {
+              if (e0 + e >= a.d_dot) {
+                const int wi = (e * EB) / 4, sh = ((e * EB) % 4) * 8;
+                wds[wi] &= ~(((1u << (8 * EB)) - 1u) << sh);
+              }
+            }
+            va = make_uint4(wds[0], wds[1], wds[2], wds[3]);
+          }
+        }
+        ra[u] = va;
+        rbv[u] = vb;
+      }
+    };
+
+    load(0);
+    for (int step = 0; step < nsteps; ++step) {
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int idx = tid + 256 * u;
+        const int row = idx / CPR, ch = idx % CPR;
+        *(uint4 *)&As[row][ch * 16] = ra[u];
+        *(uint4 *)&Bs[row][ch * 16] = rbv[u];
+        // squared norm of the vector chunk, coordinates below d_dot only
+        const int byte = ch * 16;
+        const int e0 = (step * KS + byte / ROWB) * SLAB + (byte % ROWB) / EB;
+        const uint32_t wds[4] = {rbv[u].x, rbv[u].y, rbv[u].z, rbv[u].w};
+#pragma unroll
+        for (int e = 0; e < 16 / EB; ++e) {
+          const uint32_t bits = (wds[(e * EB) / 4] >> (((e * EB) % 4) * 8)) & ((1u << (8 * EB)) - 1u);
+          const float v = qdecode(FMT, bits);
+          if (e0 + e < a.d_dot) nrm[u] += v * v;
+        }
+      }
+      __syncthreads();
+      if (step + 1 < nsteps) load(step + 1);
+#pragma unroll
+      for (int sl = 0; sl < KS; ++sl) {
+        const int off = sl * ROWB + fg * 8 * EB;
+        if (FMT == 1) {
+          bf16x8 af[2], bfv[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const uint4 x = *(const uint4 *)&As[rb + i * 16 + fr][off];
+            af[i] = __builtin_bit_cast(bf16x8, x);
+          }
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const uint4 x = *(const uint4 *)&Bs[cb + j * 16 + fr][off];
+            bfv[j] = __builtin_bit_cast(bf16x8, x);
+          }
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfv[j], acc[i][j], 0, 0, 0);
+        } else {
+          long af[2], bfv[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) af[i] = *(const long *)&As[rb + i * 16 + fr][off];
+#pragma unroll
+          for (int j = 0; j < 2; ++j) bfv[j] = *(const long *)&Bs[cb + j * 16 + fr][off];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af[i], bfv[j], acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+    // norms: CPR consecutive threads share a row
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+#pragma unroll
+      for (int off = 1; off < CPR; off <<= 1) nrm[u] += __shfl_xor(nrm[u], off);
+      const int idx = tid + 256 * u;
+      if ((idx % CPR) == 0) cn[idx / CPR] = nrm[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = rb + i * 16 + (lane >> 4) * 4 + e;
+          const int col = cb + j * 16 + (lane & 15);
+          const int v = vt * TILE_V + col;
+          if (rq[row] >= 0 && v < nvec) {
+            const float sx = csc[col], sq = rsc[row];
+            a.out[rbase[row] + v] = sx * sx * cn[col] - 2.0f * sq * sx * acc[i][j][e];
+          }
+        }
+  }
+}
+
 // ---- probe bucketing ---------------------------------------------------------
 __global__ void k_count(const int32_t *__restrict__ probes, int64_t npairs,
                         int32_t *__restrict__ cnt) {
@@ -1079,6 +1397,166 @@ hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, 
   {
     KernelTimer tm("select_scan", st);
     hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize_store(const adanns_index *ix, int32_t fmt, QuantStore &qs,
+                                 hipStream_t st) {
+  if (fmt == 1) {
+    const int64_t nv = ix->rows_pad * ix->d_pad, nc = (int64_t)ix->nl_pad * ix->d_cb_pad;
+    hipLaunchKernelGGL(k_quant_bf16, dim3(blocks_for(nv, 256)), dim3(256), 0, st, ix->vec, nv,
+                       (uint16_t *)qs.vec);
+    hipLaunchKernelGGL(k_quant_bf16, dim3(blocks_for(nc, 256)), dim3(256), 0, st, ix->cent_slab,
+                       nc, (uint16_t *)qs.cent);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_quant_fp8_slab, dim3(blocks_for(ix->rows_pad, 4)), dim3(256), 0, st,
+                     ix->vec, ix->poff, ix->nlist, ix->rows_pad, ix->d_pad, ix->d,
+                     (uint8_t *)qs.vec, qs.scale);
+  // the centroids are quantised by launch_quantize_cent_fp8
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize_cent_fp8(const adanns_index *ix, const int64_t *poff2, QuantStore &qs,
+                                    hipStream_t st) {
+  hipLaunchKernelGGL(k_quant_fp8_slab, dim3(blocks_for(ix->nl_pad, 4)), dim3(256), 0, st,
+                     ix->cent_slab, poff2, 1, (int64_t)ix->nl_pad, ix->d_cb_pad, ix->d_cb,
+                     (uint8_t *)qs.cent, qs.cent_scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize_queries(const float *Q, int64_t nq, int64_t ldq, int32_t d,
+                                   int32_t fmt, void *Qq, int64_t ldqq, float *qscale,
+                                   hipStream_t st) {
+  if (nq == 0) return hipSuccess;
+  KernelTimer tm("quantize_queries", st);
+  hipLaunchKernelGGL(k_quant_rows, dim3(blocks_for(nq, 4)), dim3(256), 0, st, Q, nq, ldq, d, fmt,
+                     Qq, ldqq, qscale);
+  return hipGetLastError();
+}
+
+hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const SearchBufs &b,
+                                   const void *Qq, int64_t ldqq, const float *qscale, int64_t nq,
+                                   int32_t d_c, int32_t d_s, int32_t nprobe, int32_t k,
+                                   int32_t rerank_k, int32_t coarse_margin, float *dist,
+                                   int64_t *ids, int32_t *user_probes, hipStream_t st) {
+  const QuantStore &qs = ix->quant[fmt];
+  // coarse first pass on the quantised centroids
+  TileQArgs t{};
+  t.Qq = (const uint8_t *)Qq;
+  t.ldqq = ldqq;
+  t.qscale = qscale;
+  t.d_dot = d_c;
+  t.vec = (const uint8_t *)qs.cent;
+  t.vscale = qs.cent_scale;
+  t.d_pad = ix->d_cb_pad;
+  t.pair_div = 1;
+  t.out = b.S;
+  t.coarse = 1;
+  t.nq = nq;
+  t.nl = ix->nlist;
+  t.nl_pad = ix->nl_pad;
+  t.qtiles = (int32_t)cdiv(nq, TILE_Q);
+  t.total_host = t.qtiles * (int32_t)cdiv(ix->nlist, TILE_V);
+  int grid = (int)std::min<int64_t>(PERSIST_WG, round_up(t.total_host, 8));
+  {
+    KernelTimer tm("tile_q_coarse", st);
+    if (fmt == 1)
+      hipLaunchKernelGGL(k_tile_dist_q<1>, dim3(grid), dim3(256), 0, st, t);
+    else
+      hipLaunchKernelGGL(k_tile_dist_q<2>, dim3(grid), dim3(256), 0, st, t);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  SelArgs s{};
+  s.mode = SEL_COARSE_QUANT;
+  s.D = b.S;
+  s.nl = ix->nlist;
+  s.K2 = std::min<int32_t>(ix->nlist, nprobe + coarse_margin);
+  s.K1 = std::min<int32_t>(ix->nlist, s.K2 + REFINE_MARGIN);
+  s.kout = nprobe;
+  s.stageB = 1;
+  s.Qs = b.Qs;
+  s.ldqs = b.ldqs;
+  s.d_dot = d_c;
+  s.d_B = d_c;
+  s.cent = ix->cent;
+  s.ld_cent = ix->d_cb_pad;
+  s.qfmt = fmt;
+  s.qvec = qs.cent;
+  s.qscale = qs.cent_scale;
+  s.qQ = Qq;
+  s.qQscale = qscale;
+  s.ldqq = ldqq;
+  s.qnpad = ix->nl_pad;
+  s.out_probes = b.probes;
+  s.out_probes2 = user_probes;
+  {
+    KernelTimer tm("select_q_coarse", st);
+    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+  }
+  e = launch_bucketing(ix, b, nq, nprobe, st);
+  if (e != hipSuccess) return e;
+  // list scan first pass on the quantised vectors
+  TileQArgs u{};
+  u.Qq = (const uint8_t *)Qq;
+  u.ldqq = ldqq;
+  u.qscale = qscale;
+  u.d_dot = d_s;
+  u.vec = (const uint8_t *)qs.vec;
+  u.vscale = qs.scale;
+  u.d_pad = ix->d_pad;
+  u.poff = ix->poff;
+  u.len = ix->len;
+  u.nlist = ix->nlist;
+  u.tile_off = b.tile_off;
+  u.bkt_off = b.bkt_off;
+  u.cnt = b.cnt;
+  u.bucket = b.bucket;
+  u.pair_div = nprobe;
+  u.pair_base = b.pair_base;
+  u.out = b.D;
+  {
+    KernelTimer tm("tile_q_scan", st);
+    if (fmt == 1)
+      hipLaunchKernelGGL(k_tile_dist_q<1>, dim3(PERSIST_WG), dim3(256), 0, st, u);
+    else
+      hipLaunchKernelGGL(k_tile_dist_q<2>, dim3(PERSIST_WG), dim3(256), 0, st, u);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  SelArgs r{};
+  r.mode = SEL_QUANT;
+  r.D = b.D;
+  r.seg_off = b.seg_off;
+  r.K2 = rerank_k;
+  r.K1 = std::min<int32_t>(rerank_k + REFINE_MARGIN, MAX_SHORTLIST);
+  r.kout = k;
+  r.stageB = 1;
+  r.Qs = b.Qs;
+  r.ldqs = b.ldqs;
+  r.d_dot = d_s;
+  r.d_B = d_s;
+  r.vec = ix->vec;
+  r.d_pad = ix->d_pad;
+  r.poff = ix->poff;
+  r.rowid = ix->rowid;
+  r.probes = b.probes;
+  r.nprobe = nprobe;
+  r.pair_base = b.pair_base;
+  r.qfmt = fmt;
+  r.qvec = qs.vec;
+  r.qscale = qs.scale;
+  r.qd_pad = ix->d_pad;
+  r.qQ = Qq;
+  r.qQscale = qscale;
+  r.ldqq = ldqq;
+  r.out_dist = dist;
+  r.out_ids = ids;
+  {
+    KernelTimer tm("select_q_scan", st);
+    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, r);
   }
   return hipGetLastError();
 }

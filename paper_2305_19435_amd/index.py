@@ -130,6 +130,42 @@ class IvfIndex:
                                    ids.data_ptr(), _ptr(probes), _stream(stream)))
         return (dist, ids, probes) if return_probes else (dist, ids)
 
+    # ---- precision form -----------------------------------------------------------
+    FORMATS = {"bf16": 1, "fp8": 2}
+
+    def set_precision(self, fmt: str, stream=None):
+        """adanns_set_precision: build the BF16 or FP8-e4m3 copy."""
+        check(lib.adanns_set_precision(self._h, self.FORMATS[fmt], _stream(stream)))
+
+    def search_precision(self, Q, d_c: int, d_s: int, nprobe: int, k: int, fmt: str,
+                         rerank_k: int, coarse_margin: int = 8, return_probes=False,
+                         stream=None, out=None):
+        """adanns_search_precision. Returns (dist, ids[, probes])."""
+        Qd = Q if (isinstance(Q, torch.Tensor) and Q.is_cuda and Q.dtype == torch.float32
+                   and Q.stride(1) == 1) else _dev_f32(Q, "cuda")
+        nq = Qd.shape[0]
+        if out is None:
+            dist = torch.empty((nq, k), dtype=torch.float32, device=Qd.device)
+            ids = torch.empty((nq, k), dtype=torch.int64, device=Qd.device)
+        else:
+            dist, ids = out
+        probes = torch.empty((nq, nprobe), dtype=torch.int32, device=Qd.device) if return_probes else None
+        check(lib.adanns_search_precision(self._h, Qd.data_ptr(), nq,
+                                          Qd.stride(0) if nq else Qd.shape[1], d_c, d_s, nprobe,
+                                          k, self.FORMATS[fmt], rerank_k, coarse_margin,
+                                          dist.data_ptr(), ids.data_ptr(), _ptr(probes),
+                                          _stream(stream)))
+        return (dist, ids, probes) if return_probes else (dist, ids)
+
+    def quantized(self, fmt: str):
+        """The low-precision copy in id order: (values [n, d], scales [n])."""
+        dt = np.uint16 if fmt == "bf16" else np.uint8
+        vals = np.empty((self.n, self.d), dtype=dt)
+        sc = np.empty(self.n, dtype=np.float32)
+        check(lib.adanns_index_quantized(self._h, self.FORMATS[fmt], vals.ctypes.data,
+                                         sc.ctypes.data))
+        return vals, sc
+
     # ---- introspection ----------------------------------------------------------
     def lists(self):
         off = np.empty(self.nlist + 1, dtype=np.int64)

@@ -1,0 +1,74 @@
+"""GPU parity of the precision form (BF16 / FP8-e4m3 first pass, exact
+re-measurement, FP32 re-rank) against the FP64 oracle, and bit-exactness of
+the stored low-precision copies."""
+import numpy as np
+import pytest
+
+from oracle import check, precision
+from parity_util import oracle_index
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_19435_amd as p
+    return p
+
+
+@pytest.fixture(scope="module")
+def prec(lib, small_data):
+    w, X, Q = small_data
+    C32, a, off, ids = oracle_index(X, w.nlist, w.d_c, 10, w.seed)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    index.set_precision("bf16")
+    index.set_precision("fp8")
+    yield w, X, Q, C32, off, ids, index
+    index.free()
+
+
+def test_stored_copies_bit_exact(prec):
+    w, X, Q, C32, off, ids, index = prec
+    vals, sc = index.quantized("bf16")
+    assert np.array_equal(vals, precision.bf16_bits(X))
+    assert np.all(sc == 1.0)
+    codes, scale = index.quantized("fp8")
+    ref_codes, ref_scale = precision.fp8_quantize_rows(X)
+    assert np.array_equal(scale, ref_scale)
+    assert np.array_equal(codes, ref_codes)
+
+
+@pytest.mark.parametrize("fmt,d_c,d_s,nprobe,k,rerank,margin", [
+    ("bf16", 16, 64, 4, 10, 20, 8),
+    ("fp8", 16, 64, 4, 10, 20, 8),
+    ("bf16", 16, 48, 8, 5, 64, 4),
+    ("fp8", 12, 64, 3, 10, 10, 0),
+    ("fp8", 16, 64, 32, 10, 256, 8),
+])
+def test_precision_parity(prec, fmt, d_c, d_s, nprobe, k, rerank, margin):
+    w, X, Q, C32, off, ids, index = prec
+    dist, gid, probes = index.search_precision(torch.from_numpy(Q).cuda(), d_c, d_s, nprobe, k,
+                                               fmt, rerank, margin, return_probes=True)
+    torch.cuda.synchronize()
+    dist, gid, probes = dist.cpu().numpy(), gid.cpu().numpy(), probes.cpu().numpy()
+    rd, ri, rp, shortlists = precision.precision_search64(
+        X, Q, C32.astype(np.float64), off, ids, d_c, d_s, nprobe, k, fmt, rerank, margin,
+        return_shortlist=True)
+    assert np.array_equal(probes, rp)
+    rep = check.Report()
+    for qi in range(len(Q)):
+        check.compare_knn(Q[qi], X, shortlists[qi], dist[qi], gid[qi], rd[qi], ri[qi], d_s,
+                          report=rep, tag=f"q{qi}")
+    assert rep.ok, rep.problems
+
+
+def test_precision_requires_copy(lib, small_data):
+    w, X, Q = small_data
+    C32, a, off, ids = oracle_index(X[:2000], 8, w.d_c, 3, w.seed)
+    index = lib.IvfIndex.import_ivf(X[:2000], C32, a)
+    with pytest.raises(lib.AdannsError):
+        index.search_precision(torch.from_numpy(Q).cuda(), w.d_c, w.d_s, 2, 10, "bf16", 20)
+    index.free()
