@@ -217,6 +217,69 @@ adanns_status adanns_timing_enable(int32_t enable);
 adanns_status adanns_timing_reset(void);
 adanns_status adanns_timing_read(const char *kernel, int64_t *launches, double *total_ms);
 
+/*
+ * Batching form: many search configurations, each with its own index,
+ * (d_c, d_s, nprobe, k) and query batch, run as one set of persistent
+ * launches over a descriptor table (coarse tiles of every configuration in
+ * one launch, list-scan tiles of every configuration in one launch, one
+ * selection launch per step), optionally captured into a hipGraph.
+ * Results equal those of adanns_search on each configuration alone.
+ *
+ * Queries are one row-major array holding the configurations' queries one
+ * after another (config 0 first), row stride ldq >= every max(d_c, d_s);
+ * dist / ids are [total queries x ldk] with ldk >= every k; row r of a
+ * configuration with k < ldk fills its first k entries. probes (optional)
+ * is [sum of nq * nprobe] int32 in configuration order.
+ */
+typedef struct adanns_batch_config {
+  const adanns_index *index;
+  int64_t nq;
+  int32_t d_c, d_s, nprobe, k;
+} adanns_batch_config;
+
+typedef struct adanns_batch adanns_batch; /* opaque, library-owned */
+
+/* Validates the configurations, sizes and allocates the batch's scratch
+ * memory and uploads the descriptors. Synchronises ``stream``. The indices
+ * must outlive the batch. Uses the autotune cache if it knows the shape. */
+adanns_status adanns_batch_create(const adanns_batch_config *cfgs, int32_t ncfg, int64_t ldq,
+                                  int64_t ldk, void *stream, adanns_batch **out);
+
+/* Enqueues the batch on ``stream``: no allocation, no host synchronisation
+ * (capturable). */
+adanns_status adanns_batch_run(adanns_batch *batch, const float *Q, float *dist, int64_t *ids,
+                               int32_t *probes, void *stream);
+
+/* Like adanns_batch_run, through a hipGraph captured on first use (and
+ * again whenever Q, dist or ids change) and replayed afterwards. The graph
+ * runs on a private stream of the batch, ordered after the work already on
+ * ``stream`` and before work enqueued on it later (events), so ``stream`` may
+ * be the default stream. Kernel timing must be off. */
+adanns_status adanns_batch_run_graph(adanns_batch *batch, const float *Q, float *dist,
+                                     int64_t *ids, void *stream);
+
+/* Scan tile shape: query-tile height tq (32, 64, 128) and persistent grid. */
+adanns_status adanns_batch_set_shape(adanns_batch *batch, int32_t tq, int32_t grid);
+
+/* Autotuner: times every (tq, grid) candidate on this batch (one warm-up and
+ * ``reps`` timed runs each, HIP events), keeps the fastest for the batch and
+ * records it in the process-wide autotune cache under the batch's shape key
+ * (d_s, nprobe and queries per list, bucketed by powers of two), which
+ * adanns_search and adanns_batch_create consult. Writes dist / ids. */
+adanns_status adanns_batch_autotune(adanns_batch *batch, const float *Q, float *dist,
+                                    int64_t *ids, int32_t reps, int32_t *tq, int32_t *grid,
+                                    void *stream);
+
+/* Total queries, current shape and scratch bytes of a batch (NULL-able). */
+adanns_status adanns_batch_info(const adanns_batch *batch, int64_t *queries, int32_t *tq,
+                                int32_t *grid, size_t *scratch_bytes);
+
+/* Releases a batch (waits for the device; NULL is a no-op). */
+void adanns_batch_free(adanns_batch *batch);
+
+/* Forgets every autotuned shape. */
+adanns_status adanns_autotune_clear(void);
+
 /* Sizes of an index. Any out pointer may be NULL. */
 adanns_status adanns_index_info(const adanns_index *index, int64_t *n, int32_t *d,
                                 int32_t *nlist, int32_t *d_c_build);

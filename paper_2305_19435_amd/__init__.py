@@ -7,5 +7,6 @@ loudly when the shared library has not been built.
 from ._lib import (AdannsError, check, last_error, lib, timing_enable, timing_read,  # noqa: F401
                    timing_reset, version)
 from .index import IvfIndex  # noqa: F401
+from .batch import Batch, autotune_clear  # noqa: F401
 
-__all__ = ["IvfIndex", "AdannsError", "version", "last_error", "lib"]
+__all__ = ["IvfIndex", "Batch", "AdannsError", "version", "last_error", "lib"]

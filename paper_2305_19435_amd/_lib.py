@@ -38,6 +38,14 @@ _SIGS = {
     "adanns_index_quantized": (C.c_int, [vp, i32, vp, vp]),
     "adanns_search_precision": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, i32, i32, i32,
                                           vp, vp, vp, vp]),
+    "adanns_batch_create": (C.c_int, [vp, i32, i64, i64, vp, PIX]),
+    "adanns_batch_run": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+    "adanns_batch_run_graph": (C.c_int, [vp, vp, vp, vp, vp]),
+    "adanns_batch_set_shape": (C.c_int, [vp, i32, i32]),
+    "adanns_batch_autotune": (C.c_int, [vp, vp, vp, vp, i32, vp, vp, vp]),
+    "adanns_batch_info": (C.c_int, [vp, vp, vp, vp, vp]),
+    "adanns_batch_free": (None, [vp]),
+    "adanns_autotune_clear": (C.c_int, []),
     "adanns_timing_enable": (C.c_int, [i32]),
     "adanns_timing_reset": (C.c_int, []),
     "adanns_timing_read": (C.c_int, [C.c_char_p, vp, vp]),
@@ -53,6 +61,12 @@ for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
     _f.restype = _res
     _f.argtypes = _args
+
+
+class BatchConfig(C.Structure):
+    """adanns_batch_config."""
+    _fields_ = [("index", vp), ("nq", i64), ("d_c", i32), ("d_s", i32), ("nprobe", i32),
+                ("k", i32)]
 
 
 class AdannsError(RuntimeError):

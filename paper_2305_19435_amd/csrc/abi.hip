@@ -233,6 +233,12 @@ SearchBufs carve(char *base, const adanns_index *ix, int64_t nq, int32_t dq_pad,
                  bool coarse, size_t *total) {
   Carver c{base, 0, 0};
   SearchBufs b{};
+  b.cfg = c.take<CfgDev>(1);
+  b.ncfg = 1;
+  b.V = ix->nlist;
+  b.Qtot = nq;
+  b.pairs = nq * nprobe;
+  b.ct_total = (int32_t)(cdiv(nq, TILE_Q) * cdiv(ix->nlist, TILE_V));
   b.ldqs = dq_pad;
   b.Qs = c.take<float>((size_t)nq * dq_pad);
   b.S = coarse ? c.take<float>((size_t)nq * ix->nlist) : nullptr;
@@ -310,6 +316,9 @@ static adanns_status kmeans_gpu(const float *X, int64_t n, int64_t ldx, int32_t 
   tmp.ptrs.push_back(d_init);
   ADANNS_HIP(hipMalloc(&d_off, (size_t)(nlist + 1) * sizeof(int64_t)));
   tmp.ptrs.push_back(d_off);
+  CfgDev *d_cfg = nullptr;  // descriptor of the assignment searches
+  ADANNS_HIP(hipMalloc(&d_cfg, sizeof(CfgDev)));
+  tmp.ptrs.push_back(d_cfg);
   float *Xc = nullptr;  // staged chunk for the final assignment of all rows
   ADANNS_HIP(hipMalloc(&Xc, (size_t)std::min(n, chunk) * dcp * sizeof(float)));
   tmp.ptrs.push_back(Xc);
@@ -348,6 +357,7 @@ static adanns_status kmeans_gpu(const float *X, int64_t n, int64_t ldx, int32_t 
     for (int64_t a0 = 0; a0 < count; a0 += chunk) {
       const int64_t m = std::min(chunk, count - a0);
       SearchBufs b{};
+      b.cfg = d_cfg;
       b.Qs = const_cast<float *>(rows) + a0 * ldr;
       b.ldqs = ldr;
       b.S = S;
@@ -384,6 +394,7 @@ static adanns_status kmeans_gpu(const float *X, int64_t n, int64_t ldx, int32_t 
     const int64_t m = std::min(chunk, n - a0);
     ADANNS_HIP(launch_stage_rows(X + a0 * ldx, ldx, nullptr, nullptr, m, d_c, Xc, dcp, st));
     SearchBufs b{};
+    b.cfg = d_cfg;
     b.Qs = Xc;
     b.ldqs = dcp;
     b.S = S;
@@ -480,14 +491,13 @@ static adanns_status search_common(const adanns_index *cix, const float *Q, int6
   void *base = nullptr;
   if ((s = get_scratch(ix, st, total, &base))) return s;
   SearchBufs b = carve((char *)base, ix, nq, dq_pad, nprobe, coarse, &total);
-  ADANNS_HIP(launch_stage_queries(Q, nq, ldq, dq, b.Qs, b.ldqs, st));
-  if (coarse) {
-    ADANNS_HIP(launch_coarse(ix, b, nq, d_c, nprobe, probes_out, st));
-  } else {
+  ADANNS_HIP(launch_store_cfg(make_cfg(ix, coarse ? d_c : 1, d_s, nprobe, k, nq), b.cfg, st));
+  if (!coarse)
     ADANNS_HIP(hipMemcpyAsync(b.probes, given_probes, (size_t)nq * nprobe * sizeof(int32_t),
                               hipMemcpyDeviceToDevice, st));
-  }
-  ADANNS_HIP(launch_scan(ix, b, nq, d_s, nprobe, k, dist, ids, st));
+  int32_t tq = TILE_Q, grid = PERSIST_WG;
+  tuned_shape(ix, d_s, nprobe, nq, &tq, &grid);
+  ADANNS_HIP(launch_search_multi(b, Q, ldq, dist, ids, k, probes_out, tq, grid, st, coarse));
   return ADANNS_OK;
 }
 

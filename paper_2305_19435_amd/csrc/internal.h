@@ -137,8 +137,40 @@ struct KernelTimer {
   ~KernelTimer() { stop(); }
 };
 
+// ---- batched (multi-configuration) search -----------------------------------
+// Descriptor of one search configuration inside a batch; an ordinary search
+// is a batch of one. Lives in device memory; the kernels find the
+// configuration of a query, pair, list or tile by binary search over the
+// prefix fields.
+struct CfgDev {
+  const float *vec;        // the configuration's index
+  const int64_t *poff;
+  const int32_t *len;
+  const int64_t *rowid;
+  const float *cent;
+  const float *cent_slab;
+  int32_t d_pad, d_cb_pad, nlist, nl_pad;
+  int32_t d_c, d_s, nprobe, k;
+  int64_t q0, nq;          // its query rows [q0, q0 + nq) of the batch
+  int64_t S0;              // its coarse scores start at S + S0 (row stride nlist)
+  int64_t pair0;           // its (query, probe) pairs [pair0, pair0 + nq * nprobe)
+  int32_t vl0;             // its lists are virtual lists [vl0, vl0 + nlist)
+  int32_t ct0;             // its coarse tiles [ct0, ct0 + qtiles * vtiles)
+  int32_t qtiles;          // coarse query tiles
+  int32_t pad_;
+};
+
+CfgDev make_cfg(const adanns_index *ix, int32_t d_c, int32_t d_s, int32_t nprobe, int32_t k,
+                int64_t nq);
+
 // ---- launch wrappers (kernels.hip) -----------------------------------------
 struct SearchBufs {
+  CfgDev *cfg;        // device descriptors (one for an ordinary search)
+  int32_t ncfg;
+  int32_t V;          // virtual lists (sum of nlist over configurations)
+  int32_t ct_total;   // coarse tiles over configurations
+  int64_t Qtot;       // query rows over configurations
+  int64_t pairs;      // pairs over configurations
   float *Qs;          // [nq][dq_pad]
   int64_t ldqs;
   float *S;           // [nq][nlist] coarse first-pass scores
@@ -158,17 +190,27 @@ hipError_t launch_stage_queries(const float *Q, int64_t nq, int64_t ldq, int32_t
 hipError_t launch_layout(const float *src, int64_t ldsrc, int32_t dsrc, const int64_t *src_row,
                          const int32_t *row_list, const int64_t *poff, int64_t rows_pad,
                          int32_t d_pad, float *dst, hipStream_t st);
+hipError_t launch_store_cfg(const CfgDev &c, CfgDev *dst, hipStream_t st);
+// Scan tile shape from the autotune cache for this search shape (unchanged
+// if the shape has not been tuned).
+void tuned_shape(const adanns_index *ix, int32_t d_s, int32_t nprobe, int64_t nq, int32_t *tq,
+                 int32_t *grid);
+// Single-configuration helpers (the descriptor is written into b.cfg first).
 hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_c,
                          int32_t nprobe, int32_t *user_probes, hipStream_t st,
                          float *out_min_dist = nullptr);
+// Batched FP32 search over b.ncfg configurations (descriptors already in
+// b.cfg). tq = query-tile height of the scan (32, 64 or 128), grid = number
+// of persistent workgroups. Enqueue only: no allocation, no host sync.
+hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq, float *dist,
+                               int64_t *ids, int64_t ldk, int32_t *user_probes, int32_t tq,
+                               int32_t grid, hipStream_t st, bool do_coarse = true);
 hipError_t launch_stage_rows(const float *X, int64_t ldx, const int64_t *rows,
                              const int32_t *rows32, int64_t nrows, int32_t dcols, float *out,
                              int64_t ldo, hipStream_t st);
 hipError_t launch_centroid_update(const float *X, int64_t ldx, const int32_t *perm,
                                   const int64_t *off, int32_t nlist, int32_t dcols, float *C,
                                   int64_t ldc, hipStream_t st);
-hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_s,
-                       int32_t nprobe, int32_t k, float *dist, int64_t *ids, hipStream_t st);
 hipError_t launch_bucketing(const adanns_index *ix, const SearchBufs &b, int64_t nq,
                             int32_t nprobe, hipStream_t st);
 hipError_t launch_gather_codes(const uint8_t *codes, int32_t M, const int64_t *rowid,

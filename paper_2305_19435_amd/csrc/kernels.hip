@@ -171,191 +171,230 @@ __global__ void k_layout(const float *__restrict__ src, int64_t ldsrc, int32_t d
 }
 
 // ---- first-pass distance tiles ------------------------------------------------
+// Finds the configuration whose prefix field ``off`` (a member pointer)
+// covers value v: the largest c with cfg[c].*off <= v.
+template <class T>
+__device__ __forceinline__ int cfg_of(const CfgDev *cfg, int ncfg, T CfgDev::*off, int64_t v) {
+  int lo = 0, hi = ncfg - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if ((int64_t)(cfg[mid].*off) <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 struct TileArgs {
-  const float *Qs;
+  const CfgDev *cfg;
+  int32_t ncfg;
+  const float *Qs;         // staged queries of the whole batch
   int64_t ldqs;
-  int32_t d_dot;           // coordinates in the dot product (d_c or d_s)
-  const float *vec;        // slab layout base
-  int32_t d_pad;
-  const int64_t *poff;     // scan: [nlist + 1] padded row offsets
-  const int32_t *len;      // scan: [nlist] list lengths
-  int32_t nlist;
-  const int32_t *tile_off; // scan: [nlist + 1] tile prefix
-  const int32_t *bkt_off;  // scan: start of each list's bucket
-  const int32_t *cnt;      // scan: pairs per list
-  const int32_t *bucket;   // scan: pair ids grouped by list
-  int32_t pair_div;        // query of a pair = pair / pair_div
+  int32_t V;               // virtual lists
+  const int32_t *tile_off; // scan: [V + 1] tile prefix over virtual lists
+  const int32_t *bkt_off;  // scan: start of each virtual list's bucket
+  const int32_t *cnt;      // scan: pairs per virtual list
+  const int32_t *bucket;   // scan: global pair ids grouped by virtual list
   const int64_t *pair_base;// scan: output offset of each pair
-  float *out;
-  // coarse mode: one list (the centroids) against all queries
-  int32_t coarse;
-  int64_t nq;
-  int32_t nl, nl_pad, qtiles, total_host;
+  float *S;                // coarse output
+  float *D;                // scan output
+  int32_t ct_total;        // coarse: tiles over configurations
 };
 
-__global__ __launch_bounds__(256) void k_tile_dist(TileArgs a) {
-  __shared__ __attribute__((aligned(16))) float As[TILE_Q][SLAB + 4];
-  __shared__ __attribute__((aligned(16))) float Bs[TILE_V][SLAB + 4];
-  __shared__ int64_t rbase[TILE_Q];
-  __shared__ int32_t rq[TILE_Q];
-  __shared__ float cn[TILE_V];
-
+// One 64-vector tile of a list against TQ query rows:
+// out[rbase[row] + v] = |x_v[:d]|^2 - 2 q_row[:d] . x_v[:d] for valid rows/vectors.
+// rq[] holds the staged-query row of each tile row (-1 = none).
+template <int TQ>
+__device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64_t ldqs,
+                                             const float *vp, int64_t npad, int nvec_left,
+                                             int d_dot, const int32_t *rq, const int64_t *rbase,
+                                             float *__restrict__ out, float (*As)[SLAB + 4],
+                                             float (*Bs)[SLAB + 4], float *cn) {
+  constexpr int NA = TQ / 32;        // float4 of A per thread per slab
+  constexpr int NB = TQ / 32;        // MFMA row blocks per wave
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int total = a.coarse ? a.total_host : a.tile_off[a.nlist];
-  const int G = gridDim.x;
-  // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
-  // contiguous run of work items so tiles that share a vector tile (the
-  // query tiles of one list) meet in the same L2.
-  const int L = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-
-  const int lr = tid >> 3;        // load row 0..31 (and +32)
-  const int lc = (tid & 7) * 4;   // load column 0..28
-  const int rb = (wv >> 1) * 32;  // this wave's 32x32 output sub-tile
-  const int cb = (wv & 1) * 32;
+  const int rbw = (wv >> 1) * (TQ / 2), cbw = (wv & 1) * 32;
   const int fr = lane & 15, fk = (lane >> 4) * 8;
+  const int lr = tid >> 3, lc = (tid & 7) * 4;
+  const int nslab = (d_dot + SLAB - 1) / SLAB;
 
+  floatx4 acc[NB][2];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+  float nrm0 = 0.f, nrm1 = 0.f;
+  float4 ra[NA], rb0, rb1;
+  const float *qp[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int q = rq[lr + 32 * u];
+    qp[u] = q >= 0 ? Qs + (int64_t)q * ldqs : nullptr;
+  }
+
+  auto load = [&](int s) {
+    const int dim = s * SLAB + lc;
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      float4 v = qp[u] ? *(const float4 *)(qp[u] + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+      if (dim + 4 > d_dot) {
+        if (dim + 0 >= d_dot) v.x = 0.f;
+        if (dim + 1 >= d_dot) v.y = 0.f;
+        if (dim + 2 >= d_dot) v.z = 0.f;
+        if (dim + 3 >= d_dot) v.w = 0.f;
+      }
+      ra[u] = v;
+    }
+    const float *src = vp + (int64_t)s * npad * SLAB;
+    rb0 = *(const float4 *)(src + lr * SLAB + lc);
+    rb1 = *(const float4 *)(src + (lr + 32) * SLAB + lc);
+  };
+
+  load(0);
+  for (int s = 0; s < nslab; ++s) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NA; ++u) *(float4 *)&As[lr + 32 * u][lc] = ra[u];
+    *(float4 *)&Bs[lr][lc] = rb0;
+    *(float4 *)&Bs[lr + 32][lc] = rb1;
+    {  // vector norms over the same prefix, from the registers just stored
+      const int dim = s * SLAB + lc;
+      const float x[4] = {rb0.x, rb0.y, rb0.z, rb0.w};
+      const float y[4] = {rb1.x, rb1.y, rb1.z, rb1.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (dim + e < d_dot) {
+          nrm0 += x[e] * x[e];
+          nrm1 += y[e] * y[e];
+        }
+      }
+    }
+    __syncthreads();
+    if (s + 1 < nslab) load(s + 1);
+
+    float af[NB][8], bf[2][8];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const float4 x0 = *(const float4 *)&As[rbw + i * 16 + fr][fk];
+      const float4 x1 = *(const float4 *)&As[rbw + i * 16 + fr][fk + 4];
+      af[i][0] = x0.x; af[i][1] = x0.y; af[i][2] = x0.z; af[i][3] = x0.w;
+      af[i][4] = x1.x; af[i][5] = x1.y; af[i][6] = x1.z; af[i][7] = x1.w;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const float4 x0 = *(const float4 *)&Bs[cbw + j * 16 + fr][fk];
+      const float4 x1 = *(const float4 *)&Bs[cbw + j * 16 + fr][fk + 4];
+      bf[j][0] = x0.x; bf[j][1] = x0.y; bf[j][2] = x0.z; bf[j][3] = x0.w;
+      bf[j][4] = x1.x; bf[j][5] = x1.y; bf[j][6] = x1.z; bf[j][7] = x1.w;
+    }
+    // MFMA k-slot (lane >> 4) carries coordinate 8 * (lane >> 4) + kb for
+    // both operands, so every coordinate of the slab is used exactly once.
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kb], bf[j][kb], acc[i][j], 0, 0, 0);
+  }
+  nrm0 += __shfl_xor(nrm0, 1);
+  nrm0 += __shfl_xor(nrm0, 2);
+  nrm0 += __shfl_xor(nrm0, 4);
+  nrm1 += __shfl_xor(nrm1, 1);
+  nrm1 += __shfl_xor(nrm1, 2);
+  nrm1 += __shfl_xor(nrm1, 4);
+  if ((tid & 7) == 0) {
+    cn[lr] = nrm0;
+    cn[lr + 32] = nrm1;
+  }
+  __syncthreads();
+  // 16x16 f32 MFMA result: lane holds column (lane & 15), rows 4*(lane>>4)+e
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = rbw + i * 16 + (lane >> 4) * 4 + e;
+        const int col = cbw + j * 16 + (lane & 15);
+        if (rq[row] >= 0 && col < nvec_left) out[rbase[row] + col] = cn[col] - 2.0f * acc[i][j][e];
+      }
+}
+
+// Persistent tile kernel over a batch. COARSE: every configuration's queries
+// against its centroids (tiles numbered per configuration); otherwise every
+// virtual list against the queries probing it.
+template <int TQ, int COARSE>
+__global__ __launch_bounds__(256) void k_tile_multi(TileArgs a) {
+  __shared__ __attribute__((aligned(16))) float As[TQ][SLAB + 4];
+  __shared__ __attribute__((aligned(16))) float Bs[TILE_V][SLAB + 4];
+  __shared__ int64_t rbase[TQ];
+  __shared__ int32_t rq[TQ];
+  __shared__ float cn[TILE_V];
+  const int tid = threadIdx.x;
+  const int total = COARSE ? a.ct_total : a.tile_off[a.V];
+  const int G = gridDim.x;
+  // XCD-aware order: workgroup b runs on XCD b % 8; each XCD gets a
+  // contiguous run of work items, so the query tiles of one vector tile meet
+  // in the same L2.
+  const int L = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
   for (int w = L; w < total; w += G) {
-    int h, qt, vt, m, nvec;
+    int c, qt, vt, m, nvec, d_dot;
     int64_t npad;
     const float *vbase;
-    if (a.coarse) {
-      h = 0;
-      qt = w % a.qtiles;
-      vt = w / a.qtiles;
-      m = (int)a.nq;
-      nvec = a.nl;
-      npad = a.nl_pad;
-      vbase = a.vec;
+    int h = 0, v = 0;
+    if (COARSE) {
+      c = cfg_of(a.cfg, a.ncfg, &CfgDev::ct0, w);
+      const CfgDev &g = a.cfg[c];
+      const int local = w - g.ct0;
+      qt = local % g.qtiles;
+      vt = local / g.qtiles;
+      m = (int)g.nq;
+      nvec = g.nlist;
+      npad = g.nl_pad;
+      vbase = g.cent_slab;
+      d_dot = g.d_c;
     } else {
-      int lo = 0, hi = a.nlist - 1;
+      int lo = 0, hi = a.V - 1;
       while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
         if (a.tile_off[mid] <= w) lo = mid; else hi = mid - 1;
       }
-      h = lo;
-      m = a.cnt[h];
-      nvec = a.len[h];
-      int64_t p0 = a.poff[h];
-      npad = a.poff[h + 1] - p0;
-      int qts = (m + TILE_Q - 1) / TILE_Q;
-      int rem = w - a.tile_off[h];
+      v = lo;
+      c = cfg_of(a.cfg, a.ncfg, &CfgDev::vl0, v);
+      const CfgDev &g = a.cfg[c];
+      h = v - g.vl0;
+      m = a.cnt[v];
+      nvec = g.len[h];
+      const int64_t p0 = g.poff[h];
+      npad = g.poff[h + 1] - p0;
+      const int qts = (m + TQ - 1) / TQ;
+      const int rem = w - a.tile_off[v];
       qt = rem % qts;
       vt = rem / qts;
-      vbase = a.vec + p0 * a.d_pad;
+      vbase = g.vec + p0 * g.d_pad;
+      d_dot = g.d_s;
     }
     __syncthreads();  // previous item's epilogue is done with rq / rbase / cn
-    if (tid < TILE_Q) {
-      int i = qt * TILE_Q + tid;
+    if (tid < TQ) {
+      const CfgDev &g = a.cfg[c];
+      const int i = qt * TQ + tid;
       if (i < m) {
-        int32_t pair = a.coarse ? i : a.bucket[a.bkt_off[h] + i];
-        rq[tid] = pair / a.pair_div;
-        rbase[tid] = a.coarse ? (int64_t)i * a.nl : a.pair_base[pair];
+        if (COARSE) {
+          rq[tid] = (int32_t)(g.q0 + i);
+          rbase[tid] = g.S0 + (int64_t)i * g.nlist;
+        } else {
+          const int32_t pair = a.bucket[a.bkt_off[v] + i];
+          rq[tid] = (int32_t)(g.q0 + (pair - g.pair0) / g.nprobe);
+          rbase[tid] = a.pair_base[pair];
+        }
       } else {
         rq[tid] = -1;
         rbase[tid] = 0;
       }
     }
     __syncthreads();
-    const int qa = rq[lr], qb = rq[lr + 32];
-    const float *qpa = a.Qs + (int64_t)(qa < 0 ? 0 : qa) * a.ldqs;
-    const float *qpb = a.Qs + (int64_t)(qb < 0 ? 0 : qb) * a.ldqs;
-    const float *vp = vbase + (int64_t)vt * TILE_V * SLAB;
-    const int nslab = (a.d_dot + SLAB - 1) / SLAB;
-
-    floatx4 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
-    float nrm0 = 0.f, nrm1 = 0.f;
-    float4 ra0, ra1, rb0, rb1;
-
-    auto load = [&](int s) {
-      const int dim = s * SLAB + lc;
-      ra0 = qa >= 0 ? *(const float4 *)(qpa + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
-      ra1 = qb >= 0 ? *(const float4 *)(qpb + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
-      if (dim + 4 > a.d_dot) {
-        if (dim + 0 >= a.d_dot) { ra0.x = 0.f; ra1.x = 0.f; }
-        if (dim + 1 >= a.d_dot) { ra0.y = 0.f; ra1.y = 0.f; }
-        if (dim + 2 >= a.d_dot) { ra0.z = 0.f; ra1.z = 0.f; }
-        if (dim + 3 >= a.d_dot) { ra0.w = 0.f; ra1.w = 0.f; }
-      }
-      const float *src = vp + (int64_t)s * npad * SLAB;
-      rb0 = *(const float4 *)(src + lr * SLAB + lc);
-      rb1 = *(const float4 *)(src + (lr + 32) * SLAB + lc);
-    };
-
-    load(0);
-    for (int s = 0; s < nslab; ++s) {
-      __syncthreads();
-      *(float4 *)&As[lr][lc] = ra0;
-      *(float4 *)&As[lr + 32][lc] = ra1;
-      *(float4 *)&Bs[lr][lc] = rb0;
-      *(float4 *)&Bs[lr + 32][lc] = rb1;
-      {  // vector norms over the same prefix, from the registers just stored
-        const int dim = s * SLAB + lc;
-        float x[4] = {rb0.x, rb0.y, rb0.z, rb0.w};
-        float y[4] = {rb1.x, rb1.y, rb1.z, rb1.w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (dim + e < a.d_dot) {
-            nrm0 += x[e] * x[e];
-            nrm1 += y[e] * y[e];
-          }
-        }
-      }
-      __syncthreads();
-      if (s + 1 < nslab) load(s + 1);
-
-      float af[2][8], bf[2][8];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        float4 x0 = *(const float4 *)&As[rb + i * 16 + fr][fk];
-        float4 x1 = *(const float4 *)&As[rb + i * 16 + fr][fk + 4];
-        af[i][0] = x0.x; af[i][1] = x0.y; af[i][2] = x0.z; af[i][3] = x0.w;
-        af[i][4] = x1.x; af[i][5] = x1.y; af[i][6] = x1.z; af[i][7] = x1.w;
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        float4 x0 = *(const float4 *)&Bs[cb + j * 16 + fr][fk];
-        float4 x1 = *(const float4 *)&Bs[cb + j * 16 + fr][fk + 4];
-        bf[j][0] = x0.x; bf[j][1] = x0.y; bf[j][2] = x0.z; bf[j][3] = x0.w;
-        bf[j][4] = x1.x; bf[j][5] = x1.y; bf[j][6] = x1.z; bf[j][7] = x1.w;
-      }
-      // MFMA k-slot (lane >> 4) carries coordinate 8 * (lane >> 4) + kb for
-      // both operands, so every coordinate of the slab is used exactly once.
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kb], bf[j][kb], acc[i][j], 0, 0, 0);
-    }
-    // norms: 8 threads share a row
-    nrm0 += __shfl_xor(nrm0, 1);
-    nrm0 += __shfl_xor(nrm0, 2);
-    nrm0 += __shfl_xor(nrm0, 4);
-    nrm1 += __shfl_xor(nrm1, 1);
-    nrm1 += __shfl_xor(nrm1, 2);
-    nrm1 += __shfl_xor(nrm1, 4);
-    if ((tid & 7) == 0) {
-      cn[lr] = nrm0;
-      cn[lr + 32] = nrm1;
-    }
-    __syncthreads();
-    // 16x16 f32 MFMA result: lane holds column (lane & 15), rows 4*(lane>>4)+e
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int row = rb + i * 16 + (lane >> 4) * 4 + e;
-          const int col = cb + j * 16 + (lane & 15);
-          const int v = vt * TILE_V + col;
-          if (rq[row] >= 0 && v < nvec) a.out[rbase[row] + v] = cn[col] - 2.0f * acc[i][j][e];
-        }
+    tile_compute<TQ>(a.Qs, a.ldqs, vbase + (int64_t)vt * TILE_V * SLAB, npad,
+                     nvec - vt * TILE_V, d_dot, rq, rbase,
+                     (COARSE ? a.S : a.D) + (int64_t)vt * TILE_V, As, Bs, cn);
   }
 }
 
@@ -411,6 +450,7 @@ struct SelArgs {
   int64_t *out_ids;
   int32_t *out_probes;
   int32_t *out_probes2;
+  int64_t ldo;             // output row stride (0 = kout)
 };
 
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
@@ -489,7 +529,7 @@ __device__ __forceinline__ void bitonic_sort(float *chi, float *clo, int64_t *ci
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
+__device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
   __shared__ uint32_t hist[2048];
   __shared__ int64_t cpos[MAX_SHORTLIST];
   __shared__ float chi[MAX_SHORTLIST], clo[MAX_SHORTLIST];
@@ -500,8 +540,8 @@ __global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
   __shared__ int s_slot;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
-  const int64_t q = blockIdx.x;
   const bool coarse = a.mode == SEL_COARSE || a.mode == SEL_COARSE_QUANT;
+  const int64_t ldo = a.ldo ? a.ldo : a.kout;
   const float *seg;
   int64_t L, seg0 = 0;
   if (coarse) {
@@ -698,12 +738,77 @@ __global__ __launch_bounds__(256) void k_select_refine(SelArgs a) {
       const int32_t hsel = has ? (int32_t)cid[j] : -1;
       a.out_probes[q * a.kout + j] = hsel;
       if (a.out_probes2) a.out_probes2[q * a.kout + j] = hsel;
-      if (a.out_dist) a.out_dist[q * a.kout + j] = has ? chi[j] : __builtin_inff();
+      if (a.out_dist) a.out_dist[q * ldo + j] = has ? chi[j] : __builtin_inff();
     } else {
-      a.out_dist[q * a.kout + j] = has ? chi[j] : __builtin_inff();
-      a.out_ids[q * a.kout + j] = has ? cid[j] : -1;
+      a.out_dist[q * ldo + j] = has ? chi[j] : __builtin_inff();
+      a.out_ids[q * ldo + j] = has ? cid[j] : -1;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_select_refine(SelArgs a) { select_body(a, blockIdx.x); }
+
+// Batched FP32 selection: one block per query row of the batch; the
+// configuration's fields are patched into the arguments.
+struct SelMultiArgs {
+  const CfgDev *cfg;
+  int32_t ncfg;
+  int32_t coarse;
+  const float *Qs;
+  int64_t ldqs;
+  const float *S;
+  const float *D;
+  const int64_t *seg_off;
+  int32_t *probes;
+  int32_t *user_probes;
+  const int64_t *pair_base;
+  float *dist;             // scan: [Qtot][ldk]; coarse: optional min distance [Qtot]
+  int64_t *ids;
+  int64_t ldk;
+};
+
+__global__ __launch_bounds__(256) void k_select_multi(SelMultiArgs m) {
+  const int64_t r = blockIdx.x;
+  const int c = cfg_of(m.cfg, m.ncfg, &CfgDev::q0, r);
+  const CfgDev &g = m.cfg[c];
+  const int64_t q = r - g.q0;
+  SelArgs a{};
+  a.Qs = m.Qs + g.q0 * m.ldqs;
+  a.ldqs = m.ldqs;
+  if (m.coarse) {
+    a.mode = SEL_COARSE;
+    a.D = m.S + g.S0;
+    a.nl = g.nlist;
+    a.K1 = min(g.nlist, min(g.nprobe + REFINE_MARGIN, MAX_SHORTLIST));
+    a.K2 = g.nprobe;
+    a.kout = g.nprobe;
+    a.d_dot = g.d_c;
+    a.cent = g.cent;
+    a.ld_cent = g.d_cb_pad;
+    a.out_probes = m.probes + g.pair0;
+    a.out_probes2 = m.user_probes ? m.user_probes + g.pair0 : nullptr;
+    a.out_dist = m.dist ? m.dist + g.q0 : nullptr;
+    a.ldo = 1;
+  } else {
+    a.mode = SEL_L2;
+    a.D = m.D;
+    a.seg_off = m.seg_off + g.q0;
+    a.K1 = min(g.k + REFINE_MARGIN, MAX_SHORTLIST);
+    a.K2 = g.k;
+    a.kout = g.k;
+    a.ldo = m.ldk;
+    a.d_dot = g.d_s;
+    a.vec = g.vec;
+    a.d_pad = g.d_pad;
+    a.poff = g.poff;
+    a.rowid = g.rowid;
+    a.probes = m.probes + g.pair0;
+    a.nprobe = g.nprobe;
+    a.pair_base = m.pair_base + g.pair0;
+    a.out_dist = m.dist + g.q0 * m.ldk;
+    a.out_ids = m.ids + g.q0 * m.ldk;
+  }
+  select_body(a, q);
 }
 
 // ---- IVF-PQ ----------------------------------------------------------------------
@@ -1146,58 +1251,73 @@ __global__ __launch_bounds__(256) void k_tile_dist_q(TileQArgs a) {
   }
 }
 
-// ---- probe bucketing ---------------------------------------------------------
-__global__ void k_count(const int32_t *__restrict__ probes, int64_t npairs,
-                        int32_t *__restrict__ cnt) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < npairs) atomicAdd(&cnt[probes[i]], 1);
+// ---- probe bucketing (batched) -------------------------------------------------
+__global__ void k_store_cfg(CfgDev c, CfgDev *dst) { *dst = c; }
+
+// cnt[virtual list of each pair] += 1
+__global__ void k_count(const int32_t *__restrict__ probes, int64_t npairs, const CfgDev *cfg,
+                        int32_t ncfg, int32_t *__restrict__ cnt) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int c = cfg_of(cfg, ncfg, &CfgDev::pair0, p);
+  atomicAdd(&cnt[cfg[c].vl0 + probes[p]], 1);
 }
 
-// One workgroup of 1024 threads: bucket offsets, tile prefix, cursor reset.
+// One workgroup of 1024 threads: bucket offsets, tile prefix (query tiles of
+// height tq x 64-vector tiles per virtual list), cursor reset.
 __global__ __launch_bounds__(1024) void k_list_scan(const int32_t *__restrict__ cnt,
-                                                    const int32_t *__restrict__ len, int32_t nlist,
-                                                    int32_t *__restrict__ bkt_off,
+                                                    const CfgDev *cfg, int32_t ncfg, int32_t V,
+                                                    int32_t tq, int32_t *__restrict__ bkt_off,
                                                     int32_t *__restrict__ tile_off,
                                                     int32_t *__restrict__ cursor) {
   __shared__ int32_t sh[16];
   const int tid = threadIdx.x;
-  const int chunk = (nlist + blockDim.x - 1) / blockDim.x;
-  const int h0 = tid * chunk, h1 = min(nlist, h0 + chunk);
+  const int chunk = (V + blockDim.x - 1) / blockDim.x;
+  const int v0 = tid * chunk, v1 = min(V, v0 + chunk);
+  auto tiles = [&](int v) {
+    const int c = cfg_of(cfg, ncfg, &CfgDev::vl0, v);
+    const int32_t len = cfg[c].len[v - cfg[c].vl0];
+    return ((cnt[v] + tq - 1) / tq) * ((len + TILE_V - 1) / TILE_V);
+  };
   int32_t sc = 0, st = 0;
-  for (int h = h0; h < h1; ++h) {
-    sc += cnt[h];
-    st += ((cnt[h] + TILE_Q - 1) / TILE_Q) * ((len[h] + TILE_V - 1) / TILE_V);
+  for (int v = v0; v < v1; ++v) {
+    sc += cnt[v];
+    st += tiles(v);
   }
   int32_t tot_t;
   int32_t ec = block_excl_scan<int32_t>(sc, sh, nullptr);
   int32_t et = block_excl_scan<int32_t>(st, sh, &tot_t);
-  for (int h = h0; h < h1; ++h) {
-    bkt_off[h] = ec;
-    tile_off[h] = et;
-    cursor[h] = 0;
-    ec += cnt[h];
-    et += ((cnt[h] + TILE_Q - 1) / TILE_Q) * ((len[h] + TILE_V - 1) / TILE_V);
+  for (int v = v0; v < v1; ++v) {
+    bkt_off[v] = ec;
+    tile_off[v] = et;
+    cursor[v] = 0;
+    ec += cnt[v];
+    et += tiles(v);
   }
-  if (tid == 0) tile_off[nlist] = tot_t;
+  if (tid == 0) tile_off[V] = tot_t;
 }
 
-__global__ void k_scatter(const int32_t *__restrict__ probes, int64_t npairs,
-                          const int32_t *__restrict__ bkt_off, int32_t *__restrict__ cursor,
-                          int32_t *__restrict__ bucket) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npairs) return;
-  int32_t h = probes[i];
-  int32_t pos = bkt_off[h] + atomicAdd(&cursor[h], 1);
-  bucket[pos] = (int32_t)i;
+__global__ void k_scatter(const int32_t *__restrict__ probes, int64_t npairs, const CfgDev *cfg,
+                          int32_t ncfg, const int32_t *__restrict__ bkt_off,
+                          int32_t *__restrict__ cursor, int32_t *__restrict__ bucket) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  const int c = cfg_of(cfg, ncfg, &CfgDev::pair0, p);
+  const int32_t v = cfg[c].vl0 + probes[p];
+  bucket[bkt_off[v] + atomicAdd(&cursor[v], 1)] = (int32_t)p;
 }
 
-__global__ void k_seg_len(const int32_t *__restrict__ probes, int64_t nq, int32_t nprobe,
-                          const int32_t *__restrict__ len, int64_t *__restrict__ seg_len) {
-  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
+// Candidates of every query row of the batch (sum of its probed list lengths).
+__global__ void k_seg_len(const int32_t *__restrict__ probes, int64_t Qtot, const CfgDev *cfg,
+                          int32_t ncfg, int64_t *__restrict__ seg_len) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= Qtot) return;
+  const int c = cfg_of(cfg, ncfg, &CfgDev::q0, r);
+  const CfgDev &g = cfg[c];
+  const int32_t *pr = probes + g.pair0 + (r - g.q0) * g.nprobe;
   int64_t s = 0;
-  for (int j = 0; j < nprobe; ++j) s += len[probes[q * nprobe + j]];
-  seg_len[q] = s;
+  for (int j = 0; j < g.nprobe; ++j) s += g.len[pr[j]];
+  seg_len[r] = s;
 }
 
 // One workgroup: out[0..n] = exclusive prefix of in[0..n).
@@ -1220,15 +1340,18 @@ __global__ __launch_bounds__(1024) void k_scan_i64(const int64_t *__restrict__ i
   if (tid == 0) out[n] = tot;
 }
 
-__global__ void k_pair_base(const int32_t *__restrict__ probes, int64_t nq, int32_t nprobe,
-                            const int32_t *__restrict__ len, const int64_t *__restrict__ seg_off,
+__global__ void k_pair_base(const int32_t *__restrict__ probes, int64_t Qtot, const CfgDev *cfg,
+                            int32_t ncfg, const int64_t *__restrict__ seg_off,
                             int64_t *__restrict__ pair_base) {
-  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nq) return;
-  int64_t s = seg_off[q];
-  for (int j = 0; j < nprobe; ++j) {
-    pair_base[q * nprobe + j] = s;
-    s += len[probes[q * nprobe + j]];
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= Qtot) return;
+  const int c = cfg_of(cfg, ncfg, &CfgDev::q0, r);
+  const CfgDev &g = cfg[c];
+  const int64_t p0 = g.pair0 + (r - g.q0) * g.nprobe;
+  int64_t s = seg_off[r];
+  for (int j = 0; j < g.nprobe; ++j) {
+    pair_base[p0 + j] = s;
+    s += g.len[probes[p0 + j]];
   }
 }
 
@@ -1237,6 +1360,48 @@ inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t
 }  // namespace
 
 // ---- launch wrappers -------------------------------------------------------------
+__global__ void k_stage_multi(const float *__restrict__ Q, int64_t ldq, const CfgDev *cfg,
+                              int32_t ncfg, int64_t Qtot, float *__restrict__ Qs, int64_t ldqs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t r = i / ldqs, col = i % ldqs;
+  if (r >= Qtot) return;
+  const int c = cfg_of(cfg, ncfg, &CfgDev::q0, r);
+  const int32_t dq = max(cfg[c].d_c, cfg[c].d_s);
+  Qs[i] = col < dq ? Q[r * ldq + col] : 0.0f;
+}
+
+CfgDev make_cfg(const adanns_index *ix, int32_t d_c, int32_t d_s, int32_t nprobe, int32_t k,
+                int64_t nq) {
+  CfgDev c{};
+  c.vec = ix->vec;
+  c.poff = ix->poff;
+  c.len = ix->len;
+  c.rowid = ix->rowid;
+  c.cent = ix->cent;
+  c.cent_slab = ix->cent_slab;
+  c.d_pad = ix->d_pad;
+  c.d_cb_pad = ix->d_cb_pad;
+  c.nlist = ix->nlist;
+  c.nl_pad = ix->nl_pad;
+  c.d_c = d_c;
+  c.d_s = d_s;
+  c.nprobe = nprobe;
+  c.k = k;
+  c.q0 = 0;
+  c.nq = nq;
+  c.S0 = 0;
+  c.pair0 = 0;
+  c.vl0 = 0;
+  c.ct0 = 0;
+  c.qtiles = (int32_t)cdiv(nq, TILE_Q);
+  return c;
+}
+
+hipError_t launch_store_cfg(const CfgDev &c, CfgDev *dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_store_cfg, dim3(1), dim3(1), 0, st, c, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_stage_queries(const float *Q, int64_t nq, int64_t ldq, int32_t dq, float *Qs,
                                 int64_t ldqs, hipStream_t st) {
   int64_t n = nq * ldqs;
@@ -1275,128 +1440,141 @@ hipError_t launch_centroid_update(const float *X, int64_t ldx, const int32_t *pe
   return hipGetLastError();
 }
 
-hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_c,
-                         int32_t nprobe, int32_t *user_probes, hipStream_t st,
-                         float *out_min_dist) {
+// Coarse step of a batch whose descriptors are in b.cfg (b.Qs already staged).
+static hipError_t coarse_multi(const SearchBufs &b, int32_t *user_probes, float *out_min_dist,
+                               int32_t grid_cap, hipStream_t st) {
   TileArgs t{};
+  t.cfg = b.cfg;
+  t.ncfg = b.ncfg;
   t.Qs = b.Qs;
   t.ldqs = b.ldqs;
-  t.d_dot = d_c;
-  t.vec = ix->cent_slab;
-  t.d_pad = ix->d_cb_pad;
-  t.pair_div = 1;
-  t.out = b.S;
-  t.coarse = 1;
-  t.nq = nq;
-  t.nl = ix->nlist;
-  t.nl_pad = ix->nl_pad;
-  t.qtiles = (int32_t)cdiv(nq, TILE_Q);
-  t.total_host = t.qtiles * (int32_t)cdiv(ix->nlist, TILE_V);
-  int grid = (int)std::min<int64_t>(PERSIST_WG, round_up(t.total_host, 8));
+  t.S = b.S;
+  t.ct_total = b.ct_total;
+  const int grid = (int)std::min<int64_t>(grid_cap, round_up(b.ct_total, 8));
   {
     KernelTimer tm("tile_dist_coarse", st);
-    hipLaunchKernelGGL(k_tile_dist, dim3(grid), dim3(256), 0, st, t);
+    hipLaunchKernelGGL((k_tile_multi<TILE_Q, 1>), dim3(grid), dim3(256), 0, st, t);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-
-  SelArgs s{};
-  s.mode = SEL_COARSE;
-  s.D = b.S;
-  s.nl = ix->nlist;
-  s.K1 = std::min<int32_t>(ix->nlist, std::min<int32_t>(nprobe + REFINE_MARGIN, MAX_SHORTLIST));
-  s.K2 = nprobe;
-  s.kout = nprobe;
-  s.Qs = b.Qs;
-  s.ldqs = b.ldqs;
-  s.d_dot = d_c;
-  s.cent = ix->cent;
-  s.ld_cent = ix->d_cb_pad;
-  s.out_probes = b.probes;
-  s.out_probes2 = user_probes;
-  s.out_dist = out_min_dist;
+  SelMultiArgs m{};
+  m.cfg = b.cfg;
+  m.ncfg = b.ncfg;
+  m.coarse = 1;
+  m.Qs = b.Qs;
+  m.ldqs = b.ldqs;
+  m.S = b.S;
+  m.probes = b.probes;
+  m.user_probes = user_probes;
+  m.dist = out_min_dist;
   {
     KernelTimer tm("select_coarse", st);
-    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+    hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(256), 0, st, m);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_bucketing(const adanns_index *ix, const SearchBufs &b, int64_t nq,
-                            int32_t nprobe, hipStream_t st) {
-  const int64_t npairs = nq * nprobe;
-  const int32_t nlist = ix->nlist;
+static hipError_t bucketing_multi(const SearchBufs &b, int32_t tq, hipStream_t st) {
   KernelTimer tmb("bucketing", st);
-  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(nlist, 256)), dim3(256), 0, st, b.cnt,
-                     (int64_t)nlist, 0);
-  hipLaunchKernelGGL(k_count, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, b.probes, npairs,
-                     b.cnt);
-  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, st, b.cnt, ix->len, nlist, b.bkt_off,
-                     b.tile_off, b.cursor);
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(npairs, 256)), dim3(256), 0, st, b.probes, npairs,
-                     b.bkt_off, b.cursor, b.bucket);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(b.V, 256)), dim3(256), 0, st, b.cnt,
+                     (int64_t)b.V, 0);
+  hipLaunchKernelGGL(k_count, dim3(blocks_for(b.pairs, 256)), dim3(256), 0, st, b.probes, b.pairs,
+                     b.cfg, b.ncfg, b.cnt);
+  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, st, b.cnt, b.cfg, b.ncfg, b.V, tq,
+                     b.bkt_off, b.tile_off, b.cursor);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(b.pairs, 256)), dim3(256), 0, st, b.probes,
+                     b.pairs, b.cfg, b.ncfg, b.bkt_off, b.cursor, b.bucket);
   // per-query segment lengths go to pair_base as a temporary, then the scan
-  hipLaunchKernelGGL(k_seg_len, dim3(blocks_for(nq, 256)), dim3(256), 0, st, b.probes, nq, nprobe,
-                     ix->len, b.pair_base);
-  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, b.pair_base, nq, b.seg_off);
-  hipLaunchKernelGGL(k_pair_base, dim3(blocks_for(nq, 256)), dim3(256), 0, st, b.probes, nq,
-                     nprobe, ix->len, b.seg_off, b.pair_base);
+  hipLaunchKernelGGL(k_seg_len, dim3(blocks_for(b.Qtot, 256)), dim3(256), 0, st, b.probes, b.Qtot,
+                     b.cfg, b.ncfg, b.pair_base);
+  hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, b.pair_base, b.Qtot, b.seg_off);
+  hipLaunchKernelGGL(k_pair_base, dim3(blocks_for(b.Qtot, 256)), dim3(256), 0, st, b.probes,
+                     b.Qtot, b.cfg, b.ncfg, b.seg_off, b.pair_base);
   tmb.stop();
   return hipGetLastError();
 }
 
-hipError_t launch_scan(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_s,
-                       int32_t nprobe, int32_t k, float *dist, int64_t *ids, hipStream_t st) {
-  const int32_t nlist = ix->nlist;
-  hipError_t e = launch_bucketing(ix, b, nq, nprobe, st);
+hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_c,
+                         int32_t nprobe, int32_t *user_probes, hipStream_t st,
+                         float *out_min_dist) {
+  const CfgDev c = make_cfg(ix, d_c, 0, nprobe, 0, nq);
+  hipError_t e = launch_store_cfg(c, b.cfg, st);
   if (e != hipSuccess) return e;
+  SearchBufs bb = b;
+  bb.ncfg = 1;
+  bb.Qtot = nq;
+  bb.ct_total = c.qtiles * (int32_t)cdiv(ix->nlist, TILE_V);
+  return coarse_multi(bb, user_probes, out_min_dist, PERSIST_WG, st);
+}
 
+hipError_t launch_bucketing(const adanns_index *ix, const SearchBufs &b, int64_t nq,
+                            int32_t nprobe, hipStream_t st) {
+  SearchBufs bb = b;
+  bb.ncfg = 1;
+  bb.V = ix->nlist;
+  bb.Qtot = nq;
+  bb.pairs = nq * nprobe;
+  return bucketing_multi(bb, TILE_Q, st);
+}
+
+template <int TQ>
+static void launch_scan_tiles(const TileArgs &t, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_tile_multi<TQ, 0>), dim3(grid), dim3(256), 0, st, t);
+}
+
+hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq, float *dist,
+                               int64_t *ids, int64_t ldk, int32_t *user_probes, int32_t tq,
+                               int32_t grid, hipStream_t st, bool do_coarse) {
+  {
+    const int64_t n = b.Qtot * b.ldqs;
+    KernelTimer tm("stage_queries", st);
+    hipLaunchKernelGGL(k_stage_multi, dim3(blocks_for(n, 256)), dim3(256), 0, st, Q, ldq, b.cfg,
+                       b.ncfg, b.Qtot, b.Qs, b.ldqs);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (do_coarse && (e = coarse_multi(b, user_probes, nullptr, PERSIST_WG, st)) != hipSuccess)
+    return e;
+  if ((e = bucketing_multi(b, tq, st)) != hipSuccess) return e;
   TileArgs t{};
+  t.cfg = b.cfg;
+  t.ncfg = b.ncfg;
   t.Qs = b.Qs;
   t.ldqs = b.ldqs;
-  t.d_dot = d_s;
-  t.vec = ix->vec;
-  t.d_pad = ix->d_pad;
-  t.poff = ix->poff;
-  t.len = ix->len;
-  t.nlist = nlist;
+  t.V = b.V;
   t.tile_off = b.tile_off;
   t.bkt_off = b.bkt_off;
   t.cnt = b.cnt;
   t.bucket = b.bucket;
-  t.pair_div = nprobe;
   t.pair_base = b.pair_base;
-  t.out = b.D;
-  t.coarse = 0;
+  t.D = b.D;
+  grid = (int)round_up(std::max(8, grid), 8);
   {
     KernelTimer tm("tile_dist_scan", st);
-    hipLaunchKernelGGL(k_tile_dist, dim3(PERSIST_WG), dim3(256), 0, st, t);
+    if (tq == 32)
+      launch_scan_tiles<32>(t, grid, st);
+    else if (tq == 128)
+      launch_scan_tiles<128>(t, grid, st);
+    else
+      launch_scan_tiles<64>(t, grid, st);
   }
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-
-  SelArgs s{};
-  s.mode = SEL_L2;
-  s.D = b.D;
-  s.seg_off = b.seg_off;
-  s.K1 = std::min<int32_t>(k + REFINE_MARGIN, MAX_SHORTLIST);
-  s.K2 = k;
-  s.kout = k;
-  s.Qs = b.Qs;
-  s.ldqs = b.ldqs;
-  s.d_dot = d_s;
-  s.vec = ix->vec;
-  s.d_pad = ix->d_pad;
-  s.poff = ix->poff;
-  s.rowid = ix->rowid;
-  s.probes = b.probes;
-  s.nprobe = nprobe;
-  s.pair_base = b.pair_base;
-  s.out_dist = dist;
-  s.out_ids = ids;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  SelMultiArgs m{};
+  m.cfg = b.cfg;
+  m.ncfg = b.ncfg;
+  m.coarse = 0;
+  m.Qs = b.Qs;
+  m.ldqs = b.ldqs;
+  m.D = b.D;
+  m.seg_off = b.seg_off;
+  m.probes = b.probes;
+  m.pair_base = b.pair_base;
+  m.dist = dist;
+  m.ids = ids;
+  m.ldk = ldk;
   {
     KernelTimer tm("select_scan", st);
-    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+    hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(256), 0, st, m);
   }
   return hipGetLastError();
 }
@@ -1442,6 +1620,8 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
                                    int32_t rerank_k, int32_t coarse_margin, float *dist,
                                    int64_t *ids, int32_t *user_probes, hipStream_t st) {
   const QuantStore &qs = ix->quant[fmt];
+  hipError_t e0 = launch_store_cfg(make_cfg(ix, d_c, d_s, nprobe, k, nq), b.cfg, st);
+  if (e0 != hipSuccess) return e0;
   // coarse first pass on the quantised centroids
   TileQArgs t{};
   t.Qq = (const uint8_t *)Qq;

@@ -1,0 +1,140 @@
+"""Batching form: one batched (and graph-captured) launch over many search
+configurations equals each configuration searched alone, bit for bit, for
+every tile shape; and matches the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from parity_util import check_search, oracle_index
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_19435_amd as p
+    return p
+
+
+@pytest.fixture(scope="module")
+def setup(lib):
+    m = synth.Mixture(128, 200, seed=31)
+    X = m.database(40_000)
+    indices = {}
+    for d_c in (16, 32, 64):
+        C32, a, off, ids = oracle_index(X, 64, d_c, 5, 31 + d_c)
+        indices[d_c] = (lib.IvfIndex.import_ivf(X, C32, a), C32, off, ids)
+    rng = np.random.default_rng(5)
+    configs = []
+    for _ in range(12):
+        d_c = int(rng.choice([16, 32, 64]))
+        d_s = int(rng.choice([32, 64, 128]))
+        nprobe = int(rng.choice([2, 4, 8]))
+        nq = int(np.round(np.exp(rng.uniform(0, np.log(300)))))
+        configs.append((d_c, d_s, nprobe, nq))
+    Qall = m.queries(sum(c[3] for c in configs))
+    yield X, indices, configs, Qall
+    for ix, *_ in indices.values():
+        ix.free()
+
+
+def _alone(indices, configs, Qall, k):
+    out = []
+    r = 0
+    for d_c, d_s, nprobe, nq in configs:
+        ix = indices[d_c][0]
+        d, i = ix.search(torch.from_numpy(Qall[r:r + nq]).cuda(), d_c, d_s, nprobe, k)
+        torch.cuda.synchronize()
+        out.append((d.cpu().numpy(), i.cpu().numpy()))
+        r += nq
+    return out
+
+
+def _split(dist, ids, configs, k):
+    res, r = [], 0
+    for c in configs:
+        res.append((dist[r:r + c[3], :k], ids[r:r + c[3], :k]))
+        r += c[3]
+    return res
+
+
+def test_batch_equals_alone_all_shapes(lib, setup):
+    X, indices, configs, Qall = setup
+    k = 10
+    alone = _alone(indices, configs, Qall, k)
+    batch = lib.Batch([(indices[c[0]][0], c[3], c[0], c[1], c[2], k) for c in configs], ldq=128)
+    Qd = torch.from_numpy(Qall).cuda()
+    for tq in (32, 64, 128):
+        for grid in (8, 1024):
+            batch.set_shape(tq, grid)
+            dist, ids = batch.run(Qd)
+            torch.cuda.synchronize()
+            got = _split(dist.cpu().numpy(), ids.cpu().numpy(), configs, k)
+            for (gd, gi), (ad, ai) in zip(got, alone):
+                assert np.array_equal(gi, ai) and np.array_equal(gd, ad), (tq, grid)
+    batch.free()
+
+
+def test_graph_replays_equal_eager(lib, setup):
+    X, indices, configs, Qall = setup
+    k = 10
+    batch = lib.Batch([(indices[c[0]][0], c[3], c[0], c[1], c[2], k) for c in configs], ldq=128)
+    Qd = torch.from_numpy(Qall).cuda()
+    ed, ei = batch.run(Qd)
+    torch.cuda.synchronize()
+    ed, ei = ed.cpu().numpy(), ei.cpu().numpy()
+    out = batch.outputs()
+    for rep in range(3):
+        out[0].fill_(-1.0)
+        out[1].fill_(-7)
+        batch.run(Qd, out=out, graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(out[1].cpu().numpy(), ei), rep
+        assert np.array_equal(out[0].cpu().numpy(), ed), rep
+        # eager work of the program's own between replays
+        batch.run(Qd)
+        torch.cuda.synchronize()
+    batch.free()
+
+
+def test_autotune_keeps_results_and_parity(lib, setup):
+    X, indices, configs, Qall = setup
+    k = 10
+    alone = _alone(indices, configs, Qall, k)
+    batch = lib.Batch([(indices[c[0]][0], c[3], c[0], c[1], c[2], k) for c in configs], ldq=128)
+    Qd = torch.from_numpy(Qall).cuda()
+    tq, grid = batch.autotune(Qd, reps=1)
+    assert tq in (32, 64, 128) and grid in (1024, 2048, 4096)
+    dist, ids = batch.run(Qd)
+    torch.cuda.synchronize()
+    got = _split(dist.cpu().numpy(), ids.cpu().numpy(), configs, k)
+    for (gd, gi), (ad, ai) in zip(got, alone):
+        assert np.array_equal(gi, ai) and np.array_equal(gd, ad)
+    # oracle parity of two configurations
+    r = 0
+    for ci, (d_c, d_s, nprobe, nq) in enumerate(configs[:4]):
+        _, C32, off, ids_ = indices[d_c]
+        Qc = Qall[r:r + nq]
+        gd, gi = got[ci]
+        ix = indices[d_c][0]
+        _, _, probes = ix.search(torch.from_numpy(Qc).cuda(), d_c, d_s, nprobe, k,
+                                 return_probes=True)
+        torch.cuda.synchronize()
+        rep = check_search(X, Qc, C32, off, ids_, d_c, d_s, nprobe, k, gd, gi,
+                           got_p=probes.cpu().numpy())
+        assert rep.ok, rep.problems
+        r += nq
+    batch.free()
+    lib.autotune_clear()
+
+
+def test_batch_invalid(lib, setup):
+    X, indices, configs, Qall = setup
+    ix = indices[16][0]
+    with pytest.raises(lib.AdannsError):
+        lib.Batch([(ix, 5, 17, 64, 4, 10)], ldq=128)       # d_c above d_c_build
+    with pytest.raises(lib.AdannsError):
+        lib.Batch([(ix, 5, 16, 64, 4, 10)], ldq=32)        # ldq too small
