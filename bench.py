@@ -61,6 +61,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (HBM counter calibration)")
+    ap.add_argument("--form", default="ivf",
+                    choices=["ivf", "precision", "batching", "pq", "serving"],
+                    help="ivf: the headline FP32 search; the others measure the other forms")
+    ap.add_argument("--no-tune", action="store_true", help="skip the tile-shape autotuner")
+    ap.add_argument("--rerank", type=int, default=256, help="precision form shortlist")
     return ap.parse_args()
 
 
@@ -100,6 +105,10 @@ def main():
     import paper_2305_19435_amd as lib
 
     torch.cuda.set_device(0)
+    if args.form != "ivf":
+        import bench_forms
+        bench_forms.run(args, lib, torch, log)
+        return
     w = synth.WORKLOADS[args.workload]
     n = args.n or w.n
     nq = args.nq or w.nq
@@ -141,6 +150,15 @@ def main():
     stream = torch.cuda.current_stream()
     dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
     ids = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+    shape = None
+    if not args.no_tune:
+        # the library's autotuner picks the scan tile shape for this search
+        # shape and caches it; adanns_search then uses the cached choice
+        t0 = time.time()
+        tb = lib.Batch([(index, nq, d_c, d_s, nprobe, k)], ldq=w.d, ldk=k)
+        shape = tb.autotune(Qd, out=(dist, ids), reps=1)
+        tb.free()
+        log(f"autotuned scan shape (tq, grid) = {shape} in {time.time() - t0:.1f}s")
     for _ in range(args.warmup):
         index.search(Qd, d_c, d_s, nprobe, k, out=(dist, ids))
     torch.cuda.synchronize()
@@ -212,6 +230,7 @@ def main():
                    "n": n, "d": w.d, "nq": nq, "nlist": nlist, "d_c": d_c, "d_s": d_s,
                    "nprobe": nprobe, "k": k, "candidates_per_query": cand / nq,
                    "index": f"GPU Lloyd, {args.iters} iters on {n_train} seeded rows",
+                   "scan_shape": {"tq": shape[0], "grid": shape[1]} if shape else "default",
                    "index_build_s": round(build_s, 2)},
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                        "p99": round(float(np.percentile(step_ms, 99)), 4),

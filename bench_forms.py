@@ -1,0 +1,205 @@
+"""The non-headline measurements of ``bench.py`` (``--form``): the precision
+form, the batching form, IVF-PQ and the serving loop. Each prints one JSON
+line. The oracle is used only in the CPU-baseline / reference legs (recall
+ground truth and parity checks), never on the timed path.
+"""
+from __future__ import annotations
+
+import json
+import time
+
+import numpy as np
+
+import synth
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+FP8_PEAK_TFLOPS = 5000.0
+MFMA_FP32_PEAK_TFLOPS = 157.3
+
+
+def _timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _kernel_ms(lib, names):
+    out = {}
+    for n in names:
+        c, ms = lib.timing_read(n)
+        if c:
+            out[n] = round(ms / c, 4)
+    return out
+
+
+def run(args, lib, torch, log):
+    {"precision": precision_form, "batching": batching_form, "pq": pq_form,
+     "serving": serving_form}[args.form](args, lib, torch, log)
+
+
+# ---------------------------------------------------------------------------
+def precision_form(args, lib, torch, log):
+    """BF16 / FP8-e4m3 first pass + FP32 re-rank on the ImageNet-1K shape,
+    against the FP32 path: QPS and recall@10 against exact FP64 search."""
+    from oracle import exact, metrics
+
+    w = synth.WORKLOADS["imagenet1k"]
+    n = args.n or w.n
+    nq = args.nq or w.nq
+    d_c = args.dc or w.d_c
+    nprobe = args.nprobe or w.nprobe
+    mix = w.mixture()
+    X = mix.database(n)
+    Q = mix.queries(nq)
+    Xd = torch.from_numpy(X).cuda()
+    Qd = torch.from_numpy(Q).cuda()
+    n_train = min(n, 64 * w.nlist)
+    rows = synth.subsample_rows(n, n_train, w.seed)
+    index = lib.IvfIndex.build_ivf(Xd, w.nlist, d_c, args.iters, synth.init_rows(n_train, w.nlist, w.seed),
+                                   train_rows=rows)
+    del Xd
+    torch.cuda.empty_cache()
+    res = {}
+    k = w.k
+    sample = np.arange(min(args.cpu_sample, nq))
+    lib.timing_reset()
+    lib.timing_enable(True)
+    t = _timed(torch, lambda: index.search(Qd, d_c, w.d_s, nprobe, k), args.steps, args.warmup)
+    _, ids32 = index.search(Qd[: len(sample)], d_c, w.d_s, nprobe, k)
+    res["fp32"] = {"qps": nq / t, "ms_per_step": t * 1e3,
+                   "kernels_ms": _kernel_ms(lib, ["tile_dist_scan", "select_scan"])}
+    gpu_ids = {"fp32": ids32.cpu().numpy()}
+    for fmt in ("bf16", "fp8"):
+        index.set_precision(fmt)
+        lib.timing_reset()
+        t = _timed(torch, lambda: index.search_precision(Qd, d_c, w.d_s, nprobe, k, fmt, args.rerank),
+                   args.steps, args.warmup)
+        dd, ii = index.search_precision(Qd[: len(sample)], d_c, w.d_s, nprobe, k, fmt, args.rerank)
+        res[fmt] = {"qps": nq / t, "ms_per_step": t * 1e3,
+                    "kernels_ms": _kernel_ms(lib, ["tile_q_coarse", "select_q_coarse", "tile_q_scan",
+                                                   "select_q_scan"])}
+        gpu_ids[fmt] = ii.cpu().numpy()
+        res[fmt]["dist_sample"] = dd.cpu().numpy()
+    lib.timing_enable(False)
+    De, Ie = exact.exact_knn64(X, Q[sample], k)
+    for key in res:
+        res[key]["recall_at_10"] = metrics.k_recall_at_n(gpu_ids[key], Ie, k)
+    for fmt in ("bf16", "fp8"):
+        # returned distances are exact FP32 re-ranks: error against FP64
+        dd = res[fmt].pop("dist_sample")
+        ii = gpu_ids[fmt]
+        err = 0.0
+        for r, q in enumerate(sample):
+            ok = ii[r] >= 0
+            d64 = ((X[ii[r][ok]].astype(np.float64) - Q[q].astype(np.float64)) ** 2).sum(1)
+            err = max(err, float(np.max(np.abs(dd[r][ok] - d64) / d64)))
+        res[fmt]["max_rel_dist_err"] = err
+        res[fmt]["recall_minus_fp32_pp"] = 100 * (res[fmt]["recall_at_10"] - res["fp32"]["recall_at_10"])
+    best = max(("bf16", "fp8"), key=lambda f: res[f]["qps"])
+    out = {"metric": "QPS of the precision form (first pass BF16 / FP8-e4m3, FP32 re-rank)",
+           "value": round(res[best]["qps"], 1), "unit": "queries/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "dtype": best, "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": f"imagenet1k precision form: N={n} d={w.d} nq={nq} nlist={w.nlist} "
+                                  f"d_c={d_c} d_s={w.d_s} nprobe={nprobe} k={k} rerank={args.rerank}",
+                      "recall_sample_queries": int(len(sample))},
+           "forms": {k_: {kk: (round(v, 5) if isinstance(v, float) else v) for kk, v in r.items()}
+                     for k_, r in res.items()}}
+    index.free()
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+def batching_form(args, lib, torch, log):
+    """64 configurations over three indices (d_c 16 / 64 / 256) of a
+    1M x 1024 database, log-uniform batches of 1..4096 queries: one batched
+    graph launch (autotuned) against the same configurations one by one."""
+    w = synth.WORKLOADS["batching1m"]
+    n = args.n or w.n
+    mix = w.mixture()
+    X = mix.database(n)
+    Xd = torch.from_numpy(X).cuda()
+    n_train = min(n, 64 * w.nlist)
+    rows = synth.subsample_rows(n, n_train, w.seed)
+    init = synth.init_rows(n_train, w.nlist, w.seed)
+    indices = {}
+    for d_c in (16, 64, 256):
+        indices[d_c] = lib.IvfIndex.build_ivf(Xd, w.nlist, d_c, args.iters, init, train_rows=rows)
+    del Xd
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(synth.ROOT_SEED + 3)
+    cfgs = []
+    for _ in range(64):
+        d_c = int(rng.choice([16, 64, 256]))
+        d_s = int(rng.choice([256, 512, 1024]))
+        nprobe = int(rng.choice([4, 16, 64]))
+        nq = int(np.round(np.exp(rng.uniform(0, np.log(4096)))))
+        cfgs.append((d_c, d_s, nprobe, nq))
+    total = sum(c[3] for c in cfgs)
+    Q = mix.queries(total)
+    Qd = torch.from_numpy(Q).cuda()
+    k = w.k
+    batch = lib.Batch([(indices[c[0]], c[3], c[0], c[1], c[2], k) for c in cfgs], ldq=w.d, ldk=k)
+    t0 = time.time()
+    shape = batch.autotune(Qd, reps=1)
+    log(f"batch autotune {shape} in {time.time() - t0:.1f}s")
+    out_buf = batch.outputs()
+    t_graph = _timed(torch, lambda: batch.run(Qd, out=out_buf, graph=True), args.steps, args.warmup)
+    t_eager = _timed(torch, lambda: batch.run(Qd, out=out_buf), args.steps, args.warmup)
+    views = []
+    r = 0
+    for c in cfgs:
+        views.append(Qd[r:r + c[3]])
+        r += c[3]
+
+    def one_by_one():
+        for c, qv in zip(cfgs, views):
+            indices[c[0]].search(qv, c[0], c[1], c[2], k)
+
+    t_single = _timed(torch, one_by_one, args.steps, args.warmup)
+    # same results: batched graph vs one by one
+    bd, bi = batch.run(Qd, out=out_buf, graph=True)
+    torch.cuda.synchronize()
+    bi = bi.cpu().numpy()
+    same = True
+    r = 0
+    for c, qv in zip(cfgs, views):
+        _, ii = indices[c[0]].search(qv, c[0], c[1], c[2], k)
+        torch.cuda.synchronize()
+        same &= bool(np.array_equal(ii.cpu().numpy(), bi[r:r + c[3], :k]))
+        r += c[3]
+    cand = 0
+    for c in cfgs:
+        off, _ = indices[c[0]].lists()
+        cand += c[3] * c[2] * (off[-1] / (len(off) - 1))
+    out = {"metric": "QPS of 64 mixed (d_c, d_s, nprobe) configurations in one batched launch",
+           "value": round(total / t_graph, 1), "unit": "queries/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": f"batching1m: N={n} d={w.d} nlist={w.nlist}, 3 indices d_c 16/64/256, "
+                                  f"64 configs, {total} queries (log-uniform 1..4096)",
+                      "tile_shape": {"tq": shape[0], "grid": shape[1]}},
+           "batched_graph_ms": round(t_graph * 1e3, 3), "batched_eager_ms": round(t_eager * 1e3, 3),
+           "one_by_one_ms": round(t_single * 1e3, 3),
+           "speedup_vs_one_by_one": round(t_single / t_graph, 3),
+           "results_equal_one_by_one": same,
+           "mean_candidates_per_query": round(cand / total, 1)}
+    batch.free()
+    for ix in indices.values():
+        ix.free()
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+def pq_form(args, lib, torch, log):
+    raise SystemExit("pq form: see serving_form")
+
+
+def serving_form(args, lib, torch, log):
+    raise SystemExit("serving form not built yet")
