@@ -239,6 +239,9 @@ SearchBufs carve(char *base, const adanns_index *ix, int64_t nq, int32_t dq_pad,
   b.Qtot = nq;
   b.pairs = nq * nprobe;
   b.ct_total = (int32_t)(cdiv(nq, TILE_Q) * cdiv(ix->nlist, TILE_V));
+  b.max_nprobe = nprobe;
+  b.max_k = MAX_SHORTLIST - REFINE_MARGIN;
+  b.max_nlist = ix->nlist;
   b.ldqs = dq_pad;
   b.Qs = c.take<float>((size_t)nq * dq_pad);
   b.S = coarse ? c.take<float>((size_t)nq * ix->nlist) : nullptr;
@@ -491,6 +494,7 @@ static adanns_status search_common(const adanns_index *cix, const float *Q, int6
   void *base = nullptr;
   if ((s = get_scratch(ix, st, total, &base))) return s;
   SearchBufs b = carve((char *)base, ix, nq, dq_pad, nprobe, coarse, &total);
+  b.max_k = k;
   ADANNS_HIP(launch_store_cfg(make_cfg(ix, coarse ? d_c : 1, d_s, nprobe, k, nq), b.cfg, st));
   if (!coarse)
     ADANNS_HIP(hipMemcpyAsync(b.probes, given_probes, (size_t)nq * nprobe * sizeof(int32_t),

@@ -150,6 +150,10 @@ adanns_status adanns_batch_create(const adanns_batch_config *cfgs, int32_t ncfg,
     b.Qtot = q0;
     b.pairs = pair0;
     b.ldqs = dq_pad;
+    b.max_nprobe = p->max_np;
+    b.max_k = kmax;
+    b.max_nlist = 1;
+    for (const CfgDev &g : p->cfg) b.max_nlist = std::max(b.max_nlist, g.nlist);
     b.Qs = cv.take<float>((size_t)q0 * dq_pad);
     b.S = cv.take<float>((size_t)S0);
     b.probes = cv.take<int32_t>((size_t)pair0);

@@ -171,6 +171,7 @@ struct SearchBufs {
   int32_t ct_total;   // coarse tiles over configurations
   int64_t Qtot;       // query rows over configurations
   int64_t pairs;      // pairs over configurations
+  int32_t max_nprobe, max_k, max_nlist;  // maxima over configurations (LDS sizing)
   float *Qs;          // [nq][dq_pad]
   int64_t ldqs;
   float *S;           // [nq][nlist] coarse first-pass scores

@@ -21,6 +21,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <mutex>
 
 namespace adanns {
 namespace {
@@ -451,6 +452,8 @@ struct SelArgs {
   int32_t *out_probes;
   int32_t *out_probes2;
   int64_t ldo;             // output row stride (0 = kout)
+  int32_t lcap;            // segment floats staged in LDS (0 = none)
+  int32_t kcap;            // candidate slots in LDS (power of two >= K1)
 };
 
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
@@ -529,14 +532,26 @@ __device__ __forceinline__ void bitonic_sort(float *chi, float *clo, int64_t *ci
   __syncthreads();
 }
 
+// Dynamic LDS of the selection kernels: histogram (reused for the staged
+// query row), the query's first-pass segment when it fits (lcap floats), and
+// the candidate arrays (kcap entries).
+__host__ __device__ inline size_t sel_smem_bytes(int32_t lcap, int32_t kcap) {
+  return 2048 * 4 + 4096 + (size_t)lcap * 4 + (size_t)kcap * (8 + 4 + 4 + 8 + 8);
+}
+
 __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
-  __shared__ uint32_t hist[2048];
-  __shared__ int64_t cpos[MAX_SHORTLIST];
-  __shared__ float chi[MAX_SHORTLIST], clo[MAX_SHORTLIST];
-  __shared__ int64_t cid[MAX_SHORTLIST];
-  __shared__ int64_t cg[MAX_SHORTLIST];   // coarse: h; scan: (h << 32) | row in list
+  extern __shared__ __attribute__((aligned(16))) unsigned char sel_smem[];
+  uint32_t *hist = (uint32_t *)sel_smem;
+  float *qstage = (float *)sel_smem;  // reuses the histogram after selection
+  uint8_t *qqstage = sel_smem + 2048 * 4;  // quantised query bytes (precision form)
+  float *segbuf = (float *)(sel_smem + 2048 * 4 + 4096);
+  int64_t *cpos = (int64_t *)(sel_smem + 2048 * 4 + 4096 + (size_t)a.lcap * 4);
+  int64_t *cid = cpos + a.kcap;
+  int64_t *cg = cid + a.kcap;         // coarse: h; scan: (h << 32) | row in list
+  float *chi = (float *)(cg + a.kcap);
+  float *clo = chi + a.kcap;
   __shared__ uint32_t sh32[16];
-  __shared__ uint32_t s_bin, s_before;
+  __shared__ uint32_t s_bin, s_before, s_min, s_max;
   __shared__ int s_slot;
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
@@ -558,19 +573,55 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
     for (int i = tid; i < ncand; i += blockDim.x) cpos[i] = i;
   } else {
     ncand = a.K1;
-    // radix selection of the K1-th smallest key: 11 + 11 + 10 bits
-    uint32_t prefix = 0, pmask = 0, need = (uint32_t)a.K1;
-    for (int pass = 0; pass < 3; ++pass) {
-      const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
-      const int nb = pass < 2 ? 2048 : 1024;
+    // stage the segment in LDS when it fits: every pass below reads it
+    const bool staged = L <= a.lcap;
+    if (staged) {  // eight independent loads in flight per thread
+      for (int64_t base = tid; base < L; base += (int64_t)blockDim.x * 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t i = base + (int64_t)blockDim.x * u;
+          v[u] = i < L ? seg[i] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t i = base + (int64_t)blockDim.x * u;
+          if (i < L) segbuf[i] = v[u];
+        }
+      }
+    }
+    const float *src = staged ? segbuf : seg;
+    // key range of the segment
+    uint32_t kmin = 0xffffffffu, kmax = 0u;
+    if (tid == 0) {
+      s_min = 0xffffffffu;
+      s_max = 0u;
+    }
+    __syncthreads();
+    for (int64_t i = tid; i < L; i += blockDim.x) {
+      const uint32_t kk = order_key(src[i]);
+      kmin = kk < kmin ? kk : kmin;
+      kmax = kk > kmax ? kk : kmax;
+    }
+    atomicMin(&s_min, kmin);
+    atomicMax(&s_max, kmax);
+    __syncthreads();
+    // radix selection of the K1-th smallest key over an adaptive window
+    // [lo, hi): each pass splits the window into at most 2048 bins
+    uint64_t lo = s_min, hi = (uint64_t)s_max + 1;
+    uint32_t need = (uint32_t)a.K1;
+    uint32_t T = 0;
+    for (int pass = 0; pass < 4; ++pass) {
+      const uint64_t width = hi - lo;
+      const int shift = width <= 2048 ? 0 : (64 - __clzll((long long)(width - 1))) - 11;
       for (int i = tid; i < 2048; i += blockDim.x) hist[i] = 0;
       __syncthreads();
       for (int64_t i = tid; i < L; i += blockDim.x) {
-        uint32_t kk = order_key(seg[i]);
-        if ((kk & pmask) == prefix) atomicAdd(&hist[(kk >> shift) & (nb - 1)], 1u);
+        const uint64_t kk = order_key(src[i]);
+        if (kk >= lo && kk < hi) atomicAdd(&hist[(uint32_t)((kk - lo) >> shift)], 1u);
       }
       __syncthreads();
-      const int per = nb / 256;
+      const int per = 2048 / blockDim.x;
       uint32_t local = 0;
       for (int e = 0; e < per; ++e) local += hist[tid * per + e];
       uint32_t excl = block_excl_scan<uint32_t>(local, sh32, nullptr);
@@ -587,24 +638,26 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
         }
       }
       __syncthreads();
-      prefix |= s_bin << shift;
-      pmask |= (uint32_t)(nb - 1) << shift;
+      const uint64_t nlo = lo + ((uint64_t)s_bin << shift);
+      const uint64_t nhi = nlo + ((uint64_t)1 << shift);
       need -= s_before;
+      lo = nlo;
+      hi = nhi < hi ? nhi : hi;
       __syncthreads();
+      if (shift == 0) break;
     }
-    // prefix is the K1-th smallest key; take every smaller key and the first
-    // ``need`` equal ones in position order.
-    const uint32_t T = prefix;
+    T = (uint32_t)lo;
+    // take every key below T and the first ``need`` equal ones in position order
     const int64_t chunk = (L + blockDim.x - 1) / blockDim.x;
     const int64_t a0 = tid * chunk, a1 = min64(L, a0 + chunk);
     uint32_t ne = 0;
-    for (int64_t i = a0; i < a1; ++i) ne += order_key(seg[i]) == T;
+    for (int64_t i = a0; i < a1; ++i) ne += order_key(src[i]) == T;
     uint32_t eq_before = block_excl_scan<uint32_t>(ne, sh32, nullptr);
     if (tid == 0) s_slot = 0;
     __syncthreads();
     const int nlt = a.K1 - (int)need;
     for (int64_t i = a0; i < a1; ++i) {
-      uint32_t kk = order_key(seg[i]);
+      uint32_t kk = order_key(src[i]);
       if (kk < T) {
         int slot = atomicAdd(&s_slot, 1);
         cpos[slot] = i;
@@ -615,9 +668,22 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
     }
   }
   __syncthreads();
+  // stage the query row (coordinates of both measures) in LDS
+  const int dq_stage = a.d_dot > a.d_B ? a.d_dot : a.d_B;
+  const bool qstaged = dq_stage <= 2048;
+  if (qstaged)
+    for (int i = tid; i < dq_stage; i += blockDim.x) qstage[i] = a.Qs[q * a.ldqs + i];
+  const int qeb = a.qfmt == 1 ? 2 : 1;
+  const bool qqstaged = (a.mode == SEL_QUANT || a.mode == SEL_COARSE_QUANT) &&
+                        (int64_t)a.d_dot * qeb <= 4096;
+  if (qqstaged) {
+    const uint8_t *src = (const uint8_t *)a.qQ + q * a.ldqq * qeb;
+    for (int i = tid; i < a.d_dot * qeb; i += blockDim.x) qqstage[i] = src[i];
+  }
+  __syncthreads();
 
   // first exact measure, one wave per candidate
-  const float *qrow = a.Qs + q * a.ldqs;
+  const float *qrow = qstaged ? qstage : a.Qs + q * a.ldqs;
   for (int c = wv; c < ncand; c += nwv) {
     const int64_t pos = cpos[c];
     float S = 0.f, C = 0.f;
@@ -627,7 +693,14 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
       gpack = pos;
       if (a.mode == SEL_COARSE) {
         const float *x = a.cent + pos * a.ld_cent;
-        for (int dim = lane; dim < a.d_dot; dim += 64) acc_sq_diff(qrow[dim], x[dim], S, C);
+        for (int d0 = lane; d0 < a.d_dot; d0 += 64 * 8) {
+          float xv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) xv[u] = d0 + 64 * u < a.d_dot ? x[d0 + 64 * u] : 0.f;
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (d0 + 64 * u < a.d_dot) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+        }
       } else {
         const float xs = a.qfmt == 2 ? a.qscale[pos] : 1.f;
         const float qs = a.qfmt == 2 ? a.qQscale[q] : 1.f;
@@ -656,8 +729,17 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
       gpack = ((int64_t)h << 32) | r;
       if (a.mode == SEL_L2) {
         const float *base = a.vec + p0 * a.d_pad + r * SLAB;
-        for (int dim = lane; dim < a.d_dot; dim += 64)
-          acc_sq_diff(qrow[dim], base[(int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)], S, C);
+        for (int d0 = lane; d0 < a.d_dot; d0 += 64 * 16) {
+          float xv[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int dim = d0 + 64 * u;
+            xv[u] = dim < a.d_dot ? base[(int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)] : 0.f;
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            if (d0 + 64 * u < a.d_dot) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+        }
       } else if (a.mode == SEL_ADC) {
         const uint8_t *code = a.codes + (p0 + r) * a.M;
         const float *qh = a.qr_hi + q * a.ldqr, *ql = a.qr_lo + q * a.ldqr;
@@ -666,7 +748,29 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
           const float x = a.cb[((int64_t)m * 256 + code[m]) * a.dsub + t];
           acc_sq_diff2(qh[dim], ql[dim], x, S, C);
         }
-      } else {  // SEL_QUANT
+      } else if (qqstaged) {  // SEL_QUANT: 16-byte chunks of the stored row
+        const float xs = a.qfmt == 2 ? a.qscale[p0 + r] : 1.f;
+        const float qs = a.qfmt == 2 ? a.qQscale[q] : 1.f;
+        const int per = 16 / qeb;  // coordinates per chunk, inside one slab
+        const uint8_t *vb = (const uint8_t *)a.qvec + (p0 * a.qd_pad + r * SLAB) * qeb;
+        for (int e0 = lane * per; e0 < a.d_dot; e0 += 64 * per) {
+          const uint4 w4 = *(const uint4 *)(vb + ((int64_t)(e0 / SLAB) * npad * SLAB + e0 % SLAB) * qeb);
+          const uint32_t wds[4] = {w4.x, w4.y, w4.z, w4.w};
+          for (int u = 0; u < per && e0 + u < a.d_dot; ++u) {
+            float qh, ql, xh, xl;
+            quant_value(a.qfmt, qqstage, e0 + u, qs, qh, ql);
+            const uint32_t bits = (wds[(u * qeb) / 4] >> (((u * qeb) % 4) * 8)) &
+                                  (qeb == 2 ? 0xffffu : 0xffu);
+            if (a.qfmt == 1) {
+              xh = bf16_to_float((uint16_t)bits);
+              xl = 0.f;
+            } else {
+              two_prod(xs, e4m3_to_float(bits), xh, xl);
+            }
+            acc_sq_diff2(qh, ql - xl, xh, S, C);
+          }
+        }
+      } else {  // SEL_QUANT, query too wide to stage
         const float xs = a.qfmt == 2 ? a.qscale[p0 + r] : 1.f;
         const float qs = a.qfmt == 2 ? a.qQscale[q] : 1.f;
         for (int dim = lane; dim < a.d_dot; dim += 64) {
@@ -712,8 +816,17 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
         const int64_t p0 = a.poff[h];
         const int64_t npad = a.poff[h + 1] - p0;
         const float *base = a.vec + p0 * a.d_pad + r * SLAB;
-        for (int dim = lane; dim < a.d_B; dim += 64)
-          acc_sq_diff(qrow[dim], base[(int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)], S, C);
+        for (int d0 = lane; d0 < a.d_B; d0 += 64 * 16) {
+          float xv[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int dim = d0 + 64 * u;
+            xv[u] = dim < a.d_B ? base[(int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)] : 0.f;
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            if (d0 + 64 * u < a.d_B) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+        }
       }
       wave_reduce_pair(S, C);
       if (lane == 0) {
@@ -746,7 +859,7 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_select_refine(SelArgs a) { select_body(a, blockIdx.x); }
+__global__ __launch_bounds__(512) void k_select_refine(SelArgs a) { select_body(a, blockIdx.x); }
 
 // Batched FP32 selection: one block per query row of the batch; the
 // configuration's fields are patched into the arguments.
@@ -765,9 +878,10 @@ struct SelMultiArgs {
   float *dist;             // scan: [Qtot][ldk]; coarse: optional min distance [Qtot]
   int64_t *ids;
   int64_t ldk;
+  int32_t lcap, kcap;
 };
 
-__global__ __launch_bounds__(256) void k_select_multi(SelMultiArgs m) {
+__global__ __launch_bounds__(512) void k_select_multi(SelMultiArgs m) {
   const int64_t r = blockIdx.x;
   const int c = cfg_of(m.cfg, m.ncfg, &CfgDev::q0, r);
   const CfgDev &g = m.cfg[c];
@@ -775,6 +889,8 @@ __global__ __launch_bounds__(256) void k_select_multi(SelMultiArgs m) {
   SelArgs a{};
   a.Qs = m.Qs + g.q0 * m.ldqs;
   a.ldqs = m.ldqs;
+  a.lcap = m.lcap;
+  a.kcap = m.kcap;
   if (m.coarse) {
     a.mode = SEL_COARSE;
     a.D = m.S + g.S0;
@@ -1370,6 +1486,53 @@ __global__ void k_stage_multi(const float *__restrict__ Q, int64_t ldq, const Cf
   Qs[i] = col < dq ? Q[r * ldq + col] : 0.0f;
 }
 
+static int32_t next_pow2(int32_t v) {
+  int32_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+constexpr int32_t SEG_LDS_CAP = 16384;   // at most this many first-pass distances staged
+
+// LDS a selection workgroup may use: the device's per-workgroup limit (the
+// function attribute is raised to it when it exceeds the 64 KB default).
+static size_t sel_smem_budget() {
+  static std::once_flag once;
+  static size_t budget = 64 * 1024;
+  std::call_once(once, [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        v > 0)
+      budget = (size_t)v;
+    if (budget > 64 * 1024) {
+      if (hipFuncSetAttribute((const void *)k_select_refine,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget) != hipSuccess ||
+          hipFuncSetAttribute((const void *)k_select_multi,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget) != hipSuccess) {
+        (void)hipGetLastError();
+        budget = 64 * 1024;
+      }
+    }
+    (void)hipGetLastError();
+  });
+  return budget;
+}
+
+// Segment floats that fit beside the histogram and kcap candidate slots.
+static int32_t seg_cap(int32_t kcap, int64_t max_len) {
+  const int64_t room = ((int64_t)sel_smem_budget() - (int64_t)sel_smem_bytes(0, kcap)) / 4;
+  const int64_t cap = std::min<int64_t>({(int64_t)SEG_LDS_CAP, room / 256 * 256, max_len});
+  return (int32_t)std::max<int64_t>(cap, 0);
+}
+
+// Sets the LDS caps of a single-configuration selection; returns its bytes.
+static size_t sel_caps(SelArgs &s, int64_t max_len) {
+  s.kcap = next_pow2(std::max(std::max(s.K1, s.kout), 1));
+  s.lcap = seg_cap(s.kcap, max_len);
+  return sel_smem_bytes(s.lcap, s.kcap);
+}
+
 CfgDev make_cfg(const adanns_index *ix, int32_t d_c, int32_t d_s, int32_t nprobe, int32_t k,
                 int64_t nq) {
   CfgDev c{};
@@ -1467,9 +1630,12 @@ static hipError_t coarse_multi(const SearchBufs &b, int32_t *user_probes, float 
   m.probes = b.probes;
   m.user_probes = user_probes;
   m.dist = out_min_dist;
+  m.kcap = next_pow2(std::min(b.max_nlist, std::min(b.max_nprobe + REFINE_MARGIN, MAX_SHORTLIST)));
+  m.lcap = seg_cap(m.kcap, b.max_nlist);
   {
     KernelTimer tm("select_coarse", st);
-    hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(256), 0, st, m);
+    hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(512),
+                       sel_smem_bytes(m.lcap, m.kcap), st, m);
   }
   return hipGetLastError();
 }
@@ -1504,6 +1670,8 @@ hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq
   bb.ncfg = 1;
   bb.Qtot = nq;
   bb.ct_total = c.qtiles * (int32_t)cdiv(ix->nlist, TILE_V);
+  bb.max_nlist = ix->nlist;
+  bb.max_nprobe = nprobe;
   return coarse_multi(bb, user_probes, out_min_dist, PERSIST_WG, st);
 }
 
@@ -1572,9 +1740,12 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
   m.dist = dist;
   m.ids = ids;
   m.ldk = ldk;
+  m.kcap = next_pow2(std::min(b.max_k + REFINE_MARGIN, MAX_SHORTLIST));
+  m.lcap = seg_cap(m.kcap, SEG_LDS_CAP);
   {
     KernelTimer tm("select_scan", st);
-    hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(256), 0, st, m);
+    hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(512),
+                       sel_smem_bytes(m.lcap, m.kcap), st, m);
   }
   return hipGetLastError();
 }
@@ -1673,8 +1844,9 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   s.out_probes = b.probes;
   s.out_probes2 = user_probes;
   {
+    const size_t smem = sel_caps(s, ix->nlist);
     KernelTimer tm("select_q_coarse", st);
-    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(512), smem, st, s);
   }
   e = launch_bucketing(ix, b, nq, nprobe, st);
   if (e != hipSuccess) return e;
@@ -1735,8 +1907,9 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   r.out_dist = dist;
   r.out_ids = ids;
   {
+    const size_t smem = sel_caps(r, SEG_LDS_CAP);
     KernelTimer tm("select_q_scan", st);
-    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, r);
+    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(512), smem, st, r);
   }
   return hipGetLastError();
 }
@@ -1805,8 +1978,9 @@ hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const Sea
   s.out_dist = dist;
   s.out_ids = ids;
   {
+    const size_t smem = sel_caps(s, SEG_LDS_CAP);
     KernelTimer tm("select_adc", st);
-    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(256), 0, st, s);
+    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(512), smem, st, s);
   }
   return hipGetLastError();
 }
