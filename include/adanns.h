@@ -150,6 +150,26 @@ adanns_status adanns_pq_import(adanns_index *index, int32_t M, int32_t d_s, cons
                                const float *codebooks, const uint8_t *codes, void *stream);
 
 /*
+ * Train and attach a plain PQ codec on the GPU (identity rotation): for each
+ * of the M blocks of d_s/M coordinates, Lloyd's k-means with 256 codewords
+ * on the training rows (as adanns_build_ivf: init_rows, host [256] int32,
+ * index the training rows; train_rows host [n_train] int64 or NULL = all
+ * rows; iters rounds), then every row of X is encoded by its nearest
+ * codeword per block (FP32 difference form, ties to the smaller index).
+ *   X  device, the index's database [n x d] FP32 (row j = id j), stride ldx.
+ * Limits: as adanns_pq_import, and d_s / M <= 32. An OPQ rotation can be
+ * attached through adanns_pq_import instead. Synchronises ``stream``.
+ */
+adanns_status adanns_pq_train(adanns_index *index, const float *X, int64_t ldx, int32_t M,
+                              int32_t d_s, int32_t iters, const int32_t *init_rows,
+                              const int64_t *train_rows, int64_t n_train, void *stream);
+
+/* A codec as stored: R host [d_s x d_s], codebooks host [M x 256 x d_s/M],
+ * codes host [n x M] in database-id order. Any may be NULL. Synchronous. */
+adanns_status adanns_pq_codec(const adanns_index *index, int32_t M, float *R, float *codebooks,
+                              uint8_t *codes);
+
+/*
  * AdANNS-IVF-PQ search (Section 4.3; Appendix A, Table "formula", IVFOPQ
  * row, read with an unquantised query): probes from the unrotated d_c
  * prefix as in adanns_search; the probed lists are scanned with the
@@ -279,6 +299,39 @@ void adanns_batch_free(adanns_batch *batch);
 
 /* Forgets every autotuned shape. */
 adanns_status adanns_autotune_clear(void);
+
+/*
+ * Serving form: an open-loop request loop over the index's PQ codecs
+ * (search as adanns_search_pq). Request i (query row i of Q, device
+ * [n x ldq]) arrives arrival_s[i] seconds after the call starts (host clock;
+ * non-decreasing) with its own budget (d_c[i], nprobe[i], M[i]) (host
+ * arrays). A host loop admits arrived requests while the device memory their
+ * searches need (staged query, coarse scores, probes, candidate distances,
+ * tables) fits in hbm_budget bytes together with the requests in flight,
+ * batches admitted requests of one budget into a step (the oldest pending
+ * request's budget first, at most max_batch requests), runs up to nstreams
+ * steps concurrently on streams of their own, and on each step's completion
+ * event records the latency of its requests and frees their budget, while
+ * newer requests keep being admitted (continuous batching). A request that
+ * alone exceeds the budget is rejected (latency -1). Results go to row i of
+ * dist / ids (device [n x k]); latency_s (host [n]) is completion minus
+ * arrival. Each stream's scratch memory is grown before the clock starts.
+ * Blocks until every request completed; synchronises the device.
+ */
+typedef struct adanns_serve_stats {
+  double wall_s;               /* first arrival window start to last completion */
+  int64_t steps;               /* search steps launched */
+  double mean_batch;           /* requests per step */
+  size_t max_inflight_bytes;   /* peak admitted bytes (never above hbm_budget) */
+  int32_t max_streams_busy;    /* peak concurrent steps */
+  int64_t rejected;            /* requests larger than the budget */
+} adanns_serve_stats;
+
+adanns_status adanns_serve(const adanns_index *index, const float *Q, int64_t ldq, int64_t n,
+                           const double *arrival_s, const int32_t *d_c, const int32_t *nprobe,
+                           const int32_t *M, int32_t k, int32_t rerank_k, int32_t d_rerank,
+                           int32_t nstreams, int32_t max_batch, size_t hbm_budget, float *dist,
+                           int64_t *ids, double *latency_s, adanns_serve_stats *stats);
 
 /* Sizes of an index. Any out pointer may be NULL. */
 adanns_status adanns_index_info(const adanns_index *index, int64_t *n, int32_t *d,

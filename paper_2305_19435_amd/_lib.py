@@ -33,6 +33,8 @@ _SIGS = {
     "adanns_ivf_import": (C.c_int, [vp, i64, i32, i64, vp, i32, i32, vp, vp, PIX]),
     "adanns_build_ivf": (C.c_int, [vp, i64, i32, i64, i32, i32, i32, vp, vp, i64, vp, vp, PIX]),
     "adanns_pq_import": (C.c_int, [vp, i32, i32, vp, vp, vp, vp]),
+    "adanns_pq_codec": (C.c_int, [vp, i32, vp, vp, vp]),
+    "adanns_pq_train": (C.c_int, [vp, vp, i64, i32, i32, i32, vp, vp, i64, vp]),
     "adanns_search_pq": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp]),
     "adanns_set_precision": (C.c_int, [vp, i32, vp]),
     "adanns_index_quantized": (C.c_int, [vp, i32, vp, vp]),
@@ -46,6 +48,8 @@ _SIGS = {
     "adanns_batch_info": (C.c_int, [vp, vp, vp, vp, vp]),
     "adanns_batch_free": (None, [vp]),
     "adanns_autotune_clear": (C.c_int, []),
+    "adanns_serve": (C.c_int, [vp, vp, i64, i64, vp, vp, vp, vp, i32, i32, i32, i32, i32,
+                               C.c_size_t, vp, vp, vp, vp]),
     "adanns_timing_enable": (C.c_int, [i32]),
     "adanns_timing_reset": (C.c_int, []),
     "adanns_timing_read": (C.c_int, [C.c_char_p, vp, vp]),
@@ -67,6 +71,13 @@ class BatchConfig(C.Structure):
     """adanns_batch_config."""
     _fields_ = [("index", vp), ("nq", i64), ("d_c", i32), ("d_s", i32), ("nprobe", i32),
                 ("k", i32)]
+
+
+class ServeStats(C.Structure):
+    """adanns_serve_stats."""
+    _fields_ = [("wall_s", C.c_double), ("steps", i64), ("mean_batch", C.c_double),
+                ("max_inflight_bytes", C.c_size_t), ("max_streams_busy", i32),
+                ("rejected", i64)]
 
 
 class AdannsError(RuntimeError):

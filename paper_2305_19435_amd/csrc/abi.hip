@@ -291,7 +291,8 @@ static adanns_status init_index_shape(adanns_index *ix, int64_t n, int32_t d, in
 static adanns_status kmeans_gpu(const float *X, int64_t n, int64_t ldx, int32_t nlist, int32_t d_c,
                                 int32_t iters, const int32_t *init_rows, const int64_t *train_rows,
                                 int64_t n_train, double *objective, hipStream_t st,
-                                std::vector<int32_t> &assign_all, float **C_out) {
+                                std::vector<int32_t> &assign_all, float **C_out,
+                                bool final_all_rows = true) {
   const int32_t dcp = (int32_t)round_up(d_c, SLAB);
   const int64_t nt = train_rows ? n_train : n;
   DevFree tmp;
@@ -389,6 +390,12 @@ static adanns_status kmeans_gpu(const float *X, int64_t n, int64_t ldx, int32_t 
     ADANNS_HIP(hipMemcpyAsync(perm, h_perm.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice, st));
     ADANNS_HIP(hipMemcpyAsync(d_off, h_off.data(), (nlist + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
     ADANNS_HIP(launch_centroid_update(Xt, dcp, perm, d_off, nlist, d_c, C, dcp, st));
+  }
+  if (!final_all_rows) {  // centroids only (the caller encodes the rows itself)
+    cix.cent = nullptr;
+    cix.cent_slab = nullptr;
+    *C_out = C;
+    return ADANNS_OK;
   }
   // final assignment of every row against the final centroids
   assign_all.assign(n, 0);
@@ -634,6 +641,87 @@ adanns_status adanns_pq_import(adanns_index *ix, int32_t M, int32_t d_s, const f
     return fail(ADANNS_EHIP);
   }
   ix->pq[M] = c;
+  return ADANNS_OK;
+}
+
+adanns_status adanns_pq_train(adanns_index *ix, const float *X, int64_t ldx, int32_t M,
+                              int32_t d_s, int32_t iters, const int32_t *init_rows,
+                              const int64_t *train_rows, int64_t n_train, void *stream) {
+  clear_error();
+  ADANNS_REQUIRE(ix != nullptr && X != nullptr && init_rows != nullptr,
+                 "index, X and init_rows must be non-NULL");
+  ADANNS_REQUIRE(ldx >= ix->d, "ldx (%lld) must be >= d (%d)", (long long)ldx, ix->d);
+  ADANNS_REQUIRE(d_s >= 1 && d_s <= ix->d && d_s <= 2048, "d_s must be in [1, min(d, 2048)]");
+  ADANNS_REQUIRE(M >= 4 && M <= 64 && M % 4 == 0, "M must be a multiple of 4 in [4, 64], got %d", M);
+  ADANNS_REQUIRE(d_s % M == 0, "M (%d) must divide d_s (%d)", M, d_s);
+  ADANNS_REQUIRE(d_s / M <= PQ_ENCODE_MAX_DSUB, "GPU training supports d_s / M <= %d",
+                 PQ_ENCODE_MAX_DSUB);
+  ADANNS_REQUIRE(iters >= 0 && iters <= 1000, "iters must be in [0, 1000]");
+  ADANNS_REQUIRE(ix->pq.find(M) == ix->pq.end(), "the index already holds a codec with M = %d", M);
+  const int64_t nt = train_rows ? n_train : ix->n;
+  ADANNS_REQUIRE(nt >= 256, "the training set must hold at least 256 rows");
+  for (int32_t c = 0; c < 256; ++c)
+    ADANNS_REQUIRE(init_rows[c] >= 0 && init_rows[c] < nt, "init_rows[%d] out of range", c);
+  if (train_rows)
+    for (int64_t j = 0; j < nt; ++j)
+      ADANNS_REQUIRE(train_rows[j] >= 0 && train_rows[j] < ix->n, "train_rows[%lld] out of range",
+                     (long long)j);
+  adanns_status s = check_async();
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int32_t dsub = d_s / M, dcp = (int32_t)round_up(dsub, SLAB);
+  DevFree tmp;
+  float *cb = nullptr, *R = nullptr;
+  uint8_t *codes_id = nullptr;
+  ADANNS_HIP(hipMalloc(&cb, (size_t)M * 256 * dsub * sizeof(float)));
+  tmp.ptrs.push_back(cb);
+  ADANNS_HIP(hipMalloc(&codes_id, (size_t)ix->n * M));
+  tmp.ptrs.push_back(codes_id);
+  std::vector<int32_t> unused;
+  for (int32_t m = 0; m < M; ++m) {
+    float *C = nullptr;
+    // Lloyd's k-means with 256 codewords on the m-th block of coordinates
+    if ((s = kmeans_gpu(X + (int64_t)m * dsub, ix->n, ldx, 256, dsub, iters, init_rows, train_rows,
+                        nt, nullptr, st, unused, &C, false))) {
+      if (C) (void)hipFree(C);
+      return s;
+    }
+    hipError_t e = hipMemcpy2DAsync(cb + (size_t)m * 256 * dsub, dsub * sizeof(float), C,
+                                    dcp * sizeof(float), dsub * sizeof(float), 256,
+                                    hipMemcpyDeviceToDevice, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(C);
+    ADANNS_HIP(e);
+  }
+  ADANNS_HIP(launch_pq_encode(X, ldx, ix->n, M, dsub, cb, codes_id, st));
+  std::vector<float> eye((size_t)d_s * d_s, 0.f);
+  for (int32_t i = 0; i < d_s; ++i) eye[(size_t)i * d_s + i] = 1.f;
+  ADANNS_HIP(hipMalloc(&R, eye.size() * sizeof(float)));
+  tmp.ptrs.push_back(R);
+  ADANNS_HIP(hipMemcpyAsync(R, eye.data(), eye.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  ADANNS_HIP(hipStreamSynchronize(st));
+  return adanns_pq_import(ix, M, d_s, R, cb, codes_id, stream);
+}
+
+adanns_status adanns_pq_codec(const adanns_index *ix, int32_t M, float *R, float *codebooks,
+                              uint8_t *codes) {
+  clear_error();
+  ADANNS_REQUIRE(ix != nullptr, "index is NULL");
+  auto it = ix->pq.find(M);
+  ADANNS_REQUIRE(it != ix->pq.end(), "the index holds no PQ codec with M = %d", M);
+  const PqCodec &c = it->second;
+  if (R) ADANNS_HIP(hipMemcpy(R, c.R, (size_t)c.d_s * c.d_s * sizeof(float), hipMemcpyDeviceToHost));
+  if (codebooks)
+    ADANNS_HIP(hipMemcpy(codebooks, c.cb, (size_t)M * 256 * c.dsub * sizeof(float),
+                         hipMemcpyDeviceToHost));
+  if (codes) {
+    std::vector<uint8_t> lay((size_t)ix->rows_pad * M);
+    ADANNS_HIP(hipMemcpy(lay.data(), c.codes, lay.size(), hipMemcpyDeviceToHost));
+    for (int32_t h = 0; h < ix->nlist; ++h)
+      for (int64_t r = 0; r < ix->h_len[h]; ++r)
+        std::memcpy(codes + (size_t)ix->h_ids[ix->h_off[h] + r] * M,
+                    &lay[(size_t)(ix->h_poff[h] + r) * M], M);
+  }
   return ADANNS_OK;
 }
 

@@ -214,6 +214,9 @@ hipError_t launch_centroid_update(const float *X, int64_t ldx, const int32_t *pe
                                   int64_t ldc, hipStream_t st);
 hipError_t launch_bucketing(const adanns_index *ix, const SearchBufs &b, int64_t nq,
                             int32_t nprobe, hipStream_t st);
+constexpr int PQ_ENCODE_MAX_DSUB = 32;
+hipError_t launch_pq_encode(const float *X, int64_t ldx, int64_t n, int32_t M, int32_t dsub,
+                            const float *cb, uint8_t *codes, hipStream_t st);
 hipError_t launch_gather_codes(const uint8_t *codes, int32_t M, const int64_t *rowid,
                                int64_t rows_pad, uint8_t *out, hipStream_t st);
 // Precision form: quantised copies, quantised queries, first passes, selection.

@@ -939,6 +939,42 @@ __global__ void k_gather_codes(const uint8_t *__restrict__ codes, int32_t M,
   out[i] = src >= 0 ? codes[src * M + m] : 0;
 }
 
+// PQ encoding: code[row][m] = the nearest of block m's 256 codewords to
+// X[row, m*dsub : (m+1)*dsub] (difference form, ties to the smaller index).
+__global__ __launch_bounds__(256) void k_pq_encode(const float *__restrict__ X, int64_t ldx,
+                                                   int64_t n, int32_t M, int32_t dsub,
+                                                   const float *__restrict__ cb,
+                                                   uint8_t *__restrict__ codes) {
+  extern __shared__ float cbs[];  // [256][dsub]
+  const int m = blockIdx.y;
+  for (int i = threadIdx.x; i < 256 * dsub; i += blockDim.x) cbs[i] = cb[(int64_t)m * 256 * dsub + i];
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  float y[PQ_ENCODE_MAX_DSUB];
+  const float *src = X + row * ldx + (int64_t)m * dsub;
+#pragma unroll
+  for (int t = 0; t < PQ_ENCODE_MAX_DSUB; ++t) y[t] = t < dsub ? src[t] : 0.f;
+  float best = __builtin_inff();
+  int bc = 0;
+  for (int c = 0; c < 256; ++c) {
+    const float *cw = cbs + c * dsub;
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < PQ_ENCODE_MAX_DSUB; ++t) {
+      if (t < dsub) {
+        const float dd = y[t] - cw[t];
+        acc += dd * dd;
+      }
+    }
+    if (acc < best) {
+      best = acc;
+      bc = c;
+    }
+  }
+  codes[row * M + m] = (uint8_t)bc;
+}
+
 // q' = q[:d_s] R in compensated FP32 (TwoProd + TwoSum), stored as a pair
 // (hi, lo). ROT_Q queries per workgroup share each read of R.
 constexpr int ROT_Q = 4;
@@ -1911,6 +1947,13 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
     KernelTimer tm("select_q_scan", st);
     hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(512), smem, st, r);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_pq_encode(const float *X, int64_t ldx, int64_t n, int32_t M, int32_t dsub,
+                            const float *cb, uint8_t *codes, hipStream_t st) {
+  hipLaunchKernelGGL(k_pq_encode, dim3(blocks_for(n, 256), M), dim3(256),
+                     256 * dsub * sizeof(float), st, X, ldx, n, M, dsub, cb, codes);
   return hipGetLastError();
 }
 

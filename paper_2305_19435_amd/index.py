@@ -113,6 +113,24 @@ class IvfIndex:
         check(lib.adanns_pq_import(self._h, M, d_s, _ptr(Rd), Cd.data_ptr(), Kd.data_ptr(),
                                    _stream(stream)))
 
+    def pq_train(self, X, M: int, d_s: int, iters: int, init_rows, train_rows=None, stream=None):
+        """adanns_pq_train: GPU-trained plain PQ codec on X (the index's rows)."""
+        Xd = X if (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32
+                   and X.stride(1) == 1) else _dev_f32(X, "cuda")
+        init = np.ascontiguousarray(init_rows, dtype=np.int32)
+        tr = None if train_rows is None else np.ascontiguousarray(train_rows, dtype=np.int64)
+        check(lib.adanns_pq_train(self._h, Xd.data_ptr(), Xd.stride(0), M, d_s, iters,
+                                  init.ctypes.data, None if tr is None else tr.ctypes.data,
+                                  0 if tr is None else len(tr), _stream(stream)))
+
+    def pq_codec(self, M: int, d_s: int):
+        """(R [d_s, d_s], codebooks [M, 256, d_s/M], codes [n, M]) as stored."""
+        R = np.empty((d_s, d_s), dtype=np.float32)
+        cb = np.empty((M, 256, d_s // M), dtype=np.float32)
+        codes = np.empty((self.n, M), dtype=np.uint8)
+        check(lib.adanns_pq_codec(self._h, M, R.ctypes.data, cb.ctypes.data, codes.ctypes.data))
+        return R, cb, codes
+
     def search_pq(self, Q, d_c: int, nprobe: int, M: int, k: int, rerank_k: int = 0,
                   d_rerank: int = 0, return_probes=False, stream=None, out=None):
         """adanns_search_pq. Returns (dist, ids[, probes])."""
@@ -165,6 +183,30 @@ class IvfIndex:
         check(lib.adanns_index_quantized(self._h, self.FORMATS[fmt], vals.ctypes.data,
                                          sc.ctypes.data))
         return vals, sc
+
+    # ---- serving form -------------------------------------------------------------
+    def serve(self, Q, arrival_s, d_c, nprobe, M, k: int, rerank_k: int = 0, d_rerank: int = 0,
+              nstreams: int = 4, max_batch: int = 1024, hbm_budget: int = 8 << 30):
+        """adanns_serve: open-loop request loop. Returns (dist, ids, latency_s, stats)."""
+        from ._lib import ServeStats
+        Qd = Q if (isinstance(Q, torch.Tensor) and Q.is_cuda and Q.dtype == torch.float32
+                   and Q.stride(1) == 1) else _dev_f32(Q, "cuda")
+        n = Qd.shape[0]
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        dc = np.ascontiguousarray(d_c, dtype=np.int32)
+        npb = np.ascontiguousarray(nprobe, dtype=np.int32)
+        mm = np.ascontiguousarray(M, dtype=np.int32)
+        dist = torch.empty((n, k), dtype=torch.float32, device=Qd.device)
+        ids = torch.empty((n, k), dtype=torch.int64, device=Qd.device)
+        lat = np.empty(n, dtype=np.float64)
+        st = ServeStats()
+        torch.cuda.synchronize()
+        check(lib.adanns_serve(self._h, Qd.data_ptr(), Qd.stride(0), n, arr.ctypes.data,
+                               dc.ctypes.data, npb.ctypes.data, mm.ctypes.data, k, rerank_k,
+                               d_rerank, nstreams, max_batch, hbm_budget, dist.data_ptr(),
+                               ids.data_ptr(), lat.ctypes.data, C.byref(st)))
+        stats = {f: getattr(st, f) for f, _ in ServeStats._fields_}
+        return dist, ids, lat, stats
 
     # ---- introspection ----------------------------------------------------------
     def lists(self):

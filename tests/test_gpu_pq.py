@@ -82,3 +82,34 @@ def test_pq_invalid(pq_small, lib):
         index.search_pq(Qd, w.d_c, 4, 16, 10, rerank_k=5, d_rerank=w.d)   # rerank_k < k
     with pytest.raises(lib.AdannsError):
         index.pq_import(16, w.d, None, codecs[16][1], codecs[16][2])      # duplicate M
+
+
+def test_pq_train_matches_oracle(lib, small_data):
+    """GPU-trained plain PQ (adanns_pq_train) against the oracle's PQ k-means."""
+    w, X, Q = small_data
+    C32, a, off, ids = oracle_index(X, w.nlist, w.d_c, 5, w.seed)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    M, iters = 8, 6
+    init = synth.init_rows(w.n, 256, w.seed, synth.STREAM_PQ, tag=3)
+    index.pq_train(torch.from_numpy(X).cuda(), M, w.d, iters, init)
+    R, cb, codes = index.pq_codec(M, w.d)
+    assert np.array_equal(R, np.eye(w.d, dtype=np.float32))
+    ref_cb = pq.pq_train64(X, M, iters, init_rows=init)
+    # Lloyd in FP32 vs FP64 may assign a near-tie point differently, which
+    # moves the two codewords involved; every other codeword must agree
+    close = np.all(np.abs(cb - ref_cb) <= 2e-5, axis=2)
+    assert close.mean() >= 0.98, close.mean()
+    ref_codes = pq.pq_encode64(X, cb.astype(np.float64))
+    diff = np.argwhere(codes != ref_codes)
+    dsub = w.d // M
+    for j, m in diff:       # only near-ties may differ
+        y = X[j, m * dsub:(m + 1) * dsub].astype(np.float64)
+        dg = ((y - cb[m, codes[j, m]]) ** 2).sum()
+        dr = ((y - cb[m, ref_codes[j, m]]) ** 2).sum()
+        assert abs(dg - dr) <= 1e-5 * max(dr, 1e-12)
+    assert len(diff) <= 0.001 * codes.size
+    # the trained codec searches like an imported one
+    dist, gid = index.search_pq(torch.from_numpy(Q).cuda(), w.d_c, 4, M, 10)
+    torch.cuda.synchronize()
+    assert np.all(gid.cpu().numpy() >= 0)
+    index.free()

@@ -1,0 +1,69 @@
+"""Serving form (adanns_serve): every request completes, admitted memory never
+exceeds the budget, and each request's result in the mix equals its result
+searched alone."""
+import numpy as np
+import pytest
+
+import synth
+from parity_util import oracle_index
+from test_gpu_pq import make_codec
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_19435_amd as p
+    return p
+
+
+@pytest.fixture(scope="module")
+def served(lib, small_data):
+    w, X, Q = small_data
+    C32, a, off, ids = oracle_index(X, w.nlist, w.d_c, 10, w.seed)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    for M, opq in ((16, True), (8, False)):
+        R32, cb32, codes = make_codec(X, M, w.d, opq, w.seed + M)
+        index.pq_import(M, w.d, R32 if opq else None, cb32, codes)
+    yield w, X, Q, index
+    index.free()
+
+
+def _requests(Q, n, qps, seed):
+    rng = np.random.default_rng(seed)
+    arrival = np.cumsum(rng.exponential(1.0 / qps, n))
+    rows = rng.integers(0, len(Q), n)
+    d_c = rng.choice([8, 16], n)
+    nprobe = rng.choice([2, 4, 8], n)
+    M = rng.choice([8, 16], n)
+    return np.ascontiguousarray(Q[rows]), arrival, d_c, nprobe, M
+
+
+def test_serve_mix_equals_alone(served):
+    w, X, Q, index = served
+    Qr, arrival, d_c, nprobe, M = _requests(Q, 400, 20000.0, 1)
+    budget = 2 << 20
+    dist, ids, lat, stats = index.serve(torch.from_numpy(Qr).cuda(), arrival, d_c, nprobe, M, 10,
+                                        nstreams=3, max_batch=32, hbm_budget=budget)
+    torch.cuda.synchronize()
+    assert np.all(lat >= 0) and stats["rejected"] == 0
+    assert 0 < stats["max_inflight_bytes"] <= budget
+    assert stats["steps"] >= 1 and stats["mean_batch"] >= 1
+    dist, ids = dist.cpu().numpy(), ids.cpu().numpy()
+    Qd = torch.from_numpy(Qr).cuda()
+    for i in range(len(Qr)):
+        d1, i1 = index.search_pq(Qd[i:i + 1], int(d_c[i]), int(nprobe[i]), int(M[i]), 10)
+        torch.cuda.synchronize()
+        assert np.array_equal(i1.cpu().numpy()[0], ids[i]), i
+        assert np.array_equal(d1.cpu().numpy()[0], dist[i]), i
+
+
+def test_serve_rejects_oversized(served):
+    w, X, Q, index = served
+    Qr, arrival, d_c, nprobe, M = _requests(Q, 20, 1000.0, 2)
+    dist, ids, lat, stats = index.serve(torch.from_numpy(Qr).cuda(), arrival, d_c, nprobe, M, 10,
+                                        nstreams=2, max_batch=4, hbm_budget=1024)
+    assert stats["rejected"] == 20 and np.all(lat == -1.0)
