@@ -150,19 +150,23 @@ adanns_status adanns_pq_import(adanns_index *index, int32_t M, int32_t d_s, cons
                                const float *codebooks, const uint8_t *codes, void *stream);
 
 /*
- * Train and attach a plain PQ codec on the GPU (identity rotation): for each
- * of the M blocks of d_s/M coordinates, Lloyd's k-means with 256 codewords
- * on the training rows (as adanns_build_ivf: init_rows, host [256] int32,
+ * Train and attach a PQ codec on the GPU for a given rotation R (device
+ * [d_s x d_s] row-major, or NULL for the identity): the training rows'
+ * first d_s coordinates are rotated (y = x[:d_s] R, compensated FP32), then
+ * for each of the M blocks of d_s/M coordinates Lloyd's k-means with 256
+ * codewords runs on them (as adanns_build_ivf: init_rows, host [256] int32,
  * index the training rows; train_rows host [n_train] int64 or NULL = all
- * rows; iters rounds), then every row of X is encoded by its nearest
- * codeword per block (FP32 difference form, ties to the smaller index).
+ * rows; iters rounds); then every row of X is rotated and encoded by its
+ * nearest codeword per block (FP32 difference form, ties to the smaller
+ * index). The rotation is not learned here (no Procrustes step); a learned
+ * OPQ rotation and its codebooks can be attached with adanns_pq_import.
  *   X  device, the index's database [n x d] FP32 (row j = id j), stride ldx.
- * Limits: as adanns_pq_import, and d_s / M <= 32. An OPQ rotation can be
- * attached through adanns_pq_import instead. Synchronises ``stream``.
+ * Limits: as adanns_pq_import, and d_s / M <= 32. Synchronises ``stream``.
  */
 adanns_status adanns_pq_train(adanns_index *index, const float *X, int64_t ldx, int32_t M,
-                              int32_t d_s, int32_t iters, const int32_t *init_rows,
-                              const int64_t *train_rows, int64_t n_train, void *stream);
+                              int32_t d_s, const float *R, int32_t iters,
+                              const int32_t *init_rows, const int64_t *train_rows,
+                              int64_t n_train, void *stream);
 
 /* A codec as stored: R host [d_s x d_s], codebooks host [M x 256 x d_s/M],
  * codes host [n x M] in database-id order. Any may be NULL. Synchronous. */

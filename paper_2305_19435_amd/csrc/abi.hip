@@ -645,8 +645,9 @@ adanns_status adanns_pq_import(adanns_index *ix, int32_t M, int32_t d_s, const f
 }
 
 adanns_status adanns_pq_train(adanns_index *ix, const float *X, int64_t ldx, int32_t M,
-                              int32_t d_s, int32_t iters, const int32_t *init_rows,
-                              const int64_t *train_rows, int64_t n_train, void *stream) {
+                              int32_t d_s, const float *R_in, int32_t iters,
+                              const int32_t *init_rows, const int64_t *train_rows,
+                              int64_t n_train, void *stream) {
   clear_error();
   ADANNS_REQUIRE(ix != nullptr && X != nullptr && init_rows != nullptr,
                  "index, X and init_rows must be non-NULL");
@@ -678,11 +679,41 @@ adanns_status adanns_pq_train(adanns_index *ix, const float *X, int64_t ldx, int
   ADANNS_HIP(hipMalloc(&codes_id, (size_t)ix->n * M));
   tmp.ptrs.push_back(codes_id);
   std::vector<int32_t> unused;
+  // training matrix: the rows themselves, or the training rows rotated by R
+  const float *Tx = X;
+  int64_t ldt = ldx, nT = ix->n;
+  const int64_t *trows = train_rows;
+  float *Rdev = nullptr, *T = nullptr, *Tlo = nullptr;
+  if (R_in) {
+    ADANNS_HIP(hipMalloc(&Rdev, (size_t)d_s * d_s * sizeof(float)));
+    tmp.ptrs.push_back(Rdev);
+    ADANNS_HIP(hipMemcpyAsync(Rdev, R_in, (size_t)d_s * d_s * sizeof(float),
+                              hipMemcpyDeviceToDevice, st));
+    float *raw = nullptr;
+    int64_t *d_tr = nullptr;
+    ADANNS_HIP(hipMalloc(&raw, (size_t)nt * d_s * sizeof(float)));
+    tmp.ptrs.push_back(raw);
+    ADANNS_HIP(hipMalloc(&T, (size_t)nt * d_s * sizeof(float)));
+    tmp.ptrs.push_back(T);
+    ADANNS_HIP(hipMalloc(&Tlo, (size_t)nt * d_s * sizeof(float)));
+    tmp.ptrs.push_back(Tlo);
+    if (train_rows) {
+      ADANNS_HIP(hipMalloc(&d_tr, (size_t)nt * sizeof(int64_t)));
+      tmp.ptrs.push_back(d_tr);
+      ADANNS_HIP(hipMemcpyAsync(d_tr, train_rows, nt * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    }
+    ADANNS_HIP(launch_stage_rows(X, ldx, d_tr, nullptr, nt, d_s, raw, d_s, st));
+    ADANNS_HIP(launch_rotate(raw, d_s, nt, Rdev, d_s, T, Tlo, d_s, st));
+    Tx = T;
+    ldt = d_s;
+    nT = nt;
+    trows = nullptr;  // T holds exactly the training rows
+  }
   for (int32_t m = 0; m < M; ++m) {
     float *C = nullptr;
     // Lloyd's k-means with 256 codewords on the m-th block of coordinates
-    if ((s = kmeans_gpu(X + (int64_t)m * dsub, ix->n, ldx, 256, dsub, iters, init_rows, train_rows,
-                        nt, nullptr, st, unused, &C, false))) {
+    if ((s = kmeans_gpu(Tx + (int64_t)m * dsub, nT, ldt, 256, dsub, iters, init_rows, trows, nt,
+                        nullptr, st, unused, &C, false))) {
       if (C) (void)hipFree(C);
       return s;
     }
@@ -693,14 +724,34 @@ adanns_status adanns_pq_train(adanns_index *ix, const float *X, int64_t ldx, int
     (void)hipFree(C);
     ADANNS_HIP(e);
   }
-  ADANNS_HIP(launch_pq_encode(X, ldx, ix->n, M, dsub, cb, codes_id, st));
-  std::vector<float> eye((size_t)d_s * d_s, 0.f);
-  for (int32_t i = 0; i < d_s; ++i) eye[(size_t)i * d_s + i] = 1.f;
-  ADANNS_HIP(hipMalloc(&R, eye.size() * sizeof(float)));
-  tmp.ptrs.push_back(R);
-  ADANNS_HIP(hipMemcpyAsync(R, eye.data(), eye.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  if (!R_in) {
+    ADANNS_HIP(launch_pq_encode(X, ldx, ix->n, M, dsub, cb, codes_id, st));
+    std::vector<float> eye((size_t)d_s * d_s, 0.f);
+    for (int32_t i = 0; i < d_s; ++i) eye[(size_t)i * d_s + i] = 1.f;
+    ADANNS_HIP(hipMalloc(&R, eye.size() * sizeof(float)));
+    tmp.ptrs.push_back(R);
+    ADANNS_HIP(hipMemcpyAsync(R, eye.data(), eye.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    ADANNS_HIP(hipStreamSynchronize(st));
+    return adanns_pq_import(ix, M, d_s, R, cb, codes_id, stream);
+  }
+  // encode every row after rotating it, in chunks
+  const int64_t chunk = 262144;
+  float *craw = nullptr, *crot = nullptr, *clo = nullptr;
+  const int64_t cm = std::min<int64_t>(chunk, ix->n);
+  ADANNS_HIP(hipMalloc(&craw, (size_t)cm * d_s * sizeof(float)));
+  tmp.ptrs.push_back(craw);
+  ADANNS_HIP(hipMalloc(&crot, (size_t)cm * d_s * sizeof(float)));
+  tmp.ptrs.push_back(crot);
+  ADANNS_HIP(hipMalloc(&clo, (size_t)cm * d_s * sizeof(float)));
+  tmp.ptrs.push_back(clo);
+  for (int64_t a0 = 0; a0 < ix->n; a0 += chunk) {
+    const int64_t m = std::min(chunk, ix->n - a0);
+    ADANNS_HIP(launch_stage_rows(X + a0 * ldx, ldx, nullptr, nullptr, m, d_s, craw, d_s, st));
+    ADANNS_HIP(launch_rotate(craw, d_s, m, Rdev, d_s, crot, clo, d_s, st));
+    ADANNS_HIP(launch_pq_encode(crot, d_s, m, M, dsub, cb, codes_id + a0 * M, st));
+  }
   ADANNS_HIP(hipStreamSynchronize(st));
-  return adanns_pq_import(ix, M, d_s, R, cb, codes_id, stream);
+  return adanns_pq_import(ix, M, d_s, Rdev, cb, codes_id, stream);
 }
 
 adanns_status adanns_pq_codec(const adanns_index *ix, int32_t M, float *R, float *codebooks,

@@ -1950,6 +1950,15 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   return hipGetLastError();
 }
 
+hipError_t launch_rotate(const float *Qs, int64_t ldqs, int64_t nq, const float *R, int32_t d_s,
+                         float *qh, float *ql, int64_t ldqr, hipStream_t st) {
+  if (nq == 0) return hipSuccess;
+  KernelTimer tm("pq_rotate", st);
+  hipLaunchKernelGGL(k_rotate, dim3((unsigned)cdiv(nq, ROT_Q)), dim3(256),
+                     ROT_Q * d_s * sizeof(float), st, Qs, ldqs, nq, R, d_s, qh, ql, ldqr);
+  return hipGetLastError();
+}
+
 hipError_t launch_pq_encode(const float *X, int64_t ldx, int64_t n, int32_t M, int32_t dsub,
                             const float *cb, uint8_t *codes, hipStream_t st) {
   hipLaunchKernelGGL(k_pq_encode, dim3(blocks_for(n, 256), M), dim3(256),
@@ -1972,12 +1981,8 @@ hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const Sea
   hipError_t e = launch_bucketing(ix, b, nq, nprobe, st);
   if (e != hipSuccess) return e;
   const int64_t ldqr = pq.d_s;
-  {
-    KernelTimer tm("pq_rotate", st);
-    hipLaunchKernelGGL(k_rotate, dim3((unsigned)cdiv(nq, ROT_Q)), dim3(256),
-                       ROT_Q * pq.d_s * sizeof(float), st, b.Qs, b.ldqs, nq, pq.R, pq.d_s, qr_hi,
-                       qr_lo, ldqr);
-  }
+  e = launch_rotate(b.Qs, b.ldqs, nq, pq.R, pq.d_s, qr_hi, qr_lo, ldqr, st);
+  if (e != hipSuccess) return e;
   {
     KernelTimer tm("pq_lut", st);
     hipLaunchKernelGGL(k_pq_lut, dim3((unsigned)nq), dim3(256), pq.d_s * sizeof(float), st, qr_hi,

@@ -113,13 +113,15 @@ class IvfIndex:
         check(lib.adanns_pq_import(self._h, M, d_s, _ptr(Rd), Cd.data_ptr(), Kd.data_ptr(),
                                    _stream(stream)))
 
-    def pq_train(self, X, M: int, d_s: int, iters: int, init_rows, train_rows=None, stream=None):
-        """adanns_pq_train: GPU-trained plain PQ codec on X (the index's rows)."""
+    def pq_train(self, X, M: int, d_s: int, iters: int, init_rows, train_rows=None, R=None,
+                 stream=None):
+        """adanns_pq_train: GPU-trained PQ codec on X (the index's rows) for rotation R."""
         Xd = X if (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32
                    and X.stride(1) == 1) else _dev_f32(X, "cuda")
         init = np.ascontiguousarray(init_rows, dtype=np.int32)
         tr = None if train_rows is None else np.ascontiguousarray(train_rows, dtype=np.int64)
-        check(lib.adanns_pq_train(self._h, Xd.data_ptr(), Xd.stride(0), M, d_s, iters,
+        Rd = None if R is None else _dev_f32(R, Xd.device)
+        check(lib.adanns_pq_train(self._h, Xd.data_ptr(), Xd.stride(0), M, d_s, _ptr(Rd), iters,
                                   init.ctypes.data, None if tr is None else tr.ctypes.data,
                                   0 if tr is None else len(tr), _stream(stream)))
 

@@ -129,6 +129,14 @@ def subsample_rows(n: int, count: int, seed: int = ROOT_SEED, tag: int = 0) -> n
     return np.sort(init_rows(n, count, seed, STREAM_MISC, tag)).astype(np.int64)
 
 
+def random_rotation(d: int, seed: int = ROOT_SEED, tag: int = 0) -> np.ndarray:
+    """A seeded random orthonormal d x d matrix (float32): the Q factor of a
+    Gaussian matrix with the signs of R's diagonal folded in (Haar measure)."""
+    g = _rng(seed, STREAM_PQ, 1000 + tag).standard_normal((d, d))
+    q, r = np.linalg.qr(g)
+    return (q * np.sign(np.diag(r))[None, :]).astype(np.float32)
+
+
 # ---- named workloads (sizes of the paper's experiments; Section 3, Appendix C) ----
 
 @dataclass(frozen=True)

@@ -113,3 +113,32 @@ def test_pq_train_matches_oracle(lib, small_data):
     torch.cuda.synchronize()
     assert np.all(gid.cpu().numpy() >= 0)
     index.free()
+
+
+def test_pq_train_with_rotation(lib, small_data):
+    """A given rotation: training and encoding happen on the rotated rows."""
+    w, X, Q = small_data
+    C32, a, off, ids = oracle_index(X, w.nlist, w.d_c, 5, w.seed)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    M, iters = 16, 5
+    R = synth.random_rotation(w.d, w.seed, tag=1)
+    np.testing.assert_allclose(R.T.astype(np.float64) @ R, np.eye(w.d), atol=1e-5)
+    rows = synth.subsample_rows(w.n, 4000, w.seed, tag=2)
+    init = synth.init_rows(len(rows), 256, w.seed, synth.STREAM_PQ, tag=4)
+    index.pq_train(torch.from_numpy(X).cuda(), M, w.d, iters, init, train_rows=rows, R=R)
+    R2, cb, codes = index.pq_codec(M, w.d)
+    assert np.array_equal(R2, R)
+    Y = X.astype(np.float64) @ R.astype(np.float64)
+    ref_cb = pq.pq_train64(Y[rows], M, iters, init_rows=init)
+    close = np.all(np.abs(cb - ref_cb) <= 2e-5, axis=2)
+    assert close.mean() >= 0.98, close.mean()
+    ref_codes = pq.pq_encode64(Y, cb.astype(np.float64))
+    diff = np.argwhere(codes != ref_codes)
+    dsub = w.d // M
+    for j, m in diff:
+        y = Y[j, m * dsub:(m + 1) * dsub]
+        dg = ((y - cb[m, codes[j, m]]) ** 2).sum()
+        dr = ((y - cb[m, ref_codes[j, m]]) ** 2).sum()
+        assert abs(dg - dr) <= 1e-5 * max(dr, 1e-12)
+    assert len(diff) <= 0.001 * codes.size
+    index.free()
