@@ -158,7 +158,7 @@ def main():
         tb = lib.Batch([(index, nq, d_c, d_s, nprobe, k)], ldq=w.d, ldk=k)
         shape = tb.autotune(Qd, out=(dist, ids), reps=1)
         tb.free()
-        log(f"autotuned scan shape (tq, grid) = {shape} in {time.time() - t0:.1f}s")
+        log(f"autotuned scan shape (tq, tv, grid) = {shape} in {time.time() - t0:.1f}s")
     for _ in range(args.warmup):
         index.search(Qd, d_c, d_s, nprobe, k, out=(dist, ids))
     torch.cuda.synchronize()
@@ -230,7 +230,7 @@ def main():
                    "n": n, "d": w.d, "nq": nq, "nlist": nlist, "d_c": d_c, "d_s": d_s,
                    "nprobe": nprobe, "k": k, "candidates_per_query": cand / nq,
                    "index": f"GPU Lloyd, {args.iters} iters on {n_train} seeded rows",
-                   "scan_shape": {"tq": shape[0], "grid": shape[1]} if shape else "default",
+                   "scan_shape": {"tq": shape[0], "tv": shape[1], "grid": shape[2]} if shape else "default",
                    "index_build_s": round(build_s, 2)},
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                        "p99": round(float(np.percentile(step_ms, 99)), 4),

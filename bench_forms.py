@@ -189,7 +189,7 @@ def batching_form(args, lib, torch, log):
            "data": "synthetic", "vs_baseline": None,
            "config": {"workload": f"batching1m: N={n} d={w.d} nlist={w.nlist}, 3 indices d_c 16/64/256, "
                                   f"64 configs, {total} queries (log-uniform 1..4096)",
-                      "tile_shape": {"tq": shape[0], "grid": shape[1]}},
+                      "tile_shape": {"tq": shape[0], "tv": shape[1], "grid": shape[2]}},
            "batched_graph_ms": round(t_graph * 1e3, 3), "batched_eager_ms": round(t_eager * 1e3, 3),
            "one_by_one_ms": round(t_single * 1e3, 3),
            "speedup_vs_one_by_one": round(t_single / t_graph, 3),

@@ -282,21 +282,22 @@ adanns_status adanns_batch_run(adanns_batch *batch, const float *Q, float *dist,
 adanns_status adanns_batch_run_graph(adanns_batch *batch, const float *Q, float *dist,
                                      int64_t *ids, void *stream);
 
-/* Scan tile shape: query-tile height tq (32, 64, 128) and persistent grid. */
-adanns_status adanns_batch_set_shape(adanns_batch *batch, int32_t tq, int32_t grid);
+/* Scan tile shape: query-tile height tq (32, 64, 128), vector-tile width tv
+ * (64, 128) and persistent grid. Results do not depend on the shape. */
+adanns_status adanns_batch_set_shape(adanns_batch *batch, int32_t tq, int32_t tv, int32_t grid);
 
-/* Autotuner: times every (tq, grid) candidate on this batch (one warm-up and
+/* Autotuner: times every (tq, tv, grid) candidate on this batch (one warm-up and
  * ``reps`` timed runs each, HIP events), keeps the fastest for the batch and
  * records it in the process-wide autotune cache under the batch's shape key
  * (d_s, nprobe and queries per list, bucketed by powers of two), which
  * adanns_search and adanns_batch_create consult. Writes dist / ids. */
 adanns_status adanns_batch_autotune(adanns_batch *batch, const float *Q, float *dist,
-                                    int64_t *ids, int32_t reps, int32_t *tq, int32_t *grid,
-                                    void *stream);
+                                    int64_t *ids, int32_t reps, int32_t *tq, int32_t *tv,
+                                    int32_t *grid, void *stream);
 
 /* Total queries, current shape and scratch bytes of a batch (NULL-able). */
 adanns_status adanns_batch_info(const adanns_batch *batch, int64_t *queries, int32_t *tq,
-                                int32_t *grid, size_t *scratch_bytes);
+                                int32_t *tv, int32_t *grid, size_t *scratch_bytes);
 
 /* Releases a batch (waits for the device; NULL is a no-op). */
 void adanns_batch_free(adanns_batch *batch);

@@ -43,9 +43,9 @@ _SIGS = {
     "adanns_batch_create": (C.c_int, [vp, i32, i64, i64, vp, PIX]),
     "adanns_batch_run": (C.c_int, [vp, vp, vp, vp, vp, vp]),
     "adanns_batch_run_graph": (C.c_int, [vp, vp, vp, vp, vp]),
-    "adanns_batch_set_shape": (C.c_int, [vp, i32, i32]),
-    "adanns_batch_autotune": (C.c_int, [vp, vp, vp, vp, i32, vp, vp, vp]),
-    "adanns_batch_info": (C.c_int, [vp, vp, vp, vp, vp]),
+    "adanns_batch_set_shape": (C.c_int, [vp, i32, i32, i32]),
+    "adanns_batch_autotune": (C.c_int, [vp, vp, vp, vp, i32, vp, vp, vp, vp]),
+    "adanns_batch_info": (C.c_int, [vp, vp, vp, vp, vp, vp]),
     "adanns_batch_free": (None, [vp]),
     "adanns_autotune_clear": (C.c_int, []),
     "adanns_serve": (C.c_int, [vp, vp, i64, i64, vp, vp, vp, vp, i32, i32, i32, i32, i32,

@@ -46,20 +46,24 @@ class Batch:
                                        _stream(stream)))
         return dist, ids
 
-    def set_shape(self, tq: int, grid: int):
-        check(lib.adanns_batch_set_shape(self._h, tq, grid))
+    def set_shape(self, tq: int, grid: int, tv: int = 64):
+        check(lib.adanns_batch_set_shape(self._h, tq, tv, grid))
 
     def autotune(self, Q, out=None, reps: int = 2, stream=None):
+        """Returns the chosen (tq, tv, grid)."""
         dist, ids = out if out is not None else self.outputs(Q.device)
-        tq, grid = C.c_int32(), C.c_int32()
+        tq, tv, grid = C.c_int32(), C.c_int32(), C.c_int32()
         check(lib.adanns_batch_autotune(self._h, Q.data_ptr(), dist.data_ptr(), ids.data_ptr(),
-                                        reps, C.byref(tq), C.byref(grid), _stream(stream)))
-        return tq.value, grid.value
+                                        reps, C.byref(tq), C.byref(tv), C.byref(grid),
+                                        _stream(stream)))
+        return tq.value, tv.value, grid.value
 
     def info(self):
-        q, tq, grid, sb = C.c_int64(), C.c_int32(), C.c_int32(), C.c_size_t()
-        check(lib.adanns_batch_info(self._h, C.byref(q), C.byref(tq), C.byref(grid), C.byref(sb)))
-        return {"queries": q.value, "tq": tq.value, "grid": grid.value, "scratch_bytes": sb.value}
+        q, tq, tv, grid, sb = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_size_t()
+        check(lib.adanns_batch_info(self._h, C.byref(q), C.byref(tq), C.byref(tv), C.byref(grid),
+                                    C.byref(sb)))
+        return {"queries": q.value, "tq": tq.value, "tv": tv.value, "grid": grid.value,
+                "scratch_bytes": sb.value}
 
     def free(self):
         if self._h is not None and self._h.value:

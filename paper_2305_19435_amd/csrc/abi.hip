@@ -506,9 +506,9 @@ static adanns_status search_common(const adanns_index *cix, const float *Q, int6
   if (!coarse)
     ADANNS_HIP(hipMemcpyAsync(b.probes, given_probes, (size_t)nq * nprobe * sizeof(int32_t),
                               hipMemcpyDeviceToDevice, st));
-  int32_t tq = TILE_Q, grid = PERSIST_WG;
-  tuned_shape(ix, d_s, nprobe, nq, &tq, &grid);
-  ADANNS_HIP(launch_search_multi(b, Q, ldq, dist, ids, k, probes_out, tq, grid, st, coarse));
+  int32_t tq = TILE_Q, tv = TILE_V, grid = PERSIST_WG;
+  tuned_shape(ix, d_s, nprobe, nq, &tq, &tv, &grid);
+  ADANNS_HIP(launch_search_multi(b, Q, ldq, dist, ids, k, probes_out, tq, tv, grid, st, coarse));
   return ADANNS_OK;
 }
 

@@ -16,7 +16,10 @@ namespace adanns {
 // expected number of queries probing a list), since that decides which
 // query-tile height and grid size keep the matrix cores busy.
 static std::mutex g_tune_mu;
-static std::map<std::string, std::pair<int32_t, int32_t>> g_tune;
+struct Shape {
+  int32_t tq, tv, grid;
+};
+static std::map<std::string, Shape> g_tune;
 
 static int log2_bucket(double v) { return v <= 1.0 ? 0 : (int)std::floor(std::log2(v)); }
 
@@ -38,7 +41,7 @@ struct adanns_batch {
   size_t scratch_bytes = 0;
   SearchBufs b{};
   int64_t ldq = 0, ldk = 0;
-  int32_t tq = TILE_Q, grid = PERSIST_WG;
+  int32_t tq = TILE_Q, tv = TILE_V, grid = PERSIST_WG;
   double per_list = 0;      // mean queries per probed list
   int32_t max_ds = 0, max_np = 0;
   hipGraph_t graph = nullptr;
@@ -54,13 +57,14 @@ struct adanns_batch {
 namespace adanns {
 
 void tuned_shape(const adanns_index *ix, int32_t d_s, int32_t nprobe, int64_t nq, int32_t *tq,
-                 int32_t *grid) {
+                 int32_t *tv, int32_t *grid) {
   const double per_list = (double)nq * nprobe / std::max(1, ix->nlist);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(tune_key(d_s, nprobe, per_list));
   if (it != g_tune.end()) {
-    *tq = it->second.first;
-    *grid = it->second.second;
+    *tq = it->second.tq;
+    *tv = it->second.tv;
+    *grid = it->second.grid;
   }
 }
 
@@ -190,8 +194,9 @@ adanns_status adanns_batch_create(const adanns_batch_config *cfgs, int32_t ncfg,
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(tune_key(p->max_ds, p->max_np, p->per_list));
     if (it != g_tune.end()) {
-      p->tq = it->second.first;
-      p->grid = it->second.second;
+      p->tq = it->second.tq;
+      p->tv = it->second.tv;
+      p->grid = it->second.grid;
     }
   }
   *out = p;
@@ -204,8 +209,8 @@ adanns_status adanns_batch_run(adanns_batch *p, const float *Q, float *dist, int
   ADANNS_REQUIRE(p != nullptr, "batch is NULL");
   if (p->b.Qtot == 0) return ADANNS_OK;
   ADANNS_REQUIRE(Q && dist && ids, "Q, dist and ids must be non-NULL");
-  ADANNS_HIP(launch_search_multi(p->b, Q, p->ldq, dist, ids, p->ldk, probes, p->tq, p->grid,
-                                 (hipStream_t)stream, true));
+  ADANNS_HIP(launch_search_multi(p->b, Q, p->ldq, dist, ids, p->ldk, probes, p->tq, p->tv,
+                                 p->grid, (hipStream_t)stream, true));
   return ADANNS_OK;
 }
 
@@ -225,8 +230,8 @@ adanns_status adanns_batch_run_graph(adanns_batch *p, const float *Q, float *dis
   if (!p->exec || p->g_Q != Q || p->g_dist != dist || p->g_ids != ids) {
     drop_graph(p);
     ADANNS_HIP(hipStreamBeginCapture(p->priv, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_search_multi(p->b, Q, p->ldq, dist, ids, p->ldk, nullptr, p->tq, p->grid,
-                                       p->priv, true);
+    hipError_t e = launch_search_multi(p->b, Q, p->ldq, dist, ids, p->ldk, nullptr, p->tq, p->tv,
+                                       p->grid, p->priv, true);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(p->priv, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -248,78 +253,90 @@ adanns_status adanns_batch_run_graph(adanns_batch *p, const float *Q, float *dis
   return ADANNS_OK;
 }
 
-adanns_status adanns_batch_set_shape(adanns_batch *p, int32_t tq, int32_t grid) {
+adanns_status adanns_batch_set_shape(adanns_batch *p, int32_t tq, int32_t tv, int32_t grid) {
   clear_error();
   ADANNS_REQUIRE(p != nullptr, "batch is NULL");
   ADANNS_REQUIRE(tq == 32 || tq == 64 || tq == 128, "tq must be 32, 64 or 128, got %d", tq);
+  ADANNS_REQUIRE(tv == 64 || tv == 128, "tv must be 64 or 128, got %d", tv);
   ADANNS_REQUIRE(grid >= 8 && grid <= 65536, "grid must be in [8, 65536], got %d", grid);
-  if (p->tq != tq || p->grid != grid) drop_graph(p);
+  grid = (int32_t)round_up(grid, 8);
+  if (p->tq != tq || p->tv != tv || p->grid != grid) drop_graph(p);
   p->tq = tq;
-  p->grid = (int32_t)round_up(grid, 8);
+  p->tv = tv;
+  p->grid = grid;
   return ADANNS_OK;
 }
 
 adanns_status adanns_batch_autotune(adanns_batch *p, const float *Q, float *dist, int64_t *ids,
-                                    int32_t reps, int32_t *tq_out, int32_t *grid_out,
-                                    void *stream) {
+                                    int32_t reps, int32_t *tq_out, int32_t *tv_out,
+                                    int32_t *grid_out, void *stream) {
   clear_error();
   ADANNS_REQUIRE(p != nullptr, "batch is NULL");
   ADANNS_REQUIRE(Q && dist && ids, "Q, dist and ids must be non-NULL");
   ADANNS_REQUIRE(reps >= 1 && reps <= 100, "reps must be in [1, 100]");
   hipStream_t st = (hipStream_t)stream;
   static const int32_t tqs[] = {32, 64, 128};
+  static const int32_t tvs[] = {64, 128};
   static const int32_t grids[] = {1024, 2048, 4096};
   hipEvent_t e0, e1;
   ADANNS_HIP(hipEventCreate(&e0));
   ADANNS_HIP(hipEventCreate(&e1));
   float best = 1e30f;
-  int32_t btq = p->tq, bgrid = p->grid;
+  int32_t btq = p->tq, btv = p->tv, bgrid = p->grid;
   for (int32_t tq : tqs) {
-    for (int32_t grid : grids) {
-      // warm-up, then timed repetitions
-      if (launch_search_multi(p->b, Q, p->ldq, dist, ids, p->ldk, nullptr, tq, grid, st, true) ||
-          hipEventRecord(e0, st)) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        set_error("launch failed during autotuning");
-        return ADANNS_EHIP;
-      }
-      for (int32_t r = 0; r < reps; ++r)
-        (void)launch_search_multi(p->b, Q, p->ldq, dist, ids, p->ldk, nullptr, tq, grid, st, true);
-      float ms = 0.f;
-      if (hipEventRecord(e1, st) || hipEventSynchronize(e1) || hipEventElapsedTime(&ms, e0, e1)) {
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        set_error("timing failed during autotuning");
-        return ADANNS_EHIP;
-      }
-      if (ms < best) {
-        best = ms;
-        btq = tq;
-        bgrid = grid;
+    for (int32_t tv : tvs) {
+      for (int32_t grid : grids) {
+        // warm-up, then timed repetitions
+        if (launch_search_multi(p->b, Q, p->ldq, dist, ids, p->ldk, nullptr, tq, tv, grid, st,
+                                true) ||
+            hipEventRecord(e0, st)) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          set_error("launch failed during autotuning");
+          return ADANNS_EHIP;
+        }
+        for (int32_t r = 0; r < reps; ++r)
+          (void)launch_search_multi(p->b, Q, p->ldq, dist, ids, p->ldk, nullptr, tq, tv, grid, st,
+                                    true);
+        float ms = 0.f;
+        if (hipEventRecord(e1, st) || hipEventSynchronize(e1) || hipEventElapsedTime(&ms, e0, e1)) {
+          (void)hipEventDestroy(e0);
+          (void)hipEventDestroy(e1);
+          set_error("timing failed during autotuning");
+          return ADANNS_EHIP;
+        }
+        if (ms < best) {
+          best = ms;
+          btq = tq;
+          btv = tv;
+          bgrid = grid;
+        }
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (p->tq != btq || p->grid != bgrid) drop_graph(p);
+  if (p->tq != btq || p->tv != btv || p->grid != bgrid) drop_graph(p);
   p->tq = btq;
+  p->tv = btv;
   p->grid = bgrid;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[tune_key(p->max_ds, p->max_np, p->per_list)] = {btq, bgrid};
+    g_tune[tune_key(p->max_ds, p->max_np, p->per_list)] = {btq, btv, bgrid};
   }
   if (tq_out) *tq_out = btq;
+  if (tv_out) *tv_out = btv;
   if (grid_out) *grid_out = bgrid;
   return ADANNS_OK;
 }
 
 adanns_status adanns_batch_info(const adanns_batch *p, int64_t *queries, int32_t *tq,
-                                int32_t *grid, size_t *scratch_bytes) {
+                                int32_t *tv, int32_t *grid, size_t *scratch_bytes) {
   clear_error();
   ADANNS_REQUIRE(p != nullptr, "batch is NULL");
   if (queries) *queries = p->b.Qtot;
   if (tq) *tq = p->tq;
+  if (tv) *tv = p->tv;
   if (grid) *grid = p->grid;
   if (scratch_bytes) *scratch_bytes = p->scratch_bytes;
   return ADANNS_OK;

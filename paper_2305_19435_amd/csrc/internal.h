@@ -195,7 +195,7 @@ hipError_t launch_store_cfg(const CfgDev &c, CfgDev *dst, hipStream_t st);
 // Scan tile shape from the autotune cache for this search shape (unchanged
 // if the shape has not been tuned).
 void tuned_shape(const adanns_index *ix, int32_t d_s, int32_t nprobe, int64_t nq, int32_t *tq,
-                 int32_t *grid);
+                 int32_t *tv, int32_t *grid);
 // Single-configuration helpers (the descriptor is written into b.cfg first).
 hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq, int32_t d_c,
                          int32_t nprobe, int32_t *user_probes, hipStream_t st,
@@ -205,7 +205,7 @@ hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq
 // of persistent workgroups. Enqueue only: no allocation, no host sync.
 hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq, float *dist,
                                int64_t *ids, int64_t ldk, int32_t *user_probes, int32_t tq,
-                               int32_t grid, hipStream_t st, bool do_coarse = true);
+                               int32_t tv, int32_t grid, hipStream_t st, bool do_coarse = true);
 hipError_t launch_stage_rows(const float *X, int64_t ldx, const int64_t *rows,
                              const int32_t *rows32, int64_t nrows, int32_t dcols, float *out,
                              int64_t ldo, hipStream_t st);

@@ -200,30 +200,35 @@ struct TileArgs {
   int32_t ct_total;        // coarse: tiles over configurations
 };
 
-// One 64-vector tile of a list against TQ query rows:
+// One TV-vector tile of a list against TQ query rows:
 // out[rbase[row] + v] = |x_v[:d]|^2 - 2 q_row[:d] . x_v[:d] for valid rows/vectors.
-// rq[] holds the staged-query row of each tile row (-1 = none).
-template <int TQ>
+// rq[] holds the staged-query row of each tile row (-1 = none). Four waves
+// in a 2 x 2 grid, each computing (TQ/2) x (TV/2) with 16x16x4 FP32 MFMA.
+template <int TQ, int TV>
 __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64_t ldqs,
                                              const float *vp, int64_t npad, int nvec_left,
                                              int d_dot, const int32_t *rq, const int64_t *rbase,
                                              float *__restrict__ out, float (*As)[SLAB + 4],
                                              float (*Bs)[SLAB + 4], float *cn) {
   constexpr int NA = TQ / 32;        // float4 of A per thread per slab
+  constexpr int NBV = TV / 32;       // float4 of B per thread per slab
   constexpr int NB = TQ / 32;        // MFMA row blocks per wave
+  constexpr int NC = TV / 32;        // MFMA column blocks per wave
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int rbw = (wv >> 1) * (TQ / 2), cbw = (wv & 1) * 32;
+  const int rbw = (wv >> 1) * (TQ / 2), cbw = (wv & 1) * (TV / 2);
   const int fr = lane & 15, fk = (lane >> 4) * 8;
   const int lr = tid >> 3, lc = (tid & 7) * 4;
   const int nslab = (d_dot + SLAB - 1) / SLAB;
 
-  floatx4 acc[NB][2];
+  floatx4 acc[NB][NC];
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
-  float nrm0 = 0.f, nrm1 = 0.f;
-  float4 ra[NA], rb0, rb1;
+    for (int j = 0; j < NC; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+  float nrm[NBV];
+#pragma unroll
+  for (int u = 0; u < NBV; ++u) nrm[u] = 0.f;
+  float4 ra[NA], rb[NBV];
   const float *qp[NA];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
@@ -245,8 +250,8 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
       ra[u] = v;
     }
     const float *src = vp + (int64_t)s * npad * SLAB;
-    rb0 = *(const float4 *)(src + lr * SLAB + lc);
-    rb1 = *(const float4 *)(src + (lr + 32) * SLAB + lc);
+#pragma unroll
+    for (int u = 0; u < NBV; ++u) rb[u] = *(const float4 *)(src + (lr + 32 * u) * SLAB + lc);
   };
 
   load(0);
@@ -254,24 +259,22 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NA; ++u) *(float4 *)&As[lr + 32 * u][lc] = ra[u];
-    *(float4 *)&Bs[lr][lc] = rb0;
-    *(float4 *)&Bs[lr + 32][lc] = rb1;
+#pragma unroll
+    for (int u = 0; u < NBV; ++u) *(float4 *)&Bs[lr + 32 * u][lc] = rb[u];
     {  // vector norms over the same prefix, from the registers just stored
       const int dim = s * SLAB + lc;
-      const float x[4] = {rb0.x, rb0.y, rb0.z, rb0.w};
-      const float y[4] = {rb1.x, rb1.y, rb1.z, rb1.w};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (dim + e < d_dot) {
-          nrm0 += x[e] * x[e];
-          nrm1 += y[e] * y[e];
-        }
+      for (int u = 0; u < NBV; ++u) {
+        const float x[4] = {rb[u].x, rb[u].y, rb[u].z, rb[u].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (dim + e < d_dot) nrm[u] += x[e] * x[e];
       }
     }
     __syncthreads();
     if (s + 1 < nslab) load(s + 1);
 
-    float af[NB][8], bf[2][8];
+    float af[NB][8], bf[NC][8];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const float4 x0 = *(const float4 *)&As[rbw + i * 16 + fr][fk];
@@ -280,7 +283,7 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
       af[i][4] = x1.x; af[i][5] = x1.y; af[i][6] = x1.z; af[i][7] = x1.w;
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NC; ++j) {
       const float4 x0 = *(const float4 *)&Bs[cbw + j * 16 + fr][fk];
       const float4 x1 = *(const float4 *)&Bs[cbw + j * 16 + fr][fk + 4];
       bf[j][0] = x0.x; bf[j][1] = x0.y; bf[j][2] = x0.z; bf[j][3] = x0.w;
@@ -293,25 +296,23 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
 #pragma unroll
       for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NC; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kb], bf[j][kb], acc[i][j], 0, 0, 0);
   }
-  nrm0 += __shfl_xor(nrm0, 1);
-  nrm0 += __shfl_xor(nrm0, 2);
-  nrm0 += __shfl_xor(nrm0, 4);
-  nrm1 += __shfl_xor(nrm1, 1);
-  nrm1 += __shfl_xor(nrm1, 2);
-  nrm1 += __shfl_xor(nrm1, 4);
-  if ((tid & 7) == 0) {
-    cn[lr] = nrm0;
-    cn[lr + 32] = nrm1;
+  // norms: 8 consecutive threads share a vector row
+#pragma unroll
+  for (int u = 0; u < NBV; ++u) {
+    nrm[u] += __shfl_xor(nrm[u], 1);
+    nrm[u] += __shfl_xor(nrm[u], 2);
+    nrm[u] += __shfl_xor(nrm[u], 4);
+    if ((tid & 7) == 0) cn[lr + 32 * u] = nrm[u];
   }
   __syncthreads();
   // 16x16 f32 MFMA result: lane holds column (lane & 15), rows 4*(lane>>4)+e
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NC; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int row = rbw + i * 16 + (lane >> 4) * 4 + e;
@@ -323,13 +324,13 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
 // Persistent tile kernel over a batch. COARSE: every configuration's queries
 // against its centroids (tiles numbered per configuration); otherwise every
 // virtual list against the queries probing it.
-template <int TQ, int COARSE>
+template <int TQ, int TV, int COARSE>
 __global__ __launch_bounds__(256) void k_tile_multi(TileArgs a) {
   __shared__ __attribute__((aligned(16))) float As[TQ][SLAB + 4];
-  __shared__ __attribute__((aligned(16))) float Bs[TILE_V][SLAB + 4];
+  __shared__ __attribute__((aligned(16))) float Bs[TV][SLAB + 4];
   __shared__ int64_t rbase[TQ];
   __shared__ int32_t rq[TQ];
-  __shared__ float cn[TILE_V];
+  __shared__ float cn[TV];
   const int tid = threadIdx.x;
   const int total = COARSE ? a.ct_total : a.tile_off[a.V];
   const int G = gridDim.x;
@@ -393,9 +394,8 @@ __global__ __launch_bounds__(256) void k_tile_multi(TileArgs a) {
       }
     }
     __syncthreads();
-    tile_compute<TQ>(a.Qs, a.ldqs, vbase + (int64_t)vt * TILE_V * SLAB, npad,
-                     nvec - vt * TILE_V, d_dot, rq, rbase,
-                     (COARSE ? a.S : a.D) + (int64_t)vt * TILE_V, As, Bs, cn);
+    tile_compute<TQ, TV>(a.Qs, a.ldqs, vbase + (int64_t)vt * TV * SLAB, npad, nvec - vt * TV,
+                         d_dot, rq, rbase, (COARSE ? a.S : a.D) + (int64_t)vt * TV, As, Bs, cn);
   }
 }
 
@@ -1419,7 +1419,8 @@ __global__ void k_count(const int32_t *__restrict__ probes, int64_t npairs, cons
 // height tq x 64-vector tiles per virtual list), cursor reset.
 __global__ __launch_bounds__(1024) void k_list_scan(const int32_t *__restrict__ cnt,
                                                     const CfgDev *cfg, int32_t ncfg, int32_t V,
-                                                    int32_t tq, int32_t *__restrict__ bkt_off,
+                                                    int32_t tq, int32_t tv,
+                                                    int32_t *__restrict__ bkt_off,
                                                     int32_t *__restrict__ tile_off,
                                                     int32_t *__restrict__ cursor) {
   __shared__ int32_t sh[16];
@@ -1429,7 +1430,7 @@ __global__ __launch_bounds__(1024) void k_list_scan(const int32_t *__restrict__ 
   auto tiles = [&](int v) {
     const int c = cfg_of(cfg, ncfg, &CfgDev::vl0, v);
     const int32_t len = cfg[c].len[v - cfg[c].vl0];
-    return ((cnt[v] + tq - 1) / tq) * ((len + TILE_V - 1) / TILE_V);
+    return ((cnt[v] + tq - 1) / tq) * ((len + tv - 1) / tv);
   };
   int32_t sc = 0, st = 0;
   for (int v = v0; v < v1; ++v) {
@@ -1652,7 +1653,7 @@ static hipError_t coarse_multi(const SearchBufs &b, int32_t *user_probes, float 
   const int grid = (int)std::min<int64_t>(grid_cap, round_up(b.ct_total, 8));
   {
     KernelTimer tm("tile_dist_coarse", st);
-    hipLaunchKernelGGL((k_tile_multi<TILE_Q, 1>), dim3(grid), dim3(256), 0, st, t);
+    hipLaunchKernelGGL((k_tile_multi<TILE_Q, TILE_V, 1>), dim3(grid), dim3(256), 0, st, t);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1676,13 +1677,13 @@ static hipError_t coarse_multi(const SearchBufs &b, int32_t *user_probes, float 
   return hipGetLastError();
 }
 
-static hipError_t bucketing_multi(const SearchBufs &b, int32_t tq, hipStream_t st) {
+static hipError_t bucketing_multi(const SearchBufs &b, int32_t tq, int32_t tv, hipStream_t st) {
   KernelTimer tmb("bucketing", st);
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(b.V, 256)), dim3(256), 0, st, b.cnt,
                      (int64_t)b.V, 0);
   hipLaunchKernelGGL(k_count, dim3(blocks_for(b.pairs, 256)), dim3(256), 0, st, b.probes, b.pairs,
                      b.cfg, b.ncfg, b.cnt);
-  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, st, b.cnt, b.cfg, b.ncfg, b.V, tq,
+  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, st, b.cnt, b.cfg, b.ncfg, b.V, tq, tv,
                      b.bkt_off, b.tile_off, b.cursor);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(b.pairs, 256)), dim3(256), 0, st, b.probes,
                      b.pairs, b.cfg, b.ncfg, b.bkt_off, b.cursor, b.bucket);
@@ -1718,17 +1719,19 @@ hipError_t launch_bucketing(const adanns_index *ix, const SearchBufs &b, int64_t
   bb.V = ix->nlist;
   bb.Qtot = nq;
   bb.pairs = nq * nprobe;
-  return bucketing_multi(bb, TILE_Q, st);
+  return bucketing_multi(bb, TILE_Q, TILE_V, st);
 }
 
-template <int TQ>
+template <int TQ, int TV>
 static void launch_scan_tiles(const TileArgs &t, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_tile_multi<TQ, 0>), dim3(grid), dim3(256), 0, st, t);
+  hipLaunchKernelGGL((k_tile_multi<TQ, TV, 0>), dim3(grid), dim3(256), 0, st, t);
 }
 
 hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq, float *dist,
                                int64_t *ids, int64_t ldk, int32_t *user_probes, int32_t tq,
-                               int32_t grid, hipStream_t st, bool do_coarse) {
+                               int32_t tv, int32_t grid, hipStream_t st, bool do_coarse) {
+  if (tq != 32 && tq != 128) tq = 64;
+  if (tv != 128) tv = 64;
   {
     const int64_t n = b.Qtot * b.ldqs;
     KernelTimer tm("stage_queries", st);
@@ -1739,7 +1742,7 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
   if (e != hipSuccess) return e;
   if (do_coarse && (e = coarse_multi(b, user_probes, nullptr, PERSIST_WG, st)) != hipSuccess)
     return e;
-  if ((e = bucketing_multi(b, tq, st)) != hipSuccess) return e;
+  if ((e = bucketing_multi(b, tq, tv, st)) != hipSuccess) return e;
   TileArgs t{};
   t.cfg = b.cfg;
   t.ncfg = b.ncfg;
@@ -1755,12 +1758,15 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
   grid = (int)round_up(std::max(8, grid), 8);
   {
     KernelTimer tm("tile_dist_scan", st);
-    if (tq == 32)
-      launch_scan_tiles<32>(t, grid, st);
-    else if (tq == 128)
-      launch_scan_tiles<128>(t, grid, st);
-    else
-      launch_scan_tiles<64>(t, grid, st);
+    if (tv == 128) {
+      if (tq == 32) launch_scan_tiles<32, 128>(t, grid, st);
+      else if (tq == 128) launch_scan_tiles<128, 128>(t, grid, st);
+      else launch_scan_tiles<64, 128>(t, grid, st);
+    } else {
+      if (tq == 32) launch_scan_tiles<32, 64>(t, grid, st);
+      else if (tq == 128) launch_scan_tiles<128, 64>(t, grid, st);
+      else launch_scan_tiles<64, 64>(t, grid, st);
+    }
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   SelMultiArgs m{};

@@ -68,13 +68,14 @@ def test_batch_equals_alone_all_shapes(lib, setup):
     batch = lib.Batch([(indices[c[0]][0], c[3], c[0], c[1], c[2], k) for c in configs], ldq=128)
     Qd = torch.from_numpy(Qall).cuda()
     for tq in (32, 64, 128):
-        for grid in (8, 1024):
-            batch.set_shape(tq, grid)
-            dist, ids = batch.run(Qd)
-            torch.cuda.synchronize()
-            got = _split(dist.cpu().numpy(), ids.cpu().numpy(), configs, k)
-            for (gd, gi), (ad, ai) in zip(got, alone):
-                assert np.array_equal(gi, ai) and np.array_equal(gd, ad), (tq, grid)
+        for tv in (64, 128):
+            for grid in (8, 1024):
+                batch.set_shape(tq, grid, tv)
+                dist, ids = batch.run(Qd)
+                torch.cuda.synchronize()
+                got = _split(dist.cpu().numpy(), ids.cpu().numpy(), configs, k)
+                for (gd, gi), (ad, ai) in zip(got, alone):
+                    assert np.array_equal(gi, ai) and np.array_equal(gd, ad), (tq, tv, grid)
     batch.free()
 
 
@@ -106,8 +107,8 @@ def test_autotune_keeps_results_and_parity(lib, setup):
     alone = _alone(indices, configs, Qall, k)
     batch = lib.Batch([(indices[c[0]][0], c[3], c[0], c[1], c[2], k) for c in configs], ldq=128)
     Qd = torch.from_numpy(Qall).cuda()
-    tq, grid = batch.autotune(Qd, reps=1)
-    assert tq in (32, 64, 128) and grid in (1024, 2048, 4096)
+    tq, tv, grid = batch.autotune(Qd, reps=1)
+    assert tq in (32, 64, 128) and tv in (64, 128) and grid in (1024, 2048, 4096)
     dist, ids = batch.run(Qd)
     torch.cuda.synchronize()
     got = _split(dist.cpu().numpy(), ids.cpu().numpy(), configs, k)
