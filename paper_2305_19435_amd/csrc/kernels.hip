@@ -28,6 +28,23 @@ namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+// Loads through a pointer that the compiler cannot prove global (one read
+// from a configuration record in memory, or chosen between LDS and global
+// memory) become flat loads, which also hold the LDS wait counter: every
+// LDS wait then waits for them too and prefetches stop overlapping. ldg
+// reads such a pointer as global memory.
+#define ADANNS_GLOBAL_AS __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ T ldg(const T *p) {
+  return *(const T ADANNS_GLOBAL_AS *)p;
+}
+// float4 is a class type whose copy goes through a generic reference, so the
+// 16-byte load is made on the native vector type.
+__device__ __forceinline__ float4 ldg4(const float *p) {
+  const floatx4 v = *(const floatx4 ADANNS_GLOBAL_AS *)p;
+  return make_float4(v[0], v[1], v[2], v[3]);
+}
+
 // Monotone map from float to uint32 (total order, -0 < +0).
 __device__ __forceinline__ uint32_t order_key(float f) {
   uint32_t u = __float_as_uint(f);
@@ -200,22 +217,32 @@ struct TileArgs {
   int32_t ct_total;        // coarse: tiles over configurations
 };
 
+__device__ __forceinline__ float f4(const float4 &v, int e) {
+  return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+}
+
 // One TV-vector tile of a list against TQ query rows:
 // out[rbase[row] + v] = |x_v[:d]|^2 - 2 q_row[:d] . x_v[:d] for valid rows/vectors.
-// rq[] holds the staged-query row of each tile row (-1 = none). Four waves
-// in a 2 x 2 grid, each computing (TQ/2) x (TV/2) with 16x16x4 FP32 MFMA.
+// rq[] holds the staged-query row of each tile row (-1 = none); the valid
+// rows are the first nrow. Four waves in a 2 x 2 grid, each computing
+// (TQ/2) x (TV/2) with 16x16x4 FP32 MFMA.
 template <int TQ, int TV>
 __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64_t ldqs,
                                              const float *vp, int64_t npad, int nvec_left,
-                                             int d_dot, const int32_t *rq, const int64_t *rbase,
-                                             float *__restrict__ out, float (*As)[SLAB + 4],
-                                             float (*Bs)[SLAB + 4], float *cn) {
+                                             int nrow, int d_dot, const int32_t *rq,
+                                             const int64_t *rbase, float *__restrict__ out,
+                                             float (*As)[SLAB + 4], float (*Bs)[SLAB + 4],
+                                             float *cn) {
   constexpr int NA = TQ / 32;        // float4 of A per thread per slab
   constexpr int NBV = TV / 32;       // float4 of B per thread per slab
   constexpr int NB = TQ / 32;        // MFMA row blocks per wave
   constexpr int NC = TV / 32;        // MFMA column blocks per wave
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int rbw = (wv >> 1) * (TQ / 2), cbw = (wv & 1) * (TV / 2);
+  const int ncol = nvec_left < TV ? nvec_left : TV;
+  // a wave whose rows or vectors all lie past the valid ones skips its MFMAs
+  const bool active = nrow > rbw && ncol > cbw;
   const int fr = lane & 15, fk = (lane >> 4) * 8;
   const int lr = tid >> 3, lc = (tid & 7) * 4;
   const int nslab = (d_dot + SLAB - 1) / SLAB;
@@ -228,76 +255,85 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
   float nrm[NBV];
 #pragma unroll
   for (int u = 0; u < NBV; ++u) nrm[u] = 0.f;
+  // Loads are unconditional so that they stay in flight across the MFMAs of
+  // the previous slab: a row past the tile's valid queries reads staged row 0
+  // and a vector past the list's length re-reads its last vector (the list's
+  // padding ends at a multiple of ROWPAD, which a TV = 128 tile can overrun);
+  // neither result is written out. Coordinates past d_dot are zeroed when
+  // the query slab is staged into LDS.
   float4 ra[NA], rb[NBV];
   const float *qp[NA];
 #pragma unroll
   for (int u = 0; u < NA; ++u) {
     const int q = rq[lr + 32 * u];
-    qp[u] = q >= 0 ? Qs + (int64_t)q * ldqs : nullptr;
+    qp[u] = Qs + (int64_t)(q >= 0 ? q : 0) * ldqs + lc;
   }
+  int vrow[NBV];
+#pragma unroll
+  for (int u = 0; u < NBV; ++u) vrow[u] = min(lr + 32 * u, ncol - 1) * SLAB + lc;
 
   auto load = [&](int s) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) ra[u] = ldg4(qp[u] + s * SLAB);
+    const float *src = vp + (int64_t)s * npad * SLAB;
+#pragma unroll
+    for (int u = 0; u < NBV; ++u) rb[u] = ldg4(src + vrow[u]);
+  };
+
+  // Registers -> LDS: slab s + 1 is in flight while slab s is multiplied.
+  // (A second LDS stage, prefetching one slab further, measured slower.)
+  auto stage = [&](int s) {
     const int dim = s * SLAB + lc;
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
-      float4 v = qp[u] ? *(const float4 *)(qp[u] + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 v = ra[u];
       if (dim + 4 > d_dot) {
         if (dim + 0 >= d_dot) v.x = 0.f;
         if (dim + 1 >= d_dot) v.y = 0.f;
         if (dim + 2 >= d_dot) v.z = 0.f;
         if (dim + 3 >= d_dot) v.w = 0.f;
       }
-      ra[u] = v;
+      *(float4 *)&As[lr + 32 * u][lc] = v;
     }
-    const float *src = vp + (int64_t)s * npad * SLAB;
 #pragma unroll
-    for (int u = 0; u < NBV; ++u) rb[u] = *(const float4 *)(src + (lr + 32 * u) * SLAB + lc);
+    for (int u = 0; u < NBV; ++u) *(float4 *)&Bs[lr + 32 * u][lc] = rb[u];
+    // vector norms over the same prefix, from the registers just stored
+#pragma unroll
+    for (int u = 0; u < NBV; ++u) {
+      const float x[4] = {rb[u].x, rb[u].y, rb[u].z, rb[u].w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (dim + e < d_dot) nrm[u] += x[e] * x[e];
+    }
   };
 
   load(0);
   for (int s = 0; s < nslab; ++s) {
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < NA; ++u) *(float4 *)&As[lr + 32 * u][lc] = ra[u];
-#pragma unroll
-    for (int u = 0; u < NBV; ++u) *(float4 *)&Bs[lr + 32 * u][lc] = rb[u];
-    {  // vector norms over the same prefix, from the registers just stored
-      const int dim = s * SLAB + lc;
-#pragma unroll
-      for (int u = 0; u < NBV; ++u) {
-        const float x[4] = {rb[u].x, rb[u].y, rb[u].z, rb[u].w};
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (dim + e < d_dot) nrm[u] += x[e] * x[e];
-      }
-    }
+    stage(s);
     __syncthreads();
     if (s + 1 < nslab) load(s + 1);
-
-    float af[NB][8], bf[NC][8];
+    if (active) {
+      // two halves of the slab: MFMA k-slot (lane >> 4) carries coordinate
+      // 8 * (lane >> 4) + 4 * half + kb for both operands, so every
+      // coordinate of the slab is used exactly once
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const float4 x0 = *(const float4 *)&As[rbw + i * 16 + fr][fk];
-      const float4 x1 = *(const float4 *)&As[rbw + i * 16 + fr][fk + 4];
-      af[i][0] = x0.x; af[i][1] = x0.y; af[i][2] = x0.z; af[i][3] = x0.w;
-      af[i][4] = x1.x; af[i][5] = x1.y; af[i][6] = x1.z; af[i][7] = x1.w;
+      for (int half = 0; half < 2; ++half) {
+        float4 af[NB], bf[NC];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) af[i] = *(const float4 *)&As[rbw + i * 16 + fr][fk + 4 * half];
+#pragma unroll
+        for (int j = 0; j < NC; ++j) bf[j] = *(const float4 *)&Bs[cbw + j * 16 + fr][fk + 4 * half];
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+          for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int j = 0; j < NC; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(f4(af[i], kb), f4(bf[j], kb),
+                                                               acc[i][j], 0, 0, 0);
+      }
     }
-#pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      const float4 x0 = *(const float4 *)&Bs[cbw + j * 16 + fr][fk];
-      const float4 x1 = *(const float4 *)&Bs[cbw + j * 16 + fr][fk + 4];
-      bf[j][0] = x0.x; bf[j][1] = x0.y; bf[j][2] = x0.z; bf[j][3] = x0.w;
-      bf[j][4] = x1.x; bf[j][5] = x1.y; bf[j][6] = x1.z; bf[j][7] = x1.w;
-    }
-    // MFMA k-slot (lane >> 4) carries coordinate 8 * (lane >> 4) + kb for
-    // both operands, so every coordinate of the slab is used exactly once.
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-#pragma unroll
-        for (int j = 0; j < NC; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][kb], bf[j][kb], acc[i][j], 0, 0, 0);
   }
   // norms: 8 consecutive threads share a vector row
 #pragma unroll
@@ -321,11 +357,12 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
       }
 }
 
-// Persistent tile kernel over a batch. COARSE: every configuration's queries
+// Persistent tile kernel over a batch (two workgroups per CU: the register
+// budget is held to 256 per lane). COARSE: every configuration's queries
 // against its centroids (tiles numbered per configuration); otherwise every
 // virtual list against the queries probing it.
 template <int TQ, int TV, int COARSE>
-__global__ __launch_bounds__(256) void k_tile_multi(TileArgs a) {
+__global__ __launch_bounds__(256, 2) void k_tile_multi(TileArgs a) {
   __shared__ __attribute__((aligned(16))) float As[TQ][SLAB + 4];
   __shared__ __attribute__((aligned(16))) float Bs[TV][SLAB + 4];
   __shared__ int64_t rbase[TQ];
@@ -365,9 +402,9 @@ __global__ __launch_bounds__(256) void k_tile_multi(TileArgs a) {
       const CfgDev &g = a.cfg[c];
       h = v - g.vl0;
       m = a.cnt[v];
-      nvec = g.len[h];
-      const int64_t p0 = g.poff[h];
-      npad = g.poff[h + 1] - p0;
+      nvec = ldg(g.len + h);
+      const int64_t p0 = ldg(g.poff + h);
+      npad = ldg(g.poff + h + 1) - p0;
       const int qts = (m + TQ - 1) / TQ;
       const int rem = w - a.tile_off[v];
       qt = rem % qts;
@@ -395,7 +432,8 @@ __global__ __launch_bounds__(256) void k_tile_multi(TileArgs a) {
     }
     __syncthreads();
     tile_compute<TQ, TV>(a.Qs, a.ldqs, vbase + (int64_t)vt * TV * SLAB, npad, nvec - vt * TV,
-                         d_dot, rq, rbase, (COARSE ? a.S : a.D) + (int64_t)vt * TV, As, Bs, cn);
+                         min(TQ, m - qt * TQ), d_dot, rq, rbase,
+                         (COARSE ? a.S : a.D) + (int64_t)vt * TV, As, Bs, cn);
   }
 }
 
@@ -499,13 +537,24 @@ __device__ __forceinline__ float bf16_to_float(uint16_t b) {
 }
 
 // Quantised value (as an exact pair) of coordinate ``i`` of a quantised row.
-__device__ __forceinline__ void quant_value(int32_t fmt, const void *base, int64_t idx, float scale,
+template <class P>
+__device__ __forceinline__ void quant_value(int32_t fmt, P base, int64_t idx, float scale,
                                             float &hi, float &lo) {
   if (fmt == 1) {
-    hi = bf16_to_float(((const uint16_t *)base)[idx]);
+    hi = bf16_to_float(ldg((const uint16_t *)base + idx));
     lo = 0.f;
   } else {
-    two_prod(scale, e4m3_to_float(((const uint8_t *)base)[idx]), hi, lo);
+    two_prod(scale, e4m3_to_float(ldg((const uint8_t *)base + idx)), hi, lo);
+  }
+}
+// The staged quantised query row in LDS.
+__device__ __forceinline__ void quant_value(int32_t fmt, const uint8_t *lds, int64_t idx,
+                                            float scale, float &hi, float &lo, bool) {
+  if (fmt == 1) {
+    hi = bf16_to_float(((const uint16_t *)lds)[idx]);
+    lo = 0.f;
+  } else {
+    two_prod(scale, e4m3_to_float(lds[idx]), hi, lo);
   }
 }
 
@@ -590,82 +639,102 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
         }
       }
     }
-    const float *src = staged ? segbuf : seg;
-    // key range of the segment
-    uint32_t kmin = 0xffffffffu, kmax = 0u;
-    if (tid == 0) {
-      s_min = 0xffffffffu;
-      s_max = 0u;
-    }
-    __syncthreads();
-    for (int64_t i = tid; i < L; i += blockDim.x) {
-      const uint32_t kk = order_key(src[i]);
-      kmin = kk < kmin ? kk : kmin;
-      kmax = kk > kmax ? kk : kmax;
-    }
-    atomicMin(&s_min, kmin);
-    atomicMax(&s_max, kmax);
-    __syncthreads();
-    // radix selection of the K1-th smallest key over an adaptive window
-    // [lo, hi): each pass splits the window into at most 2048 bins
-    uint64_t lo = s_min, hi = (uint64_t)s_max + 1;
-    uint32_t need = (uint32_t)a.K1;
-    uint32_t T = 0;
-    for (int pass = 0; pass < 4; ++pass) {
-      const uint64_t width = hi - lo;
-      const int shift = width <= 2048 ? 0 : (64 - __clzll((long long)(width - 1))) - 11;
-      for (int i = tid; i < 2048; i += blockDim.x) hist[i] = 0;
+    // The segment is read from LDS or from global memory; the generic lambda
+    // is instantiated for each so that neither becomes a flat access.
+    auto select_from = [&](auto src) {
+      // key range of the segment
+      uint32_t kmin = 0xffffffffu, kmax = 0u;
+      if (tid == 0) {
+        s_min = 0xffffffffu;
+        s_max = 0u;
+      }
       __syncthreads();
       for (int64_t i = tid; i < L; i += blockDim.x) {
-        const uint64_t kk = order_key(src[i]);
-        if (kk >= lo && kk < hi) atomicAdd(&hist[(uint32_t)((kk - lo) >> shift)], 1u);
+        const uint32_t kk = order_key(src[i]);
+        kmin = kk < kmin ? kk : kmin;
+        kmax = kk > kmax ? kk : kmax;
       }
+      atomicMin(&s_min, kmin);
+      atomicMax(&s_max, kmax);
       __syncthreads();
-      const int per = 2048 / blockDim.x;
-      uint32_t local = 0;
-      for (int e = 0; e < per; ++e) local += hist[tid * per + e];
-      uint32_t excl = block_excl_scan<uint32_t>(local, sh32, nullptr);
-      if (excl < need && need <= excl + local) {
-        uint32_t c = excl;
-        for (int e = 0; e < per; ++e) {
-          uint32_t hb = hist[tid * per + e];
-          if (c + hb >= need) {
-            s_bin = (uint32_t)(tid * per + e);
-            s_before = c;
-            break;
+      // radix selection of the K1-th smallest key over an adaptive window
+      // [lo, hi): each pass splits the window into at most 2048 bins; the
+      // last pass has unit bins, so T is exact and hist[s_bin] counts the
+      // keys equal to T
+      uint64_t lo = s_min, hi = (uint64_t)s_max + 1;
+      uint32_t need = (uint32_t)a.K1;
+      for (int pass = 0; pass < 4; ++pass) {
+        const uint64_t width = hi - lo;
+        const int shift = width <= 2048 ? 0 : (64 - __clzll((long long)(width - 1))) - 11;
+        for (int i = tid; i < 2048; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        for (int64_t i = tid; i < L; i += blockDim.x) {
+          const uint64_t kk = order_key(src[i]);
+          if (kk >= lo && kk < hi) atomicAdd(&hist[(uint32_t)((kk - lo) >> shift)], 1u);
+        }
+        __syncthreads();
+        const int per = 2048 / blockDim.x;
+        uint32_t local = 0;
+        for (int e = 0; e < per; ++e) local += hist[tid * per + e];
+        uint32_t excl = block_excl_scan<uint32_t>(local, sh32, nullptr);
+        if (excl < need && need <= excl + local) {
+          uint32_t c = excl;
+          for (int e = 0; e < per; ++e) {
+            uint32_t hb = hist[tid * per + e];
+            if (c + hb >= need) {
+              s_bin = (uint32_t)(tid * per + e);
+              s_before = c;
+              break;
+            }
+            c += hb;
           }
-          c += hb;
+        }
+        __syncthreads();
+        const uint64_t nlo = lo + ((uint64_t)s_bin << shift);
+        const uint64_t nhi = nlo + ((uint64_t)1 << shift);
+        need -= s_before;
+        lo = nlo;
+        hi = nhi < hi ? nhi : hi;
+        __syncthreads();
+        if (shift == 0) break;
+      }
+      const uint32_t T = (uint32_t)lo;
+      const uint32_t n_eq = hist[s_bin];
+      if (tid == 0) s_slot = 0;
+      __syncthreads();
+      if (n_eq == need) {
+        // every key equal to T is taken: one coalesced pass, any slot order
+        for (int64_t i = tid; i < L; i += blockDim.x) {
+          if (order_key(src[i]) <= T) {
+            const int slot = atomicAdd(&s_slot, 1);
+            cpos[slot] = i;
+          }
+        }
+      } else {
+        // take every key below T and the first ``need`` equal ones in
+        // position order
+        const int64_t chunk = (L + blockDim.x - 1) / blockDim.x;
+        const int64_t a0 = tid * chunk, a1 = min64(L, a0 + chunk);
+        uint32_t ne = 0;
+        for (int64_t i = a0; i < a1; ++i) ne += order_key(src[i]) == T;
+        uint32_t eq_before = block_excl_scan<uint32_t>(ne, sh32, nullptr);
+        const int nlt = a.K1 - (int)need;
+        for (int64_t i = a0; i < a1; ++i) {
+          uint32_t kk = order_key(src[i]);
+          if (kk < T) {
+            int slot = atomicAdd(&s_slot, 1);
+            cpos[slot] = i;
+          } else if (kk == T) {
+            if (eq_before < need) cpos[nlt + eq_before] = i;
+            ++eq_before;
+          }
         }
       }
-      __syncthreads();
-      const uint64_t nlo = lo + ((uint64_t)s_bin << shift);
-      const uint64_t nhi = nlo + ((uint64_t)1 << shift);
-      need -= s_before;
-      lo = nlo;
-      hi = nhi < hi ? nhi : hi;
-      __syncthreads();
-      if (shift == 0) break;
-    }
-    T = (uint32_t)lo;
-    // take every key below T and the first ``need`` equal ones in position order
-    const int64_t chunk = (L + blockDim.x - 1) / blockDim.x;
-    const int64_t a0 = tid * chunk, a1 = min64(L, a0 + chunk);
-    uint32_t ne = 0;
-    for (int64_t i = a0; i < a1; ++i) ne += order_key(src[i]) == T;
-    uint32_t eq_before = block_excl_scan<uint32_t>(ne, sh32, nullptr);
-    if (tid == 0) s_slot = 0;
-    __syncthreads();
-    const int nlt = a.K1 - (int)need;
-    for (int64_t i = a0; i < a1; ++i) {
-      uint32_t kk = order_key(src[i]);
-      if (kk < T) {
-        int slot = atomicAdd(&s_slot, 1);
-        cpos[slot] = i;
-      } else if (kk == T) {
-        if (eq_before < need) cpos[nlt + eq_before] = i;
-        ++eq_before;
-      }
-    }
+    };
+    if (staged)
+      select_from(segbuf);
+    else
+      select_from((const float ADANNS_GLOBAL_AS *)seg);
   }
   __syncthreads();
   // stage the query row (coordinates of both measures) in LDS
@@ -682,8 +751,10 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
   }
   __syncthreads();
 
-  // first exact measure, one wave per candidate
-  const float *qrow = qstaged ? qstage : a.Qs + q * a.ldqs;
+  // first exact measure, one wave per candidate; the query row is read from
+  // LDS when staged, else from global memory (one instantiation each)
+  const float ADANNS_GLOBAL_AS *qglob = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
+  auto measure1 = [&](auto qrow) {
   for (int c = wv; c < ncand; c += nwv) {
     const int64_t pos = cpos[c];
     float S = 0.f, C = 0.f;
@@ -696,14 +767,14 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
         for (int d0 = lane; d0 < a.d_dot; d0 += 64 * 8) {
           float xv[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) xv[u] = d0 + 64 * u < a.d_dot ? x[d0 + 64 * u] : 0.f;
+          for (int u = 0; u < 8; ++u) xv[u] = d0 + 64 * u < a.d_dot ? ldg(x + d0 + 64 * u) : 0.f;
 #pragma unroll
           for (int u = 0; u < 8; ++u)
             if (d0 + 64 * u < a.d_dot) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
         }
       } else {
-        const float xs = a.qfmt == 2 ? a.qscale[pos] : 1.f;
-        const float qs = a.qfmt == 2 ? a.qQscale[q] : 1.f;
+        const float xs = a.qfmt == 2 ? ldg(a.qscale + pos) : 1.f;
+        const float qs = a.qfmt == 2 ? ldg(a.qQscale + q) : 1.f;
         for (int dim = lane; dim < a.d_dot; dim += 64) {
           float qh, ql, xh, xl;
           quant_value(a.qfmt, a.qQ, q * a.ldqq + dim, qs, qh, ql);
@@ -723,9 +794,9 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
       }
       const int32_t h = a.probes[q * a.nprobe + lo];
       const int64_t r = pabs - pb[lo];
-      const int64_t p0 = a.poff[h];
-      const int64_t npad = a.poff[h + 1] - p0;
-      id = a.rowid[p0 + r];
+      const int64_t p0 = ldg(a.poff + h);
+      const int64_t npad = ldg(a.poff + h + 1) - p0;
+      id = ldg(a.rowid + p0 + r);
       gpack = ((int64_t)h << 32) | r;
       if (a.mode == SEL_L2) {
         const float *base = a.vec + p0 * a.d_pad + r * SLAB;
@@ -734,7 +805,8 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
 #pragma unroll
           for (int u = 0; u < 16; ++u) {
             const int dim = d0 + 64 * u;
-            xv[u] = dim < a.d_dot ? base[(int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)] : 0.f;
+            xv[u] = dim < a.d_dot ? ldg(base + (int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB))
+                                  : 0.f;
           }
 #pragma unroll
           for (int u = 0; u < 16; ++u)
@@ -745,20 +817,21 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
         const float *qh = a.qr_hi + q * a.ldqr, *ql = a.qr_lo + q * a.ldqr;
         for (int dim = lane; dim < a.d_dot; dim += 64) {
           const int m = dim / a.dsub, t = dim - m * a.dsub;
-          const float x = a.cb[((int64_t)m * 256 + code[m]) * a.dsub + t];
-          acc_sq_diff2(qh[dim], ql[dim], x, S, C);
+          const float x = ldg(a.cb + ((int64_t)m * 256 + ldg(code + m)) * a.dsub + t);
+          acc_sq_diff2(ldg(qh + dim), ldg(ql + dim), x, S, C);
         }
       } else if (qqstaged) {  // SEL_QUANT: 16-byte chunks of the stored row
-        const float xs = a.qfmt == 2 ? a.qscale[p0 + r] : 1.f;
-        const float qs = a.qfmt == 2 ? a.qQscale[q] : 1.f;
+        const float xs = a.qfmt == 2 ? ldg(a.qscale + p0 + r) : 1.f;
+        const float qs = a.qfmt == 2 ? ldg(a.qQscale + q) : 1.f;
         const int per = 16 / qeb;  // coordinates per chunk, inside one slab
         const uint8_t *vb = (const uint8_t *)a.qvec + (p0 * a.qd_pad + r * SLAB) * qeb;
         for (int e0 = lane * per; e0 < a.d_dot; e0 += 64 * per) {
-          const uint4 w4 = *(const uint4 *)(vb + ((int64_t)(e0 / SLAB) * npad * SLAB + e0 % SLAB) * qeb);
-          const uint32_t wds[4] = {w4.x, w4.y, w4.z, w4.w};
+          typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+          const u32x4 w4 = ldg((const u32x4 *)(vb + ((int64_t)(e0 / SLAB) * npad * SLAB + e0 % SLAB) * qeb));
+          const uint32_t wds[4] = {w4[0], w4[1], w4[2], w4[3]};
           for (int u = 0; u < per && e0 + u < a.d_dot; ++u) {
             float qh, ql, xh, xl;
-            quant_value(a.qfmt, qqstage, e0 + u, qs, qh, ql);
+            quant_value(a.qfmt, qqstage, e0 + u, qs, qh, ql, true);
             const uint32_t bits = (wds[(u * qeb) / 4] >> (((u * qeb) % 4) * 8)) &
                                   (qeb == 2 ? 0xffffu : 0xffu);
             if (a.qfmt == 1) {
@@ -771,8 +844,8 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
           }
         }
       } else {  // SEL_QUANT, query too wide to stage
-        const float xs = a.qfmt == 2 ? a.qscale[p0 + r] : 1.f;
-        const float qs = a.qfmt == 2 ? a.qQscale[q] : 1.f;
+        const float xs = a.qfmt == 2 ? ldg(a.qscale + p0 + r) : 1.f;
+        const float qs = a.qfmt == 2 ? ldg(a.qQscale + q) : 1.f;
         for (int dim = lane; dim < a.d_dot; dim += 64) {
           float qh, ql, xh, xl;
           quant_value(a.qfmt, a.qQ, q * a.ldqq + dim, qs, qh, ql);
@@ -791,6 +864,11 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
       cg[c] = gpack;
     }
   }
+  };
+  if (qstaged)
+    measure1(qstage);
+  else
+    measure1(qglob);
   int P2 = 1;
   while (P2 < ncand) P2 <<= 1;
   for (int c = ncand + tid; c < P2; c += blockDim.x) {
@@ -805,23 +883,25 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
   if (a.stageB) {
     // second exact measure (FP32 L2 on d_B coordinates) of the K2 best
     nres = ncand < a.K2 ? ncand : a.K2;
+    auto measure2 = [&](auto qrow) {
     for (int c = wv; c < nres; c += nwv) {
       float S = 0.f, C = 0.f;
       if (coarse) {
         const float *x = a.cent + cg[c] * a.ld_cent;
-        for (int dim = lane; dim < a.d_B; dim += 64) acc_sq_diff(qrow[dim], x[dim], S, C);
+        for (int dim = lane; dim < a.d_B; dim += 64) acc_sq_diff(qrow[dim], ldg(x + dim), S, C);
       } else {
         const int32_t h = (int32_t)(cg[c] >> 32);
         const int64_t r = cg[c] & 0xffffffffll;
-        const int64_t p0 = a.poff[h];
-        const int64_t npad = a.poff[h + 1] - p0;
+        const int64_t p0 = ldg(a.poff + h);
+        const int64_t npad = ldg(a.poff + h + 1) - p0;
         const float *base = a.vec + p0 * a.d_pad + r * SLAB;
         for (int d0 = lane; d0 < a.d_B; d0 += 64 * 16) {
           float xv[16];
 #pragma unroll
           for (int u = 0; u < 16; ++u) {
             const int dim = d0 + 64 * u;
-            xv[u] = dim < a.d_B ? base[(int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)] : 0.f;
+            xv[u] = dim < a.d_B ? ldg(base + (int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB))
+                                : 0.f;
           }
 #pragma unroll
           for (int u = 0; u < 16; ++u)
@@ -834,6 +914,11 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
         clo[c] = C;
       }
     }
+    };
+    if (qstaged)
+      measure2(qstage);
+    else
+      measure2(qglob);
     __syncthreads();
     int P3 = 1;
     while (P3 < nres) P3 <<= 1;
