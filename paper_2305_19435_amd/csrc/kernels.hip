@@ -936,7 +936,8 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
       const int32_t hsel = has ? (int32_t)cid[j] : -1;
       a.out_probes[q * a.kout + j] = hsel;
       if (a.out_probes2) a.out_probes2[q * a.kout + j] = hsel;
-      if (a.out_dist) a.out_dist[q * ldo + j] = has ? chi[j] : __builtin_inff();
+      // coarse distance output: the nearest centroid's distance per query
+      if (a.out_dist && j == 0) a.out_dist[q * ldo] = has ? chi[0] : __builtin_inff();
     } else {
       a.out_dist[q * ldo + j] = has ? chi[j] : __builtin_inff();
       a.out_ids[q * ldo + j] = has ? cid[j] : -1;
@@ -960,7 +961,7 @@ struct SelMultiArgs {
   int32_t *probes;
   int32_t *user_probes;
   const int64_t *pair_base;
-  float *dist;             // scan: [Qtot][ldk]; coarse: optional min distance [Qtot]
+  float *dist;             // scan: [Qtot][ldk]; coarse: optional nearest distance [Qtot]
   int64_t *ids;
   int64_t ldk;
   int32_t lcap, kcap;
@@ -1010,6 +1011,187 @@ __global__ __launch_bounds__(512) void k_select_multi(SelMultiArgs m) {
     a.out_ids = m.ids + g.q0 * m.ldk;
   }
   select_body(a, q);
+}
+
+// Per-query selection when at most WSEL_K candidates are kept (K1 <= 64):
+// one wave per query, no LDS and no barriers. The K1 smallest first-pass
+// distances are kept as a sorted list spread over the lanes, keyed by
+// (order_key(distance) << 32 | position), so that ties go to the earlier
+// position exactly as in select_body; each batch of 64 distances is filtered
+// against the list's K1-th entry with one ballot and only the survivors are
+// inserted. The candidates are then re-measured exactly (compensated FP32,
+// same order of accumulation as select_body) and sorted across lanes by
+// (distance pair, id). Results are identical to k_select_multi's.
+constexpr int WSEL_K = 64;
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {
+  const uint32_t lo = __shfl_up((uint32_t)v, d);
+  const uint32_t hi = __shfl_up((uint32_t)(v >> 32), d);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int64_t shfl_xor64(int64_t v, int m) {
+  const uint32_t lo = __shfl_xor((uint32_t)(uint64_t)v, m);
+  const uint32_t hi = __shfl_xor((uint32_t)((uint64_t)v >> 32), m);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qtot) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= Qtot) return;  // whole waves leave; nothing below synchronises the block
+  const int c = cfg_of(m.cfg, m.ncfg, &CfgDev::q0, r);
+  const CfgDev &g = m.cfg[c];
+  const int64_t q = r - g.q0;
+  const bool coarse = m.coarse != 0;
+  const float *seg;
+  int64_t L, seg0 = 0;
+  int K1, kout, d_dot;
+  if (coarse) {
+    seg = m.S + g.S0 + q * g.nlist;
+    L = g.nlist;
+    K1 = min(g.nlist, min(g.nprobe + REFINE_MARGIN, MAX_SHORTLIST));
+    kout = g.nprobe;
+    d_dot = g.d_c;
+  } else {
+    seg0 = m.seg_off[r];
+    seg = m.D + seg0;
+    L = m.seg_off[r + 1] - seg0;
+    K1 = min(g.k + REFINE_MARGIN, MAX_SHORTLIST);
+    kout = g.k;
+    d_dot = g.d_s;
+  }
+
+  // 1. the K1 smallest (key, position) composites, sorted over lanes
+  const float ADANNS_GLOBAL_AS *sg = (const float ADANNS_GLOBAL_AS *)seg;
+  uint64_t best = ~0ull, thr = ~0ull;
+  constexpr int U = 4;
+  for (int64_t base = 0; base < L; base += 64 * U) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + 64 * u + lane;
+      v[u] = i < L ? sg[i] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + 64 * u + lane;
+      const uint64_t comp = i < L ? ((uint64_t)order_key(v[u]) << 32) | (uint64_t)i : ~0ull;
+      uint64_t mask = __ballot(comp < thr);
+      while (mask) {
+        const int b = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const uint64_t x = readlane64(comp, b);
+        if (x < thr) {
+          const uint64_t up = shfl_up64(best, 1);
+          if (!(best < x)) best = (lane == 0 || up < x) ? x : up;
+          thr = readlane64(best, K1 - 1);
+        }
+      }
+    }
+  }
+  const int ncand = (int)min64(L, (int64_t)K1);
+
+  // 2. where each candidate lives (lane j < ncand holds candidate j)
+  int64_t my_id = INT64_MAX, my_npad = 0;
+  const float *my_base = nullptr;
+  if (lane < ncand) {
+    const int64_t pos = (int64_t)(uint32_t)best;
+    if (coarse) {
+      my_id = pos;
+      my_base = g.cent + pos * g.d_cb_pad;
+    } else {
+      const int64_t pabs = seg0 + pos;
+      const int64_t *pb = m.pair_base + g.pair0 + q * g.nprobe;
+      int lo = 0, hi = g.nprobe - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ldg(pb + mid) <= pabs) lo = mid; else hi = mid - 1;
+      }
+      const int32_t h = ldg(m.probes + g.pair0 + q * g.nprobe + lo);
+      const int64_t rr = pabs - ldg(pb + lo);
+      const int64_t p0 = ldg(g.poff + h);
+      my_npad = ldg(g.poff + h + 1) - p0;
+      my_id = ldg(g.rowid + p0 + rr);
+      my_base = g.vec + p0 * g.d_pad + rr * SLAB;
+    }
+  }
+
+  // 3. exact re-measurement, one candidate at a time over the lanes
+  const float ADANNS_GLOBAL_AS *qrow =
+      (const float ADANNS_GLOBAL_AS *)(m.Qs + r * m.ldqs);
+  float myS = __builtin_inff(), myC = 0.f;
+  for (int cc = 0; cc < ncand; ++cc) {
+    const float ADANNS_GLOBAL_AS *x =
+        (const float ADANNS_GLOBAL_AS *)readlane64((uint64_t)my_base, cc);
+    float S = 0.f, C = 0.f;
+    if (coarse) {
+      for (int d0 = lane; d0 < d_dot; d0 += 64 * 8) {
+        float xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = d0 + 64 * u < d_dot ? x[d0 + 64 * u] : 0.f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (d0 + 64 * u < d_dot) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+      }
+    } else {
+      const int64_t npad = (int64_t)readlane64((uint64_t)my_npad, cc);
+      for (int d0 = lane; d0 < d_dot; d0 += 64 * 16) {
+        float xv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int dim = d0 + 64 * u;
+          xv[u] = dim < d_dot ? x[(int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (d0 + 64 * u < d_dot) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+      }
+    }
+    wave_reduce_pair(S, C);
+    if (lane == cc) {
+      myS = S;
+      myC = C;
+    }
+  }
+
+  // 4. bitonic sort of the 64 lanes by (S, C, id); lanes past ncand hold
+  // (+inf, 0, INT64_MAX) and sort last
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const float oS = __shfl_xor(myS, j), oC = __shfl_xor(myC, j);
+      const int64_t oid = shfl_xor64(my_id, j);
+      const bool up = (lane & k) == 0, lower = (lane & j) == 0;
+      const bool other_less = pair_less(oS, oC, oid, myS, myC, my_id);
+      if ((lower == up) ? other_less : !other_less) {
+        myS = oS;
+        myC = oC;
+        my_id = oid;
+      }
+    }
+  }
+
+  // 5. outputs
+  if (lane < kout) {
+    const bool has = lane < ncand;
+    if (coarse) {
+      const int32_t hsel = has ? (int32_t)my_id : -1;
+      m.probes[g.pair0 + q * kout + lane] = hsel;
+      if (m.user_probes) m.user_probes[g.pair0 + q * kout + lane] = hsel;
+      if (m.dist && lane == 0) m.dist[r] = has ? myS : __builtin_inff();
+    } else {
+      m.dist[r * m.ldk + lane] = has ? myS : __builtin_inff();
+      m.ids[r * m.ldk + lane] = has ? my_id : -1;
+    }
+  }
 }
 
 // ---- IVF-PQ ----------------------------------------------------------------------
@@ -1756,8 +1938,12 @@ static hipError_t coarse_multi(const SearchBufs &b, int32_t *user_probes, float 
   m.lcap = seg_cap(m.kcap, b.max_nlist);
   {
     KernelTimer tm("select_coarse", st);
-    hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(512),
-                       sel_smem_bytes(m.lcap, m.kcap), st, m);
+    if (b.max_nprobe + REFINE_MARGIN <= WSEL_K)
+      hipLaunchKernelGGL(k_select_wave, dim3((unsigned)cdiv(b.Qtot, 4)), dim3(256), 0, st, m,
+                         b.Qtot);
+    else
+      hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(512),
+                         sel_smem_bytes(m.lcap, m.kcap), st, m);
   }
   return hipGetLastError();
 }
@@ -1871,8 +2057,12 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
   m.lcap = seg_cap(m.kcap, SEG_LDS_CAP);
   {
     KernelTimer tm("select_scan", st);
-    hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(512),
-                       sel_smem_bytes(m.lcap, m.kcap), st, m);
+    if (b.max_k + REFINE_MARGIN <= WSEL_K)
+      hipLaunchKernelGGL(k_select_wave, dim3((unsigned)cdiv(b.Qtot, 4)), dim3(256), 0, st, m,
+                         b.Qtot);
+    else
+      hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(512),
+                         sel_smem_bytes(m.lcap, m.kcap), st, m);
   }
   return hipGetLastError();
 }
