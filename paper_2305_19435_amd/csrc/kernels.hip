@@ -1071,7 +1071,7 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
   // 1. the K1 smallest (key, position) composites, sorted over lanes
   const float ADANNS_GLOBAL_AS *sg = (const float ADANNS_GLOBAL_AS *)seg;
   uint64_t best = ~0ull, thr = ~0ull;
-  constexpr int U = 4;
+  constexpr int U = 16;  // loads in flight per lane
   for (int64_t base = 0; base < L; base += 64 * U) {
     float v[U];
 #pragma unroll
@@ -1123,41 +1123,65 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
     }
   }
 
-  // 3. exact re-measurement, one candidate at a time over the lanes
+  // 3. exact re-measurement over the lanes, two candidates at a time so
+  // that both candidates' loads are in flight together
   const float ADANNS_GLOBAL_AS *qrow =
       (const float ADANNS_GLOBAL_AS *)(m.Qs + r * m.ldqs);
   float myS = __builtin_inff(), myC = 0.f;
-  for (int cc = 0; cc < ncand; ++cc) {
-    const float ADANNS_GLOBAL_AS *x =
+  for (int cc = 0; cc < ncand; cc += 2) {
+    const bool two = cc + 1 < ncand;
+    const float ADANNS_GLOBAL_AS *x0 =
         (const float ADANNS_GLOBAL_AS *)readlane64((uint64_t)my_base, cc);
-    float S = 0.f, C = 0.f;
+    const float ADANNS_GLOBAL_AS *x1 =
+        (const float ADANNS_GLOBAL_AS *)readlane64((uint64_t)my_base, two ? cc + 1 : cc);
+    float S0 = 0.f, C0 = 0.f, S1 = 0.f, C1 = 0.f;
     if (coarse) {
       for (int d0 = lane; d0 < d_dot; d0 += 64 * 8) {
-        float xv[8];
+        float xa[8], xb[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) xv[u] = d0 + 64 * u < d_dot ? x[d0 + 64 * u] : 0.f;
+        for (int u = 0; u < 8; ++u) {
+          const int dim = d0 + 64 * u;
+          xa[u] = dim < d_dot ? x0[dim] : 0.f;
+          xb[u] = dim < d_dot ? x1[dim] : 0.f;
+        }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          if (d0 + 64 * u < d_dot) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+          if (d0 + 64 * u < d_dot) {
+            const float qv = qrow[d0 + 64 * u];
+            acc_sq_diff(qv, xa[u], S0, C0);
+            acc_sq_diff(qv, xb[u], S1, C1);
+          }
       }
     } else {
-      const int64_t npad = (int64_t)readlane64((uint64_t)my_npad, cc);
+      const int64_t np0 = (int64_t)readlane64((uint64_t)my_npad, cc);
+      const int64_t np1 = (int64_t)readlane64((uint64_t)my_npad, two ? cc + 1 : cc);
       for (int d0 = lane; d0 < d_dot; d0 += 64 * 16) {
-        float xv[16];
+        float xa[16], xb[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
           const int dim = d0 + 64 * u;
-          xv[u] = dim < d_dot ? x[(int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB)] : 0.f;
+          const int64_t sl = dim / SLAB, t = dim % SLAB;
+          xa[u] = dim < d_dot ? x0[sl * np0 * SLAB + t] : 0.f;
+          xb[u] = dim < d_dot ? x1[sl * np1 * SLAB + t] : 0.f;
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u)
-          if (d0 + 64 * u < d_dot) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+          if (d0 + 64 * u < d_dot) {
+            const float qv = qrow[d0 + 64 * u];
+            acc_sq_diff(qv, xa[u], S0, C0);
+            acc_sq_diff(qv, xb[u], S1, C1);
+          }
       }
     }
-    wave_reduce_pair(S, C);
+    wave_reduce_pair(S0, C0);
+    wave_reduce_pair(S1, C1);
     if (lane == cc) {
-      myS = S;
-      myC = C;
+      myS = S0;
+      myC = C0;
+    }
+    if (two && lane == cc + 1) {
+      myS = S1;
+      myC = C1;
     }
   }
 

@@ -125,7 +125,10 @@ def medium(lib):
     index.free()
 
 
-@pytest.mark.parametrize("d_c,d_s,nprobe,k", [(32, 256, 8, 10), (24, 200, 16, 50), (32, 96, 2, 10)])
+@pytest.mark.parametrize("d_c,d_s,nprobe,k", [
+    (32, 256, 8, 10), (24, 200, 16, 50), (32, 96, 2, 10),
+    (32, 256, 60, 60),    # shortlists past 64: the workgroup-per-query selection
+])
 def test_medium_parity(medium, d_c, d_s, nprobe, k):
     X, Q, C32, off, ids, index = medium
     dist, gid, probes = _run(index, Q, d_c, d_s, nprobe, k)
