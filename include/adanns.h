@@ -48,7 +48,8 @@ typedef enum adanns_status {
   ADANNS_ENOMEM = -2,      /* device or host allocation failed */
   ADANNS_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
   ADANNS_EUNSUPPORTED = -4,/* valid request this build does not support */
-  ADANNS_EBUDGET = -5      /* request exceeds an admission budget */
+  ADANNS_EBUDGET = -5,     /* request exceeds an admission budget */
+  ADANNS_EIO = -6          /* a file could not be opened, read or written, or is malformed */
 } adanns_status;
 
 typedef enum adanns_format {
@@ -348,6 +349,18 @@ adanns_status adanns_index_lists(const adanns_index *index, int64_t *offsets, in
 
 /* The centroids as stored: host [nlist x d_c_build] FP32. Synchronous. */
 adanns_status adanns_index_centroids(const adanns_index *index, float *centroids);
+
+/* Persistence of a built index (the stored form of what Algorithm 1's
+ * construction returns: centroids and inverted lists, plus the vectors in
+ * their list layout and every PQ codec). adanns_index_save waits for the
+ * device, then writes ``path`` (created or truncated). adanns_index_load
+ * reads such a file onto the current device on ``stream`` and returns a new
+ * index in *out (release with adanns_index_free). Low-precision copies are
+ * not stored: call adanns_set_precision again after a load. A file that is
+ * not a complete index of this format version gives ADANNS_EIO and leaves
+ * *out untouched. */
+adanns_status adanns_index_save(const adanns_index *index, const char *path);
+adanns_status adanns_index_load(const char *path, void *stream, adanns_index **out);
 
 /* Device bytes held by the index, scratch memory included. */
 size_t adanns_index_device_bytes(const adanns_index *index);

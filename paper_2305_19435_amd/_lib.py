@@ -60,6 +60,8 @@ _SIGS = {
     "adanns_index_centroids": (C.c_int, [vp, vp]),
     "adanns_index_device_bytes": (C.c_size_t, [vp]),
     "adanns_index_free": (None, [vp]),
+    "adanns_index_save": (C.c_int, [vp, C.c_char_p]),
+    "adanns_index_load": (C.c_int, [C.c_char_p, vp, vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)

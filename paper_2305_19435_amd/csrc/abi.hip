@@ -136,6 +136,7 @@ void free_index_memory(adanns_index *ix) {
 }
 
 // Lays out lists, ids and vectors for a validated assignment (host array).
+// With X == NULL the vector layout is allocated but not filled.
 adanns_status build_layout(adanns_index *ix, const float *X, int64_t ldx,
                            const std::vector<int32_t> &assign, hipStream_t st) {
   const int64_t n = ix->n;
@@ -187,8 +188,9 @@ adanns_status build_layout(adanns_index *ix, const float *X, int64_t ldx,
                             hipMemcpyHostToDevice, st));
   ADANNS_HIP(hipMemcpyAsync(d_row_list, row_list.data(), ix->rows_pad * sizeof(int32_t),
                             hipMemcpyHostToDevice, st));
-  ADANNS_HIP(launch_layout(X, ldx, ix->d, ix->rowid, d_row_list, ix->poff, ix->rows_pad, ix->d_pad,
-                           ix->vec, st));
+  if (X)
+    ADANNS_HIP(launch_layout(X, ldx, ix->d, ix->rowid, d_row_list, ix->poff, ix->rows_pad,
+                             ix->d_pad, ix->vec, st));
   ADANNS_HIP(hipStreamSynchronize(st));
   return ADANNS_OK;
 }
@@ -1016,6 +1018,212 @@ size_t adanns_index_device_bytes(const adanns_index *cix) {
   size_t b = ix->own_bytes;
   for (auto &kv : ix->scratch) b += kv.second.bytes;
   return b;
+}
+
+// ---- persistence ----------------------------------------------------------
+// File: "ADANNSIX", u32 version, u32 0, i64 n, i32 d, i32 nlist, i32 d_cb,
+// i32 d_pad, i64 rows_pad, i64 offsets[nlist + 1], i64 ids[n], f32
+// centroids[nlist][d_cb], f32 vectors[rows_pad][d_pad] (list layout), i32
+// number of PQ codecs, then per codec i32 M, i32 d_s, f32 R[d_s][d_s], f32
+// codebooks[M][256][d_s / M], u8 codes[rows_pad][M] (list layout), and
+// "XINSNNDA". Little-endian, as the host writes it.
+static const char kIxMagic[8] = {'A', 'D', 'A', 'N', 'N', 'S', 'I', 'X'};
+static const char kIxTrailer[8] = {'X', 'I', 'N', 'S', 'N', 'N', 'D', 'A'};
+static const uint32_t kIxVersion = 1;
+
+namespace {
+struct File {
+  FILE *f = nullptr;
+  ~File() {
+    if (f) std::fclose(f);
+  }
+  bool put(const void *p, size_t n) { return std::fwrite(p, 1, n, f) == n; }
+  bool get(void *p, size_t n) { return std::fread(p, 1, n, f) == n; }
+};
+
+adanns_status dev_to_file(File &fl, const void *dev, size_t bytes) {
+  std::vector<char> buf(std::min<size_t>(std::max<size_t>(bytes, 1), size_t(64) << 20));
+  for (size_t o = 0; o < bytes; o += buf.size()) {
+    const size_t n = std::min(buf.size(), bytes - o);
+    ADANNS_HIP(hipMemcpy(buf.data(), (const char *)dev + o, n, hipMemcpyDeviceToHost));
+    if (!fl.put(buf.data(), n)) {
+      set_error("write failed");
+      return ADANNS_EIO;
+    }
+  }
+  return ADANNS_OK;
+}
+
+adanns_status file_to_dev(File &fl, void *dev, size_t bytes, hipStream_t st) {
+  std::vector<char> buf(std::min<size_t>(std::max<size_t>(bytes, 1), size_t(64) << 20));
+  for (size_t o = 0; o < bytes; o += buf.size()) {
+    const size_t n = std::min(buf.size(), bytes - o);
+    if (!fl.get(buf.data(), n)) {
+      set_error("the file ends before the index does");
+      return ADANNS_EIO;
+    }
+    ADANNS_HIP(hipMemcpyAsync((char *)dev + o, buf.data(), n, hipMemcpyHostToDevice, st));
+    ADANNS_HIP(hipStreamSynchronize(st));
+  }
+  return ADANNS_OK;
+}
+}  // namespace
+
+adanns_status adanns_index_save(const adanns_index *ix, const char *path) {
+  clear_error();
+  ADANNS_REQUIRE(ix != nullptr && path != nullptr, "index and path must be non-NULL");
+  ADANNS_HIP(hipDeviceSynchronize());
+  File fl;
+  fl.f = std::fopen(path, "wb");
+  if (!fl.f) {
+    set_error("cannot open %s for writing", path);
+    return ADANNS_EIO;
+  }
+  const uint32_t ver[2] = {kIxVersion, 0};
+  const int32_t dims[4] = {ix->d, ix->nlist, ix->d_cb, ix->d_pad};
+  bool ok = fl.put(kIxMagic, 8) && fl.put(ver, 8) && fl.put(&ix->n, 8) && fl.put(dims, 16) &&
+            fl.put(&ix->rows_pad, 8) &&
+            fl.put(ix->h_off.data(), (ix->nlist + 1) * sizeof(int64_t)) &&
+            fl.put(ix->h_ids.data(), ix->n * sizeof(int64_t));
+  if (!ok) {
+    set_error("write failed: %s", path);
+    return ADANNS_EIO;
+  }
+  std::vector<float> cent((size_t)ix->nlist * ix->d_cb);
+  ADANNS_HIP(hipMemcpy2D(cent.data(), ix->d_cb * sizeof(float), ix->cent,
+                         ix->d_cb_pad * sizeof(float), ix->d_cb * sizeof(float), ix->nlist,
+                         hipMemcpyDeviceToHost));
+  if (!fl.put(cent.data(), cent.size() * sizeof(float))) {
+    set_error("write failed: %s", path);
+    return ADANNS_EIO;
+  }
+  adanns_status s;
+  if ((s = dev_to_file(fl, ix->vec, (size_t)ix->rows_pad * ix->d_pad * sizeof(float)))) return s;
+  const int32_t npq = (int32_t)ix->pq.size();
+  if (!fl.put(&npq, 4)) {
+    set_error("write failed: %s", path);
+    return ADANNS_EIO;
+  }
+  for (const auto &kv : ix->pq) {
+    const PqCodec &c = kv.second;
+    const int32_t hdr[2] = {c.M, c.d_s};
+    if (!fl.put(hdr, 8)) {
+      set_error("write failed: %s", path);
+      return ADANNS_EIO;
+    }
+    if ((s = dev_to_file(fl, c.R, (size_t)c.d_s * c.d_s * sizeof(float))) ||
+        (s = dev_to_file(fl, c.cb, (size_t)c.M * 256 * c.dsub * sizeof(float))) ||
+        (s = dev_to_file(fl, c.codes, (size_t)ix->rows_pad * c.M)))
+      return s;
+  }
+  if (!fl.put(kIxTrailer, 8) || std::fflush(fl.f) != 0) {
+    set_error("write failed: %s", path);
+    return ADANNS_EIO;
+  }
+  return ADANNS_OK;
+}
+
+adanns_status adanns_index_load(const char *path, void *stream, adanns_index **out) {
+  clear_error();
+  ADANNS_REQUIRE(path != nullptr && out != nullptr, "path and out must be non-NULL");
+  adanns_status s;
+  hipStream_t st = (hipStream_t)stream;
+  File fl;
+  fl.f = std::fopen(path, "rb");
+  if (!fl.f) {
+    set_error("cannot open %s", path);
+    return ADANNS_EIO;
+  }
+  auto bad = [&](const char *what) {
+    set_error("%s is not an index file of this version (%s)", path, what);
+    return ADANNS_EIO;
+  };
+  char magic[8];
+  uint32_t ver[2];
+  int64_t n = 0, rows_pad = 0;
+  int32_t dims[4];
+  if (!fl.get(magic, 8) || std::memcmp(magic, kIxMagic, 8) != 0) return bad("magic");
+  if (!fl.get(ver, 8) || ver[0] != kIxVersion) return bad("version");
+  if (!fl.get(&n, 8) || !fl.get(dims, 16) || !fl.get(&rows_pad, 8)) return bad("header");
+  const int32_t d = dims[0], nlist = dims[1], d_cb = dims[2];
+  if (n < 1 || n >= (int64_t(1) << 31) || d < 1 || d > 8192 || nlist < 1 || nlist > 65536 ||
+      d_cb < 1 || d_cb > d || dims[3] != (int32_t)round_up(d, SLAB))
+    return bad("sizes");
+  std::vector<int64_t> off(nlist + 1), ids(n);
+  if (!fl.get(off.data(), off.size() * 8) || !fl.get(ids.data(), ids.size() * 8))
+    return bad("lists");
+  if (off[0] != 0 || off[nlist] != n) return bad("offsets");
+  std::vector<int32_t> assign(n, -1);
+  for (int32_t h = 0; h < nlist; ++h) {
+    if (off[h + 1] < off[h]) return bad("offsets");
+    for (int64_t i = off[h]; i < off[h + 1]; ++i) {
+      const int64_t j = ids[i];
+      if (j < 0 || j >= n || assign[j] != -1) return bad("ids");
+      if (i > off[h] && ids[i - 1] >= j) return bad("list order");
+      assign[j] = h;
+    }
+  }
+  std::vector<float> cent((size_t)nlist * d_cb);
+  if (!fl.get(cent.data(), cent.size() * sizeof(float))) return bad("centroids");
+  // the file's host part is checked before any device work
+  if ((s = check_async())) return s;
+  adanns_index *ix = new (std::nothrow) adanns_index();
+  if (!ix) {
+    set_error("out of host memory");
+    return ADANNS_ENOMEM;
+  }
+  auto fail = [&](adanns_status e) {
+    free_index_memory(ix);
+    delete ix;
+    return e;
+  };
+  init_index_shape(ix, n, d, nlist, d_cb);
+  if ((s = build_layout(ix, nullptr, 0, assign, st))) return fail(s);
+  if (ix->rows_pad != rows_pad) return fail(bad("layout rows"));
+  {
+    DevFree tmp;
+    float *dc = nullptr;
+    if (hipMalloc(&dc, cent.size() * sizeof(float)) != hipSuccess) {
+      set_error("out of device memory");
+      return fail(ADANNS_ENOMEM);
+    }
+    tmp.ptrs.push_back(dc);
+    if (hipMemcpy(dc, cent.data(), cent.size() * sizeof(float), hipMemcpyHostToDevice)) {
+      set_error("HIP error while loading the centroids");
+      return fail(ADANNS_EHIP);
+    }
+    if ((s = build_centroids(ix, dc, d_cb, st))) return fail(s);
+  }
+  if ((s = file_to_dev(fl, ix->vec, (size_t)rows_pad * ix->d_pad * sizeof(float), st)))
+    return fail(s);
+  int32_t npq = 0;
+  if (!fl.get(&npq, 4) || npq < 0 || npq > 16) return fail(bad("codec count"));
+  for (int32_t i = 0; i < npq; ++i) {
+    int32_t hdr[2];
+    if (!fl.get(hdr, 8)) return fail(bad("codec header"));
+    PqCodec c;
+    c.M = hdr[0];
+    c.d_s = hdr[1];
+    if (c.M < 4 || c.M > 64 || c.M % 4 || c.d_s < 1 || c.d_s > d || c.d_s > 2048 ||
+        c.d_s % c.M || ix->pq.count(c.M))
+      return fail(bad("codec sizes"));
+    c.dsub = c.d_s / c.M;
+    // registered first so that a failure below releases it with the index
+    ix->pq[c.M] = c;
+    PqCodec &cc = ix->pq[c.M];
+    if ((s = dmalloc(ix, (void **)&cc.R, (size_t)c.d_s * c.d_s * sizeof(float))) ||
+        (s = dmalloc(ix, (void **)&cc.cb, (size_t)c.M * 256 * c.dsub * sizeof(float))) ||
+        (s = dmalloc(ix, (void **)&cc.codes, (size_t)rows_pad * c.M)))
+      return fail(s);
+    if ((s = file_to_dev(fl, cc.R, (size_t)c.d_s * c.d_s * sizeof(float), st)) ||
+        (s = file_to_dev(fl, cc.cb, (size_t)c.M * 256 * c.dsub * sizeof(float), st)) ||
+        (s = file_to_dev(fl, cc.codes, (size_t)rows_pad * c.M, st)))
+      return fail(s);
+  }
+  char trailer[8];
+  if (!fl.get(trailer, 8) || std::memcmp(trailer, kIxTrailer, 8) != 0) return fail(bad("trailer"));
+  *out = ix;
+  return ADANNS_OK;
 }
 
 void adanns_index_free(adanns_index *ix) {

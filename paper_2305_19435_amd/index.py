@@ -71,6 +71,17 @@ class IvfIndex:
         ix = cls(out.value)
         return (ix, obj) if return_objective else ix
 
+    @classmethod
+    def load(cls, path, stream=None) -> "IvfIndex":
+        """adanns_index_load: an index written by save(), onto the current device."""
+        out = C.c_void_p()
+        check(lib.adanns_index_load(str(path).encode(), _stream(stream), C.byref(out)))
+        return cls(out.value)
+
+    def save(self, path):
+        """adanns_index_save: centroids, lists, vectors and PQ codecs to ``path``."""
+        check(lib.adanns_index_save(self._h, str(path).encode()))
+
     # ---- search ---------------------------------------------------------------
     def search(self, Q, d_c: int, d_s: int, nprobe: int, k: int, return_probes=False,
                stream=None, out=None):

@@ -52,3 +52,27 @@ def test_validation_before_device_work(lib):
     assert L.adanns_index_info(None, None, None, None, None) == -1
     assert L.adanns_index_device_bytes(None) == 0
     L.adanns_index_free(None)
+
+
+def test_index_file_checked_before_device_work(lib, tmp_path):
+    """A file that is not an index is refused (ADANNS_EIO) from its host part
+    alone; NULL arguments are EINVAL."""
+    L = lib.lib
+    out = C.c_void_p()
+    assert L.adanns_index_load(None, None, C.byref(out)) == -1
+    assert L.adanns_index_save(None, b"/nonexistent/x") == -1
+    missing = tmp_path / "missing.adanns"
+    assert L.adanns_index_load(str(missing).encode(), None, C.byref(out)) == -6
+    assert "cannot open" in lib.last_error()
+    junk = tmp_path / "junk.adanns"
+    junk.write_bytes(b"NOTANIDX" + b"\0" * 64)
+    assert L.adanns_index_load(str(junk).encode(), None, C.byref(out)) == -6
+    assert "magic" in lib.last_error()
+    # right magic, wrong version; then a truncated header
+    junk.write_bytes(b"ADANNSIX" + (99).to_bytes(4, "little") + b"\0" * 4)
+    assert L.adanns_index_load(str(junk).encode(), None, C.byref(out)) == -6
+    assert "version" in lib.last_error()
+    junk.write_bytes(b"ADANNSIX" + (1).to_bytes(4, "little") + b"\0" * 4 + b"\1\0")
+    assert L.adanns_index_load(str(junk).encode(), None, C.byref(out)) == -6
+    assert "header" in lib.last_error()
+    assert out.value is None

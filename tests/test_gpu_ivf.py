@@ -136,3 +136,39 @@ def test_medium_parity(medium, d_c, d_s, nprobe, k):
     rep = check_search(X, Q, C32, off, ids, d_c, d_s, nprobe, k, dist, gid, got_p=probes,
                        queries=sample)
     assert rep.ok, rep.problems
+
+
+def test_save_load_roundtrip(small, lib, tmp_path):
+    """A saved and reloaded index (with a PQ codec) searches bit for bit like
+    the original, and holds the same lists, centroids and codec."""
+    w, X, Q, C32, off, ids, index = small
+    assign = np.empty(len(X), dtype=np.int32)
+    for h in range(len(off) - 1):
+        assign[ids[off[h]:off[h + 1]]] = h
+    rng = np.random.default_rng(5)
+    M = 8
+    cb = rng.standard_normal((M, 256, w.d // M)).astype(np.float32) * 0.1
+    codes = rng.integers(0, 256, size=(len(X), M), dtype=np.uint8)
+    ix = lib.IvfIndex.import_ivf(X, C32, assign)
+    ix.pq_import(M, w.d, None, cb, codes)
+    path = tmp_path / "ix.adanns"
+    ix.save(path)
+    ix2 = lib.IvfIndex.load(path)
+    o1, i1 = ix.lists()
+    o2, i2 = ix2.lists()
+    assert np.array_equal(o1, o2) and np.array_equal(i1, i2)
+    assert np.array_equal(ix.centroids(), ix2.centroids())
+    a = _run(ix, Q, w.d_c, w.d_s, w.nprobe, w.k)
+    b = _run(ix2, Q, w.d_c, w.d_s, w.nprobe, w.k)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    Qd = torch.from_numpy(Q).cuda()
+    p1 = ix.search_pq(Qd, w.d_c, w.nprobe, M, w.k)
+    p2 = ix2.search_pq(Qd, w.d_c, w.nprobe, M, w.k)
+    torch.cuda.synchronize()
+    for x, y in zip(p1, p2):
+        assert torch.equal(x, y)
+    for x, y in zip(ix.pq_codec(M, w.d), ix2.pq_codec(M, w.d)):
+        assert np.array_equal(x, y)
+    ix.free()
+    ix2.free()

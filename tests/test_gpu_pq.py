@@ -142,3 +142,32 @@ def test_pq_train_with_rotation(lib, small_data):
         assert abs(dg - dr) <= 1e-5 * max(dr, 1e-12)
     assert len(diff) <= 0.001 * codes.size
     index.free()
+
+
+@pytest.mark.parametrize("d_s,M", [(64, 16), (32, 8)])
+def test_exhaustive_opq_prefix(lib, small_data, d_s, M):
+    """AdANNS-OPQ without clustering (Section 4.2): one list holding every
+    vector, ADC over the d_s prefix with d_s/M-dimensional blocks. Both sides
+    scan all N codes; the oracle is ivfpq_search64 with a single list."""
+    w, X, Q = small_data
+    C1 = X.astype(np.float64).mean(axis=0, keepdims=True).astype(np.float32)
+    a = np.zeros(len(X), dtype=np.int32)
+    index = lib.IvfIndex.import_ivf(X, C1, a)
+    R32, cb32, codes = make_codec(X, M, d_s, True, w.seed + 100 + d_s)
+    index.pq_import(M, d_s, R32, cb32, codes)
+    k = 10
+    dist, gid = index.search_pq(torch.from_numpy(Q).cuda(), w.d, 1, M, k)
+    torch.cuda.synchronize()
+    dist, gid = dist.cpu().numpy(), gid.cpu().numpy()
+    off = np.array([0, len(X)], dtype=np.int64)
+    ids = np.arange(len(X), dtype=np.int64)
+    rd, ri, _, cands, luts = pq.ivfpq_search64(
+        Q, C1.astype(np.float64), off, ids, codes, R32.astype(np.float64),
+        cb32.astype(np.float64), w.d, 1, k, return_candidates=True)
+    rep = check.Report()
+    for qi in range(len(Q)):
+        fn = (lambda lut: (lambda idx: pq.adc_dist64(lut, codes[np.asarray(idx)])))(luts[qi])
+        check.compare_knn(Q[qi], X, cands[qi], dist[qi], gid[qi], rd[qi], ri[qi], d_s,
+                          report=rep, tag=f"q{qi}", dist64=fn)
+    assert rep.ok, rep.problems
+    index.free()
