@@ -266,12 +266,13 @@ def pq_form(args, lib, torch, log):
             t = _timed(torch, lambda: index.search_pq(Qd, w.d_c, nprobe, M, 10), args.steps,
                        args.warmup)
             kern = _kernel_ms(lib, ["pq_rotate", "pq_lut", "adc_scan", "select_adc"])
-            # ADC scan traffic: every probed list's codes once per (query, probe)
+            # ADC scan algorithmic bytes: every probed list's codes once per
+            # (query, probe), plus each query's table once
             off, _ = index.lists()
             _, _, probes = index.search_pq(Qd, w.d_c, nprobe, M, 10, return_probes=True)
             torch.cuda.synchronize()
             cand = int(np.diff(off)[probes.cpu().numpy().astype(np.int64)].sum())
-            bytes_ = cand * M + nq * nprobe * M * 256 * 4
+            bytes_ = cand * M + nq * M * 256 * 4
             gbs = bytes_ / (kern.get("adc_scan", 1e9) * 1e-3) / 1e9
             res[f"np{nprobe}_M{M}"] = {"qps": nq / t, "ms_per_step": t * 1e3, "kernels_ms": kern,
                                        "adc_algorithmic_bytes": bytes_, "adc_gbs": gbs,

@@ -588,6 +588,183 @@ __host__ __device__ inline size_t sel_smem_bytes(int32_t lcap, int32_t kcap) {
   return 2048 * 4 + 4096 + (size_t)lcap * 4 + (size_t)kcap * (8 + 4 + 4 + 8 + 8);
 }
 
+// Where a candidate lives. Coarse modes: a centroid (id = gpack = row = h).
+// Scan modes: row r of list h, at layout row p0 + r.
+struct CandLoc {
+  int64_t id, gpack, row, p0, npad;
+};
+
+__device__ __forceinline__ CandLoc locate(const SelArgs &a, bool coarse, int64_t q, int64_t seg0,
+                                          int64_t pos) {
+  CandLoc L{pos, pos, pos, 0, 0};
+  if (coarse) return L;
+  const int64_t pabs = seg0 + pos;
+  const int64_t *pb = a.pair_base + q * a.nprobe;
+  int lo = 0, hi = a.nprobe - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ldg(pb + mid) <= pabs) lo = mid; else hi = mid - 1;
+  }
+  const int32_t h = ldg(a.probes + q * a.nprobe + lo);
+  const int64_t r = pabs - ldg(pb + lo);
+  L.p0 = ldg(a.poff + h);
+  L.npad = ldg(a.poff + h + 1) - L.p0;
+  L.id = ldg(a.rowid + L.p0 + r);
+  L.gpack = ((int64_t)h << 32) | r;
+  L.row = L.p0 + r;
+  return L;
+}
+
+__device__ __forceinline__ CandLoc locate_packed(const SelArgs &a, bool coarse, int64_t gpack) {
+  CandLoc L{0, gpack, gpack, 0, 0};
+  if (coarse) return L;
+  const int32_t h = (int32_t)(gpack >> 32);
+  L.p0 = ldg(a.poff + h);
+  L.npad = ldg(a.poff + h + 1) - L.p0;
+  L.row = L.p0 + (gpack & 0xffffffffll);
+  return L;
+}
+
+// First exact measure of one candidate over the lanes of a wave: the value
+// the method ranks by (SelMode), as the unevaluated pair S + C. ``qrow`` is
+// the FP32 query row (LDS or global); ``qq_lds`` the staged quantised query
+// row in LDS, or NULL to read it from global memory. Each lane accumulates
+// its coordinates lane, lane + 64, ... in increasing order; loads are
+// issued in batches so that several are in flight.
+template <class QP>
+__device__ __forceinline__ void measure1(const SelArgs &a, int64_t q, const CandLoc &L, QP qrow,
+                                         const uint8_t *qq_lds, int lane, float &S, float &C) {
+  const int d = a.d_dot;
+  if (a.mode == SEL_COARSE) {
+    const float *x = a.cent + L.row * a.ld_cent;
+    for (int d0 = lane; d0 < d; d0 += 64 * 8) {
+      float xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = d0 + 64 * u < d ? ldg(x + d0 + 64 * u) : 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (d0 + 64 * u < d) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+    }
+  } else if (a.mode == SEL_L2) {
+    const float *base = a.vec + L.p0 * a.d_pad + (L.row - L.p0) * SLAB;
+    for (int d0 = lane; d0 < d; d0 += 64 * 16) {
+      float xv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int dim = d0 + 64 * u;
+        xv[u] = dim < d ? ldg(base + (int64_t)(dim / SLAB) * L.npad * SLAB + (dim % SLAB)) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (d0 + 64 * u < d) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+    }
+  } else if (a.mode == SEL_ADC) {
+    const uint8_t *code = a.codes + L.row * a.M;
+    const float *qh = a.qr_hi + q * a.ldqr, *ql = a.qr_lo + q * a.ldqr;
+    for (int d0 = lane; d0 < d; d0 += 64 * 8) {
+      uint32_t cm[8];
+      float x[8], h8[8], l8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int dim = d0 + 64 * u;
+        cm[u] = dim < d ? ldg(code + dim / a.dsub) : 0u;
+        h8[u] = dim < d ? ldg(qh + dim) : 0.f;
+        l8[u] = dim < d ? ldg(ql + dim) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int dim = d0 + 64 * u;
+        const int m = dim / a.dsub, t = dim - m * a.dsub;
+        x[u] = dim < d ? ldg(a.cb + ((int64_t)m * 256 + cm[u]) * a.dsub + t) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (d0 + 64 * u < d) acc_sq_diff2(h8[u], l8[u], x[u], S, C);
+    }
+  } else {  // SEL_QUANT, SEL_COARSE_QUANT: quantised query vs quantised row
+    const bool cq = a.mode == SEL_COARSE_QUANT;
+    const float xs = a.qfmt == 2 ? ldg(a.qscale + L.row) : 1.f;
+    const float qs = a.qfmt == 2 ? ldg(a.qQscale + q) : 1.f;
+    const int qeb = a.qfmt == 1 ? 2 : 1;
+    if (!cq) {  // 16-byte chunks of the stored row, inside one slab
+      const int per = 16 / qeb;
+      const uint8_t *vb =
+          (const uint8_t *)a.qvec + (L.p0 * a.qd_pad + (L.row - L.p0) * SLAB) * qeb;
+      for (int e0 = lane * per; e0 < d; e0 += 64 * per) {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 w4 =
+            ldg((const u32x4 *)(vb + ((int64_t)(e0 / SLAB) * L.npad * SLAB + e0 % SLAB) * qeb));
+        // the query's bytes at the same coordinates (rows are 16-byte aligned)
+        const u32x4 q4 = qq_lds ? *(const u32x4 *)(qq_lds + (int64_t)e0 * qeb)
+                                : ldg((const u32x4 *)((const uint8_t *)a.qQ +
+                                                      (q * a.ldqq + e0) * qeb));
+        const uint32_t wds[4] = {w4[0], w4[1], w4[2], w4[3]};
+        const uint32_t qds[4] = {q4[0], q4[1], q4[2], q4[3]};
+        const uint32_t msk = qeb == 2 ? 0xffffu : 0xffu;
+        for (int u = 0; u < per && e0 + u < d; ++u) {
+          const int sh = ((u * qeb) % 4) * 8;
+          const uint32_t bits = (wds[(u * qeb) / 4] >> sh) & msk;
+          const uint32_t qbits = (qds[(u * qeb) / 4] >> sh) & msk;
+          float qh, ql, xh, xl;
+          if (a.qfmt == 1) {
+            qh = bf16_to_float((uint16_t)qbits);
+            ql = 0.f;
+            xh = bf16_to_float((uint16_t)bits);
+            xl = 0.f;
+          } else {
+            two_prod(qs, e4m3_to_float(qbits), qh, ql);
+            two_prod(xs, e4m3_to_float(bits), xh, xl);
+          }
+          acc_sq_diff2(qh, ql - xl, xh, S, C);
+        }
+      }
+    } else {
+      for (int dim = lane; dim < d; dim += 64) {
+        float qh, ql, xh, xl;
+        if (qq_lds)
+          quant_value(a.qfmt, qq_lds, dim, qs, qh, ql, true);
+        else
+          quant_value(a.qfmt, a.qQ, q * a.ldqq + dim, qs, qh, ql);
+        quant_value(a.qfmt, a.qvec,
+                    ((int64_t)(dim / SLAB) * a.qnpad + L.row) * SLAB + (dim % SLAB), xs, xh, xl);
+        acc_sq_diff2(qh, ql - xl, xh, S, C);  // (qh + ql) - (xh + xl)
+      }
+    }
+  }
+}
+
+// Second exact measure: FP32 squared L2 on the first d_B coordinates
+// (centroid rows, or the slab layout).
+template <class QP>
+__device__ __forceinline__ void measureB(const SelArgs &a, bool coarse, const CandLoc &L, QP qrow,
+                                         int lane, float &S, float &C) {
+  const int d = a.d_B;
+  if (coarse) {
+    const float *x = a.cent + L.row * a.ld_cent;
+    for (int d0 = lane; d0 < d; d0 += 64 * 8) {
+      float xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) xv[u] = d0 + 64 * u < d ? ldg(x + d0 + 64 * u) : 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (d0 + 64 * u < d) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+    }
+  } else {
+    const float *base = a.vec + L.p0 * a.d_pad + (L.row - L.p0) * SLAB;
+    for (int d0 = lane; d0 < d; d0 += 64 * 16) {
+      float xv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int dim = d0 + 64 * u;
+        xv[u] = dim < d ? ldg(base + (int64_t)(dim / SLAB) * L.npad * SLAB + (dim % SLAB)) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (d0 + 64 * u < d) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+    }
+  }
+}
+
 __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
   extern __shared__ __attribute__((aligned(16))) unsigned char sel_smem[];
   uint32_t *hist = (uint32_t *)sel_smem;
@@ -754,121 +931,24 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
   // first exact measure, one wave per candidate; the query row is read from
   // LDS when staged, else from global memory (one instantiation each)
   const float ADANNS_GLOBAL_AS *qglob = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
-  auto measure1 = [&](auto qrow) {
-  for (int c = wv; c < ncand; c += nwv) {
-    const int64_t pos = cpos[c];
-    float S = 0.f, C = 0.f;
-    int64_t id, gpack;
-    if (coarse) {
-      id = pos;
-      gpack = pos;
-      if (a.mode == SEL_COARSE) {
-        const float *x = a.cent + pos * a.ld_cent;
-        for (int d0 = lane; d0 < a.d_dot; d0 += 64 * 8) {
-          float xv[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) xv[u] = d0 + 64 * u < a.d_dot ? ldg(x + d0 + 64 * u) : 0.f;
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (d0 + 64 * u < a.d_dot) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
-        }
-      } else {
-        const float xs = a.qfmt == 2 ? ldg(a.qscale + pos) : 1.f;
-        const float qs = a.qfmt == 2 ? ldg(a.qQscale + q) : 1.f;
-        for (int dim = lane; dim < a.d_dot; dim += 64) {
-          float qh, ql, xh, xl;
-          quant_value(a.qfmt, a.qQ, q * a.ldqq + dim, qs, qh, ql);
-          quant_value(a.qfmt, a.qvec,
-                      ((int64_t)(dim / SLAB) * a.qnpad + pos) * SLAB + (dim % SLAB), xs, xh, xl);
-          // (qh + ql) - (xh + xl)
-          acc_sq_diff2(qh, ql - xl, xh, S, C);
-        }
-      }
-    } else {
-      const int64_t pabs = seg0 + pos;
-      const int64_t *pb = a.pair_base + q * a.nprobe;
-      int lo = 0, hi = a.nprobe - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (pb[mid] <= pabs) lo = mid; else hi = mid - 1;
-      }
-      const int32_t h = a.probes[q * a.nprobe + lo];
-      const int64_t r = pabs - pb[lo];
-      const int64_t p0 = ldg(a.poff + h);
-      const int64_t npad = ldg(a.poff + h + 1) - p0;
-      id = ldg(a.rowid + p0 + r);
-      gpack = ((int64_t)h << 32) | r;
-      if (a.mode == SEL_L2) {
-        const float *base = a.vec + p0 * a.d_pad + r * SLAB;
-        for (int d0 = lane; d0 < a.d_dot; d0 += 64 * 16) {
-          float xv[16];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const int dim = d0 + 64 * u;
-            xv[u] = dim < a.d_dot ? ldg(base + (int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB))
-                                  : 0.f;
-          }
-#pragma unroll
-          for (int u = 0; u < 16; ++u)
-            if (d0 + 64 * u < a.d_dot) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
-        }
-      } else if (a.mode == SEL_ADC) {
-        const uint8_t *code = a.codes + (p0 + r) * a.M;
-        const float *qh = a.qr_hi + q * a.ldqr, *ql = a.qr_lo + q * a.ldqr;
-        for (int dim = lane; dim < a.d_dot; dim += 64) {
-          const int m = dim / a.dsub, t = dim - m * a.dsub;
-          const float x = ldg(a.cb + ((int64_t)m * 256 + ldg(code + m)) * a.dsub + t);
-          acc_sq_diff2(ldg(qh + dim), ldg(ql + dim), x, S, C);
-        }
-      } else if (qqstaged) {  // SEL_QUANT: 16-byte chunks of the stored row
-        const float xs = a.qfmt == 2 ? ldg(a.qscale + p0 + r) : 1.f;
-        const float qs = a.qfmt == 2 ? ldg(a.qQscale + q) : 1.f;
-        const int per = 16 / qeb;  // coordinates per chunk, inside one slab
-        const uint8_t *vb = (const uint8_t *)a.qvec + (p0 * a.qd_pad + r * SLAB) * qeb;
-        for (int e0 = lane * per; e0 < a.d_dot; e0 += 64 * per) {
-          typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-          const u32x4 w4 = ldg((const u32x4 *)(vb + ((int64_t)(e0 / SLAB) * npad * SLAB + e0 % SLAB) * qeb));
-          const uint32_t wds[4] = {w4[0], w4[1], w4[2], w4[3]};
-          for (int u = 0; u < per && e0 + u < a.d_dot; ++u) {
-            float qh, ql, xh, xl;
-            quant_value(a.qfmt, qqstage, e0 + u, qs, qh, ql, true);
-            const uint32_t bits = (wds[(u * qeb) / 4] >> (((u * qeb) % 4) * 8)) &
-                                  (qeb == 2 ? 0xffffu : 0xffu);
-            if (a.qfmt == 1) {
-              xh = bf16_to_float((uint16_t)bits);
-              xl = 0.f;
-            } else {
-              two_prod(xs, e4m3_to_float(bits), xh, xl);
-            }
-            acc_sq_diff2(qh, ql - xl, xh, S, C);
-          }
-        }
-      } else {  // SEL_QUANT, query too wide to stage
-        const float xs = a.qfmt == 2 ? ldg(a.qscale + p0 + r) : 1.f;
-        const float qs = a.qfmt == 2 ? ldg(a.qQscale + q) : 1.f;
-        for (int dim = lane; dim < a.d_dot; dim += 64) {
-          float qh, ql, xh, xl;
-          quant_value(a.qfmt, a.qQ, q * a.ldqq + dim, qs, qh, ql);
-          quant_value(a.qfmt, a.qvec,
-                      p0 * a.qd_pad + ((int64_t)(dim / SLAB) * npad + r) * SLAB + (dim % SLAB), xs,
-                      xh, xl);
-          acc_sq_diff2(qh, ql - xl, xh, S, C);
-        }
+  auto run1 = [&](auto qrow) {
+    for (int c = wv; c < ncand; c += nwv) {
+      const CandLoc Lc = locate(a, coarse, q, seg0, cpos[c]);
+      float S = 0.f, C = 0.f;
+      measure1(a, q, Lc, qrow, qqstaged ? qqstage : nullptr, lane, S, C);
+      wave_reduce_pair(S, C);
+      if (lane == 0) {
+        chi[c] = S;
+        clo[c] = C;
+        cid[c] = Lc.id;
+        cg[c] = Lc.gpack;
       }
     }
-    wave_reduce_pair(S, C);
-    if (lane == 0) {
-      chi[c] = S;
-      clo[c] = C;
-      cid[c] = id;
-      cg[c] = gpack;
-    }
-  }
   };
   if (qstaged)
-    measure1(qstage);
+    run1(qstage);
   else
-    measure1(qglob);
+    run1(qglob);
   int P2 = 1;
   while (P2 < ncand) P2 <<= 1;
   for (int c = ncand + tid; c < P2; c += blockDim.x) {
@@ -883,42 +963,21 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
   if (a.stageB) {
     // second exact measure (FP32 L2 on d_B coordinates) of the K2 best
     nres = ncand < a.K2 ? ncand : a.K2;
-    auto measure2 = [&](auto qrow) {
-    for (int c = wv; c < nres; c += nwv) {
-      float S = 0.f, C = 0.f;
-      if (coarse) {
-        const float *x = a.cent + cg[c] * a.ld_cent;
-        for (int dim = lane; dim < a.d_B; dim += 64) acc_sq_diff(qrow[dim], ldg(x + dim), S, C);
-      } else {
-        const int32_t h = (int32_t)(cg[c] >> 32);
-        const int64_t r = cg[c] & 0xffffffffll;
-        const int64_t p0 = ldg(a.poff + h);
-        const int64_t npad = ldg(a.poff + h + 1) - p0;
-        const float *base = a.vec + p0 * a.d_pad + r * SLAB;
-        for (int d0 = lane; d0 < a.d_B; d0 += 64 * 16) {
-          float xv[16];
-#pragma unroll
-          for (int u = 0; u < 16; ++u) {
-            const int dim = d0 + 64 * u;
-            xv[u] = dim < a.d_B ? ldg(base + (int64_t)(dim / SLAB) * npad * SLAB + (dim % SLAB))
-                                : 0.f;
-          }
-#pragma unroll
-          for (int u = 0; u < 16; ++u)
-            if (d0 + 64 * u < a.d_B) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+    auto run2 = [&](auto qrow) {
+      for (int c = wv; c < nres; c += nwv) {
+        float S = 0.f, C = 0.f;
+        measureB(a, coarse, locate_packed(a, coarse, cg[c]), qrow, lane, S, C);
+        wave_reduce_pair(S, C);
+        if (lane == 0) {
+          chi[c] = S;
+          clo[c] = C;
         }
       }
-      wave_reduce_pair(S, C);
-      if (lane == 0) {
-        chi[c] = S;
-        clo[c] = C;
-      }
-    }
     };
     if (qstaged)
-      measure2(qstage);
+      run2(qstage);
     else
-      measure2(qglob);
+      run2(qglob);
     __syncthreads();
     int P3 = 1;
     while (P3 < nres) P3 <<= 1;
@@ -946,6 +1005,17 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
 }
 
 __global__ __launch_bounds__(512) void k_select_refine(SelArgs a) { select_body(a, blockIdx.x); }
+
+// The same selection and measures for one query on one wave, without LDS
+// or barriers, when K1 <= 64 (see k_select_wave below for the list
+// mechanics). Results equal select_body's.
+__device__ void wave_select(const SelArgs &a, const int64_t q, const int lane);
+
+__global__ __launch_bounds__(256) void k_select_refine_wave(SelArgs a, int64_t nq) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= nq) return;  // whole waves leave; nothing synchronises the block
+  wave_select(a, q, threadIdx.x & 63);
+}
 
 // Batched FP32 selection: one block per query row of the batch; the
 // configuration's fields are patched into the arguments.
@@ -1040,6 +1110,128 @@ __device__ __forceinline__ int64_t shfl_xor64(int64_t v, int m) {
   const uint32_t lo = __shfl_xor((uint32_t)(uint64_t)v, m);
   const uint32_t hi = __shfl_xor((uint32_t)((uint64_t)v >> 32), m);
   return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ void bitonic_lanes(float &S, float &C, int64_t &id, int64_t &gp,
+                                              int lane) {
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const float oS = __shfl_xor(S, j), oC = __shfl_xor(C, j);
+      const int64_t oid = shfl_xor64(id, j), ogp = shfl_xor64(gp, j);
+      const bool up = (lane & k) == 0, lower = (lane & j) == 0;
+      const bool other_less = pair_less(oS, oC, oid, S, C, id);
+      if ((lower == up) ? other_less : !other_less) {
+        S = oS;
+        C = oC;
+        id = oid;
+        gp = ogp;
+      }
+    }
+  }
+}
+
+__device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
+  const bool coarse = a.mode == SEL_COARSE || a.mode == SEL_COARSE_QUANT;
+  const int64_t ldo = a.ldo ? a.ldo : a.kout;
+  const float *seg;
+  int64_t L, seg0 = 0;
+  if (coarse) {
+    seg = a.D + q * a.nl;
+    L = a.nl;
+  } else {
+    seg0 = a.seg_off[q];
+    seg = a.D + seg0;
+    L = a.seg_off[q + 1] - seg0;
+  }
+  // 1. the K1 smallest (key, position) composites, sorted over the lanes
+  const int K1 = a.K1;
+  const float ADANNS_GLOBAL_AS *sg = (const float ADANNS_GLOBAL_AS *)seg;
+  uint64_t best = ~0ull, thr = ~0ull;
+  constexpr int U = 16;
+  for (int64_t base = 0; base < L; base += 64 * U) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + 64 * u + lane;
+      v[u] = i < L ? sg[i] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + 64 * u + lane;
+      const uint64_t comp = i < L ? ((uint64_t)order_key(v[u]) << 32) | (uint64_t)i : ~0ull;
+      uint64_t mask = __ballot(comp < thr);
+      while (mask) {
+        const int b = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const uint64_t x = readlane64(comp, b);
+        if (x < thr) {
+          const uint64_t up = shfl_up64(best, 1);
+          if (!(best < x)) best = (lane == 0 || up < x) ? x : up;
+          thr = readlane64(best, K1 - 1);
+        }
+      }
+    }
+  }
+  const int ncand = (int)min64(L, (int64_t)K1);
+  // 2. lane j < ncand locates candidate j
+  CandLoc mine{INT64_MAX, -1, 0, 0, 0};
+  if (lane < ncand) mine = locate(a, coarse, q, seg0, (int64_t)(uint32_t)best);
+  // 3. first exact measure, one candidate at a time over the lanes
+  const float ADANNS_GLOBAL_AS *qglob = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
+  float myS = __builtin_inff(), myC = 0.f;
+  for (int cc = 0; cc < ncand; ++cc) {
+    CandLoc Lc;
+    Lc.id = (int64_t)readlane64((uint64_t)mine.id, cc);
+    Lc.gpack = (int64_t)readlane64((uint64_t)mine.gpack, cc);
+    Lc.row = (int64_t)readlane64((uint64_t)mine.row, cc);
+    Lc.p0 = (int64_t)readlane64((uint64_t)mine.p0, cc);
+    Lc.npad = (int64_t)readlane64((uint64_t)mine.npad, cc);
+    float S = 0.f, C = 0.f;
+    measure1(a, q, Lc, qglob, nullptr, lane, S, C);
+    wave_reduce_pair(S, C);
+    if (lane == cc) {
+      myS = S;
+      myC = C;
+    }
+  }
+  int64_t myid = mine.id, mygp = mine.gpack;
+  bitonic_lanes(myS, myC, myid, mygp, lane);
+  int nres = ncand;
+  if (a.stageB) {
+    // second exact measure (FP32 L2 on d_B coordinates) of the K2 best
+    nres = ncand < a.K2 ? ncand : a.K2;
+    if (lane >= nres) {
+      myS = __builtin_inff();
+      myC = 0.f;
+      myid = INT64_MAX;
+      mygp = -1;
+    }
+    for (int cc = 0; cc < nres; ++cc) {
+      const int64_t gp = (int64_t)readlane64((uint64_t)mygp, cc);
+      float S = 0.f, C = 0.f;
+      measureB(a, coarse, locate_packed(a, coarse, gp), qglob, lane, S, C);
+      wave_reduce_pair(S, C);
+      if (lane == cc) {
+        myS = S;
+        myC = C;
+      }
+    }
+    bitonic_lanes(myS, myC, myid, mygp, lane);
+  }
+  if (lane < a.kout) {
+    const bool has = lane < nres;
+    if (coarse) {
+      const int32_t hsel = has ? (int32_t)myid : -1;
+      a.out_probes[q * a.kout + lane] = hsel;
+      if (a.out_probes2) a.out_probes2[q * a.kout + lane] = hsel;
+      if (a.out_dist && lane == 0) a.out_dist[q * ldo] = has ? myS : __builtin_inff();
+    } else {
+      a.out_dist[q * ldo + lane] = has ? myS : __builtin_inff();
+      a.out_ids[q * ldo + lane] = has ? myid : -1;
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qtot) {
@@ -1267,57 +1459,52 @@ __global__ __launch_bounds__(256) void k_pq_encode(const float *__restrict__ X, 
 }
 
 // q' = q[:d_s] R in compensated FP32 (TwoProd + TwoSum), stored as a pair
-// (hi, lo). ROT_Q queries per workgroup share each read of R.
-constexpr int ROT_Q = 4;
-constexpr int ROT_MAXC = 8;  // output columns per thread: d_s <= 2048
+// (hi, lo). A workgroup computes ROT_Q queries x 256 output columns
+// (blockIdx.y picks the columns); the queries share each read of R.
+constexpr int ROT_Q = 16;
+constexpr int ROT_CHUNK = 512;  // query coordinates staged in LDS at a time
 __global__ __launch_bounds__(256) void k_rotate(const float *__restrict__ Qs, int64_t ldqs,
                                                 int64_t nq, const float *__restrict__ R,
                                                 int32_t d_s, float *__restrict__ qh,
                                                 float *__restrict__ ql, int64_t ldqr) {
 #pragma clang fp contract(off)
-  extern __shared__ float qsh[];  // [ROT_Q][d_s]
+  __shared__ float qsh[ROT_Q][ROT_CHUNK];
   const int tid = threadIdx.x;
   const int64_t q0 = (int64_t)blockIdx.x * ROT_Q;
-  for (int i = tid; i < ROT_Q * d_s; i += blockDim.x) {
-    const int qq = i / d_s, c = i % d_s;
-    qsh[i] = q0 + qq < nq ? Qs[(q0 + qq) * ldqs + c] : 0.f;
-  }
-  __syncthreads();
-  float S[ROT_Q][ROT_MAXC], C[ROT_Q][ROT_MAXC];
+  const int j = blockIdx.y * 256 + tid;
+  float S[ROT_Q], C[ROT_Q];
 #pragma unroll
-  for (int a = 0; a < ROT_Q; ++a)
-#pragma unroll
-    for (int b = 0; b < ROT_MAXC; ++b) S[a][b] = C[a][b] = 0.f;
-  for (int i = 0; i < d_s; ++i) {
-#pragma unroll
-    for (int b = 0; b < ROT_MAXC; ++b) {
-      const int j = tid + b * 256;
-      if (j < d_s) {
-        const float r = R[(int64_t)i * d_s + j];
+  for (int a = 0; a < ROT_Q; ++a) S[a] = C[a] = 0.f;
+  for (int i0 = 0; i0 < d_s; i0 += ROT_CHUNK) {
+    const int ni = min(ROT_CHUNK, d_s - i0);
+    __syncthreads();  // the previous chunk is consumed
+    for (int e = tid; e < ROT_Q * ROT_CHUNK; e += blockDim.x) {
+      const int qq = e / ROT_CHUNK, c = e % ROT_CHUNK;
+      qsh[qq][c] = (q0 + qq < nq && c < ni) ? Qs[(q0 + qq) * ldqs + i0 + c] : 0.f;
+    }
+    __syncthreads();
+    if (j < d_s) {
+      for (int i = 0; i < ni; ++i) {
+        const float r = R[(int64_t)(i0 + i) * d_s + j];
 #pragma unroll
         for (int a = 0; a < ROT_Q; ++a) {
           float p, pe, t, te;
-          two_prod(qsh[a * d_s + i], r, p, pe);
-          two_sum(S[a][b], p, t, te);
-          S[a][b] = t;
-          C[a][b] = C[a][b] + (te + pe);
+          two_prod(qsh[a][i], r, p, pe);
+          two_sum(S[a], p, t, te);
+          S[a] = t;
+          C[a] = C[a] + (te + pe);
         }
       }
     }
   }
+  if (j >= d_s) return;
 #pragma unroll
   for (int a = 0; a < ROT_Q; ++a) {
-    if (q0 + a >= nq) continue;
-#pragma unroll
-    for (int b = 0; b < ROT_MAXC; ++b) {
-      const int j = tid + b * 256;
-      if (j < d_s) {
-        float hi, lo;
-        two_sum(S[a][b], C[a][b], hi, lo);
-        qh[(q0 + a) * ldqr + j] = hi;
-        ql[(q0 + a) * ldqr + j] = lo;
-      }
-    }
+    if (q0 + a >= nq) break;
+    float hi, lo;
+    two_sum(S[a], C[a], hi, lo);
+    qh[(q0 + a) * ldqr + j] = hi;
+    ql[(q0 + a) * ldqr + j] = lo;
   }
 }
 
@@ -1343,11 +1530,15 @@ __global__ __launch_bounds__(256) void k_pq_lut(const float *__restrict__ qh, in
 }
 
 // ADC scan of one (query, probe) pair: the query's table is held in LDS and
-// every vector of the probed list sums M table entries picked by its codes.
+// every vector of the probed list sums the M table entries its codes pick
+// (in code order m = 0..M-1). One pair per workgroup: the pairs of a query
+// re-read its table from L2, but their lists' latencies overlap (several
+// pairs per workgroup, each loading its table once, measured slower).
 __global__ __launch_bounds__(256) void k_adc_scan(const float *__restrict__ lut, int32_t M,
                                                   const uint8_t *__restrict__ codes,
                                                   const int32_t *__restrict__ probes,
-                                                  int32_t nprobe, const int64_t *__restrict__ poff,
+                                                  int32_t nprobe,
+                                                  const int64_t *__restrict__ poff,
                                                   const int32_t *__restrict__ len,
                                                   const int64_t *__restrict__ pair_base,
                                                   float *__restrict__ D) {
@@ -1357,22 +1548,40 @@ __global__ __launch_bounds__(256) void k_adc_scan(const float *__restrict__ lut,
   const float4 *src = (const float4 *)(lut + q * M * 256);
   for (int i = threadIdx.x; i < M * 64; i += blockDim.x) ((float4 *)tab)[i] = src[i];
   __syncthreads();
-  const int32_t h = probes[pair];
-  const int32_t n = len[h];
-  const uint8_t *cbase = codes + poff[h] * M;
-  float *out = D + pair_base[pair];
-  for (int r = threadIdx.x; r < n; r += blockDim.x) {
-    const uint32_t *row = (const uint32_t *)(cbase + (int64_t)r * M);
-    float acc = 0.f;
-    for (int w = 0; w < (M >> 2); ++w) {
-      const uint32_t c4 = row[w];
-      const int m = w * 4;
-      acc += tab[(m + 0) * 256 + (c4 & 0xff)];
-      acc += tab[(m + 1) * 256 + ((c4 >> 8) & 0xff)];
-      acc += tab[(m + 2) * 256 + ((c4 >> 16) & 0xff)];
-      acc += tab[(m + 3) * 256 + (c4 >> 24)];
+  {
+    const int32_t h = probes[pair];
+    const int32_t n = len[h];
+    const uint8_t *cbase = codes + poff[h] * M;
+    float *out = D + pair_base[pair];
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+      float acc = 0.f;
+      if ((M & 15) == 0) {  // 16 codes per load (rows are 16-byte aligned)
+        const uint4 *row = (const uint4 *)(cbase + (int64_t)r * M);
+        for (int w = 0; w < (M >> 4); ++w) {
+          const uint4 c16 = row[w];
+          const uint32_t wd[4] = {c16.x, c16.y, c16.z, c16.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int m = w * 16 + e * 4;
+            acc += tab[(m + 0) * 256 + (wd[e] & 0xff)];
+            acc += tab[(m + 1) * 256 + ((wd[e] >> 8) & 0xff)];
+            acc += tab[(m + 2) * 256 + ((wd[e] >> 16) & 0xff)];
+            acc += tab[(m + 3) * 256 + (wd[e] >> 24)];
+          }
+        }
+      } else {
+        const uint32_t *row = (const uint32_t *)(cbase + (int64_t)r * M);
+        for (int w = 0; w < (M >> 2); ++w) {
+          const uint32_t c4 = row[w];
+          const int m = w * 4;
+          acc += tab[(m + 0) * 256 + (c4 & 0xff)];
+          acc += tab[(m + 1) * 256 + ((c4 >> 8) & 0xff)];
+          acc += tab[(m + 2) * 256 + ((c4 >> 16) & 0xff)];
+          acc += tab[(m + 3) * 256 + (c4 >> 24)];
+        }
+      }
+      out[r] = acc;
     }
-    out[r] = acc;
   }
 }
 
@@ -1855,6 +2064,18 @@ static int32_t seg_cap(int32_t kcap, int64_t max_len) {
 }
 
 // Sets the LDS caps of a single-configuration selection; returns its bytes.
+// One query per wave when the first shortlist fits the lanes and the exact
+// measures are short (one wave measures the candidates one after another);
+// else one workgroup of eight waves per query.
+static void launch_select(const SelArgs &s, int64_t nq, size_t smem, hipStream_t st) {
+  if (nq == 0) return;
+  const int64_t measure = (int64_t)s.K1 * s.d_dot + (s.stageB ? (int64_t)s.K2 * s.d_B : 0);
+  if (s.K1 <= WSEL_K && s.kout <= WSEL_K && measure <= 96 * 1024)
+    hipLaunchKernelGGL(k_select_refine_wave, dim3((unsigned)cdiv(nq, 4)), dim3(256), 0, st, s, nq);
+  else
+    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(512), smem, st, s);
+}
+
 static size_t sel_caps(SelArgs &s, int64_t max_len) {
   s.kcap = next_pow2(std::max(std::max(s.K1, s.kout), 1));
   s.lcap = seg_cap(s.kcap, max_len);
@@ -2187,7 +2408,7 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   {
     const size_t smem = sel_caps(s, ix->nlist);
     KernelTimer tm("select_q_coarse", st);
-    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(512), smem, st, s);
+    launch_select(s, nq, smem, st);
   }
   e = launch_bucketing(ix, b, nq, nprobe, st);
   if (e != hipSuccess) return e;
@@ -2250,7 +2471,7 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   {
     const size_t smem = sel_caps(r, SEG_LDS_CAP);
     KernelTimer tm("select_q_scan", st);
-    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(512), smem, st, r);
+    launch_select(r, nq, smem, st);
   }
   return hipGetLastError();
 }
@@ -2259,8 +2480,8 @@ hipError_t launch_rotate(const float *Qs, int64_t ldqs, int64_t nq, const float 
                          float *qh, float *ql, int64_t ldqr, hipStream_t st) {
   if (nq == 0) return hipSuccess;
   KernelTimer tm("pq_rotate", st);
-  hipLaunchKernelGGL(k_rotate, dim3((unsigned)cdiv(nq, ROT_Q)), dim3(256),
-                     ROT_Q * d_s * sizeof(float), st, Qs, ldqs, nq, R, d_s, qh, ql, ldqr);
+  hipLaunchKernelGGL(k_rotate, dim3((unsigned)cdiv(nq, ROT_Q), (unsigned)cdiv(d_s, 256)),
+                     dim3(256), 0, st, Qs, ldqs, nq, R, d_s, qh, ql, ldqr);
   return hipGetLastError();
 }
 
@@ -2295,9 +2516,10 @@ hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const Sea
   }
   {
     KernelTimer tm("adc_scan", st);
-    hipLaunchKernelGGL(k_adc_scan, dim3((unsigned)(nq * nprobe)), dim3(256),
-                       pq.M * 256 * sizeof(float), st, lut, pq.M, pq.codes, b.probes, nprobe,
-                       ix->poff, ix->len, b.pair_base, b.D);
+    if (nq > 0)
+      hipLaunchKernelGGL(k_adc_scan, dim3((unsigned)(nq * nprobe)), dim3(256),
+                         pq.M * 256 * sizeof(float), st, lut, pq.M, pq.codes, b.probes, nprobe,
+                         ix->poff, ix->len, b.pair_base, b.D);
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -2333,7 +2555,7 @@ hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const Sea
   {
     const size_t smem = sel_caps(s, SEG_LDS_CAP);
     KernelTimer tm("select_adc", st);
-    hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(512), smem, st, s);
+    launch_select(s, nq, smem, st);
   }
   return hipGetLastError();
 }
