@@ -78,17 +78,18 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str, per_launch_units: float):
-    """HBM bytes per launch from committed counter summaries, if they were
-    taken on the current kernel source; otherwise None."""
+def measured_traffic(kernel: str, workload: str, shape):
+    """HBM bytes per launch of ``kernel`` at tile shape ``shape`` (tq, tv, grid)
+    from the committed counter summary, if it was taken on the current kernel
+    source; otherwise None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or shape is None:
         return None
     with open(path) as fh:
         t = json.load(fh)
     if t.get("kernel_source_digest") != kernel_source_digest():
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t.get("hbm_bytes_per_launch_by_shape", {}).get("%dx%dx%d" % tuple(shape))
 
 
 def main():
@@ -202,7 +203,7 @@ def main():
         roof = {"kernel": dominant, "bound": "mfma", "achieved": round(ach, 2),
                 "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / MFMA_FP32_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(dominant, w.name, 1.0),
+                "traffic": measured_traffic(dominant, w.name, shape),
                 "algorithmic_flops_per_launch": flops[dominant],
                 "avg_launch_ms": round(kern[dominant], 4)}
     else:
