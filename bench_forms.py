@@ -1,5 +1,5 @@
 """The non-headline measurements of ``bench.py`` (``--form``): the precision
-form, the batching form, IVF-PQ and the serving loop. Each prints one JSON
+form, the batching form, IVF-PQ, the serving loop and the data diagnostics. Each prints one JSON
 line. The oracle is used only in the CPU-baseline / reference legs (recall
 ground truth and parity checks), never on the timed path.
 """
@@ -40,7 +40,7 @@ def _kernel_ms(lib, names):
 
 def run(args, lib, torch, log):
     {"precision": precision_form, "batching": batching_form, "pq": pq_form,
-     "serving": serving_form}[args.form](args, lib, torch, log)
+     "serving": serving_form, "diagnostics": diagnostics_form}[args.form](args, lib, torch, log)
 
 
 # ---------------------------------------------------------------------------
@@ -332,5 +332,76 @@ def serving_form(args, lib, torch, log):
            "latency_by_nprobe_ms": per_budget,
            "stats": {k_: (float(v) if isinstance(v, float) else int(v)) for k_, v in stats.items()},
            "completed": int(ok.sum())}
+    index.free()
+    print(json.dumps(out), flush=True)
+
+
+def diagnostics_form(args, lib, torch, log):
+    """Is the synthetic data Matryoshka-like? Centroid 1-Recall@N of the
+    coarse step at prefix d_c against the full-width ranking (the paper's
+    centroid study, Appendix: the highest width is the ground truth), from
+    the library's coarse step on full-width centroids; plus the relative
+    contrast of prefixes on a bounded sample with the oracle."""
+    from oracle import metrics
+
+    w = synth.WORKLOADS["imagenet1k"]
+    n = args.n or w.n
+    nq = args.nq or w.nq
+    mix = w.mixture()
+    X = mix.database(n)
+    Q = mix.queries(nq)
+    Xd = torch.from_numpy(X).cuda()
+    Qd = torch.from_numpy(Q).cuda()
+    n_train = min(n, 64 * w.nlist)
+    tr = synth.subsample_rows(n, n_train, w.seed)
+    init = synth.init_rows(n_train, w.nlist, w.seed)
+    t0 = time.time()
+    index = lib.IvfIndex.build_ivf(Xd, w.nlist, w.d, args.iters, init, train_rows=tr)
+    torch.cuda.synchronize()
+    log(f"full-width IVF (nlist {w.nlist}, d_c {w.d}) built in {time.time() - t0:.1f}s")
+    del Xd
+    torch.cuda.empty_cache()
+    Ns = [1, 2, 4, 8, 16, 32, 64]
+    widths = [8, 16, 32, 64, 128, 256, 512, 1024, 2048]
+    probes = {}
+    lib.timing_reset()
+    lib.timing_enable(True)
+    for dc in widths:
+        # the scan budget is irrelevant here; the coarse step returns probes
+        # (query chunks bound the first-pass scratch)
+        parts = []
+        for q0 in range(0, nq, 5000):
+            _, _, p = index.search(Qd[q0:q0 + 5000], dc, 8, max(Ns), 1, return_probes=True)
+            parts.append(p.cpu().numpy())
+        probes[dc] = np.concatenate(parts)
+    lib.timing_enable(False)
+    coarse_ms = _kernel_ms(lib, ["tile_dist_coarse", "select_coarse"])
+    truth = probes[w.d][:, 0]
+    rec = {f"d_c={dc}": {f"N={N}": round(float(np.mean(np.any(probes[dc][:, :N] == truth[:, None],
+                                                                 axis=1))), 4) for N in Ns}
+           for dc in widths}
+    # the same numbers from the oracle on a sample (FP64 ranking of the
+    # library's centroids)
+    C = index.centroids()
+    sample = np.arange(min(args.cpu_sample, nq))
+    check = {}
+    for dc in (8, 64, 512):
+        for N in (1, 8):
+            ref = metrics.centroid_recall(Q[sample], C, dc, 1, N)
+            got = float(np.mean(np.any(probes[dc][sample, :N] == truth[sample, None], axis=1)))
+            check[f"d_c={dc},N={N}"] = {"oracle": ref, "library": got}
+    rng = np.random.default_rng(synth.ROOT_SEED + 55)
+    rows = np.sort(rng.choice(n, size=min(n, 65536), replace=False))
+    rc = {f"d={d}": round(metrics.relative_contrast(X[rows], Q[:16], d), 4)
+          for d in (8, 32, 128, 512, 2048)}
+    out = {"metric": "centroid 1-Recall@N of the coarse step at prefix d_c (full-width truth)",
+           "value": rec["d_c=64"]["N=8"], "unit": "fraction", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": f"imagenet1k: N={n} d={w.d} nq={nq} nlist={w.nlist}, "
+                                  f"centroids on the full width; value at d_c=64, N=8"},
+           "centroid_recall": rec, "coarse_kernels_ms": coarse_ms,
+           "oracle_check_sample": {"queries": len(sample), "values": check},
+           "relative_contrast": {"values": rc,
+                                 "sample": "16 queries x 65,536 seeded database rows, oracle FP64"}}
     index.free()
     print(json.dumps(out), flush=True)
