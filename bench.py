@@ -225,6 +225,33 @@ def main():
     scan_bytes = 4.0 * n * d_s  # one read of the d_s prefix of every vector
     roof["scan_hbm_floor_frac"] = round(scan_bytes / (kern.get("tile_dist_scan", 1e9) * 1e-3)
                                         / 1e9 / HBM_PEAK_GBS, 4)
+    # measured copy bandwidth of this GPU (1 GiB read + 1 GiB written), for
+    # context beside the published 8 TB/s
+    a_ = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b_ = torch.empty_like(a_)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b_.copy_(a_)
+    e0.record()
+    for _ in range(5):
+        b_.copy_(a_)
+    e1.record()
+    torch.cuda.synchronize()
+    roof["stream_copy_gbs"] = round(5 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a_, b_
+    # every other kernel of the step against its own bound (algorithmic work)
+    sel_bytes = 4.0 * cand + nq * (k + 8) * d_s * 4.0  # first-pass values + gathered rows
+    others = {}
+    if "tile_dist_coarse" in kern:
+        t_ = flops["tile_dist_coarse"] / (kern["tile_dist_coarse"] * 1e-3) / 1e12
+        others["tile_dist_coarse"] = {"bound": "mfma", "achieved": round(t_, 2),
+                                      "unit": "TFLOP/s",
+                                      "frac": round(t_ / MFMA_FP32_PEAK_TFLOPS, 4)}
+    if "select_scan" in kern:
+        g_ = sel_bytes / (kern["select_scan"] * 1e-3) / 1e9
+        others["select_scan"] = {"bound": "hbm", "achieved": round(g_, 1), "unit": "GB/s",
+                                 "frac": round(g_ / HBM_PEAK_GBS, 4),
+                                 "algorithmic_bytes_per_launch": sel_bytes}
+    roof["other_kernels"] = others
 
     out = {
         "metric": METRIC,

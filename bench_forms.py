@@ -203,16 +203,17 @@ def batching_form(args, lib, torch, log):
 
 # ---------------------------------------------------------------------------
 def _nq_index(args, lib, torch, log):
-    """The NQ-shaped IVF-PQ index: N x 768 vectors stored FP16 (converted to
-    FP32 on the device for the layout), nlist 16384 on the d_c = 64 prefix,
-    GPU-trained PQ codecs with M = 32 and 64 after a seeded random rotation."""
+    """The NQ-shaped IVF-PQ index: N x 768 vectors stored FP16 (handed to the
+    library as FP16; the index converts them to FP32 in its layout), nlist
+    16384 on the d_c = 64 prefix, GPU-trained PQ codecs with M = 32 and 64
+    after a seeded random rotation."""
     w = synth.WORKLOADS["nq21m"]
     n = args.n or w.n
     mix = w.mixture()
     t0 = time.time()
     X16 = mix.database(n, dtype=np.float16)
     log(f"generated {X16.shape} fp16 in {time.time() - t0:.1f}s")
-    Xd = torch.from_numpy(X16).cuda().float()
+    Xd = torch.from_numpy(X16).cuda()
     torch.cuda.synchronize()
     nlist = w.nlist if n >= 64 * w.nlist else max(64, int(np.sqrt(n)))
     n_train = min(n, 64 * nlist)

@@ -52,6 +52,13 @@ typedef enum adanns_status {
   ADANNS_EIO = -6          /* a file could not be opened, read or written, or is malformed */
 } adanns_status;
 
+/* Element type of a database matrix handed to the library. Half elements
+ * convert exactly to FP32; the index stores FP32. */
+typedef enum adanns_dtype {
+  ADANNS_DTYPE_F32 = 0,
+  ADANNS_DTYPE_F16 = 1     /* IEEE binary16 */
+} adanns_dtype;
+
 typedef enum adanns_format {
   ADANNS_FP32 = 0,
   ADANNS_BF16 = 1,         /* round-to-nearest-even bfloat16 */
@@ -68,7 +75,8 @@ const char *adanns_version(void);
  * Import an IVF index whose clustering was computed elsewhere (Section 3,
  * "Inverted File Index": centroids plus the inverted file of each cluster's
  * members; Algorithm 1, construction on the d_c_build prefix).
- *   X         device, [n x d] FP32 rows, row stride ldx >= d. Copied.
+ *   X         device, [n x d] rows of element type ``dtype`` (adanns_dtype),
+ *             row stride ldx >= d elements. Copied (converted to FP32).
  *   centroids device, [nlist x d_c_build] FP32, row stride d_c_build. Copied.
  *   assign    device, [n] int32, the list of each row, each in [0, nlist).
  * Lists keep their members in ascending row order; a row's id is its index
@@ -76,7 +84,7 @@ const char *adanns_version(void);
  * 1 <= d_c_build <= d, n < 2^31. Synchronises ``stream``.
  * On success *out owns the index; release it with adanns_index_free().
  */
-adanns_status adanns_ivf_import(const float *X, int64_t n, int32_t d, int64_t ldx,
+adanns_status adanns_ivf_import(const void *X, int64_t n, int32_t d, int64_t ldx, int32_t dtype,
                                 const float *centroids, int32_t nlist, int32_t d_c_build,
                                 const int32_t *assign, void *stream, adanns_index **out);
 
@@ -84,7 +92,8 @@ adanns_status adanns_ivf_import(const float *X, int64_t n, int32_t d, int64_t ld
  * Build an IVF index on the GPU: Lloyd's k-means on X[:, :d_c] (Section 3,
  * "Inverted File Index"; Section 4.1; Algorithm 1, construction), then one
  * final assignment of every row, which defines the inverted lists.
- *   X          device, [n x d] FP32, row stride ldx >= d. Copied.
+ *   X          device, [n x d] of element type ``dtype``, row stride ldx >= d
+ *              elements. Copied (converted to FP32).
  *   train_rows host, [n_train] int64 rows of X the iterations run on, or
  *              NULL for all rows (then n_train is ignored).
  *   init_rows  host, [nlist] int32 indices into the training rows: the
@@ -99,8 +108,8 @@ adanns_status adanns_ivf_import(const float *X, int64_t n, int32_t d, int64_t ld
  * FP32). Limits as adanns_ivf_import; the training set must hold at least
  * nlist rows. Synchronises ``stream``; allocates temporary device memory.
  */
-adanns_status adanns_build_ivf(const float *X, int64_t n, int32_t d, int64_t ldx, int32_t nlist,
-                               int32_t d_c, int32_t iters, const int32_t *init_rows,
+adanns_status adanns_build_ivf(const void *X, int64_t n, int32_t d, int64_t ldx, int32_t dtype,
+                               int32_t nlist, int32_t d_c, int32_t iters, const int32_t *init_rows,
                                const int64_t *train_rows, int64_t n_train, double *objective,
                                void *stream, adanns_index **out);
 
@@ -161,11 +170,12 @@ adanns_status adanns_pq_import(adanns_index *index, int32_t M, int32_t d_s, cons
  * nearest codeword per block (FP32 difference form, ties to the smaller
  * index). The rotation is not learned here (no Procrustes step); a learned
  * OPQ rotation and its codebooks can be attached with adanns_pq_import.
- *   X  device, the index's database [n x d] FP32 (row j = id j), stride ldx.
+ *   X  device, the index's database [n x d] of element type ``dtype`` (row j =
+ *      id j), stride ldx elements.
  * Limits: as adanns_pq_import, and d_s / M <= 32. Synchronises ``stream``.
  */
-adanns_status adanns_pq_train(adanns_index *index, const float *X, int64_t ldx, int32_t M,
-                              int32_t d_s, const float *R, int32_t iters,
+adanns_status adanns_pq_train(adanns_index *index, const void *X, int64_t ldx, int32_t dtype,
+                              int32_t M, int32_t d_s, const float *R, int32_t iters,
                               const int32_t *init_rows, const int64_t *train_rows,
                               int64_t n_train, void *stream);
 

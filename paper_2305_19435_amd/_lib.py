@@ -30,11 +30,12 @@ PIX = C.POINTER(vp)
 _SIGS = {
     "adanns_last_error": (C.c_char_p, []),
     "adanns_version": (C.c_char_p, []),
-    "adanns_ivf_import": (C.c_int, [vp, i64, i32, i64, vp, i32, i32, vp, vp, PIX]),
-    "adanns_build_ivf": (C.c_int, [vp, i64, i32, i64, i32, i32, i32, vp, vp, i64, vp, vp, PIX]),
+    "adanns_ivf_import": (C.c_int, [vp, i64, i32, i64, i32, vp, i32, i32, vp, vp, PIX]),
+    "adanns_build_ivf": (C.c_int, [vp, i64, i32, i64, i32, i32, i32, i32, vp, vp, i64, vp, vp,
+                                   PIX]),
     "adanns_pq_import": (C.c_int, [vp, i32, i32, vp, vp, vp, vp]),
     "adanns_pq_codec": (C.c_int, [vp, i32, vp, vp, vp]),
-    "adanns_pq_train": (C.c_int, [vp, vp, i64, i32, i32, vp, i32, vp, vp, i64, vp]),
+    "adanns_pq_train": (C.c_int, [vp, vp, i64, i32, i32, i32, vp, i32, vp, vp, i64, vp]),
     "adanns_search_pq": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp]),
     "adanns_set_precision": (C.c_int, [vp, i32, vp]),
     "adanns_index_quantized": (C.c_int, [vp, i32, vp, vp]),

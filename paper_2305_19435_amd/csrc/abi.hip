@@ -137,8 +137,8 @@ void free_index_memory(adanns_index *ix) {
 
 // Lays out lists, ids and vectors for a validated assignment (host array).
 // With X == NULL the vector layout is allocated but not filled.
-adanns_status build_layout(adanns_index *ix, const float *X, int64_t ldx,
-                           const std::vector<int32_t> &assign, hipStream_t st) {
+adanns_status build_layout(adanns_index *ix, const Mat &X, const std::vector<int32_t> &assign,
+                           hipStream_t st) {
   const int64_t n = ix->n;
   const int32_t nlist = ix->nlist;
   std::vector<int64_t> cnt(nlist, 0);
@@ -188,9 +188,9 @@ adanns_status build_layout(adanns_index *ix, const float *X, int64_t ldx,
                             hipMemcpyHostToDevice, st));
   ADANNS_HIP(hipMemcpyAsync(d_row_list, row_list.data(), ix->rows_pad * sizeof(int32_t),
                             hipMemcpyHostToDevice, st));
-  if (X)
-    ADANNS_HIP(launch_layout(X, ldx, ix->d, ix->rowid, d_row_list, ix->poff, ix->rows_pad,
-                             ix->d_pad, ix->vec, st));
+  if (X.p)
+    ADANNS_HIP(launch_layout(X, ix->d, ix->rowid, d_row_list, ix->poff, ix->rows_pad, ix->d_pad,
+                             ix->vec, st));
   ADANNS_HIP(hipStreamSynchronize(st));
   return ADANNS_OK;
 }
@@ -224,7 +224,7 @@ adanns_status build_centroids(adanns_index *ix, const float *centroids, int64_t 
   ADANNS_HIP(hipMemcpyAsync(d_poff, poff.data(), 2 * sizeof(int64_t), hipMemcpyHostToDevice, st));
   ADANNS_HIP(hipMemcpyAsync(d_rl, row_list.data(), ix->nl_pad * sizeof(int32_t),
                             hipMemcpyHostToDevice, st));
-  ADANNS_HIP(launch_layout(ix->cent, ix->d_cb_pad, ix->d_cb, d_src, d_rl, d_poff, ix->nl_pad,
+  ADANNS_HIP(launch_layout(f32mat(ix->cent, ix->d_cb_pad), ix->d_cb, d_src, d_rl, d_poff, ix->nl_pad,
                            ix->d_cb_pad, ix->cent_slab, st));
   ADANNS_HIP(hipStreamSynchronize(st));
   return ADANNS_OK;
@@ -290,7 +290,7 @@ static adanns_status init_index_shape(adanns_index *ix, int64_t n, int32_t d, in
 // Lloyd's k-means on the GPU. Assignment = the coarse step with one probe
 // (first-pass MFMA scores, exact re-measurement of the best few, ties to the
 // smaller index); update = per-centroid mean in a fixed summation order.
-static adanns_status kmeans_gpu(const float *X, int64_t n, int64_t ldx, int32_t nlist, int32_t d_c,
+static adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t d_c,
                                 int32_t iters, const int32_t *init_rows, const int64_t *train_rows,
                                 int64_t n_train, double *objective, hipStream_t st,
                                 std::vector<int32_t> &assign_all, float **C_out,
@@ -333,9 +333,9 @@ static adanns_status kmeans_gpu(const float *X, int64_t n, int64_t ldx, int32_t 
     tmp.ptrs.push_back(d_rows);
     ADANNS_HIP(hipMemcpyAsync(d_rows, train_rows, nt * sizeof(int64_t), hipMemcpyHostToDevice, st));
   }
-  ADANNS_HIP(launch_stage_rows(X, ldx, d_rows, nullptr, nt, d_c, Xt, dcp, st));
+  ADANNS_HIP(launch_stage_rows(X, d_rows, nullptr, nt, d_c, Xt, dcp, st));
   ADANNS_HIP(hipMemcpyAsync(d_init, init_rows, nlist * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  ADANNS_HIP(launch_stage_rows(Xt, dcp, nullptr, d_init, nlist, d_c, C, dcp, st));
+  ADANNS_HIP(launch_stage_rows(f32mat(Xt, dcp), nullptr, d_init, nlist, d_c, C, dcp, st));
   cix.cent = C;
 
   std::vector<int32_t> h_asg(nt);
@@ -359,7 +359,8 @@ static adanns_status kmeans_gpu(const float *X, int64_t n, int64_t ldx, int32_t 
 
   auto assign_rows = [&](const float *rows, int64_t ldr, int64_t count, int32_t *out_asg,
                          float *out_min) -> adanns_status {
-    ADANNS_HIP(launch_layout(C, dcp, d_c, d_src, d_rl, d_poff1, cix.nl_pad, dcp, cix.cent_slab, st));
+    ADANNS_HIP(launch_layout(f32mat(C, dcp), d_c, d_src, d_rl, d_poff1, cix.nl_pad, dcp,
+                             cix.cent_slab, st));
     for (int64_t a0 = 0; a0 < count; a0 += chunk) {
       const int64_t m = std::min(chunk, count - a0);
       SearchBufs b{};
@@ -401,10 +402,11 @@ static adanns_status kmeans_gpu(const float *X, int64_t n, int64_t ldx, int32_t 
   }
   // final assignment of every row against the final centroids
   assign_all.assign(n, 0);
-  ADANNS_HIP(launch_layout(C, dcp, d_c, d_src, d_rl, d_poff1, cix.nl_pad, dcp, cix.cent_slab, st));
+  ADANNS_HIP(launch_layout(f32mat(C, dcp), d_c, d_src, d_rl, d_poff1, cix.nl_pad, dcp,
+                           cix.cent_slab, st));
   for (int64_t a0 = 0; a0 < n; a0 += chunk) {
     const int64_t m = std::min(chunk, n - a0);
-    ADANNS_HIP(launch_stage_rows(X + a0 * ldx, ldx, nullptr, nullptr, m, d_c, Xc, dcp, st));
+    ADANNS_HIP(launch_stage_rows(X.rows(a0), nullptr, nullptr, m, d_c, Xc, dcp, st));
     SearchBufs b{};
     b.cfg = d_cfg;
     b.Qs = Xc;
@@ -436,7 +438,7 @@ const char *adanns_last_error(void) { return g_err; }
 
 const char *adanns_version(void) { return "adanns-mi355x 0.1 (gfx950)"; }
 
-adanns_status adanns_ivf_import(const float *X, int64_t n, int32_t d, int64_t ldx,
+adanns_status adanns_ivf_import(const void *X, int64_t n, int32_t d, int64_t ldx, int32_t dtype,
                                 const float *centroids, int32_t nlist, int32_t d_c_build,
                                 const int32_t *assign, void *stream, adanns_index **out) {
   clear_error();
@@ -446,6 +448,8 @@ adanns_status adanns_ivf_import(const float *X, int64_t n, int32_t d, int64_t ld
                  (long long)n);
   ADANNS_REQUIRE(d >= 1 && d <= 8192, "d must be in [1, 8192], got %d", d);
   ADANNS_REQUIRE(ldx >= d, "ldx (%lld) must be >= d (%d)", (long long)ldx, d);
+  ADANNS_REQUIRE(dtype == ADANNS_DTYPE_F32 || dtype == ADANNS_DTYPE_F16,
+                 "dtype must be ADANNS_DTYPE_F32 or ADANNS_DTYPE_F16, got %d", dtype);
   ADANNS_REQUIRE(nlist >= 1 && nlist <= 65536, "nlist must be in [1, 65536], got %d", nlist);
   ADANNS_REQUIRE(d_c_build >= 1 && d_c_build <= d, "d_c_build must be in [1, d], got %d",
                  d_c_build);
@@ -464,7 +468,8 @@ adanns_status adanns_ivf_import(const float *X, int64_t n, int32_t d, int64_t ld
     return ADANNS_ENOMEM;
   }
   init_index_shape(ix, n, d, nlist, d_c_build);
-  if ((s = build_layout(ix, X, ldx, h_assign, st)) || (s = build_centroids(ix, centroids, d_c_build, st))) {
+  if ((s = build_layout(ix, Mat{X, ldx, dtype}, h_assign, st)) ||
+      (s = build_centroids(ix, centroids, d_c_build, st))) {
     free_index_memory(ix);
     delete ix;
     return s;
@@ -546,7 +551,8 @@ adanns_status adanns_search_probes(const adanns_index *index, const float *Q, in
   return search_common(index, Q, nq, ldq, 0, d_s, nprobe, probes, k, dist, ids, nullptr, stream);
 }
 
-adanns_status adanns_build_ivf(const float *X, int64_t n, int32_t d, int64_t ldx, int32_t nlist,
+adanns_status adanns_build_ivf(const void *X, int64_t n, int32_t d, int64_t ldx, int32_t dtype,
+                               int32_t nlist,
                                int32_t d_c, int32_t iters, const int32_t *init_rows,
                                const int64_t *train_rows, int64_t n_train, double *objective,
                                void *stream, adanns_index **out) {
@@ -557,6 +563,8 @@ adanns_status adanns_build_ivf(const float *X, int64_t n, int32_t d, int64_t ldx
                  (long long)n);
   ADANNS_REQUIRE(d >= 1 && d <= 8192, "d must be in [1, 8192], got %d", d);
   ADANNS_REQUIRE(ldx >= d, "ldx (%lld) must be >= d (%d)", (long long)ldx, d);
+  ADANNS_REQUIRE(dtype == ADANNS_DTYPE_F32 || dtype == ADANNS_DTYPE_F16,
+                 "dtype must be ADANNS_DTYPE_F32 or ADANNS_DTYPE_F16, got %d", dtype);
   ADANNS_REQUIRE(nlist >= 1 && nlist <= 65536, "nlist must be in [1, 65536], got %d", nlist);
   ADANNS_REQUIRE(d_c >= 1 && d_c <= d, "d_c must be in [1, d], got %d", d_c);
   ADANNS_REQUIRE(iters >= 0 && iters <= 1000, "iters must be in [0, 1000], got %d", iters);
@@ -575,8 +583,9 @@ adanns_status adanns_build_ivf(const float *X, int64_t n, int32_t d, int64_t ldx
   hipStream_t st = (hipStream_t)stream;
   std::vector<int32_t> assign;
   float *C = nullptr;
-  if ((s = kmeans_gpu(X, n, ldx, nlist, d_c, iters, init_rows, train_rows, nt, objective, st,
-                      assign, &C))) {
+  const Mat Xm{X, ldx, dtype};
+  if ((s = kmeans_gpu(Xm, n, nlist, d_c, iters, init_rows, train_rows, nt, objective, st, assign,
+                      &C))) {
     if (C) (void)hipFree(C);
     return s;
   }
@@ -587,7 +596,7 @@ adanns_status adanns_build_ivf(const float *X, int64_t n, int32_t d, int64_t ldx
     return ADANNS_ENOMEM;
   }
   init_index_shape(ix, n, d, nlist, d_c);
-  if ((s = build_layout(ix, X, ldx, assign, st)) ||
+  if ((s = build_layout(ix, Xm, assign, st)) ||
       (s = build_centroids(ix, C, round_up(d_c, SLAB), st))) {
     (void)hipFree(C);
     free_index_memory(ix);
@@ -646,7 +655,8 @@ adanns_status adanns_pq_import(adanns_index *ix, int32_t M, int32_t d_s, const f
   return ADANNS_OK;
 }
 
-adanns_status adanns_pq_train(adanns_index *ix, const float *X, int64_t ldx, int32_t M,
+adanns_status adanns_pq_train(adanns_index *ix, const void *X, int64_t ldx, int32_t dtype,
+                              int32_t M,
                               int32_t d_s, const float *R_in, int32_t iters,
                               const int32_t *init_rows, const int64_t *train_rows,
                               int64_t n_train, void *stream) {
@@ -654,6 +664,8 @@ adanns_status adanns_pq_train(adanns_index *ix, const float *X, int64_t ldx, int
   ADANNS_REQUIRE(ix != nullptr && X != nullptr && init_rows != nullptr,
                  "index, X and init_rows must be non-NULL");
   ADANNS_REQUIRE(ldx >= ix->d, "ldx (%lld) must be >= d (%d)", (long long)ldx, ix->d);
+  ADANNS_REQUIRE(dtype == ADANNS_DTYPE_F32 || dtype == ADANNS_DTYPE_F16,
+                 "dtype must be ADANNS_DTYPE_F32 or ADANNS_DTYPE_F16, got %d", dtype);
   ADANNS_REQUIRE(d_s >= 1 && d_s <= ix->d && d_s <= 2048, "d_s must be in [1, min(d, 2048)]");
   ADANNS_REQUIRE(M >= 4 && M <= 64 && M % 4 == 0, "M must be a multiple of 4 in [4, 64], got %d", M);
   ADANNS_REQUIRE(d_s % M == 0, "M (%d) must divide d_s (%d)", M, d_s);
@@ -682,8 +694,9 @@ adanns_status adanns_pq_train(adanns_index *ix, const float *X, int64_t ldx, int
   tmp.ptrs.push_back(codes_id);
   std::vector<int32_t> unused;
   // training matrix: the rows themselves, or the training rows rotated by R
-  const float *Tx = X;
-  int64_t ldt = ldx, nT = ix->n;
+  const Mat Xm{X, ldx, dtype};
+  Mat Tx = Xm;
+  int64_t nT = ix->n;
   const int64_t *trows = train_rows;
   float *Rdev = nullptr, *T = nullptr, *Tlo = nullptr;
   if (R_in) {
@@ -704,17 +717,16 @@ adanns_status adanns_pq_train(adanns_index *ix, const float *X, int64_t ldx, int
       tmp.ptrs.push_back(d_tr);
       ADANNS_HIP(hipMemcpyAsync(d_tr, train_rows, nt * sizeof(int64_t), hipMemcpyHostToDevice, st));
     }
-    ADANNS_HIP(launch_stage_rows(X, ldx, d_tr, nullptr, nt, d_s, raw, d_s, st));
+    ADANNS_HIP(launch_stage_rows(Xm, d_tr, nullptr, nt, d_s, raw, d_s, st));
     ADANNS_HIP(launch_rotate(raw, d_s, nt, Rdev, d_s, T, Tlo, d_s, st));
-    Tx = T;
-    ldt = d_s;
+    Tx = f32mat(T, d_s);
     nT = nt;
     trows = nullptr;  // T holds exactly the training rows
   }
   for (int32_t m = 0; m < M; ++m) {
     float *C = nullptr;
     // Lloyd's k-means with 256 codewords on the m-th block of coordinates
-    if ((s = kmeans_gpu(Tx + (int64_t)m * dsub, nT, ldt, 256, dsub, iters, init_rows, trows, nt,
+    if ((s = kmeans_gpu(Tx.cols((int64_t)m * dsub), nT, 256, dsub, iters, init_rows, trows, nt,
                         nullptr, st, unused, &C, false))) {
       if (C) (void)hipFree(C);
       return s;
@@ -727,7 +739,7 @@ adanns_status adanns_pq_train(adanns_index *ix, const float *X, int64_t ldx, int
     ADANNS_HIP(e);
   }
   if (!R_in) {
-    ADANNS_HIP(launch_pq_encode(X, ldx, ix->n, M, dsub, cb, codes_id, st));
+    ADANNS_HIP(launch_pq_encode(Xm, ix->n, M, dsub, cb, codes_id, st));
     std::vector<float> eye((size_t)d_s * d_s, 0.f);
     for (int32_t i = 0; i < d_s; ++i) eye[(size_t)i * d_s + i] = 1.f;
     ADANNS_HIP(hipMalloc(&R, eye.size() * sizeof(float)));
@@ -748,9 +760,9 @@ adanns_status adanns_pq_train(adanns_index *ix, const float *X, int64_t ldx, int
   tmp.ptrs.push_back(clo);
   for (int64_t a0 = 0; a0 < ix->n; a0 += chunk) {
     const int64_t m = std::min(chunk, ix->n - a0);
-    ADANNS_HIP(launch_stage_rows(X + a0 * ldx, ldx, nullptr, nullptr, m, d_s, craw, d_s, st));
+    ADANNS_HIP(launch_stage_rows(Xm.rows(a0), nullptr, nullptr, m, d_s, craw, d_s, st));
     ADANNS_HIP(launch_rotate(craw, d_s, m, Rdev, d_s, crot, clo, d_s, st));
-    ADANNS_HIP(launch_pq_encode(crot, d_s, m, M, dsub, cb, codes_id + a0 * M, st));
+    ADANNS_HIP(launch_pq_encode(f32mat(crot, d_s), m, M, dsub, cb, codes_id + a0 * M, st));
   }
   ADANNS_HIP(hipStreamSynchronize(st));
   return adanns_pq_import(ix, M, d_s, Rdev, cb, codes_id, stream);
@@ -1178,7 +1190,7 @@ adanns_status adanns_index_load(const char *path, void *stream, adanns_index **o
     return e;
   };
   init_index_shape(ix, n, d, nlist, d_cb);
-  if ((s = build_layout(ix, nullptr, 0, assign, st))) return fail(s);
+  if ((s = build_layout(ix, Mat{}, assign, st))) return fail(s);
   if (ix->rows_pad != rows_pad) return fail(bad("layout rows"));
   {
     DevFree tmp;

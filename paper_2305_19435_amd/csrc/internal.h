@@ -186,9 +186,21 @@ struct SearchBufs {
   float *D;           // first-pass distances, query-segmented
 };
 
+// A row-major matrix of FP32 or IEEE-half elements (the caller's database,
+// or an internal FP32 buffer). Half elements convert exactly to FP32.
+struct Mat {
+  const void *p = nullptr;
+  int64_t ld = 0;
+  int32_t type = 0;  // adanns_dtype: 0 FP32, 1 FP16
+  size_t esize() const { return type ? 2 : 4; }
+  Mat rows(int64_t r0) const { return Mat{(const char *)p + r0 * ld * esize(), ld, type}; }
+  Mat cols(int64_t c0) const { return Mat{(const char *)p + c0 * esize(), ld, type}; }
+};
+inline Mat f32mat(const float *p, int64_t ld) { return Mat{p, ld, 0}; }
+
 hipError_t launch_stage_queries(const float *Q, int64_t nq, int64_t ldq, int32_t dq,
                                 float *Qs, int64_t ldqs, hipStream_t st);
-hipError_t launch_layout(const float *src, int64_t ldsrc, int32_t dsrc, const int64_t *src_row,
+hipError_t launch_layout(const Mat &src, int32_t dsrc, const int64_t *src_row,
                          const int32_t *row_list, const int64_t *poff, int64_t rows_pad,
                          int32_t d_pad, float *dst, hipStream_t st);
 hipError_t launch_store_cfg(const CfgDev &c, CfgDev *dst, hipStream_t st);
@@ -206,9 +218,9 @@ hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq
 hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq, float *dist,
                                int64_t *ids, int64_t ldk, int32_t *user_probes, int32_t tq,
                                int32_t tv, int32_t grid, hipStream_t st, bool do_coarse = true);
-hipError_t launch_stage_rows(const float *X, int64_t ldx, const int64_t *rows,
-                             const int32_t *rows32, int64_t nrows, int32_t dcols, float *out,
-                             int64_t ldo, hipStream_t st);
+hipError_t launch_stage_rows(const Mat &X, const int64_t *rows, const int32_t *rows32,
+                             int64_t nrows, int32_t dcols, float *out, int64_t ldo,
+                             hipStream_t st);
 hipError_t launch_centroid_update(const float *X, int64_t ldx, const int32_t *perm,
                                   const int64_t *off, int32_t nlist, int32_t dcols, float *C,
                                   int64_t ldc, hipStream_t st);
@@ -218,8 +230,8 @@ constexpr int PQ_ENCODE_MAX_DSUB = 32;
 // q' = q[:d_s] R (compensated), rows of Qs -> (hi, lo) pairs.
 hipError_t launch_rotate(const float *Qs, int64_t ldqs, int64_t nq, const float *R, int32_t d_s,
                          float *qh, float *ql, int64_t ldqr, hipStream_t st);
-hipError_t launch_pq_encode(const float *X, int64_t ldx, int64_t n, int32_t M, int32_t dsub,
-                            const float *cb, uint8_t *codes, hipStream_t st);
+hipError_t launch_pq_encode(const Mat &X, int64_t n, int32_t M, int32_t dsub, const float *cb,
+                            uint8_t *codes, hipStream_t st);
 hipError_t launch_gather_codes(const uint8_t *codes, int32_t M, const int64_t *rowid,
                                int64_t rows_pad, uint8_t *out, hipStream_t st);
 // Precision form: quantised copies, quantised queries, first passes, selection.

@@ -130,14 +130,15 @@ __global__ void k_stage_queries(const float *__restrict__ Q, int64_t nq, int64_t
 }
 
 // Rows (optionally gathered through ``rows``) copied to a zero-padded buffer.
-__global__ void k_stage_rows(const float *__restrict__ X, int64_t ldx, const int64_t *__restrict__ rows,
+template <class T>
+__global__ void k_stage_rows(const T *__restrict__ X, int64_t ldx, const int64_t *__restrict__ rows,
                              const int32_t *__restrict__ rows32, int64_t nrows, int32_t dcols,
                              float *__restrict__ out, int64_t ldo) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t r = i / ldo, c = i % ldo;
   if (r >= nrows) return;
   int64_t src = rows ? rows[r] : (rows32 ? (int64_t)rows32[r] : r);
-  out[i] = c < dcols ? X[src * ldx + c] : 0.0f;
+  out[i] = c < dcols ? (float)X[src * ldx + c] : 0.0f;
 }
 
 // Lloyd update: centroid h becomes the mean of its members (perm[off[h] ..
@@ -171,7 +172,8 @@ __global__ __launch_bounds__(256) void k_centroid_update(const float *__restrict
 }
 
 // Slab layout writer: one thread per destination element.
-__global__ void k_layout(const float *__restrict__ src, int64_t ldsrc, int32_t dsrc,
+template <class T>
+__global__ void k_layout(const T *__restrict__ src, int64_t ldsrc, int32_t dsrc,
                          const int64_t *__restrict__ src_row, const int32_t *__restrict__ row_list,
                          const int64_t *__restrict__ poff, int64_t rows_pad, int32_t d_pad,
                          float *__restrict__ dst) {
@@ -184,7 +186,7 @@ __global__ void k_layout(const float *__restrict__ src, int64_t ldsrc, int32_t d
   int64_t npad = poff[h + 1] - p0;
   int64_t r = g - p0;
   int64_t sr = src_row[g];
-  float v = (sr >= 0 && dim < dsrc) ? src[sr * ldsrc + dim] : 0.0f;
+  float v = (sr >= 0 && dim < dsrc) ? (float)src[sr * ldsrc + dim] : 0.0f;
   dst[p0 * d_pad + ((int64_t)(dim / SLAB) * npad + r) * SLAB + (dim % SLAB)] = v;
 }
 
@@ -1424,7 +1426,8 @@ __global__ void k_gather_codes(const uint8_t *__restrict__ codes, int32_t M,
 
 // PQ encoding: code[row][m] = the nearest of block m's 256 codewords to
 // X[row, m*dsub : (m+1)*dsub] (difference form, ties to the smaller index).
-__global__ __launch_bounds__(256) void k_pq_encode(const float *__restrict__ X, int64_t ldx,
+template <class T>
+__global__ __launch_bounds__(256) void k_pq_encode(const T *__restrict__ X, int64_t ldx,
                                                    int64_t n, int32_t M, int32_t dsub,
                                                    const float *__restrict__ cb,
                                                    uint8_t *__restrict__ codes) {
@@ -1435,9 +1438,9 @@ __global__ __launch_bounds__(256) void k_pq_encode(const float *__restrict__ X, 
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n) return;
   float y[PQ_ENCODE_MAX_DSUB];
-  const float *src = X + row * ldx + (int64_t)m * dsub;
+  const T *src = X + row * ldx + (int64_t)m * dsub;
 #pragma unroll
-  for (int t = 0; t < PQ_ENCODE_MAX_DSUB; ++t) y[t] = t < dsub ? src[t] : 0.f;
+  for (int t = 0; t < PQ_ENCODE_MAX_DSUB; ++t) y[t] = t < dsub ? (float)src[t] : 0.f;
   float best = __builtin_inff();
   int bc = 0;
   for (int c = 0; c < 256; ++c) {
@@ -2123,23 +2126,33 @@ hipError_t launch_stage_queries(const float *Q, int64_t nq, int64_t ldq, int32_t
   return hipGetLastError();
 }
 
-hipError_t launch_layout(const float *src, int64_t ldsrc, int32_t dsrc, const int64_t *src_row,
+hipError_t launch_layout(const Mat &src, int32_t dsrc, const int64_t *src_row,
                          const int32_t *row_list, const int64_t *poff, int64_t rows_pad,
                          int32_t d_pad, float *dst, hipStream_t st) {
   int64_t n = rows_pad * d_pad;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_layout, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, ldsrc, dsrc,
-                     src_row, row_list, poff, rows_pad, d_pad, dst);
+  if (src.type == 1)
+    hipLaunchKernelGGL(k_layout<_Float16>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                       (const _Float16 *)src.p, src.ld, dsrc, src_row, row_list, poff, rows_pad,
+                       d_pad, dst);
+  else
+    hipLaunchKernelGGL(k_layout<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                       (const float *)src.p, src.ld, dsrc, src_row, row_list, poff, rows_pad,
+                       d_pad, dst);
   return hipGetLastError();
 }
 
-hipError_t launch_stage_rows(const float *X, int64_t ldx, const int64_t *rows,
-                             const int32_t *rows32, int64_t nrows, int32_t dcols, float *out,
-                             int64_t ldo, hipStream_t st) {
+hipError_t launch_stage_rows(const Mat &X, const int64_t *rows, const int32_t *rows32,
+                             int64_t nrows, int32_t dcols, float *out, int64_t ldo,
+                             hipStream_t st) {
   int64_t n = nrows * ldo;
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_stage_rows, dim3(blocks_for(n, 256)), dim3(256), 0, st, X, ldx, rows, rows32,
-                     nrows, dcols, out, ldo);
+  if (X.type == 1)
+    hipLaunchKernelGGL(k_stage_rows<_Float16>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                       (const _Float16 *)X.p, X.ld, rows, rows32, nrows, dcols, out, ldo);
+  else
+    hipLaunchKernelGGL(k_stage_rows<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                       (const float *)X.p, X.ld, rows, rows32, nrows, dcols, out, ldo);
   return hipGetLastError();
 }
 
@@ -2485,10 +2498,17 @@ hipError_t launch_rotate(const float *Qs, int64_t ldqs, int64_t nq, const float 
   return hipGetLastError();
 }
 
-hipError_t launch_pq_encode(const float *X, int64_t ldx, int64_t n, int32_t M, int32_t dsub,
-                            const float *cb, uint8_t *codes, hipStream_t st) {
-  hipLaunchKernelGGL(k_pq_encode, dim3(blocks_for(n, 256), M), dim3(256),
-                     256 * dsub * sizeof(float), st, X, ldx, n, M, dsub, cb, codes);
+hipError_t launch_pq_encode(const Mat &X, int64_t n, int32_t M, int32_t dsub, const float *cb,
+                            uint8_t *codes, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (X.type == 1)
+    hipLaunchKernelGGL(k_pq_encode<_Float16>, dim3(blocks_for(n, 256), M), dim3(256),
+                       256 * dsub * sizeof(float), st, (const _Float16 *)X.p, X.ld, n, M, dsub, cb,
+                       codes);
+  else
+    hipLaunchKernelGGL(k_pq_encode<float>, dim3(blocks_for(n, 256), M), dim3(256),
+                       256 * dsub * sizeof(float), st, (const float *)X.p, X.ld, n, M, dsub, cb,
+                       codes);
   return hipGetLastError();
 }
 

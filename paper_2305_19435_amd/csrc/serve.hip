@@ -121,8 +121,8 @@ adanns_status adanns_serve(const adanns_index *index, const float *Q, int64_t ld
     std::memcpy(sl.rows_host, reqs.data(), cnt * sizeof(int64_t));
     ADANNS_HIP(hipMemcpyAsync(sl.rows_dev, sl.rows_host, cnt * sizeof(int64_t),
                               hipMemcpyHostToDevice, sl.st));
-    ADANNS_HIP(launch_stage_rows(Q, ldq, sl.rows_dev, nullptr, cnt, (int32_t)ldq, sl.Qstep, ldq,
-                                 sl.st));
+    ADANNS_HIP(launch_stage_rows(f32mat(Q, ldq), sl.rows_dev, nullptr, cnt, (int32_t)ldq, sl.Qstep,
+                                 ldq, sl.st));
     const int64_t r0 = reqs[0];
     adanns_status e = adanns_search_pq(ix, sl.Qstep, cnt, ldq, d_c[r0], nprobe[r0], M[r0], k,
                                        rerank_k, d_rerank, sl.dstep, sl.istep, nullptr, sl.st);

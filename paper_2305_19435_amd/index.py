@@ -24,6 +24,20 @@ def _dev_f32(x, dev):
     return t.to(device=dev, dtype=torch.float32).contiguous()
 
 
+def _dev_x(X, dev="cuda"):
+    """A database matrix as the library takes it: a CUDA tensor with unit
+    column stride, FP32 or FP16 (kept as given), anything else as FP32.
+    Returns (tensor, adanns_dtype code)."""
+    if (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype in (torch.float32, torch.float16)
+            and X.dim() == 2 and X.stride(1) == 1):
+        return X, (1 if X.dtype == torch.float16 else 0)
+    if isinstance(X, np.ndarray) and X.dtype == np.float16:
+        return torch.from_numpy(np.ascontiguousarray(X)).to(dev), 1
+    if isinstance(X, torch.Tensor) and X.dtype == torch.float16:
+        return X.to(dev).contiguous(), 1
+    return _dev_f32(X, dev), 0
+
+
 def _dev_i32(x, dev):
     t = x if isinstance(x, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(x))
     return t.to(device=dev, dtype=torch.int32).contiguous()
@@ -41,14 +55,14 @@ class IvfIndex:
     # ---- construction -------------------------------------------------------
     @classmethod
     def import_ivf(cls, X, centroids, assign, device="cuda", stream=None) -> "IvfIndex":
-        """adanns_ivf_import: X [n, d] FP32, centroids [nlist, d_c_build], assign [n]."""
+        """adanns_ivf_import: X [n, d] FP32 or FP16, centroids [nlist, d_c_build],
+        assign [n]."""
         dev = torch.device(device)
-        Xd = X if (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32
-                   and X.stride(1) == 1) else _dev_f32(X, dev)
+        Xd, xt = _dev_x(X, dev)
         Cd = _dev_f32(centroids, dev)
         Ad = _dev_i32(assign, dev)
         out = C.c_void_p()
-        check(lib.adanns_ivf_import(Xd.data_ptr(), Xd.shape[0], Xd.shape[1], Xd.stride(0),
+        check(lib.adanns_ivf_import(Xd.data_ptr(), Xd.shape[0], Xd.shape[1], Xd.stride(0), xt,
                                     Cd.data_ptr(), Cd.shape[0], Cd.shape[1], Ad.data_ptr(),
                                     _stream(stream), C.byref(out)))
         return cls(out.value)
@@ -56,14 +70,14 @@ class IvfIndex:
     @classmethod
     def build_ivf(cls, X, nlist: int, d_c: int, iters: int, init_rows, train_rows=None,
                   stream=None, return_objective=False):
-        """adanns_build_ivf: GPU Lloyd k-means on X[:, :d_c] (X a CUDA FP32 tensor)."""
-        Xd = X if (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32
-                   and X.stride(1) == 1) else _dev_f32(X, "cuda")
+        """adanns_build_ivf: GPU Lloyd k-means on X[:, :d_c] (X FP32 or FP16)."""
+        Xd, xt = _dev_x(X)
         init = np.ascontiguousarray(init_rows, dtype=np.int32)
         tr = None if train_rows is None else np.ascontiguousarray(train_rows, dtype=np.int64)
         obj = np.zeros(iters + 1, dtype=np.float64)
         out = C.c_void_p()
-        check(lib.adanns_build_ivf(Xd.data_ptr(), Xd.shape[0], Xd.shape[1], Xd.stride(0), nlist,
+        check(lib.adanns_build_ivf(Xd.data_ptr(), Xd.shape[0], Xd.shape[1], Xd.stride(0), xt,
+                                   nlist,
                                    d_c, iters, init.ctypes.data,
                                    None if tr is None else tr.ctypes.data,
                                    0 if tr is None else len(tr), obj.ctypes.data,
@@ -126,13 +140,13 @@ class IvfIndex:
 
     def pq_train(self, X, M: int, d_s: int, iters: int, init_rows, train_rows=None, R=None,
                  stream=None):
-        """adanns_pq_train: GPU-trained PQ codec on X (the index's rows) for rotation R."""
-        Xd = X if (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32
-                   and X.stride(1) == 1) else _dev_f32(X, "cuda")
+        """adanns_pq_train: GPU-trained PQ codec on X (the index's rows, FP32 or
+        FP16) for rotation R."""
+        Xd, xt = _dev_x(X)
         init = np.ascontiguousarray(init_rows, dtype=np.int32)
         tr = None if train_rows is None else np.ascontiguousarray(train_rows, dtype=np.int64)
         Rd = None if R is None else _dev_f32(R, Xd.device)
-        check(lib.adanns_pq_train(self._h, Xd.data_ptr(), Xd.stride(0), M, d_s, _ptr(Rd), iters,
+        check(lib.adanns_pq_train(self._h, Xd.data_ptr(), Xd.stride(0), xt, M, d_s, _ptr(Rd), iters,
                                   init.ctypes.data, None if tr is None else tr.ctypes.data,
                                   0 if tr is None else len(tr), _stream(stream)))
 

@@ -41,12 +41,14 @@ def test_validation_before_device_work(lib):
     L = lib.lib
     out = C.c_void_p()
     # NULL outputs / pointers and out-of-range sizes are rejected with EINVAL
-    assert L.adanns_ivf_import(None, 10, 4, 4, None, 2, 2, None, None, None) == -1
-    assert L.adanns_ivf_import(1, 0, 4, 4, 1, 2, 2, 1, None, C.byref(out)) == -1
+    assert L.adanns_ivf_import(None, 10, 4, 4, 0, None, 2, 2, None, None, None) == -1
+    assert L.adanns_ivf_import(1, 0, 4, 4, 0, 1, 2, 2, 1, None, C.byref(out)) == -1
     assert "n must be" in lib.last_error()
-    assert L.adanns_ivf_import(1, 10, 4, 3, 1, 2, 2, 1, None, C.byref(out)) == -1
-    assert L.adanns_ivf_import(1, 10, 4, 4, 1, 0, 2, 1, None, C.byref(out)) == -1
-    assert L.adanns_ivf_import(1, 10, 4, 4, 1, 2, 5, 1, None, C.byref(out)) == -1
+    assert L.adanns_ivf_import(1, 10, 4, 3, 0, 1, 2, 2, 1, None, C.byref(out)) == -1
+    assert L.adanns_ivf_import(1, 10, 4, 4, 2, 1, 2, 2, 1, None, C.byref(out)) == -1
+    assert "dtype" in lib.last_error()
+    assert L.adanns_ivf_import(1, 10, 4, 4, 0, 1, 0, 2, 1, None, C.byref(out)) == -1
+    assert L.adanns_ivf_import(1, 10, 4, 4, 0, 1, 2, 5, 1, None, C.byref(out)) == -1
     assert L.adanns_search(None, None, 0, 4, 1, 1, 1, 1, None, None, None, None) == -1
     assert "index is NULL" in lib.last_error()
     assert L.adanns_index_info(None, None, None, None, None) == -1

@@ -79,3 +79,41 @@ def test_build_ivf_invalid(lib, small_data):
         bad = synth.init_rows(w.n, w.nlist)
         bad[0] = w.n
         lib.IvfIndex.build_ivf(Xd, w.nlist, w.d_c, 3, bad)
+
+
+def test_fp16_database_equals_fp32_of_the_same_values(lib, small_data):
+    """An FP16 database (ADANNS_DTYPE_F16) builds, imports and trains exactly
+    like the FP32 matrix holding the same (half-representable) values."""
+    w, X, Q = small_data
+    X16 = X.astype(np.float16)
+    X32 = X16.astype(np.float32)
+    init = synth.init_rows(w.n, w.nlist, w.seed)
+    a16, o16 = lib.IvfIndex.build_ivf(torch.from_numpy(X16).cuda(), w.nlist, w.d_c, 5, init,
+                                      return_objective=True)
+    a32, o32 = lib.IvfIndex.build_ivf(torch.from_numpy(X32).cuda(), w.nlist, w.d_c, 5, init,
+                                      return_objective=True)
+    assert np.array_equal(o16, o32)
+    assert np.array_equal(a16.centroids(), a32.centroids())
+    for x, y in zip(a16.lists(), a32.lists()):
+        assert np.array_equal(x, y)
+    Qd = torch.from_numpy(Q).cuda()
+    r16 = a16.search(Qd, w.d_c, w.d_s, w.nprobe, w.k)
+    r32 = a32.search(Qd, w.d_c, w.d_s, w.nprobe, w.k)
+    torch.cuda.synchronize()
+    assert torch.equal(r16[0], r32[0]) and torch.equal(r16[1], r32[1])
+    pinit = synth.init_rows(w.n, 256, w.seed, synth.STREAM_PQ)
+    a16.pq_train(torch.from_numpy(X16).cuda(), 8, w.d, 3, pinit)
+    a32.pq_train(torch.from_numpy(X32).cuda(), 8, w.d, 3, pinit)
+    for x, y in zip(a16.pq_codec(8, w.d), a32.pq_codec(8, w.d)):
+        assert np.array_equal(x, y)
+    C = a32.centroids()
+    off, ids = a32.lists()
+    assign = np.empty(w.n, dtype=np.int32)
+    for h in range(w.nlist):
+        assign[ids[off[h]:off[h + 1]]] = h
+    i16 = lib.IvfIndex.import_ivf(X16, C, assign)
+    s16 = i16.search(Qd, w.d_c, w.d_s, w.nprobe, w.k)
+    torch.cuda.synchronize()
+    assert torch.equal(s16[0], r32[0]) and torch.equal(s16[1], r32[1])
+    for ix in (a16, a32, i16):
+        ix.free()
