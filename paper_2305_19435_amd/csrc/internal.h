@@ -227,7 +227,7 @@ hipError_t launch_centroid_update(const float *X, int64_t ldx, const int32_t *pe
 hipError_t launch_bucketing(const adanns_index *ix, const SearchBufs &b, int64_t nq,
                             int32_t nprobe, hipStream_t st);
 constexpr int PQ_ENCODE_MAX_DSUB = 32;
-// q' = q[:d_s] R (compensated), rows of Qs -> (hi, lo) pairs.
+// q' = q[:d_s] R (FP64 accumulation), rows of Qs -> (hi, lo) FP32 pairs.
 hipError_t launch_rotate(const float *Qs, int64_t ldqs, int64_t nq, const float *R, int32_t d_s,
                          float *qh, float *ql, int64_t ldqr, hipStream_t st);
 hipError_t launch_pq_encode(const Mat &X, int64_t n, int32_t M, int32_t dsub, const float *cb,

@@ -1461,42 +1461,36 @@ __global__ __launch_bounds__(256) void k_pq_encode(const T *__restrict__ X, int6
   codes[row * M + m] = (uint8_t)bc;
 }
 
-// q' = q[:d_s] R in compensated FP32 (TwoProd + TwoSum), stored as a pair
-// (hi, lo). A workgroup computes ROT_Q queries x 256 output columns
-// (blockIdx.y picks the columns); the queries share each read of R.
+// q' = q[:d_s] R accumulated in FP64 (products of FP32 values are exact in
+// FP64), stored as the FP32 pair (hi, lo) with hi + lo = the FP64 sum to
+// within 2^-48 relative. A workgroup computes ROT_Q queries x 256 output
+// columns (blockIdx.y picks the columns); the queries share each read of R.
 constexpr int ROT_Q = 16;
-constexpr int ROT_CHUNK = 512;  // query coordinates staged in LDS at a time
+constexpr int ROT_CHUNK = 256;  // query coordinates staged in LDS (as FP64) at a time
 __global__ __launch_bounds__(256) void k_rotate(const float *__restrict__ Qs, int64_t ldqs,
                                                 int64_t nq, const float *__restrict__ R,
                                                 int32_t d_s, float *__restrict__ qh,
                                                 float *__restrict__ ql, int64_t ldqr) {
-#pragma clang fp contract(off)
-  __shared__ float qsh[ROT_Q][ROT_CHUNK];
+  __shared__ double qsh[ROT_CHUNK][ROT_Q];  // a coordinate's ROT_Q values side by side
   const int tid = threadIdx.x;
   const int64_t q0 = (int64_t)blockIdx.x * ROT_Q;
   const int j = blockIdx.y * 256 + tid;
-  float S[ROT_Q], C[ROT_Q];
+  double acc[ROT_Q];
 #pragma unroll
-  for (int a = 0; a < ROT_Q; ++a) S[a] = C[a] = 0.f;
+  for (int a = 0; a < ROT_Q; ++a) acc[a] = 0.0;
   for (int i0 = 0; i0 < d_s; i0 += ROT_CHUNK) {
     const int ni = min(ROT_CHUNK, d_s - i0);
     __syncthreads();  // the previous chunk is consumed
     for (int e = tid; e < ROT_Q * ROT_CHUNK; e += blockDim.x) {
       const int qq = e / ROT_CHUNK, c = e % ROT_CHUNK;
-      qsh[qq][c] = (q0 + qq < nq && c < ni) ? Qs[(q0 + qq) * ldqs + i0 + c] : 0.f;
+      qsh[c][qq] = (q0 + qq < nq && c < ni) ? (double)Qs[(q0 + qq) * ldqs + i0 + c] : 0.0;
     }
     __syncthreads();
     if (j < d_s) {
       for (int i = 0; i < ni; ++i) {
-        const float r = R[(int64_t)(i0 + i) * d_s + j];
+        const double r = (double)R[(int64_t)(i0 + i) * d_s + j];
 #pragma unroll
-        for (int a = 0; a < ROT_Q; ++a) {
-          float p, pe, t, te;
-          two_prod(qsh[a][i], r, p, pe);
-          two_sum(S[a], p, t, te);
-          S[a] = t;
-          C[a] = C[a] + (te + pe);
-        }
+        for (int a = 0; a < ROT_Q; ++a) acc[a] = __builtin_fma(qsh[i][a], r, acc[a]);
       }
     }
   }
@@ -1504,32 +1498,48 @@ __global__ __launch_bounds__(256) void k_rotate(const float *__restrict__ Qs, in
 #pragma unroll
   for (int a = 0; a < ROT_Q; ++a) {
     if (q0 + a >= nq) break;
-    float hi, lo;
-    two_sum(S[a], C[a], hi, lo);
+    const float hi = (float)acc[a];
     qh[(q0 + a) * ldqr + j] = hi;
-    ql[(q0 + a) * ldqr + j] = lo;
+    ql[(q0 + a) * ldqr + j] = (float)(acc[a] - (double)hi);
   }
 }
 
-// LUT[q][m][c] = |q'_m - C_m[c]|^2 in FP32 from the rotated query's high part.
+// LUT[q][m][c] = |q'_m - C_m[c]|^2 in FP32 (difference form, t = 0..dsub-1
+// in order) from the rotated query's high part. A workgroup takes block m
+// for LUT_Q queries: block m's 256 codewords are staged in LDS (LUT_T
+// coordinates at a time) and thread c fills entry c of every query's table.
+constexpr int LUT_Q = 16;
+constexpr int LUT_T = 32;
 __global__ __launch_bounds__(256) void k_pq_lut(const float *__restrict__ qh, int64_t ldqr,
-                                                const float *__restrict__ cb, int32_t M,
-                                                int32_t dsub, float *__restrict__ lut) {
-  extern __shared__ float qrow[];
-  const int64_t q = blockIdx.x;
-  const int d_s = M * dsub;
-  for (int i = threadIdx.x; i < d_s; i += blockDim.x) qrow[i] = qh[q * ldqr + i];
-  __syncthreads();
-  const int c = threadIdx.x;  // blockDim.x == 256 codewords
-  for (int m = 0; m < M; ++m) {
-    const float *cw = cb + ((int64_t)m * 256 + c) * dsub;
-    float acc = 0.f;
-    for (int t = 0; t < dsub; ++t) {
-      const float dd = qrow[m * dsub + t] - cw[t];
-      acc += dd * dd;
+                                                int64_t nq, const float *__restrict__ cb,
+                                                int32_t M, int32_t dsub, float *__restrict__ lut) {
+  __shared__ float cw[256][LUT_T + 1];  // odd stride: thread c's row starts in its own bank
+  __shared__ float qv[LUT_Q][LUT_T];
+  const int m = blockIdx.y, c = threadIdx.x;
+  const int64_t q0 = (int64_t)blockIdx.x * LUT_Q;
+  float acc[LUT_Q];
+#pragma unroll
+  for (int a = 0; a < LUT_Q; ++a) acc[a] = 0.f;
+  for (int t0 = 0; t0 < dsub; t0 += LUT_T) {
+    const int tn = min(LUT_T, dsub - t0);
+    __syncthreads();  // the previous chunk is consumed
+    for (int i = threadIdx.x; i < 256 * tn; i += blockDim.x)
+      cw[i / tn][i % tn] = cb[((int64_t)m * 256 + i / tn) * dsub + t0 + i % tn];
+    for (int i = threadIdx.x; i < LUT_Q * tn; i += blockDim.x) {
+      const int64_t q = q0 + i / tn;
+      qv[i / tn][i % tn] = q < nq ? qh[q * ldqr + (int64_t)m * dsub + t0 + i % tn] : 0.f;
     }
-    lut[(q * M + m) * 256 + c] = acc;
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < LUT_Q; ++a)
+      for (int t = 0; t < tn; ++t) {
+        const float dd = qv[a][t] - cw[c][t];
+        acc[a] += dd * dd;
+      }
   }
+#pragma unroll
+  for (int a = 0; a < LUT_Q; ++a)
+    if (q0 + a < nq) lut[((q0 + a) * M + m) * 256 + c] = acc[a];
 }
 
 // ADC scan of one (query, probe) pair: the query's table is held in LDS and
@@ -2531,8 +2541,9 @@ hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const Sea
   if (e != hipSuccess) return e;
   {
     KernelTimer tm("pq_lut", st);
-    hipLaunchKernelGGL(k_pq_lut, dim3((unsigned)nq), dim3(256), pq.d_s * sizeof(float), st, qr_hi,
-                       ldqr, pq.cb, pq.M, pq.dsub, lut);
+    if (nq > 0)
+      hipLaunchKernelGGL(k_pq_lut, dim3((unsigned)cdiv(nq, LUT_Q), (unsigned)pq.M), dim3(256), 0,
+                         st, qr_hi, ldqr, nq, pq.cb, pq.M, pq.dsub, lut);
   }
   {
     KernelTimer tm("adc_scan", st);
