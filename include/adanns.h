@@ -113,6 +113,13 @@ adanns_status adanns_build_ivf(const void *X, int64_t n, int32_t d, int64_t ldx,
                                const int64_t *train_rows, int64_t n_train, double *objective,
                                void *stream, adanns_index **out);
 
+/* Search scratch (staged queries, scores, buckets and every candidate's
+ * first-pass value) grows with nq. adanns_search and adanns_search_probes
+ * split a batch whose scratch would exceed ``bytes`` into query chunks run
+ * one after another on the stream (results unchanged). 0 restores the
+ * default of 32 GiB. Process-wide; affects calls made afterwards. */
+adanns_status adanns_set_search_scratch_cap(size_t bytes);
+
 /*
  * AdANNS-IVF search (Algorithm 1, inference; Appendix A, Table "formula"):
  * probes = the nprobe clusters nearest to Q[i, :d_c] on the centroids'

@@ -62,6 +62,7 @@ _SIGS = {
     "adanns_index_device_bytes": (C.c_size_t, [vp]),
     "adanns_index_free": (None, [vp]),
     "adanns_index_save": (C.c_int, [vp, C.c_char_p]),
+    "adanns_set_search_scratch_cap": (C.c_int, [C.c_size_t]),
     "adanns_index_load": (C.c_int, [C.c_char_p, vp, vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -116,3 +117,8 @@ def timing_read(kernel: str):
     ms = C.c_double()
     check(lib.adanns_timing_read(kernel.encode(), C.addressof(n), C.addressof(ms)))
     return n.value, ms.value
+
+
+def set_search_scratch_cap(nbytes: int = 0):
+    """adanns_set_search_scratch_cap: split larger searches into query chunks."""
+    check(lib.adanns_set_search_scratch_cap(int(nbytes)))

@@ -478,6 +478,8 @@ adanns_status adanns_ivf_import(const void *X, int64_t n, int32_t d, int64_t ldx
   return ADANNS_OK;
 }
 
+static std::atomic<size_t> g_scratch_cap{kSearchScratchCap};
+
 static adanns_status search_common(const adanns_index *cix, const float *Q, int64_t nq,
                                    int64_t ldq, int32_t d_c, int32_t d_s, int32_t nprobe,
                                    const int32_t *given_probes, int32_t k, float *dist,
@@ -503,19 +505,39 @@ static adanns_status search_common(const adanns_index *cix, const float *Q, int6
   hipStream_t st = (hipStream_t)stream;
   const int32_t dq = std::max(coarse ? d_c : 0, d_s);
   const int32_t dq_pad = (int32_t)round_up(dq, SLAB);
-  size_t total = 0;
-  carve(nullptr, ix, nq, dq_pad, nprobe, coarse, &total);
-  void *base = nullptr;
-  if ((s = get_scratch(ix, st, total, &base))) return s;
-  SearchBufs b = carve((char *)base, ix, nq, dq_pad, nprobe, coarse, &total);
-  b.max_k = k;
-  ADANNS_HIP(launch_store_cfg(make_cfg(ix, coarse ? d_c : 1, d_s, nprobe, k, nq), b.cfg, st));
-  if (!coarse)
-    ADANNS_HIP(hipMemcpyAsync(b.probes, given_probes, (size_t)nq * nprobe * sizeof(int32_t),
-                              hipMemcpyDeviceToDevice, st));
-  int32_t tq = TILE_Q, tv = TILE_V, grid = PERSIST_WG;
-  tuned_shape(ix, d_s, nprobe, nq, &tq, &tv, &grid);
-  ADANNS_HIP(launch_search_multi(b, Q, ldq, dist, ids, k, probes_out, tq, tv, grid, st, coarse));
+  // The scratch grows with the batch (first-pass values of every candidate):
+  // a batch whose scratch would pass the cap runs in query chunks.
+  const size_t cap = g_scratch_cap.load();
+  auto scratch_of = [&](int64_t m) {
+    size_t t = 0;
+    carve(nullptr, ix, m, dq_pad, nprobe, coarse, &t);
+    return t;
+  };
+  int64_t chunk = nq;
+  while (chunk > 1 && scratch_of(chunk) > cap) chunk = (chunk + 1) / 2;
+  for (int64_t r0 = 0; r0 < nq; r0 += chunk) {
+    const int64_t m = std::min(chunk, nq - r0);
+    size_t total = scratch_of(m);
+    void *base = nullptr;
+    if ((s = get_scratch(ix, st, total, &base))) return s;
+    SearchBufs b = carve((char *)base, ix, m, dq_pad, nprobe, coarse, &total);
+    b.max_k = k;
+    ADANNS_HIP(launch_store_cfg(make_cfg(ix, coarse ? d_c : 1, d_s, nprobe, k, m), b.cfg, st));
+    if (!coarse)
+      ADANNS_HIP(hipMemcpyAsync(b.probes, given_probes + r0 * nprobe,
+                                (size_t)m * nprobe * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    int32_t tq = TILE_Q, tv = TILE_V, grid = PERSIST_WG;
+    tuned_shape(ix, d_s, nprobe, m, &tq, &tv, &grid);
+    ADANNS_HIP(launch_search_multi(b, Q + r0 * ldq, ldq, dist + r0 * k, ids + r0 * k,
+                                   k, probes_out ? probes_out + r0 * nprobe : nullptr, tq, tv,
+                                   grid, st, coarse));
+  }
+  return ADANNS_OK;
+}
+
+adanns_status adanns_set_search_scratch_cap(size_t bytes) {
+  clear_error();
+  g_scratch_cap.store(bytes ? bytes : kSearchScratchCap);
   return ADANNS_OK;
 }
 

@@ -28,6 +28,9 @@ constexpr int TILE_V = 64;     // vectors per distance tile
 constexpr int MAX_SHORTLIST = 1024;
 constexpr int REFINE_MARGIN = 8;   // extra first-pass candidates re-measured exactly
 constexpr int PERSIST_WG = 2048;   // workgroups of the persistent tile kernel (multiple of 8)
+// Default largest per-call search scratch before a batch is split into
+// query chunks (adanns_set_search_scratch_cap changes it).
+constexpr size_t kSearchScratchCap = size_t(32) << 30;
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }

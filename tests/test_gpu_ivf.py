@@ -172,3 +172,21 @@ def test_save_load_roundtrip(small, lib, tmp_path):
         assert np.array_equal(x, y)
     ix.free()
     ix2.free()
+
+
+def test_chunked_search_equals_whole(small, lib):
+    """A scratch cap far below one batch's scratch splits the search into
+    query chunks; results are bit for bit those of the whole batch."""
+    w, X, Q, C32, off, ids, index = small
+    whole = _run(index, Q, w.d_c, w.d_s, w.nprobe, w.k)
+    try:
+        lib.set_search_scratch_cap(64 * 1024)
+        parts = _run(index, Q, w.d_c, w.d_s, w.nprobe, w.k)
+        P = whole[2]
+        d2, g2 = index.search_probes(torch.from_numpy(Q).cuda(), P, w.d_s, w.k)
+        torch.cuda.synchronize()
+    finally:
+        lib.set_search_scratch_cap(0)
+    for x, y in zip(whole, parts):
+        assert np.array_equal(x, y)
+    assert np.array_equal(d2.cpu().numpy(), whole[0]) and np.array_equal(g2.cpu().numpy(), whole[1])
