@@ -2271,7 +2271,15 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
                                int32_t tv, int32_t grid, hipStream_t st, bool do_coarse) {
   if (tq != 32 && tq != 128) tq = 64;
   if (tv != 128) tv = 64;
-  {
+  // The kernels read query rows through 16-byte loads up to the 32-coordinate
+  // slab that holds the last coordinate they use, and mask what lies past it;
+  // rows that are 16-byte aligned and at least that wide are read in place,
+  // others are first staged into zero-padded rows.
+  SearchBufs bq = b;
+  if (ldq % 4 == 0 && ((uintptr_t)Q & 15) == 0 && ldq >= b.ldqs) {
+    bq.Qs = const_cast<float *>(Q);
+    bq.ldqs = ldq;
+  } else {
     const int64_t n = b.Qtot * b.ldqs;
     KernelTimer tm("stage_queries", st);
     hipLaunchKernelGGL(k_stage_multi, dim3(blocks_for(n, 256)), dim3(256), 0, st, Q, ldq, b.cfg,
@@ -2279,14 +2287,14 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (do_coarse && (e = coarse_multi(b, user_probes, nullptr, PERSIST_WG, st)) != hipSuccess)
+  if (do_coarse && (e = coarse_multi(bq, user_probes, nullptr, PERSIST_WG, st)) != hipSuccess)
     return e;
-  if ((e = bucketing_multi(b, tq, tv, st)) != hipSuccess) return e;
+  if ((e = bucketing_multi(bq, tq, tv, st)) != hipSuccess) return e;
   TileArgs t{};
   t.cfg = b.cfg;
   t.ncfg = b.ncfg;
-  t.Qs = b.Qs;
-  t.ldqs = b.ldqs;
+  t.Qs = bq.Qs;
+  t.ldqs = bq.ldqs;
   t.V = b.V;
   t.tile_off = b.tile_off;
   t.bkt_off = b.bkt_off;
@@ -2312,8 +2320,8 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
   m.cfg = b.cfg;
   m.ncfg = b.ncfg;
   m.coarse = 0;
-  m.Qs = b.Qs;
-  m.ldqs = b.ldqs;
+  m.Qs = bq.Qs;
+  m.ldqs = bq.ldqs;
   m.D = b.D;
   m.seg_off = b.seg_off;
   m.probes = b.probes;
