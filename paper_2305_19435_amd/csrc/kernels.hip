@@ -27,6 +27,7 @@ namespace adanns {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // Loads through a pointer that the compiler cannot prove global (one read
 // from a configuration record in memory, or chosen between LDS and global
@@ -227,7 +228,8 @@ __device__ __forceinline__ float f4(const float4 &v, int e) {
 // out[rbase[row] + v] = |x_v[:d]|^2 - 2 q_row[:d] . x_v[:d] for valid rows/vectors.
 // rq[] holds the staged-query row of each tile row (-1 = none); the valid
 // rows are the first nrow. Four waves in a 2 x 2 grid, each computing
-// (TQ/2) x (TV/2) with 16x16x4 FP32 MFMA.
+// (TQ/2) x (TV/2) with 32x32x2 FP32 MFMA blocks (16x16x4 blocks when a
+// wave's share is narrower than 32).
 template <int TQ, int TV>
 __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64_t ldqs,
                                              const float *vp, int64_t npad, int nvec_left,
@@ -254,6 +256,15 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int j = 0; j < NC; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+  constexpr bool BIG = TQ >= 64 && TV >= 64;
+  constexpr int NB32 = BIG ? TQ / 64 : 1, NC32 = BIG ? TV / 64 : 1;
+  floatx16 acc32[NB32][NC32];
+#pragma unroll
+  for (int i = 0; i < NB32; ++i)
+#pragma unroll
+    for (int j = 0; j < NC32; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc32[i][j][e] = 0.f;
   float nrm[NBV];
 #pragma unroll
   for (int u = 0; u < NBV; ++u) nrm[u] = 0.f;
@@ -316,6 +327,27 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
     __syncthreads();
     if (s + 1 < nslab) load(s + 1);
     if (active) {
+      if constexpr (BIG) {
+        // 32x32x2 blocks: MFMA k-slot (lane >> 5) at step t carries coordinate
+        // 16 * (lane >> 5) + t for both operands
+        const int r32 = lane & 31, k32 = (lane >> 5) * 16;
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          float4 af[NB32], bf[NC32];
+#pragma unroll
+          for (int i = 0; i < NB32; ++i) af[i] = *(const float4 *)&As[rbw + i * 32 + r32][k32 + 4 * q4];
+#pragma unroll
+          for (int j = 0; j < NC32; ++j) bf[j] = *(const float4 *)&Bs[cbw + j * 32 + r32][k32 + 4 * q4];
+#pragma unroll
+          for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int i = 0; i < NB32; ++i)
+#pragma unroll
+              for (int j = 0; j < NC32; ++j)
+                acc32[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(f4(af[i], kb), f4(bf[j], kb),
+                                                                   acc32[i][j], 0, 0, 0);
+        }
+      } else {
       // two halves of the slab: MFMA k-slot (lane >> 4) carries coordinate
       // 8 * (lane >> 4) + 4 * half + kb for both operands, so every
       // coordinate of the slab is used exactly once
@@ -335,6 +367,7 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(f4(af[i], kb), f4(bf[j], kb),
                                                                acc[i][j], 0, 0, 0);
       }
+      }
     }
   }
   // norms: 8 consecutive threads share a vector row
@@ -346,6 +379,21 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
     if ((tid & 7) == 0) cn[lr + 32 * u] = nrm[u];
   }
   __syncthreads();
+  if constexpr (BIG) {
+    // 32x32 f32 MFMA result: lane holds column (lane & 31), register e holds
+    // row 8 * (e / 4) + 4 * (lane >> 5) + e % 4
+#pragma unroll
+    for (int i = 0; i < NB32; ++i)
+#pragma unroll
+      for (int j = 0; j < NC32; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int row = rbw + i * 32 + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4);
+          const int col = cbw + j * 32 + (lane & 31);
+          if (rq[row] >= 0 && col < nvec_left) out[rbase[row] + col] = cn[col] - 2.0f * acc32[i][j][e];
+        }
+    return;
+  }
   // 16x16 f32 MFMA result: lane holds column (lane & 15), rows 4*(lane>>4)+e
 #pragma unroll
   for (int i = 0; i < NB; ++i)
