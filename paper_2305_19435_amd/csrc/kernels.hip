@@ -1590,30 +1590,44 @@ __global__ __launch_bounds__(256) void k_pq_lut(const float *__restrict__ qh, in
     if (q0 + a < nq) lut[((q0 + a) * M + m) * 256 + c] = acc[a];
 }
 
-// ADC scan of one (query, probe) pair: the query's table is held in LDS and
-// every vector of the probed list sums the M table entries its codes pick
-// (in code order m = 0..M-1). One pair per workgroup: the pairs of a query
-// re-read its table from L2, but their lists' latencies overlap (several
-// pairs per workgroup, each loading its table once, measured slower).
-__global__ __launch_bounds__(256) void k_adc_scan(const float *__restrict__ lut, int32_t M,
-                                                  const uint8_t *__restrict__ codes,
-                                                  const int32_t *__restrict__ probes,
-                                                  int32_t nprobe,
-                                                  const int64_t *__restrict__ poff,
-                                                  const int32_t *__restrict__ len,
-                                                  const int64_t *__restrict__ pair_base,
-                                                  float *__restrict__ D) {
+// ADC scan: a workgroup holds one query's table in LDS and walks G of its
+// probed lists one after another, every thread taking rows of the current
+// list; each row sums the M table entries its codes pick (in code order
+// m = 0..M-1). 1024 threads share one table, so that a CU holds enough waves
+// to hide the table reads' latency. The next list's location is loaded while
+// the current one is scanned.
+constexpr int ADC_THREADS = 1024;
+__global__ __launch_bounds__(ADC_THREADS) void k_adc_scan(const float *__restrict__ lut, int32_t M,
+                                                          const uint8_t *__restrict__ codes,
+                                                          const int32_t *__restrict__ probes,
+                                                          int32_t nprobe, int32_t G,
+                                                          const int64_t *__restrict__ poff,
+                                                          const int32_t *__restrict__ len,
+                                                          const int64_t *__restrict__ pair_base,
+                                                          float *__restrict__ D) {
   extern __shared__ float tab[];  // [M][256]
-  const int64_t pair = blockIdx.x;
-  const int64_t q = pair / nprobe;
+  const int gpq = (nprobe + G - 1) / G;
+  const int64_t q = blockIdx.x / gpq;
+  const int j0 = (int)(blockIdx.x % gpq) * G, j1 = min(nprobe, j0 + G);
   const float4 *src = (const float4 *)(lut + q * M * 256);
   for (int i = threadIdx.x; i < M * 64; i += blockDim.x) ((float4 *)tab)[i] = src[i];
   __syncthreads();
-  {
+  auto where = [&](int j, int32_t &n, const uint8_t *&cbase, float *&out) {
+    const int64_t pair = q * nprobe + j;
     const int32_t h = probes[pair];
-    const int32_t n = len[h];
-    const uint8_t *cbase = codes + poff[h] * M;
-    float *out = D + pair_base[pair];
+    n = len[h];
+    cbase = codes + poff[h] * M;
+    out = D + pair_base[pair];
+  };
+  int32_t n;
+  const uint8_t *cbase;
+  float *out;
+  where(j0, n, cbase, out);
+  for (int j = j0; j < j1; ++j) {
+    int32_t n2 = 0;
+    const uint8_t *cb2 = nullptr;
+    float *out2 = nullptr;
+    if (j + 1 < j1) where(j + 1, n2, cb2, out2);
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
       float acc = 0.f;
       if ((M & 15) == 0) {  // 16 codes per load (rows are 16-byte aligned)
@@ -1643,6 +1657,9 @@ __global__ __launch_bounds__(256) void k_adc_scan(const float *__restrict__ lut,
       }
       out[r] = acc;
     }
+    n = n2;
+    cbase = cb2;
+    out = out2;
   }
 }
 
@@ -2603,9 +2620,11 @@ hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const Sea
   }
   {
     KernelTimer tm("adc_scan", st);
+    // lists per workgroup: as many as keep about 512 workgroups in flight
+    const int32_t G = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nprobe, nq * nprobe / 512));
     if (nq > 0)
-      hipLaunchKernelGGL(k_adc_scan, dim3((unsigned)(nq * nprobe)), dim3(256),
-                         pq.M * 256 * sizeof(float), st, lut, pq.M, pq.codes, b.probes, nprobe,
+      hipLaunchKernelGGL(k_adc_scan, dim3((unsigned)(nq * cdiv(nprobe, G))), dim3(ADC_THREADS),
+                         pq.M * 256 * sizeof(float), st, lut, pq.M, pq.codes, b.probes, nprobe, G,
                          ix->poff, ix->len, b.pair_base, b.D);
   }
   e = hipGetLastError();
