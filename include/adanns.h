@@ -114,10 +114,11 @@ adanns_status adanns_build_ivf(const void *X, int64_t n, int32_t d, int64_t ldx,
                                void *stream, adanns_index **out);
 
 /* Search scratch (staged queries, scores, buckets and every candidate's
- * first-pass value) grows with nq. adanns_search and adanns_search_probes
- * split a batch whose scratch would exceed ``bytes`` into query chunks run
- * one after another on the stream (results unchanged). 0 restores the
- * default of 32 GiB. Process-wide; affects calls made afterwards. */
+ * first-pass value) grows with nq. adanns_search, adanns_search_probes,
+ * adanns_search_pq and adanns_search_precision split a batch whose scratch
+ * would exceed ``bytes`` into query chunks run one after another on the
+ * stream (results unchanged). 0 restores the default of 32 GiB.
+ * Process-wide; affects calls made afterwards. */
 adanns_status adanns_set_search_scratch_cap(size_t bytes);
 
 /*

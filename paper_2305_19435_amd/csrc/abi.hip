@@ -843,11 +843,27 @@ adanns_status adanns_search_pq(const adanns_index *cix, const float *Q, int64_t 
   if (s) return s;
   hipStream_t st = (hipStream_t)stream;
   const int32_t dq_pad = (int32_t)round_up(dq, SLAB);
+  auto bytes_of = [&](int64_t m, size_t *carved) {
+    size_t t = 0;
+    carve(nullptr, ix, m, dq_pad, nprobe, true, &t);
+    if (carved) *carved = t;
+    return t + (size_t)round_up((size_t)m * pq.d_s * 4, 256) * 2 +
+           (size_t)round_up((size_t)m * M * 256 * 4, 256) + 1024;
+  };
+  if (nq > 1 && bytes_of(nq, nullptr) > g_scratch_cap.load()) {  // query chunks
+    int64_t chunk = nq;
+    while (chunk > 1 && bytes_of(chunk, nullptr) > g_scratch_cap.load()) chunk = (chunk + 1) / 2;
+    for (int64_t r0 = 0; r0 < nq; r0 += chunk) {
+      const int64_t m = std::min(chunk, nq - r0);
+      if ((s = adanns_search_pq(ix, Q + r0 * ldq, m, ldq, d_c, nprobe, M, k, rerank_k, d_rerank,
+                                dist + r0 * k, ids + r0 * k, probes ? probes + r0 * nprobe : nullptr,
+                                stream)))
+        return s;
+    }
+    return ADANNS_OK;
+  }
   size_t total = 0;
-  SearchBufs b0 = carve(nullptr, ix, nq, dq_pad, nprobe, true, &total);
-  (void)b0;
-  const size_t extra = (size_t)round_up((size_t)nq * pq.d_s * 4, 256) * 2 +
-                       (size_t)round_up((size_t)nq * M * 256 * 4, 256) + 1024;
+  const size_t extra = bytes_of(nq, &total) - total;
   void *base = nullptr;
   if ((s = get_scratch(ix, st, total + extra, &base))) return s;
   SearchBufs b = carve((char *)base, ix, nq, dq_pad, nprobe, true, &total);
@@ -944,10 +960,27 @@ adanns_status adanns_search_precision(const adanns_index *cix, const float *Q, i
   const int32_t dq = std::max(d_c, d_s);
   const int32_t dq_pad = (int32_t)round_up(dq, SLAB);
   const size_t eb = fmt == ADANNS_BF16 ? 2 : 1;
+  auto bytes_of = [&](int64_t m, size_t *carved) {
+    size_t t = 0;
+    carve(nullptr, ix, m, dq_pad, nprobe, true, &t);
+    if (carved) *carved = t;
+    return t + (size_t)round_up((size_t)m * ix->d_pad * eb, 256) +
+           (size_t)round_up((size_t)m * 4, 256) + 1024;
+  };
+  if (nq > 1 && bytes_of(nq, nullptr) > g_scratch_cap.load()) {  // query chunks
+    int64_t chunk = nq;
+    while (chunk > 1 && bytes_of(chunk, nullptr) > g_scratch_cap.load()) chunk = (chunk + 1) / 2;
+    for (int64_t r0 = 0; r0 < nq; r0 += chunk) {
+      const int64_t m = std::min(chunk, nq - r0);
+      if ((s = adanns_search_precision(ix, Q + r0 * ldq, m, ldq, d_c, d_s, nprobe, k, fmt,
+                                       rerank_k, coarse_margin, dist + r0 * k, ids + r0 * k,
+                                       probes ? probes + r0 * nprobe : nullptr, stream)))
+        return s;
+    }
+    return ADANNS_OK;
+  }
   size_t total = 0;
-  carve(nullptr, ix, nq, dq_pad, nprobe, true, &total);
-  const size_t extra = (size_t)round_up((size_t)nq * ix->d_pad * eb, 256) +
-                       (size_t)round_up((size_t)nq * 4, 256) + 1024;
+  const size_t extra = bytes_of(nq, &total) - total;
   void *base = nullptr;
   if ((s = get_scratch(ix, st, total + extra, &base))) return s;
   SearchBufs b = carve((char *)base, ix, nq, dq_pad, nprobe, true, &total);

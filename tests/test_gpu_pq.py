@@ -171,3 +171,19 @@ def test_exhaustive_opq_prefix(lib, small_data, d_s, M):
                           report=rep, tag=f"q{qi}", dist64=fn)
     assert rep.ok, rep.problems
     index.free()
+
+
+def test_pq_chunked_equals_whole(pq_small, lib):
+    w, X, Q, C32, off, ids, index, codecs = pq_small
+    Qd = torch.from_numpy(Q).cuda()
+    whole = index.search_pq(Qd, w.d_c, 4, 16, 10, rerank_k=40, d_rerank=w.d, return_probes=True)
+    torch.cuda.synchronize()
+    try:
+        lib.set_search_scratch_cap(64 * 1024)
+        parts = index.search_pq(Qd, w.d_c, 4, 16, 10, rerank_k=40, d_rerank=w.d,
+                                return_probes=True)
+        torch.cuda.synchronize()
+    finally:
+        lib.set_search_scratch_cap(0)
+    for x, y in zip(whole, parts):
+        assert torch.equal(x, y)

@@ -72,3 +72,18 @@ def test_precision_requires_copy(lib, small_data):
     with pytest.raises(lib.AdannsError):
         index.search_precision(torch.from_numpy(Q).cuda(), w.d_c, w.d_s, 2, 10, "bf16", 20)
     index.free()
+
+
+def test_precision_chunked_equals_whole(prec, lib):
+    w, X, Q, C32, off, ids, index = prec
+    Qd = torch.from_numpy(Q).cuda()
+    whole = index.search_precision(Qd, w.d_c, w.d_s, 4, 10, "fp8", 20, 8, return_probes=True)
+    torch.cuda.synchronize()
+    try:
+        lib.set_search_scratch_cap(64 * 1024)
+        parts = index.search_precision(Qd, w.d_c, w.d_s, 4, 10, "fp8", 20, 8, return_probes=True)
+        torch.cuda.synchronize()
+    finally:
+        lib.set_search_scratch_cap(0)
+    for x, y in zip(whole, parts):
+        assert torch.equal(x, y)
