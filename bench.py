@@ -62,7 +62,8 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (HBM counter calibration)")
     ap.add_argument("--form", default="ivf",
-                    choices=["ivf", "precision", "batching", "pq", "serving", "diagnostics"],
+                    choices=["ivf", "precision", "batching", "pq", "serving", "diagnostics",
+                             "sweep"],
                     help="ivf: the headline FP32 search; the others measure the other forms")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile-shape autotuner")
     ap.add_argument("--rerank", type=int, default=256, help="precision form shortlist")

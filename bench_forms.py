@@ -40,7 +40,8 @@ def _kernel_ms(lib, names):
 
 def run(args, lib, torch, log):
     {"precision": precision_form, "batching": batching_form, "pq": pq_form,
-     "serving": serving_form, "diagnostics": diagnostics_form}[args.form](args, lib, torch, log)
+     "serving": serving_form, "diagnostics": diagnostics_form,
+     "sweep": sweep_form}[args.form](args, lib, torch, log)
 
 
 # ---------------------------------------------------------------------------
@@ -405,4 +406,77 @@ def diagnostics_form(args, lib, torch, log):
            "relative_contrast": {"values": rc,
                                  "sample": "16 queries x 65,536 seeded database rows, oracle FP64"}}
     index.free()
+    print(json.dumps(out), flush=True)
+
+
+def sweep_form(args, lib, torch, log):
+    """The image-retrieval configuration's full grid: one index per d_c in
+    {8, ..., 2048} (Lloyd on that prefix), searched at d_s = 2048 with nprobe
+    in {1, ..., 64}: QPS of the whole 50k-query batch, recall@10 against exact
+    search (the library's exhaustive search, nprobe = nlist at d_s = d, which
+    the parity tests pin to the FP64 oracle), the cost model's multiply-adds
+    per query (Appendix B.1 as read), and the coarse contraction's MFMA rate.
+    Scan tile shapes come from the library's autotuner (one run per nprobe)."""
+    w = synth.WORKLOADS["imagenet1k"]
+    n = args.n or w.n
+    nq = args.nq or w.nq
+    k, d_s, nlist = w.k, w.d_s, w.nlist
+    mix = w.mixture()
+    X = mix.database(n)
+    Q = mix.queries(nq)
+    Xd = torch.from_numpy(X).cuda()
+    Qd = torch.from_numpy(Q).cuda()
+    n_train = min(n, 64 * nlist)
+    tr = synth.subsample_rows(n, n_train, w.seed)
+    init = synth.init_rows(n_train, nlist, w.seed)
+    widths = [8, 16, 32, 64, 128, 256, 512, 1024, 2048]
+    probes = [1, 2, 4, 8, 16, 32, 64]
+    truth = None
+    grid = {}
+    for dc in widths:
+        t0 = time.time()
+        index = lib.IvfIndex.build_ivf(Xd, nlist, dc, args.iters, init, train_rows=tr)
+        torch.cuda.synchronize()
+        log(f"d_c={dc}: index built in {time.time() - t0:.1f}s")
+        if truth is None:  # exact top-k: every list, full width
+            t0 = time.time()
+            _, truth = index.search(Qd, dc, d_s, nlist, k)
+            torch.cuda.synchronize()
+            truth = truth.cpu().numpy()
+            log(f"exact top-{k} of {nq} queries (exhaustive search) in {time.time() - t0:.1f}s")
+        dist = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+        ids = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+        if dc == widths[0]:
+            # tile shapes for every nprobe (the autotuner's cache key does not
+            # depend on the index, so these serve every d_c)
+            for npb in probes:
+                tb = lib.Batch([(index, nq, dc, d_s, npb, k)], ldq=w.d, ldk=k)
+                tb.autotune(Qd, out=(dist, ids), reps=1)
+                tb.free()
+        for npb in probes:
+            lib.timing_reset()
+            lib.timing_enable(True)
+            t = _timed(torch, lambda: index.search(Qd, dc, d_s, npb, k, out=(dist, ids)),
+                       max(2, args.steps // 2), 1)
+            lib.timing_enable(False)
+            kern = _kernel_ms(lib, ["tile_dist_coarse", "tile_dist_scan", "select_scan"])
+            got = ids.cpu().numpy()
+            hits = sum(len(set(a.tolist()) & set(b.tolist())) for a, b in zip(got, truth))
+            coarse_tf = (2.0 * nq * nlist * dc / (kern["tile_dist_coarse"] * 1e-3) / 1e12
+                         if "tile_dist_coarse" in kern else None)
+            grid[f"d_c={dc},nprobe={npb}"] = {
+                "qps": round(nq / t, 1), "ms_per_step": round(t * 1e3, 3),
+                "recall_at_10": round(hits / (k * nq), 5),
+                "cost_macs_per_query": dc * nlist + npb * d_s * n / nlist,
+                "kernels_ms": kern,
+                "coarse_mfma_tflops": None if coarse_tf is None else round(coarse_tf, 2),
+                "coarse_mfma_frac": None if coarse_tf is None else round(coarse_tf / MFMA_FP32_PEAK_TFLOPS, 4)}
+        index.free()
+    best = max(grid.values(), key=lambda r: r["qps"] if r["recall_at_10"] >= 0.69 else 0)
+    out = {"metric": "QPS and recall@10 over the (d_c, nprobe) grid, 50k-query batches",
+           "value": best["qps"], "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": f"imagenet1k: N={n} d={w.d} nq={nq} nlist={nlist} d_s={d_s} "
+                                  f"k={k}; one index per d_c; value = best QPS at recall@10 >= 0.69"},
+           "grid": grid}
     print(json.dumps(out), flush=True)
