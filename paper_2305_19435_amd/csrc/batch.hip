@@ -69,6 +69,7 @@ void tuned_shape(const adanns_index *ix, int32_t d_s, int32_t nprobe, int64_t nq
 }
 
 static void drop_graph(adanns_batch *p) {
+  if (p->exec && p->priv) (void)hipStreamSynchronize(p->priv);  // no replay still in flight
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   p->exec = nullptr;
