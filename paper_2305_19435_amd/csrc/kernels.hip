@@ -22,12 +22,12 @@
 #include <algorithm>
 #include <cstdio>
 #include <mutex>
+#include <type_traits>
 
 namespace adanns {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // Loads through a pointer that the compiler cannot prove global (one read
 // from a configuration record in memory, or chosen between LDS and global
@@ -227,9 +227,9 @@ __device__ __forceinline__ float f4(const float4 &v, int e) {
 // One TV-vector tile of a list against TQ query rows:
 // out[rbase[row] + v] = |x_v[:d]|^2 - 2 q_row[:d] . x_v[:d] for valid rows/vectors.
 // rq[] holds the staged-query row of each tile row (-1 = none); the valid
-// rows are the first nrow. Four waves in a 2 x 2 grid, each computing
-// (TQ/2) x (TV/2) with 32x32x2 FP32 MFMA blocks (16x16x4 blocks when a
-// wave's share is narrower than 32).
+// rows are the first nrow. This register-staged form serves the narrow
+// tiles (TQ = 32): four waves in a 2 x 2 grid, each computing (TQ/2) x (TV/2)
+// with 16x16x4 FP32 MFMA blocks; wider tiles use tile_compute_dma below.
 template <int TQ, int TV>
 __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64_t ldqs,
                                              const float *vp, int64_t npad, int nvec_left,
@@ -256,15 +256,6 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int j = 0; j < NC; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
-  constexpr bool BIG = TQ >= 64 && TV >= 64;
-  constexpr int NB32 = BIG ? TQ / 64 : 1, NC32 = BIG ? TV / 64 : 1;
-  floatx16 acc32[NB32][NC32];
-#pragma unroll
-  for (int i = 0; i < NB32; ++i)
-#pragma unroll
-    for (int j = 0; j < NC32; ++j)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) acc32[i][j][e] = 0.f;
   float nrm[NBV];
 #pragma unroll
   for (int u = 0; u < NBV; ++u) nrm[u] = 0.f;
@@ -327,27 +318,6 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
     __syncthreads();
     if (s + 1 < nslab) load(s + 1);
     if (active) {
-      if constexpr (BIG) {
-        // 32x32x2 blocks: MFMA k-slot (lane >> 5) at step t carries coordinate
-        // 16 * (lane >> 5) + t for both operands
-        const int r32 = lane & 31, k32 = (lane >> 5) * 16;
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-          float4 af[NB32], bf[NC32];
-#pragma unroll
-          for (int i = 0; i < NB32; ++i) af[i] = *(const float4 *)&As[rbw + i * 32 + r32][k32 + 4 * q4];
-#pragma unroll
-          for (int j = 0; j < NC32; ++j) bf[j] = *(const float4 *)&Bs[cbw + j * 32 + r32][k32 + 4 * q4];
-#pragma unroll
-          for (int kb = 0; kb < 4; ++kb)
-#pragma unroll
-            for (int i = 0; i < NB32; ++i)
-#pragma unroll
-              for (int j = 0; j < NC32; ++j)
-                acc32[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(f4(af[i], kb), f4(bf[j], kb),
-                                                                   acc32[i][j], 0, 0, 0);
-        }
-      } else {
       // two halves of the slab: MFMA k-slot (lane >> 4) carries coordinate
       // 8 * (lane >> 4) + 4 * half + kb for both operands, so every
       // coordinate of the slab is used exactly once
@@ -367,7 +337,6 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(f4(af[i], kb), f4(bf[j], kb),
                                                                acc[i][j], 0, 0, 0);
       }
-      }
     }
   }
   // norms: 8 consecutive threads share a vector row
@@ -379,21 +348,6 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
     if ((tid & 7) == 0) cn[lr + 32 * u] = nrm[u];
   }
   __syncthreads();
-  if constexpr (BIG) {
-    // 32x32 f32 MFMA result: lane holds column (lane & 31), register e holds
-    // row 8 * (e / 4) + 4 * (lane >> 5) + e % 4
-#pragma unroll
-    for (int i = 0; i < NB32; ++i)
-#pragma unroll
-      for (int j = 0; j < NC32; ++j)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int row = rbw + i * 32 + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4);
-          const int col = cbw + j * 32 + (lane & 31);
-          if (rq[row] >= 0 && col < nvec_left) out[rbase[row] + col] = cn[col] - 2.0f * acc32[i][j][e];
-        }
-    return;
-  }
   // 16x16 f32 MFMA result: lane holds column (lane & 15), rows 4*(lane>>4)+e
 #pragma unroll
   for (int i = 0; i < NB; ++i)
@@ -407,14 +361,191 @@ __device__ __forceinline__ void tile_compute(const float *__restrict__ Qs, int64
       }
 }
 
+// LDS-DMA form of the tile for TQ, TV >= 64. Every lane copies 16-byte
+// chunks from global memory straight into LDS (global_load_lds_dwordx4); two
+// LDS stages alternate, so one barrier per slab remains and no registers
+// carry the next slab. A stage holds each operand row as 32 floats without
+// padding; 16-byte chunk c of row r sits at position c ^ f(r), with
+// f(r) = (r & 7) ^ ((r >> 3) & 1), which spreads the 16-byte reads of 8 or 16
+// consecutive rows over all LDS banks. Four waves in a 2 x 2 grid compute
+// (TQ/2) x (TV/2) each with 16x16x4 FP32 MFMA blocks. Vector norms are summed
+// from the B fragments the MFMAs read.
+__device__ __forceinline__ int swz(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+// s_waitcnt immediate for vmcnt(n) with the other counters left free
+constexpr int vm_wait_imm(int n) { return 0x0F70 | (n & 15) | ((n >> 4) << 14); }
+template <int I> using ic = std::integral_constant<int, I>;
+
+template <int TQ, int TV>
+__device__ __forceinline__ void tile_compute_dma(const float *__restrict__ Qs, int64_t ldqs,
+                                                 const float *vp, int64_t npad, int nvec_left,
+                                                 int nrow, int d_dot, const int32_t *rq,
+                                                 const int64_t *rbase, float *__restrict__ out,
+                                                 float *A0, float *B0, float *A1, float *B1,
+                                                 float *cn) {
+  static_assert(TQ >= 64 && TV >= 64, "LDS-DMA tile needs TQ, TV >= 64");
+  constexpr int NA = TQ / 32;   // 16-byte copies of A per lane per slab
+  constexpr int NBV = TV / 32;  // 16-byte copies of B per lane per slab
+  constexpr int NB16 = TQ / 32, NC16 = TV / 32;  // 16x16 blocks per wave
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rbw = (wv >> 1) * (TQ / 2), cbw = (wv & 1) * (TV / 2);
+  const int ncol = nvec_left < TV ? nvec_left : TV;
+  // a wave whose rows or vectors all lie past the valid ones skips its MFMAs
+  const bool active = nrow > rbw && ncol > cbw;
+  const int nslab = (d_dot + SLAB - 1) / SLAB;
+
+  // Copy side: wave instruction u fills rows (4u + wv) * 8 .. + 7, lane l
+  // writing LDS chunk (l & 7) of row (l >> 3) of that block. Copies are
+  // unconditional: a row past the tile's valid queries reads staged row 0 and
+  // a vector past the list's length re-reads its last vector; neither result
+  // is written out.
+  const int lrow = lane >> 3;
+  const int gch = (lane & 7) ^ lrow ^ (wv & 1);  // global chunk: (l & 7) ^ f(row)
+  const float *qp[NA];
+#pragma unroll
+  for (int u = 0; u < NA; ++u) {
+    const int q = rq[(4 * u + wv) * 8 + lrow];
+    qp[u] = Qs + (int64_t)(q >= 0 ? q : 0) * ldqs + gch * 4;
+  }
+  int vrow[NBV];
+#pragma unroll
+  for (int u = 0; u < NBV; ++u) vrow[u] = min((4 * u + wv) * 8 + lrow, ncol - 1) * SLAB + gch * 4;
+  auto issue = [&](int s, float *A, float *B) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u)
+      __builtin_amdgcn_global_load_lds(
+          (const void *)(qp[u] + s * SLAB),
+          (__attribute__((address_space(3))) void *)(A + (4 * u + wv) * 8 * SLAB), 16, 0, 0);
+    const float *src = vp + (int64_t)s * npad * SLAB;
+#pragma unroll
+    for (int u = 0; u < NBV; ++u)
+      __builtin_amdgcn_global_load_lds(
+          (const void *)(src + vrow[u]),
+          (__attribute__((address_space(3))) void *)(B + (4 * u + wv) * 8 * SLAB), 16, 0, 0);
+  };
+  // The last slab of a prefix that ends inside it: every lane zeroes, in the
+  // stage just filled, the coordinates past the prefix of the chunks it
+  // copied (both operands, so that values past the prefix never meet), then
+  // the workgroup synchronises again.
+  auto clip = [&](float *A, float *B, int lim) {
+    const int c = (lane & 7) * 4;  // LDS position of this lane's chunks
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (gch * 4 + e >= lim) {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) A[((4 * u + wv) * 8 + lrow) * SLAB + c + e] = 0.f;
+#pragma unroll
+        for (int u = 0; u < NBV; ++u) B[((4 * u + wv) * 8 + lrow) * SLAB + c + e] = 0.f;
+      }
+    __syncthreads();
+  };
+
+  floatx4 acc[NB16][NC16];
+#pragma unroll
+  for (int i = 0; i < NB16; ++i)
+#pragma unroll
+    for (int j = 0; j < NC16; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+  float nrm[NC16];
+#pragma unroll
+  for (int j = 0; j < NC16; ++j) nrm[j] = 0.f;
+  // Read side: in half h of a slab, lane l reads row (l & 15) of each
+  // 16-row block, global chunk 2 (l >> 4) + h; MFMA k-slot (l >> 4) at step t
+  // then carries coordinate 8 (l >> 4) + 4 h + t for both operands.
+  const int r16 = lane & 15, g16 = lane >> 4;
+  const int sw16 = swz(r16);
+  auto compute = [&](const float *A, const float *B) {
+    float4 af[2][NB16], bf[2][NC16];
+    auto fetch = [&](int h) {
+      const int off = (((2 * g16 + h) ^ sw16) << 2);
+#pragma unroll
+      for (int i = 0; i < NB16; ++i) af[h][i] = *(const float4 *)&A[(rbw + i * 16 + r16) * SLAB + off];
+#pragma unroll
+      for (int j = 0; j < NC16; ++j) bf[h][j] = *(const float4 *)&B[(cbw + j * 16 + r16) * SLAB + off];
+    };
+    fetch(0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 0) fetch(1);
+#pragma unroll
+      for (int j = 0; j < NC16; ++j)
+        nrm[j] += bf[h][j].x * bf[h][j].x + bf[h][j].y * bf[h][j].y + bf[h][j].z * bf[h][j].z +
+                  bf[h][j].w * bf[h][j].w;
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int i = 0; i < NB16; ++i)
+#pragma unroll
+          for (int j = 0; j < NC16; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(f4(af[h][i], kb), f4(bf[h][j], kb),
+                                                             acc[i][j], 0, 0, 0);
+    }
+    // Schedule: the first half's reads, then the second half's reads spread
+    // over the first half's MFMAs (six MFMAs after each), then the remaining
+    // MFMAs, the norms last.
+    constexpr int NR = NB16 + NC16, NM = NB16 * NC16 * 4, SPREAD = NM / NR < 6 ? NM / NR : 6;
+    __builtin_amdgcn_sched_group_barrier(0x100, NR, 0);
+#pragma unroll
+    for (int t = 0; t < NR; ++t) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, SPREAD, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 2 * NM - NR * SPREAD, 0);
+    __builtin_amdgcn_sched_group_barrier(0x002, 64, 0);
+  };
+
+  // Stage J holds slab s; the copy of slab s + 1 is in flight meanwhile.
+  __builtin_amdgcn_s_waitcnt(vm_wait_imm(0));  // the previous item's stores first
+  issue(0, A0, B0);
+  int s = 0;
+  auto step = [&](auto J) -> bool {
+    constexpr int j = decltype(J)::value;
+    float *A = j == 0 ? A0 : A1, *B = j == 0 ? B0 : B1;
+    __builtin_amdgcn_s_waitcnt(vm_wait_imm(0));  // this wave's copies of slab s have landed
+    __syncthreads();  // slab s is in stage j; every wave is done with stage 1 - j
+    if (s + 1 < nslab) issue(s + 1, j == 0 ? A1 : A0, j == 0 ? B1 : B0);
+    if (d_dot - s * SLAB < SLAB) clip(A, B, d_dot - s * SLAB);
+    if (active) compute(A, B);
+    return ++s >= nslab;
+  };
+  for (;;) {
+    if (step(ic<0>{})) break;
+    if (step(ic<1>{})) break;
+  }
+  // norms: the four lane groups of a column hold its four coordinate ranges;
+  // waves 0 and 1 cover every column (wave 0 is always active, wave 1
+  // whenever its columns hold vectors)
+#pragma unroll
+  for (int j = 0; j < NC16; ++j) {
+    nrm[j] += __shfl_xor(nrm[j], 16);
+    nrm[j] += __shfl_xor(nrm[j], 32);
+    if (wv < 2 && active && lane < 16) cn[cbw + j * 16 + lane] = nrm[j];
+  }
+  __syncthreads();
+  // 16x16 f32 MFMA result: lane holds column (lane & 15), rows 4 (lane >> 4) + e
+#pragma unroll
+  for (int i = 0; i < NB16; ++i)
+#pragma unroll
+    for (int j = 0; j < NC16; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = rbw + i * 16 + 4 * (lane >> 4) + e;
+        const int col = cbw + j * 16 + (lane & 15);
+        if (rq[row] >= 0 && col < nvec_left) out[rbase[row] + col] = cn[col] - 2.0f * acc[i][j][e];
+      }
+}
+
 // Persistent tile kernel over a batch (two workgroups per CU: the register
 // budget is held to 256 per lane). COARSE: every configuration's queries
 // against its centroids (tiles numbered per configuration); otherwise every
 // virtual list against the queries probing it.
 template <int TQ, int TV, int COARSE>
 __global__ __launch_bounds__(256, 2) void k_tile_multi(TileArgs a) {
-  __shared__ __attribute__((aligned(16))) float As[TQ][SLAB + 4];
-  __shared__ __attribute__((aligned(16))) float Bs[TV][SLAB + 4];
+  constexpr bool DMA = TQ >= 64 && TV >= 64;
+  // two unpadded stages for the LDS-DMA tile, one padded stage otherwise
+  __shared__ __attribute__((aligned(16))) float As[DMA ? TQ * SLAB : TQ * (SLAB + 4)];
+  __shared__ __attribute__((aligned(16))) float Bs[DMA ? TV * SLAB : TV * (SLAB + 4)];
+  __shared__ __attribute__((aligned(16))) float As1[DMA ? TQ * SLAB : 4];
+  __shared__ __attribute__((aligned(16))) float Bs1[DMA ? TV * SLAB : 4];
   __shared__ int64_t rbase[TQ];
   __shared__ int32_t rq[TQ];
   __shared__ float cn[TV];
@@ -481,9 +612,15 @@ __global__ __launch_bounds__(256, 2) void k_tile_multi(TileArgs a) {
       }
     }
     __syncthreads();
-    tile_compute<TQ, TV>(a.Qs, a.ldqs, vbase + (int64_t)vt * TV * SLAB, npad, nvec - vt * TV,
-                         min(TQ, m - qt * TQ), d_dot, rq, rbase,
-                         (COARSE ? a.S : a.D) + (int64_t)vt * TV, As, Bs, cn);
+    if constexpr (DMA)
+      tile_compute_dma<TQ, TV>(a.Qs, a.ldqs, vbase + (int64_t)vt * TV * SLAB, npad,
+                               nvec - vt * TV, min(TQ, m - qt * TQ), d_dot, rq, rbase,
+                               (COARSE ? a.S : a.D) + (int64_t)vt * TV, As, Bs, As1, Bs1, cn);
+    else
+      tile_compute<TQ, TV>(a.Qs, a.ldqs, vbase + (int64_t)vt * TV * SLAB, npad, nvec - vt * TV,
+                           min(TQ, m - qt * TQ), d_dot, rq, rbase,
+                           (COARSE ? a.S : a.D) + (int64_t)vt * TV,
+                           (float(*)[SLAB + 4])As, (float(*)[SLAB + 4])Bs, cn);
   }
 }
 
