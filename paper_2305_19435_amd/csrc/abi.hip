@@ -250,6 +250,7 @@ SearchBufs carve(char *base, const adanns_index *ix, int64_t nq, int32_t dq_pad,
   b.probes = c.take<int32_t>((size_t)nq * nprobe);
   b.cnt = c.take<int32_t>(ix->nlist);
   b.cursor = c.take<int32_t>(ix->nlist);
+  b.work = c.take<int32_t>(8);
   b.bkt_off = c.take<int32_t>(ix->nlist);
   b.tile_off = c.take<int32_t>(ix->nlist + 1);
   b.bucket = c.take<int32_t>((size_t)nq * nprobe);

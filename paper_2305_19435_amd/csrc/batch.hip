@@ -164,6 +164,7 @@ adanns_status adanns_batch_create(const adanns_batch_config *cfgs, int32_t ncfg,
     b.probes = cv.take<int32_t>((size_t)pair0);
     b.cnt = cv.take<int32_t>(V);
     b.cursor = cv.take<int32_t>(V);
+    b.work = cv.take<int32_t>(8);
     b.bkt_off = cv.take<int32_t>(V);
     b.tile_off = cv.take<int32_t>(V + 1);
     b.bucket = cv.take<int32_t>((size_t)pair0);

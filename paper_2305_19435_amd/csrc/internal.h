@@ -181,6 +181,7 @@ struct SearchBufs {
   int32_t *probes;    // [nq][nprobe]
   int32_t *cnt;       // [nlist]
   int32_t *cursor;    // [nlist]
+  int32_t *work;      // [8] scan work counters, one per XCD
   int32_t *bkt_off;   // [nlist]
   int32_t *tile_off;  // [nlist + 1]
   int32_t *bucket;    // [nq * nprobe]

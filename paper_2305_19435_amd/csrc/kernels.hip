@@ -218,6 +218,7 @@ struct TileArgs {
   float *S;                // coarse output
   float *D;                // scan output
   int32_t ct_total;        // coarse: tiles over configurations
+  int32_t *work;           // scan: [8] work counters, zero at launch
 };
 
 __device__ __forceinline__ float f4(const float4 &v, int e) {
@@ -552,11 +553,24 @@ __global__ __launch_bounds__(256, 2) void k_tile_multi(TileArgs a) {
   const int tid = threadIdx.x;
   const int total = COARSE ? a.ct_total : a.tile_off[a.V];
   const int G = gridDim.x;
-  // XCD-aware order: workgroup b runs on XCD b % 8; each XCD gets a
-  // contiguous run of work items, so the query tiles of one vector tile meet
-  // in the same L2.
-  const int L = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-  for (int w = L; w < total; w += G) {
+  // XCD-aware order: workgroup b runs on XCD b % 8. Coarse: each XCD gets a
+  // contiguous run of work items. Scan: XCD x owns the x-th eighth of the
+  // items (lists in order, query tile fastest) and its workgroups take them
+  // one at a time from the XCD's counter, so the items in flight on one XCD
+  // stay a window of consecutive items however unevenly they last, and the
+  // query and vector tiles they share meet in that XCD's L2.
+  const int xcd = blockIdx.x & 7;
+  const int per = (total + 7) / 8;
+  const int w_end = COARSE ? total : min(total, (xcd + 1) * per);
+  __shared__ int s_item;
+  for (int w = COARSE ? xcd * (G >> 3) + (blockIdx.x >> 3) : 0;; w += G) {
+    if (!COARSE) {
+      __syncthreads();  // every thread has read the previous s_item
+      if (tid == 0) s_item = xcd * per + atomicAdd(&a.work[xcd], 1);
+      __syncthreads();
+      w = s_item;
+    }
+    if (w >= w_end) break;
     int c, qt, vt, m, nvec, d_dot;
     int64_t npad;
     const float *vbase;
@@ -2131,15 +2145,18 @@ __global__ void k_count(const int32_t *__restrict__ probes, int64_t npairs, cons
 }
 
 // One workgroup of 1024 threads: bucket offsets, tile prefix (query tiles of
-// height tq x 64-vector tiles per virtual list), cursor reset.
+// height tq x tv-vector tiles per virtual list), cursor and scan work counter
+// reset.
 __global__ __launch_bounds__(1024) void k_list_scan(const int32_t *__restrict__ cnt,
                                                     const CfgDev *cfg, int32_t ncfg, int32_t V,
                                                     int32_t tq, int32_t tv,
                                                     int32_t *__restrict__ bkt_off,
                                                     int32_t *__restrict__ tile_off,
-                                                    int32_t *__restrict__ cursor) {
+                                                    int32_t *__restrict__ cursor,
+                                                    int32_t *__restrict__ work) {
   __shared__ int32_t sh[16];
   const int tid = threadIdx.x;
+  if (tid < 8) work[tid] = 0;
   const int chunk = (V + blockDim.x - 1) / blockDim.x;
   const int v0 = tid * chunk, v1 = min(V, v0 + chunk);
   auto tiles = [&](int v) {
@@ -2425,7 +2442,7 @@ static hipError_t bucketing_multi(const SearchBufs &b, int32_t tq, int32_t tv, h
   hipLaunchKernelGGL(k_count, dim3(blocks_for(b.pairs, 256)), dim3(256), 0, st, b.probes, b.pairs,
                      b.cfg, b.ncfg, b.cnt);
   hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, st, b.cnt, b.cfg, b.ncfg, b.V, tq, tv,
-                     b.bkt_off, b.tile_off, b.cursor);
+                     b.bkt_off, b.tile_off, b.cursor, b.work);
   hipLaunchKernelGGL(k_scatter, dim3(blocks_for(b.pairs, 256)), dim3(256), 0, st, b.probes,
                      b.pairs, b.cfg, b.ncfg, b.bkt_off, b.cursor, b.bucket);
   // per-query segment lengths go to pair_base as a temporary, then the scan
@@ -2504,6 +2521,7 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
   t.bucket = b.bucket;
   t.pair_base = b.pair_base;
   t.D = b.D;
+  t.work = b.work;
   grid = (int)round_up(std::max(8, grid), 8);
   {
     KernelTimer tm("tile_dist_scan", st);
