@@ -64,6 +64,8 @@ def precision_form(args, lib, torch, log):
     rows = synth.subsample_rows(n, n_train, w.seed)
     index = lib.IvfIndex.build_ivf(Xd, w.nlist, d_c, args.iters, synth.init_rows(n_train, w.nlist, w.seed),
                                    train_rows=rows)
+    if not args.no_row_copy:
+        index.add_row_copy()
     del Xd
     torch.cuda.empty_cache()
     res = {}
@@ -137,6 +139,8 @@ def batching_form(args, lib, torch, log):
     indices = {}
     for d_c in (16, 64, 256):
         indices[d_c] = lib.IvfIndex.build_ivf(Xd, w.nlist, d_c, args.iters, init, train_rows=rows)
+        if not args.no_row_copy:
+            indices[d_c].add_row_copy()
     del Xd
     torch.cuda.empty_cache()
     rng = np.random.default_rng(synth.ROOT_SEED + 3)
@@ -433,9 +437,12 @@ def sweep_form(args, lib, torch, log):
     probes = [1, 2, 4, 8, 16, 32, 64]
     truth = None
     grid = {}
+    shapes = {}
     for dc in widths:
         t0 = time.time()
         index = lib.IvfIndex.build_ivf(Xd, nlist, dc, args.iters, init, train_rows=tr)
+        if not args.no_row_copy:
+            index.add_row_copy()
         torch.cuda.synchronize()
         log(f"d_c={dc}: index built in {time.time() - t0:.1f}s")
         if truth is None:  # exact top-k: every list, full width
@@ -451,7 +458,8 @@ def sweep_form(args, lib, torch, log):
             # depend on the index, so these serve every d_c)
             for npb in probes:
                 tb = lib.Batch([(index, nq, dc, d_s, npb, k)], ldq=w.d, ldk=k)
-                tb.autotune(Qd, out=(dist, ids), reps=1)
+                shapes[f"nprobe={npb}"] = dict(zip(("tq", "tv", "grid"),
+                                                   tb.autotune(Qd, out=(dist, ids), reps=1)))
                 tb.free()
         for npb in probes:
             lib.timing_reset()
@@ -478,5 +486,5 @@ def sweep_form(args, lib, torch, log):
            "dtype": "f32", "data": "synthetic", "vs_baseline": None,
            "config": {"workload": f"imagenet1k: N={n} d={w.d} nq={nq} nlist={nlist} d_s={d_s} "
                                   f"k={k}; one index per d_c; value = best QPS at recall@10 >= 0.69"},
-           "grid": grid}
+           "scan_shapes": shapes, "grid": grid}
     print(json.dumps(out), flush=True)

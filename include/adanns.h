@@ -221,6 +221,21 @@ adanns_status adanns_search_pq(const adanns_index *index, const float *Q, int64_
 adanns_status adanns_set_precision(adanns_index *index, int32_t fmt, void *stream);
 
 /*
+ * Optional row-major FP32 copy of the index's vectors (rows in list order,
+ * d_pad floats each), read by every exact re-measurement of a shortlist
+ * (the FP32 distance of Appendix A's formula table, after any first pass)
+ * instead of the list slab layout: each candidate then becomes one
+ * contiguous read instead of one 128-byte piece per 32 coordinates. Costs
+ * rows_pad x d_pad x 4 bytes of device memory, held until the index is
+ * freed; results are bit-identical with and without it. Searches and
+ * batches created after this call use it; batches created before keep
+ * reading the slab layout. Idempotent. Synchronises ``stream``.
+ * Errors: ADANNS_EINVAL (NULL index, no FP32 vectors), ADANNS_ENOMEM,
+ * ADANNS_EHIP.
+ */
+adanns_status adanns_index_add_row_copy(adanns_index *index, void *stream);
+
+/*
  * Precision-form search. Queries are quantised the same way (one scale per
  * query over its first d coordinates, so ldq >= d). Coarse: first-pass
  * scores of quantised query and centroid prefixes on BF16 / FP8 MFMA with

@@ -115,7 +115,7 @@ adanns_status dmalloc(adanns_index *ix, void **p, size_t bytes) {
 }
 
 void free_index_memory(adanns_index *ix) {
-  void *ptrs[] = {ix->vec, ix->poff, ix->len, ix->rowid, ix->cent, ix->cent_slab};
+  void *ptrs[] = {ix->vec, ix->rows, ix->poff, ix->len, ix->rowid, ix->cent, ix->cent_slab};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &qsv : ix->quant) {
@@ -925,6 +925,28 @@ adanns_status adanns_set_precision(adanns_index *ix, int32_t fmt, void *stream) 
     return fail(ADANNS_EHIP);
   }
   ix->quant[fmt] = q;
+  return ADANNS_OK;
+}
+
+adanns_status adanns_index_add_row_copy(adanns_index *ix, void *stream) {
+  clear_error();
+  ADANNS_REQUIRE(ix != nullptr, "index is NULL");
+  ADANNS_REQUIRE(ix->vec != nullptr, "the index holds no FP32 vectors to copy");
+  if (ix->rows) return ADANNS_OK;
+  adanns_status s = check_async();
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  float *rows = nullptr;
+  if ((s = dmalloc(ix, (void **)&rows, (size_t)ix->rows_pad * ix->d_pad * sizeof(float))))
+    return s;
+  if (launch_slab_to_rows(ix, rows, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(rows);
+    ix->own_bytes -= (size_t)ix->rows_pad * ix->d_pad * sizeof(float);
+    set_error("HIP error while copying the vectors");
+    return ADANNS_EHIP;
+  }
+  ix->rows = rows;
   return ADANNS_OK;
 }
 

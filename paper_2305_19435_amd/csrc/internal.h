@@ -110,6 +110,8 @@ struct adanns_index {
   std::vector<int64_t> top_prefix;     // sum of the p largest list lengths, p = 0..nlist
   // device memory owned by the index
   float *vec = nullptr;                // slab layout, rows_pad * d_pad floats
+  float *rows = nullptr;               // optional row-major copy of vec [rows_pad][d_pad]
+                                       // (list order) read by the exact re-measures
   int64_t *poff = nullptr;             // [nlist + 1]
   int32_t *len = nullptr;              // [nlist]
   int64_t *rowid = nullptr;            // [rows_pad], -1 on padding rows
@@ -147,6 +149,7 @@ struct KernelTimer {
 // prefix fields.
 struct CfgDev {
   const float *vec;        // the configuration's index
+  const float *rows;       // its row-major copy, or NULL
   const int64_t *poff;
   const int32_t *len;
   const int64_t *rowid;
@@ -239,6 +242,8 @@ hipError_t launch_pq_encode(const Mat &X, int64_t n, int32_t M, int32_t dsub, co
 hipError_t launch_gather_codes(const uint8_t *codes, int32_t M, const int64_t *rowid,
                                int64_t rows_pad, uint8_t *out, hipStream_t st);
 // Precision form: quantised copies, quantised queries, first passes, selection.
+// Row-major copy of the index's slab layout into rows [rows_pad][d_pad].
+hipError_t launch_slab_to_rows(const adanns_index *ix, float *rows, hipStream_t st);
 hipError_t launch_quantize_store(const adanns_index *ix, int32_t fmt, QuantStore &qs,
                                  hipStream_t st);
 hipError_t launch_quantize_cent_fp8(const adanns_index *ix, const int64_t *poff2, QuantStore &qs,

@@ -665,6 +665,7 @@ struct SelArgs {
   const float *cent;       // coarse: [nl][ld_cent]
   int32_t ld_cent;
   const float *vec;        // scan: slab layout
+  const float *rows;       // scan: row-major copy of vec, or NULL
   int32_t d_pad;
   const int64_t *poff;
   const int64_t *rowid;
@@ -847,13 +848,17 @@ __device__ __forceinline__ void measure1(const SelArgs &a, int64_t q, const Cand
         if (d0 + 64 * u < d) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
     }
   } else if (a.mode == SEL_L2) {
-    const float *base = a.vec + L.p0 * a.d_pad + (L.row - L.p0) * SLAB;
+    // slab layout: coordinate dim of the row sits at (dim / SLAB) * npad *
+    // SLAB + dim % SLAB; in the row-major copy at dim (npad = 1)
+    const float *base = a.rows ? a.rows + L.row * a.d_pad
+                               : a.vec + L.p0 * a.d_pad + (L.row - L.p0) * SLAB;
+    const int64_t np = a.rows ? 1 : L.npad;
     for (int d0 = lane; d0 < d; d0 += 64 * 16) {
       float xv[16];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int dim = d0 + 64 * u;
-        xv[u] = dim < d ? ldg(base + (int64_t)(dim / SLAB) * L.npad * SLAB + (dim % SLAB)) : 0.f;
+        xv[u] = dim < d ? ldg(base + (int64_t)(dim / SLAB) * np * SLAB + (dim % SLAB)) : 0.f;
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u)
@@ -951,13 +956,15 @@ __device__ __forceinline__ void measureB(const SelArgs &a, bool coarse, const Ca
         if (d0 + 64 * u < d) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
     }
   } else {
-    const float *base = a.vec + L.p0 * a.d_pad + (L.row - L.p0) * SLAB;
+    const float *base = a.rows ? a.rows + L.row * a.d_pad
+                               : a.vec + L.p0 * a.d_pad + (L.row - L.p0) * SLAB;
+    const int64_t np = a.rows ? 1 : L.npad;
     for (int d0 = lane; d0 < d; d0 += 64 * 16) {
       float xv[16];
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         const int dim = d0 + 64 * u;
-        xv[u] = dim < d ? ldg(base + (int64_t)(dim / SLAB) * L.npad * SLAB + (dim % SLAB)) : 0.f;
+        xv[u] = dim < d ? ldg(base + (int64_t)(dim / SLAB) * np * SLAB + (dim % SLAB)) : 0.f;
       }
 #pragma unroll
       for (int u = 0; u < 16; ++u)
@@ -1272,6 +1279,7 @@ __global__ __launch_bounds__(512) void k_select_multi(SelMultiArgs m) {
     a.ldo = m.ldk;
     a.d_dot = g.d_s;
     a.vec = g.vec;
+    a.rows = g.rows;
     a.d_pad = g.d_pad;
     a.poff = g.poff;
     a.rowid = g.rowid;
@@ -1510,9 +1518,10 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
       const int32_t h = ldg(m.probes + g.pair0 + q * g.nprobe + lo);
       const int64_t rr = pabs - ldg(pb + lo);
       const int64_t p0 = ldg(g.poff + h);
-      my_npad = ldg(g.poff + h + 1) - p0;
       my_id = ldg(g.rowid + p0 + rr);
-      my_base = g.vec + p0 * g.d_pad + rr * SLAB;
+      // slab layout, or the row-major copy (read with npad = 1)
+      my_npad = g.rows ? 1 : ldg(g.poff + h + 1) - p0;
+      my_base = g.rows ? g.rows + (p0 + rr) * g.d_pad : g.vec + p0 * g.d_pad + rr * SLAB;
     }
   }
 
@@ -2318,6 +2327,7 @@ CfgDev make_cfg(const adanns_index *ix, int32_t d_c, int32_t d_s, int32_t nprobe
                 int64_t nq) {
   CfgDev c{};
   c.vec = ix->vec;
+  c.rows = ix->rows;
   c.poff = ix->poff;
   c.len = ix->len;
   c.rowid = ix->rowid;
@@ -2563,6 +2573,31 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
   return hipGetLastError();
 }
 
+// Row-major copy of the slab layout: rows[g][dim] = coordinate dim of layout
+// row g (list order). One block column per list; coalesced writes.
+__global__ void k_slab_to_rows(const float *__restrict__ vec, const int64_t *__restrict__ poff,
+                               int32_t d_pad, float *__restrict__ rows) {
+  const int h = blockIdx.y;
+  const int64_t p0 = poff[h], np = poff[h + 1] - p0;
+  const float *src = vec + p0 * d_pad;
+  float *dst = rows + p0 * d_pad;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np * d_pad;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / d_pad;
+    const int dim = (int)(i - r * d_pad);
+    dst[i] = src[(int64_t)(dim / SLAB) * np * SLAB + r * SLAB + dim % SLAB];
+  }
+}
+
+hipError_t launch_slab_to_rows(const adanns_index *ix, float *rows, hipStream_t st) {
+  if (ix->nlist == 0) return hipSuccess;
+  const int64_t per_list = std::max<int64_t>(1, (int64_t)ix->max_len * ix->d_pad);
+  const unsigned bx = (unsigned)std::min<int64_t>(64, cdiv(per_list, 256));
+  hipLaunchKernelGGL(k_slab_to_rows, dim3(bx, (unsigned)ix->nlist), dim3(256), 0, st, ix->vec,
+                     ix->poff, ix->d_pad, rows);
+  return hipGetLastError();
+}
+
 hipError_t launch_quantize_store(const adanns_index *ix, int32_t fmt, QuantStore &qs,
                                  hipStream_t st) {
   if (fmt == 1) {
@@ -2704,6 +2739,7 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   r.d_dot = d_s;
   r.d_B = d_s;
   r.vec = ix->vec;
+  r.rows = ix->rows;
   r.d_pad = ix->d_pad;
   r.poff = ix->poff;
   r.rowid = ix->rowid;
@@ -2798,6 +2834,7 @@ hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const Sea
   s.d_dot = pq.d_s;
   s.d_B = d_rerank;
   s.vec = ix->vec;
+  s.rows = ix->rows;
   s.d_pad = ix->d_pad;
   s.poff = ix->poff;
   s.rowid = ix->rowid;

@@ -178,6 +178,11 @@ class IvfIndex:
     # ---- precision form -----------------------------------------------------------
     FORMATS = {"bf16": 1, "fp8": 2}
 
+    def add_row_copy(self, stream=None):
+        """adanns_index_add_row_copy: row-major FP32 copy read by the exact
+        re-measurements (results unchanged)."""
+        check(lib.adanns_index_add_row_copy(self._h, _stream(stream)))
+
     def set_precision(self, fmt: str, stream=None):
         """adanns_set_precision: build the BF16 or FP8-e4m3 copy."""
         check(lib.adanns_set_precision(self._h, self.FORMATS[fmt], _stream(stream)))

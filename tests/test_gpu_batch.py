@@ -139,3 +139,37 @@ def test_batch_invalid(lib, setup):
         lib.Batch([(ix, 5, 17, 64, 4, 10)], ldq=128)       # d_c above d_c_build
     with pytest.raises(lib.AdannsError):
         lib.Batch([(ix, 5, 16, 64, 4, 10)], ldq=32)        # ldq too small
+
+
+def test_all_shapes_ragged_prefixes_parity(lib, setup):
+    """Every tile shape on prefixes that end inside a 32-coordinate slab
+    (coarse and scan), against the FP64 oracle on the library's probes; one
+    list is probed by enough queries to fill several 128-row query tiles."""
+    X, indices, configs, Qall = setup
+    k = 10
+    _, C32, off, ids_ = indices[16]
+    ix = indices[16][0]
+    cfgs = [(12, 40, 4, 300), (16, 33, 8, 57), (9, 97, 2, 1)]
+    batch = lib.Batch([(ix, nq, d_c, d_s, nprobe, k) for d_c, d_s, nprobe, nq in cfgs], ldq=128)
+    # the first configuration repeats three queries 100 times each, so that
+    # its probed lists hold one to three full 128-row query tiles
+    Q = np.concatenate([np.repeat(Qall[:3], 100, axis=0), Qall[3:3 + 58]])
+    Qd = torch.from_numpy(Q).cuda()
+    for tq in (32, 64, 128):
+        for tv in (64, 128):
+            batch.set_shape(tq, 1024, tv)
+            dist, ids = batch.run(Qd)
+            torch.cuda.synchronize()
+            dist, ids = dist.cpu().numpy(), ids.cpu().numpy()
+            r = 0
+            for d_c, d_s, nprobe, nq in cfgs:
+                Qc = Q[r:r + nq]
+                _, _, probes = ix.search(torch.from_numpy(Qc).cuda(), d_c, d_s, nprobe, k,
+                                         return_probes=True)
+                torch.cuda.synchronize()
+                rep = check_search(X, Qc, C32, off, ids_, d_c, d_s, nprobe, k,
+                                   dist[r:r + nq, :k], ids[r:r + nq, :k],
+                                   got_p=probes.cpu().numpy(), queries=range(0, nq, 7))
+                assert rep.ok, ((tq, tv), (d_c, d_s), rep.problems)
+                r += nq
+    batch.free()
