@@ -66,8 +66,8 @@ def parse():
                              "sweep"],
                     help="ivf: the headline FP32 search; the others measure the other forms")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile-shape autotuner")
-    ap.add_argument("--no-row-copy", action="store_true",
-                    help="re-measure candidates from the slab layout (no row-major copy)")
+    ap.add_argument("--row-copy", action="store_true",
+                    help="add the row-major copy of the vectors that the exact re-measures read")
     ap.add_argument("--rerank", type=int, default=256, help="precision form shortlist")
     return ap.parse_args()
 
@@ -142,7 +142,7 @@ def main():
     log(f"GPU index built in {build_s:.1f}s; objective {obj[0]:.1f} -> {obj[-1]:.1f}")
     del Xd
     torch.cuda.empty_cache()
-    if not args.no_row_copy:
+    if args.row_copy:
         index.add_row_copy()
 
     if args.calibrate_copy:
@@ -278,8 +278,8 @@ def main():
                    "index": f"GPU Lloyd, {args.iters} iters on {n_train} seeded rows",
                    "scan_shape": {"tq": shape[0], "tv": shape[1], "grid": shape[2]} if shape else "default",
                    "index_build_s": round(build_s, 2),
-                   "remeasure_from": "slab layout" if args.no_row_copy else
-                                     "row-major copy of the vectors",
+                   "remeasure_from": "row-major copy of the vectors" if args.row_copy else
+                                     "slab layout",
                    "index_device_bytes": index.device_bytes()},
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 4),
                        "p99": round(float(np.percentile(step_ms, 99)), 4),

@@ -64,7 +64,7 @@ def precision_form(args, lib, torch, log):
     rows = synth.subsample_rows(n, n_train, w.seed)
     index = lib.IvfIndex.build_ivf(Xd, w.nlist, d_c, args.iters, synth.init_rows(n_train, w.nlist, w.seed),
                                    train_rows=rows)
-    if not args.no_row_copy:
+    if args.row_copy:
         index.add_row_copy()
     del Xd
     torch.cuda.empty_cache()
@@ -139,7 +139,7 @@ def batching_form(args, lib, torch, log):
     indices = {}
     for d_c in (16, 64, 256):
         indices[d_c] = lib.IvfIndex.build_ivf(Xd, w.nlist, d_c, args.iters, init, train_rows=rows)
-        if not args.no_row_copy:
+        if args.row_copy:
             indices[d_c].add_row_copy()
     del Xd
     torch.cuda.empty_cache()
@@ -441,7 +441,7 @@ def sweep_form(args, lib, torch, log):
     for dc in widths:
         t0 = time.time()
         index = lib.IvfIndex.build_ivf(Xd, nlist, dc, args.iters, init, train_rows=tr)
-        if not args.no_row_copy:
+        if args.row_copy:
             index.add_row_copy()
         torch.cuda.synchronize()
         log(f"d_c={dc}: index built in {time.time() - t0:.1f}s")

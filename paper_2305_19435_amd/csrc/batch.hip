@@ -56,9 +56,19 @@ struct adanns_batch {
 
 namespace adanns {
 
+// Untuned scan shape: 64 x 128 tiles once a probed list meets a few dozen
+// queries (the autotuner's usual pick there), else the 64 x 64 default.
+static void default_shape(double per_list, int32_t *tq, int32_t *tv) {
+  if (per_list >= 32) {
+    *tq = 64;
+    *tv = 128;
+  }
+}
+
 void tuned_shape(const adanns_index *ix, int32_t d_s, int32_t nprobe, int64_t nq, int32_t *tq,
                  int32_t *tv, int32_t *grid) {
   const double per_list = (double)nq * nprobe / std::max(1, ix->nlist);
+  default_shape(per_list, tq, tv);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(tune_key(d_s, nprobe, per_list));
   if (it != g_tune.end()) {
@@ -192,6 +202,7 @@ adanns_status adanns_batch_create(const adanns_batch_config *cfgs, int32_t ncfg,
     delete p;
     return ADANNS_EHIP;
   }
+  default_shape(p->per_list, &p->tq, &p->tv);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(tune_key(p->max_ds, p->max_np, p->per_list));

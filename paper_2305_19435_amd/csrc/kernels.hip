@@ -539,6 +539,8 @@ __device__ __forceinline__ void tile_compute_dma(const float *__restrict__ Qs, i
 // budget is held to 256 per lane). COARSE: every configuration's queries
 // against its centroids (tiles numbered per configuration); otherwise every
 // virtual list against the queries probing it.
+constexpr int SCAN_CHUNK = 64;  // consecutive scan items an XCD takes in a row
+
 template <int TQ, int TV, int COARSE>
 __global__ __launch_bounds__(256, 2) void k_tile_multi(TileArgs a) {
   constexpr bool DMA = TQ >= 64 && TV >= 64;
@@ -554,23 +556,27 @@ __global__ __launch_bounds__(256, 2) void k_tile_multi(TileArgs a) {
   const int total = COARSE ? a.ct_total : a.tile_off[a.V];
   const int G = gridDim.x;
   // XCD-aware order: workgroup b runs on XCD b % 8. Coarse: each XCD gets a
-  // contiguous run of work items. Scan: XCD x owns the x-th eighth of the
-  // items (lists in order, query tile fastest) and its workgroups take them
-  // one at a time from the XCD's counter, so the items in flight on one XCD
-  // stay a window of consecutive items however unevenly they last, and the
-  // query and vector tiles they share meet in that XCD's L2.
+  // contiguous run of work items. Scan: the items (lists in order, query
+  // tile fastest) are dealt to the XCDs in chunks of SCAN_CHUNK consecutive
+  // items, chunk c to XCD c % 8, and an XCD's workgroups take its items one
+  // at a time from the XCD's counter. The items in flight on one XCD thus
+  // stay a window of consecutive items however unevenly they last (the query
+  // and vector tiles they share meet in that XCD's L2), and regions of the
+  // item order that cost more (longer prefixes, longer lists) are spread
+  // over every XCD.
   const int xcd = blockIdx.x & 7;
-  const int per = (total + 7) / 8;
-  const int w_end = COARSE ? total : min(total, (xcd + 1) * per);
   __shared__ int s_item;
   for (int w = COARSE ? xcd * (G >> 3) + (blockIdx.x >> 3) : 0;; w += G) {
     if (!COARSE) {
       __syncthreads();  // every thread has read the previous s_item
-      if (tid == 0) s_item = xcd * per + atomicAdd(&a.work[xcd], 1);
+      if (tid == 0) {
+        const int k = atomicAdd(&a.work[xcd], 1);
+        s_item = ((k / SCAN_CHUNK) * 8 + xcd) * SCAN_CHUNK + k % SCAN_CHUNK;
+      }
       __syncthreads();
       w = s_item;
     }
-    if (w >= w_end) break;
+    if (w >= total) break;
     int c, qt, vt, m, nvec, d_dot;
     int64_t npad;
     const float *vbase;
