@@ -854,21 +854,29 @@ __device__ __forceinline__ void measure1(const SelArgs &a, int64_t q, const Cand
         if (d0 + 64 * u < d) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
     }
   } else if (a.mode == SEL_L2) {
-    // slab layout: coordinate dim of the row sits at (dim / SLAB) * npad *
-    // SLAB + dim % SLAB; in the row-major copy at dim (npad = 1)
+    // lane l takes coordinates 4l + 256u + e (u = 0, 1, ..., e = 0..3) in
+    // that order, read as 16-byte pieces: in the slab layout coordinate dim
+    // of the row sits at (dim / SLAB) * npad * SLAB + dim % SLAB, in the
+    // row-major copy at dim (npad = 1). k_select_wave accumulates in the
+    // same order, so both give the same bits.
     const float *base = a.rows ? a.rows + L.row * a.d_pad
                                : a.vec + L.p0 * a.d_pad + (L.row - L.p0) * SLAB;
     const int64_t np = a.rows ? 1 : L.npad;
-    for (int d0 = lane; d0 < d; d0 += 64 * 16) {
-      float xv[16];
+    for (int d0 = 4 * lane; d0 < d; d0 += 256 * 4) {
+      float4 xv[4];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int dim = d0 + 64 * u;
-        xv[u] = dim < d ? ldg(base + (int64_t)(dim / SLAB) * np * SLAB + (dim % SLAB)) : 0.f;
+      for (int u = 0; u < 4; ++u) {
+        const int dim = d0 + 256 * u;
+        xv[u] = dim < d ? ldg4(base + (int64_t)(dim / SLAB) * np * SLAB + dim % SLAB)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (d0 + 64 * u < d) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int dim = d0 + 256 * u + e;
+          if (dim < d) acc_sq_diff(qrow[dim], f4(xv[u], e), S, C);
+        }
     }
   } else if (a.mode == SEL_ADC) {
     const uint8_t *code = a.codes + L.row * a.M;
@@ -1308,6 +1316,9 @@ __global__ __launch_bounds__(512) void k_select_multi(SelMultiArgs m) {
 // same order of accumulation as select_body) and sorted across lanes by
 // (distance pair, id). Results are identical to k_select_multi's.
 constexpr int WSEL_K = 64;
+// candidates re-measured together by k_select_wave (three keep two waves
+// per SIMD; four need more than 256 registers)
+constexpr int SELW_G = 3;
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -1449,6 +1460,10 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
   }
 }
 
+// COARSE: the coarse step's selection (m.coarse set), else the scan's; two
+// instantiations, so that the coarse one does not carry the registers of the
+// scan's three-candidate re-measure.
+template <bool COARSE>
 __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qtot) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -1456,7 +1471,7 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
   const int c = cfg_of(m.cfg, m.ncfg, &CfgDev::q0, r);
   const CfgDev &g = m.cfg[c];
   const int64_t q = r - g.q0;
-  const bool coarse = m.coarse != 0;
+  constexpr bool coarse = COARSE;
   const float *seg;
   int64_t L, seg0 = 0;
   int K1, kout, d_dot;
@@ -1478,7 +1493,7 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
   // 1. the K1 smallest (key, position) composites, sorted over lanes
   const float ADANNS_GLOBAL_AS *sg = (const float ADANNS_GLOBAL_AS *)seg;
   uint64_t best = ~0ull, thr = ~0ull;
-  constexpr int U = 16;  // loads in flight per lane
+  constexpr int U = COARSE ? 16 : 32;  // loads in flight per lane
   for (int64_t base = 0; base < L; base += 64 * U) {
     float v[U];
 #pragma unroll
@@ -1531,11 +1546,65 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
     }
   }
 
-  // 3. exact re-measurement over the lanes, two candidates at a time so
-  // that both candidates' loads are in flight together
+  // 3. exact re-measurement over the lanes
   const float ADANNS_GLOBAL_AS *qrow =
       (const float ADANNS_GLOBAL_AS *)(m.Qs + r * m.ldqs);
   float myS = __builtin_inff(), myC = 0.f;
+  // vectors: SELW_G candidates at a time, lane l taking coordinates
+  // 4l + 256u + e in that order (as measure1), up to 2048 coordinates per
+  // pass read as 16-byte pieces, so that SELW_G x 8 + 8 loads are in flight
+  // per lane; the query row's rows are 16-byte aligned and padded to the
+  // slab width.
+  if (!coarse)
+  for (int cc = 0; cc < ncand; cc += SELW_G) {
+    const float ADANNS_GLOBAL_AS *xp[SELW_G];
+    int64_t np[SELW_G];
+#pragma unroll
+    for (int gi = 0; gi < SELW_G; ++gi) {
+      const int c = cc + gi < ncand ? cc + gi : ncand - 1;
+      xp[gi] = (const float ADANNS_GLOBAL_AS *)readlane64((uint64_t)my_base, c);
+      np[gi] = (int64_t)readlane64((uint64_t)my_npad, c);
+    }
+    float S[SELW_G], C[SELW_G];
+#pragma unroll
+    for (int gi = 0; gi < SELW_G; ++gi) S[gi] = C[gi] = 0.f;
+    for (int d0 = 4 * lane; d0 < d_dot; d0 += 256 * 8) {
+      float4 qv[8], xv[SELW_G][8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int dim = d0 + 256 * u;
+        qv[u] = dim < d_dot ? ldg4((const float *)qrow + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int gi = 0; gi < SELW_G; ++gi)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int dim = d0 + 256 * u;
+          xv[gi][u] = dim < d_dot
+                          ? ldg4((const float *)xp[gi] + (int64_t)(dim / SLAB) * np[gi] * SLAB + dim % SLAB)
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (d0 + 256 * u + e < d_dot)
+#pragma unroll
+            for (int gi = 0; gi < SELW_G; ++gi)
+              acc_sq_diff(f4(qv[u], e), f4(xv[gi][u], e), S[gi], C[gi]);
+    }
+#pragma unroll
+    for (int gi = 0; gi < SELW_G; ++gi) {
+      wave_reduce_pair(S[gi], C[gi]);
+      if (cc + gi < ncand && lane == cc + gi) {
+        myS = S[gi];
+        myC = C[gi];
+      }
+    }
+  }
+  // centroids: two at a time, lane l taking coordinates l, l + 64, ... (as
+  // measure1's coarse measure)
+  if (coarse)
   for (int cc = 0; cc < ncand; cc += 2) {
     const bool two = cc + 1 < ncand;
     const float ADANNS_GLOBAL_AS *x0 =
@@ -1543,7 +1612,7 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
     const float ADANNS_GLOBAL_AS *x1 =
         (const float ADANNS_GLOBAL_AS *)readlane64((uint64_t)my_base, two ? cc + 1 : cc);
     float S0 = 0.f, C0 = 0.f, S1 = 0.f, C1 = 0.f;
-    if (coarse) {
+    {
       for (int d0 = lane; d0 < d_dot; d0 += 64 * 8) {
         float xa[8], xb[8];
 #pragma unroll
@@ -1554,26 +1623,6 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-          if (d0 + 64 * u < d_dot) {
-            const float qv = qrow[d0 + 64 * u];
-            acc_sq_diff(qv, xa[u], S0, C0);
-            acc_sq_diff(qv, xb[u], S1, C1);
-          }
-      }
-    } else {
-      const int64_t np0 = (int64_t)readlane64((uint64_t)my_npad, cc);
-      const int64_t np1 = (int64_t)readlane64((uint64_t)my_npad, two ? cc + 1 : cc);
-      for (int d0 = lane; d0 < d_dot; d0 += 64 * 16) {
-        float xa[16], xb[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          const int dim = d0 + 64 * u;
-          const int64_t sl = dim / SLAB, t = dim % SLAB;
-          xa[u] = dim < d_dot ? x0[sl * np0 * SLAB + t] : 0.f;
-          xb[u] = dim < d_dot ? x1[sl * np1 * SLAB + t] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
           if (d0 + 64 * u < d_dot) {
             const float qv = qrow[d0 + 64 * u];
             acc_sq_diff(qv, xa[u], S0, C0);
@@ -2442,7 +2491,7 @@ static hipError_t coarse_multi(const SearchBufs &b, int32_t *user_probes, float 
   {
     KernelTimer tm("select_coarse", st);
     if (b.max_nprobe + REFINE_MARGIN <= WSEL_K)
-      hipLaunchKernelGGL(k_select_wave, dim3((unsigned)cdiv(b.Qtot, 4)), dim3(256), 0, st, m,
+      hipLaunchKernelGGL(k_select_wave<true>, dim3((unsigned)cdiv(b.Qtot, 4)), dim3(256), 0, st, m,
                          b.Qtot);
     else
       hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(512),
@@ -2570,7 +2619,7 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
   {
     KernelTimer tm("select_scan", st);
     if (b.max_k + REFINE_MARGIN <= WSEL_K)
-      hipLaunchKernelGGL(k_select_wave, dim3((unsigned)cdiv(b.Qtot, 4)), dim3(256), 0, st, m,
+      hipLaunchKernelGGL(k_select_wave<false>, dim3((unsigned)cdiv(b.Qtot, 4)), dim3(256), 0, st, m,
                          b.Qtot);
     else
       hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(512),
