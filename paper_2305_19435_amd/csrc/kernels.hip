@@ -1726,52 +1726,87 @@ __global__ __launch_bounds__(256) void k_pq_encode(const T *__restrict__ X, int6
 
 // q' = q[:d_s] R accumulated in FP64 (products of FP32 values are exact in
 // FP64), stored as the FP32 pair (hi, lo) with hi + lo = the FP64 sum to
-// within 2^-48 relative. A workgroup computes ROT_Q queries x 256 output
-// columns (blockIdx.y picks the columns); the queries share each read of R.
-constexpr int ROT_Q = 16;
-constexpr int ROT_CHUNK = 256;  // query coordinates staged in LDS (as FP64) at a time
+// within 2^-48 relative. FP64 matrix cores: a workgroup computes ROT_Q
+// queries x ROT_C output columns, wave w the 16 queries 16w.. against four
+// 16-column blocks with v_mfma_f64_16x16x4f64 (lane l supplies A[l % 16][l /
+// 16] and B[l / 16][l % 16]; it receives D[l / 16 + 4 r][l % 16], r = 0..3,
+// a different row order from the FP32 16x16x4 form). Q and R are staged in
+// LDS as FP64, ROT_K coordinates at a time.
+constexpr int ROT_Q = 64, ROT_C = 64, ROT_K = 32;
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_rotate(const float *__restrict__ Qs, int64_t ldqs,
                                                 int64_t nq, const float *__restrict__ R,
                                                 int32_t d_s, float *__restrict__ qh,
                                                 float *__restrict__ ql, int64_t ldqr) {
-  __shared__ double qsh[ROT_CHUNK][ROT_Q];  // a coordinate's ROT_Q values side by side
-  const int tid = threadIdx.x;
+  constexpr int NPA = ROT_Q * ROT_K / 256, NPB = ROT_K * ROT_C / 256;  // per thread
+  __shared__ double As[ROT_K][ROT_Q + 1];  // As[k][query]
+  __shared__ double Bs[ROT_K][ROT_C + 1];  // Bs[k][column]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t q0 = (int64_t)blockIdx.x * ROT_Q;
-  const int j = blockIdx.y * 256 + tid;
-  double acc[ROT_Q];
+  const int c0 = blockIdx.y * ROT_C;
+  doublex4 acc[ROT_C / 16];
 #pragma unroll
-  for (int a = 0; a < ROT_Q; ++a) acc[a] = 0.0;
-  for (int i0 = 0; i0 < d_s; i0 += ROT_CHUNK) {
-    const int ni = min(ROT_CHUNK, d_s - i0);
+  for (int j = 0; j < ROT_C / 16; ++j) acc[j] = (doublex4){0.0, 0.0, 0.0, 0.0};
+  // the next chunk's values are loaded into registers while this one's
+  // MFMAs run
+  float pa[NPA], pb[NPB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < NPA; ++e) {
+      const int i = tid + 256 * e, qq = i / ROT_K, kk = i % ROT_K;
+      const int64_t q = q0 + qq;
+      pa[e] = (q < nq && k0 + kk < d_s) ? Qs[q * ldqs + k0 + kk] : 0.f;
+    }
+#pragma unroll
+    for (int e = 0; e < NPB; ++e) {
+      const int i = tid + 256 * e, kk = i / ROT_C, cc = i % ROT_C;
+      pb[e] = (k0 + kk < d_s && c0 + cc < d_s) ? R[(int64_t)(k0 + kk) * d_s + c0 + cc] : 0.f;
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < d_s; k0 += ROT_K) {
     __syncthreads();  // the previous chunk is consumed
-    for (int e = tid; e < ROT_Q * ROT_CHUNK; e += blockDim.x) {
-      const int qq = e / ROT_CHUNK, c = e % ROT_CHUNK;
-      qsh[c][qq] = (q0 + qq < nq && c < ni) ? (double)Qs[(q0 + qq) * ldqs + i0 + c] : 0.0;
+#pragma unroll
+    for (int e = 0; e < NPA; ++e) {
+      const int i = tid + 256 * e;
+      As[i % ROT_K][i / ROT_K] = (double)pa[e];
+    }
+#pragma unroll
+    for (int e = 0; e < NPB; ++e) {
+      const int i = tid + 256 * e;
+      Bs[i / ROT_C][i % ROT_C] = (double)pb[e];
     }
     __syncthreads();
-    if (j < d_s) {
-      for (int i = 0; i < ni; ++i) {
-        const double r = (double)R[(int64_t)(i0 + i) * d_s + j];
+    if (k0 + ROT_K < d_s) load(k0 + ROT_K);
 #pragma unroll
-        for (int a = 0; a < ROT_Q; ++a) acc[a] = __builtin_fma(qsh[i][a], r, acc[a]);
-      }
+    for (int ks = 0; ks < ROT_K; ks += 4) {
+      const double a = As[ks + (lane >> 4)][16 * wv + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < ROT_C / 16; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Bs[ks + (lane >> 4)][16 * j + (lane & 15)],
+                                                      acc[j], 0, 0, 0);
     }
   }
-  if (j >= d_s) return;
 #pragma unroll
-  for (int a = 0; a < ROT_Q; ++a) {
-    if (q0 + a >= nq) break;
-    const float hi = (float)acc[a];
-    qh[(q0 + a) * ldqr + j] = hi;
-    ql[(q0 + a) * ldqr + j] = (float)(acc[a] - (double)hi);
-  }
+  for (int j = 0; j < ROT_C / 16; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t q = q0 + 16 * wv + (lane >> 4) + 4 * r;
+      const int c = c0 + 16 * j + (lane & 15);
+      if (q < nq && c < d_s) {
+        const float hi = (float)acc[j][r];
+        qh[q * ldqr + c] = hi;
+        ql[q * ldqr + c] = (float)(acc[j][r] - (double)hi);
+      }
+    }
 }
 
 // LUT[q][m][c] = |q'_m - C_m[c]|^2 in FP32 (difference form, t = 0..dsub-1
 // in order) from the rotated query's high part. A workgroup takes block m
 // for LUT_Q queries: block m's 256 codewords are staged in LDS (LUT_T
 // coordinates at a time) and thread c fills entry c of every query's table.
-constexpr int LUT_Q = 16;
+constexpr int LUT_Q = 64;
 constexpr int LUT_T = 32;
 __global__ __launch_bounds__(256) void k_pq_lut(const float *__restrict__ qh, int64_t ldqr,
                                                 int64_t nq, const float *__restrict__ cb,
@@ -2822,7 +2857,7 @@ hipError_t launch_rotate(const float *Qs, int64_t ldqs, int64_t nq, const float 
                          float *qh, float *ql, int64_t ldqr, hipStream_t st) {
   if (nq == 0) return hipSuccess;
   KernelTimer tm("pq_rotate", st);
-  hipLaunchKernelGGL(k_rotate, dim3((unsigned)cdiv(nq, ROT_Q), (unsigned)cdiv(d_s, 256)),
+  hipLaunchKernelGGL(k_rotate, dim3((unsigned)cdiv(nq, ROT_Q), (unsigned)cdiv(d_s, ROT_C)),
                      dim3(256), 0, st, Qs, ldqs, nq, R, d_s, qh, ql, ldqr);
   return hipGetLastError();
 }
