@@ -910,32 +910,46 @@ __device__ __forceinline__ void measure1(const SelArgs &a, int64_t q, const Cand
       const int per = 16 / qeb;
       const uint8_t *vb =
           (const uint8_t *)a.qvec + (L.p0 * a.qd_pad + (L.row - L.p0) * SLAB) * qeb;
-      for (int e0 = lane * per; e0 < d; e0 += 64 * per) {
-        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-        const u32x4 w4 =
-            ldg((const u32x4 *)(vb + ((int64_t)(e0 / SLAB) * L.npad * SLAB + e0 % SLAB) * qeb));
-        // the query's bytes at the same coordinates (rows are 16-byte aligned)
-        const u32x4 q4 = qq_lds ? *(const u32x4 *)(qq_lds + (int64_t)e0 * qeb)
-                                : ldg((const u32x4 *)((const uint8_t *)a.qQ +
-                                                      (q * a.ldqq + e0) * qeb));
-        const uint32_t wds[4] = {w4[0], w4[1], w4[2], w4[3]};
-        const uint32_t qds[4] = {q4[0], q4[1], q4[2], q4[3]};
-        const uint32_t msk = qeb == 2 ? 0xffffu : 0xffu;
-        for (int u = 0; u < per && e0 + u < d; ++u) {
-          const int sh = ((u * qeb) % 4) * 8;
-          const uint32_t bits = (wds[(u * qeb) / 4] >> sh) & msk;
-          const uint32_t qbits = (qds[(u * qeb) / 4] >> sh) & msk;
-          float qh, ql, xh, xl;
-          if (a.qfmt == 1) {
-            qh = bf16_to_float((uint16_t)qbits);
-            ql = 0.f;
-            xh = bf16_to_float((uint16_t)bits);
-            xl = 0.f;
-          } else {
-            two_prod(qs, e4m3_to_float(qbits), qh, ql);
-            two_prod(xs, e4m3_to_float(bits), xh, xl);
+      // QB chunks per lane are loaded before any is used (the same order of
+      // accumulation as one chunk at a time)
+      typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+      constexpr int QB = 4;
+      for (int e00 = lane * per; e00 < d; e00 += 64 * per * QB) {
+        u32x4 w4s[QB], q4s[QB];
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+          const int e0 = e00 + 64 * per * b;
+          if (e0 < d) {
+            w4s[b] = ldg((const u32x4 *)(vb + ((int64_t)(e0 / SLAB) * L.npad * SLAB + e0 % SLAB) * qeb));
+            // the query's bytes at the same coordinates (rows are 16-byte aligned)
+            q4s[b] = qq_lds ? *(const u32x4 *)(qq_lds + (int64_t)e0 * qeb)
+                            : ldg((const u32x4 *)((const uint8_t *)a.qQ + (q * a.ldqq + e0) * qeb));
           }
-          acc_sq_diff2(qh, ql - xl, xh, S, C);
+        }
+#pragma unroll
+        for (int b = 0; b < QB; ++b) {
+          const int e0 = e00 + 64 * per * b;
+          if (e0 >= d) break;
+          const u32x4 w4 = w4s[b], q4 = q4s[b];
+          const uint32_t wds[4] = {w4[0], w4[1], w4[2], w4[3]};
+          const uint32_t qds[4] = {q4[0], q4[1], q4[2], q4[3]};
+          const uint32_t msk = qeb == 2 ? 0xffffu : 0xffu;
+          for (int u = 0; u < per && e0 + u < d; ++u) {
+            const int sh = ((u * qeb) % 4) * 8;
+            const uint32_t bits = (wds[(u * qeb) / 4] >> sh) & msk;
+            const uint32_t qbits = (qds[(u * qeb) / 4] >> sh) & msk;
+            float qh, ql, xh, xl;
+            if (a.qfmt == 1) {
+              qh = bf16_to_float((uint16_t)qbits);
+              ql = 0.f;
+              xh = bf16_to_float((uint16_t)bits);
+              xl = 0.f;
+            } else {
+              two_prod(qs, e4m3_to_float(qbits), qh, ql);
+              two_prod(xs, e4m3_to_float(bits), xh, xl);
+            }
+            acc_sq_diff2(qh, ql - xl, xh, S, C);
+          }
         }
       }
     } else {
@@ -970,19 +984,26 @@ __device__ __forceinline__ void measureB(const SelArgs &a, bool coarse, const Ca
         if (d0 + 64 * u < d) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
     }
   } else {
+    // lane l takes coordinates 4l + 256u + e in that order, read as 16-byte
+    // pieces, 2048 coordinates per pass
     const float *base = a.rows ? a.rows + L.row * a.d_pad
                                : a.vec + L.p0 * a.d_pad + (L.row - L.p0) * SLAB;
     const int64_t np = a.rows ? 1 : L.npad;
-    for (int d0 = lane; d0 < d; d0 += 64 * 16) {
-      float xv[16];
+    for (int d0 = 4 * lane; d0 < d; d0 += 256 * 8) {
+      float4 xv[8];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int dim = d0 + 64 * u;
-        xv[u] = dim < d ? ldg(base + (int64_t)(dim / SLAB) * np * SLAB + (dim % SLAB)) : 0.f;
+      for (int u = 0; u < 8; ++u) {
+        const int dim = d0 + 256 * u;
+        xv[u] = dim < d ? ldg4(base + (int64_t)(dim / SLAB) * np * SLAB + dim % SLAB)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (d0 + 64 * u < d) acc_sq_diff(qrow[d0 + 64 * u], xv[u], S, C);
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int dim = d0 + 256 * u + e;
+          if (dim < d) acc_sq_diff(qrow[dim], f4(xv[u], e), S, C);
+        }
     }
   }
 }
