@@ -2052,6 +2052,7 @@ struct TileQArgs {
   int32_t coarse;
   int64_t nq;
   int32_t nl, nl_pad, qtiles, total_host;
+  int32_t *work;           // scan: [8] work counters, zero at launch
 };
 
 // First pass of the precision form: s_x^2 |x_hat|^2 - 2 s_q s_x (q_hat . x_hat)
@@ -2075,13 +2076,27 @@ __global__ __launch_bounds__(256) void k_tile_dist_q(TileQArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int total = a.coarse ? a.total_host : a.tile_off[a.nlist];
   const int G = gridDim.x;
-  const int L = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
   const int rb = (wv >> 1) * 32, cb = (wv & 1) * 32;
   const int fr = lane & 15, fg = lane >> 4;
   const int nslab_dot = (a.d_dot + SLAB - 1) / SLAB;
   const int nsteps = (nslab_dot + KS - 1) / KS;
 
-  for (int w = L; w < total; w += G) {
+  // work items as in k_tile_multi: coarse, a contiguous run per XCD; scan,
+  // chunks of SCAN_CHUNK items dealt to the XCDs and taken one at a time
+  // from the XCD's counter
+  const int xcd = blockIdx.x & 7;
+  __shared__ int s_item;
+  for (int w = a.coarse ? xcd * (G >> 3) + (blockIdx.x >> 3) : 0;; w += G) {
+    if (!a.coarse) {
+      __syncthreads();  // every thread has read the previous s_item
+      if (tid == 0) {
+        const int k = atomicAdd(&a.work[xcd], 1);
+        s_item = ((k / SCAN_CHUNK) * 8 + xcd) * SCAN_CHUNK + k % SCAN_CHUNK;
+      }
+      __syncthreads();
+      w = s_item;
+    }
+    if (w >= total) break;
     int h, qt, vt, m, nvec;
     int64_t npad, p0;
     if (a.coarse) {
@@ -2829,6 +2844,7 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   u.tile_off = b.tile_off;
   u.bkt_off = b.bkt_off;
   u.cnt = b.cnt;
+  u.work = b.work;
   u.bucket = b.bucket;
   u.pair_div = nprobe;
   u.pair_base = b.pair_base;
