@@ -232,7 +232,8 @@ hipError_t launch_centroid_update(const float *X, int64_t ldx, const int32_t *pe
                                   const int64_t *off, int32_t nlist, int32_t dcols, float *C,
                                   int64_t ldc, hipStream_t st);
 hipError_t launch_bucketing(const adanns_index *ix, const SearchBufs &b, int64_t nq,
-                            int32_t nprobe, hipStream_t st);
+                            int32_t nprobe, hipStream_t st,
+                            int32_t tq = TILE_Q, int32_t tv = TILE_V);
 constexpr int PQ_ENCODE_MAX_DSUB = 32;
 // q' = q[:d_s] R (FP64 accumulation), rows of Qs -> (hi, lo) FP32 pairs.
 hipError_t launch_rotate(const float *Qs, int64_t ldqs, int64_t nq, const float *R, int32_t d_s,

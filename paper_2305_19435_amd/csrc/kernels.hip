@@ -2267,6 +2267,238 @@ __global__ __launch_bounds__(256) void k_tile_dist_q(TileQArgs a) {
   }
 }
 
+// LDS-DMA form of the precision form's scan tile (TQ x TV, TQ, TV >= 64),
+// built like tile_compute_dma: every stage holds 128 bytes of each operand
+// row (SC = 64 BF16 or 128 e4m3 coordinates, KS slabs), copied straight into
+// LDS by 16-byte global_load_lds_dwordx4 with chunk c of row r at position
+// c ^ f(r); two stages, one barrier per stage; four waves in a 2 x 2 grid,
+// each (TQ/2) x (TV/2) in 16x16x32 MFMA blocks. Lane l reads, per k-step of
+// 32 coordinates, the 8 values at coordinates 8 (l >> 4) .. of row l & 15,
+// for both operands. Quantised norms are summed from the decoded B fragments.
+// Coordinates past d_dot are zeroed in LDS on the last stage (both
+// operands); copies that would start past a row's stored width re-read an
+// earlier piece of it, which is zeroed too.
+constexpr int QTILE_Q = 128, QTILE_V = 128;  // precision-form scan tile
+
+template <int FMT, int TQ, int TV>
+__global__ __launch_bounds__(256, 2) void k_tile_q_scan(TileQArgs a) {
+  constexpr int EB = FMT == 1 ? 2 : 1;
+  constexpr int KS = 128 / (SLAB * EB);    // slabs per stage
+  constexpr int SC = KS * SLAB;            // coordinates per stage
+  constexpr int CPS = SLAB * EB / 16;      // 16-byte chunks per slab row
+  constexpr int EPC = 16 / EB;             // coordinates per chunk
+  constexpr int NA = TQ / 32, NBV = TV / 32;
+  constexpr int NB16 = TQ / 32, NC16 = TV / 32;
+  constexpr int NKS = SC / 32;             // MFMA k-steps per stage
+  __shared__ __attribute__((aligned(16))) uint8_t A0[TQ * 128], A1[TQ * 128];
+  __shared__ __attribute__((aligned(16))) uint8_t B0[TV * 128], B1[TV * 128];
+  __shared__ int64_t rbase[TQ];
+  __shared__ int32_t rq[TQ];
+  __shared__ float rsc[TQ], csc[TV], cn[TV];
+  __shared__ int s_item;
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rbw = (wv >> 1) * (TQ / 2), cbw = (wv & 1) * (TV / 2);
+  const int total = a.tile_off[a.nlist];
+  const int xcd = blockIdx.x & 7;
+  const int nstage = (a.d_dot + SC - 1) / SC;
+  const int nslab_dot = (a.d_dot + SLAB - 1) / SLAB;
+  const int lrow = lane >> 3;
+  const int gch = (lane & 7) ^ lrow ^ (wv & 1);  // global chunk of this lane's copies
+  const int r16 = lane & 15, g16 = lane >> 4;
+  const int sw16 = swz(r16);
+
+  for (;;) {
+    __syncthreads();  // every thread has read the previous s_item; epilogue done
+    if (tid == 0) {
+      const int k = atomicAdd(&a.work[xcd], 1);
+      s_item = ((k / SCAN_CHUNK) * 8 + xcd) * SCAN_CHUNK + k % SCAN_CHUNK;
+    }
+    __syncthreads();
+    const int w = s_item;
+    if (w >= total) break;
+    int lo = 0, hi = a.nlist - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ldg(a.tile_off + mid) <= w) lo = mid; else hi = mid - 1;
+    }
+    const int h = lo;
+    const int m = ldg(a.cnt + h), nvec = ldg(a.len + h);
+    const int64_t p0 = ldg(a.poff + h), npad = ldg(a.poff + h + 1) - p0;
+    const int qts = (m + TQ - 1) / TQ;
+    const int rem = w - ldg(a.tile_off + h);
+    const int qt = rem % qts, vt = rem / qts;
+    const int ncol = min(TV, nvec - vt * TV);
+    const int nrow = min(TQ, m - qt * TQ);
+    if (tid < TQ) {
+      const int i = qt * TQ + tid;
+      if (i < m) {
+        const int32_t pair = ldg(a.bucket + ldg(a.bkt_off + h) + i);
+        const int32_t qq = pair / a.pair_div;
+        rq[tid] = qq;
+        rbase[tid] = ldg(a.pair_base + pair);
+        rsc[tid] = FMT == 2 ? ldg(a.qscale + qq) : 1.f;
+      } else {
+        rq[tid] = -1;
+        rbase[tid] = 0;
+        rsc[tid] = 0.f;
+      }
+    } else if (tid < TQ + TV) {
+      const int col = tid - TQ;
+      csc[col] = (FMT == 2 && col < ncol) ? ldg(a.vscale + p0 + vt * TV + col) : 1.f;
+    }
+    __syncthreads();
+    const bool active = nrow > rbw && ncol > cbw;
+    const uint8_t *vbase = a.vec + (p0 * a.d_pad + (int64_t)vt * TV * SLAB) * EB;
+    // copy side: wave instruction u fills rows (4u + wv) * 8 .. + 7
+    const uint8_t *qp[NA];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int q = rq[(4 * u + wv) * 8 + lrow];
+      qp[u] = a.Qq + (int64_t)(q >= 0 ? q : 0) * a.ldqq * EB;
+    }
+    int vrow[NBV];
+#pragma unroll
+    for (int u = 0; u < NBV; ++u) vrow[u] = min((4 * u + wv) * 8 + lrow, ncol - 1);
+    auto issue = [&](int s, uint8_t *A, uint8_t *B) {
+      // this lane's chunk: coordinates s * SC + gch * EPC .., in slab sl
+      int sl = s * KS + gch / CPS;
+      int c0 = s * SC + gch * EPC;
+      if (sl >= nslab_dot) {  // past the prefix: re-read the first piece (zeroed)
+        sl = 0;
+        c0 = 0;
+      }
+#pragma unroll
+      for (int u = 0; u < NA; ++u)
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(qp[u] + (int64_t)c0 * EB),
+            (__attribute__((address_space(3))) void *)(A + (4 * u + wv) * 8 * 128), 16, 0, 0);
+#pragma unroll
+      for (int u = 0; u < NBV; ++u)
+        __builtin_amdgcn_global_load_lds(
+            (const void *)(vbase + ((int64_t)sl * npad * SLAB + (int64_t)vrow[u] * SLAB) * EB +
+                           (gch % CPS) * 16),
+            (__attribute__((address_space(3))) void *)(B + (4 * u + wv) * 8 * 128), 16, 0, 0);
+    };
+    auto clip = [&](uint8_t *A, uint8_t *B, int lim) {
+      const int c = (lane & 7) * 16;  // LDS position of this lane's chunks
+#pragma unroll
+      for (int e = 0; e < EPC; ++e)
+        if (gch * EPC + e >= lim) {
+#pragma unroll
+          for (int u = 0; u < NA; ++u)
+#pragma unroll
+            for (int b = 0; b < EB; ++b) A[((4 * u + wv) * 8 + lrow) * 128 + c + e * EB + b] = 0;
+#pragma unroll
+          for (int u = 0; u < NBV; ++u)
+#pragma unroll
+            for (int b = 0; b < EB; ++b) B[((4 * u + wv) * 8 + lrow) * 128 + c + e * EB + b] = 0;
+        }
+      __syncthreads();
+    };
+    floatx4 acc[NB16][NC16];
+#pragma unroll
+    for (int i = 0; i < NB16; ++i)
+#pragma unroll
+      for (int j = 0; j < NC16; ++j) acc[i][j] = (floatx4){0.f, 0.f, 0.f, 0.f};
+    float nrm[NC16];
+#pragma unroll
+    for (int j = 0; j < NC16; ++j) nrm[j] = 0.f;
+    auto compute = [&](const uint8_t *A, const uint8_t *B) {
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        // chunk and byte of this lane's 8 values at k-step ks
+        const int ch = FMT == 1 ? 4 * ks + g16 : 2 * ks + (g16 >> 1);
+        const int inner = FMT == 1 ? 0 : (g16 & 1) * 8;
+        const int off = ((ch ^ sw16) << 4) + inner;
+        if constexpr (FMT == 1) {
+          bf16x8 af[NB16], bfv[NC16];
+#pragma unroll
+          for (int i = 0; i < NB16; ++i)
+            af[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)&A[(rbw + i * 16 + r16) * 128 + off]);
+#pragma unroll
+          for (int j = 0; j < NC16; ++j) {
+            const uint4 x = *(const uint4 *)&B[(cbw + j * 16 + r16) * 128 + off];
+            bfv[j] = __builtin_bit_cast(bf16x8, x);
+            const uint32_t wd[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              const float v0 = __uint_as_float(wd[t] << 16), v1 = __uint_as_float(wd[t] & 0xffff0000u);
+              nrm[j] += v0 * v0 + v1 * v1;
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < NB16; ++i)
+#pragma unroll
+            for (int j = 0; j < NC16; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfv[j], acc[i][j], 0, 0, 0);
+        } else {
+          long af[NB16], bfv[NC16];
+#pragma unroll
+          for (int i = 0; i < NB16; ++i) af[i] = *(const long *)&A[(rbw + i * 16 + r16) * 128 + off];
+#pragma unroll
+          for (int j = 0; j < NC16; ++j) {
+            bfv[j] = *(const long *)&B[(cbw + j * 16 + r16) * 128 + off];
+            const int lo32 = (int)(uint32_t)bfv[j], hi32 = (int)(uint32_t)((uint64_t)bfv[j] >> 32);
+            const float v[8] = {
+                __builtin_amdgcn_cvt_f32_fp8(lo32, 0), __builtin_amdgcn_cvt_f32_fp8(lo32, 1),
+                __builtin_amdgcn_cvt_f32_fp8(lo32, 2), __builtin_amdgcn_cvt_f32_fp8(lo32, 3),
+                __builtin_amdgcn_cvt_f32_fp8(hi32, 0), __builtin_amdgcn_cvt_f32_fp8(hi32, 1),
+                __builtin_amdgcn_cvt_f32_fp8(hi32, 2), __builtin_amdgcn_cvt_f32_fp8(hi32, 3)};
+#pragma unroll
+            for (int t = 0; t < 8; ++t) nrm[j] += v[t] * v[t];
+          }
+#pragma unroll
+          for (int i = 0; i < NB16; ++i)
+#pragma unroll
+            for (int j = 0; j < NC16; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af[i], bfv[j], acc[i][j], 0, 0, 0);
+        }
+      }
+    };
+    __builtin_amdgcn_s_waitcnt(vm_wait_imm(0));  // the previous item's stores first
+    issue(0, A0, B0);
+    int s = 0;
+    auto step = [&](auto J) -> bool {
+      constexpr int j = decltype(J)::value;
+      uint8_t *A = j == 0 ? A0 : A1, *B = j == 0 ? B0 : B1;
+      __builtin_amdgcn_s_waitcnt(vm_wait_imm(0));  // this wave's copies of stage s landed
+      __syncthreads();  // stage s is in buffer j; every wave is done with 1 - j
+      if (s + 1 < nstage) issue(s + 1, j == 0 ? A1 : A0, j == 0 ? B1 : B0);
+      if (a.d_dot - s * SC < SC) clip(A, B, a.d_dot - s * SC);
+      if (active) compute(A, B);
+      return ++s >= nstage;
+    };
+    for (;;) {
+      if (step(ic<0>{})) break;
+      if (step(ic<1>{})) break;
+    }
+    // norms: the four lane groups of a column hold its coordinate ranges
+#pragma unroll
+    for (int j = 0; j < NC16; ++j) {
+      nrm[j] += __shfl_xor(nrm[j], 16);
+      nrm[j] += __shfl_xor(nrm[j], 32);
+      if (wv < 2 && active && lane < 16) cn[cbw + j * 16 + lane] = nrm[j];
+    }
+    __syncthreads();
+    // 16x16 f32 MFMA result: lane holds column (lane & 15), rows 4 (lane >> 4) + e
+#pragma unroll
+    for (int i = 0; i < NB16; ++i)
+#pragma unroll
+      for (int j = 0; j < NC16; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = rbw + i * 16 + 4 * (lane >> 4) + e;
+          const int col = cbw + j * 16 + (lane & 15);
+          if (rq[row] >= 0 && col < ncol) {
+            const float sx = csc[col], sq = rsc[row];
+            a.out[rbase[row] + vt * TV + col] = sx * sx * cn[col] - 2.0f * sq * sx * acc[i][j][e];
+          }
+        }
+  }
+}
+
 // ---- probe bucketing (batched) -------------------------------------------------
 __global__ void k_store_cfg(CfgDev c, CfgDev *dst) { *dst = c; }
 
@@ -2612,13 +2844,13 @@ hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq
 }
 
 hipError_t launch_bucketing(const adanns_index *ix, const SearchBufs &b, int64_t nq,
-                            int32_t nprobe, hipStream_t st) {
+                            int32_t nprobe, hipStream_t st, int32_t tq, int32_t tv) {
   SearchBufs bb = b;
   bb.ncfg = 1;
   bb.V = ix->nlist;
   bb.Qtot = nq;
   bb.pairs = nq * nprobe;
-  return bucketing_multi(bb, TILE_Q, TILE_V, st);
+  return bucketing_multi(bb, tq, tv, st);
 }
 
 template <int TQ, int TV>
@@ -2827,7 +3059,7 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
     KernelTimer tm("select_q_coarse", st);
     launch_select(s, nq, smem, st);
   }
-  e = launch_bucketing(ix, b, nq, nprobe, st);
+  e = launch_bucketing(ix, b, nq, nprobe, st, QTILE_Q, QTILE_V);
   if (e != hipSuccess) return e;
   // list scan first pass on the quantised vectors
   TileQArgs u{};
@@ -2852,9 +3084,9 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   {
     KernelTimer tm("tile_q_scan", st);
     if (fmt == 1)
-      hipLaunchKernelGGL(k_tile_dist_q<1>, dim3(PERSIST_WG), dim3(256), 0, st, u);
+      hipLaunchKernelGGL((k_tile_q_scan<1, QTILE_Q, QTILE_V>), dim3(PERSIST_WG), dim3(256), 0, st, u);
     else
-      hipLaunchKernelGGL(k_tile_dist_q<2>, dim3(PERSIST_WG), dim3(256), 0, st, u);
+      hipLaunchKernelGGL((k_tile_q_scan<2, QTILE_Q, QTILE_V>), dim3(PERSIST_WG), dim3(256), 0, st, u);
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
