@@ -2049,7 +2049,6 @@ struct TileQArgs {
   int32_t pair_div;
   const int64_t *pair_base;
   float *out;
-  int32_t coarse;
   int64_t nq;
   int32_t nl, nl_pad, qtiles, total_host;
   int32_t *work;           // scan: [8] work counters, zero at launch
@@ -2057,8 +2056,10 @@ struct TileQArgs {
 
 // First pass of the precision form: s_x^2 |x_hat|^2 - 2 s_q s_x (q_hat . x_hat)
 // on BF16 (FMT 1) or e4m3 (FMT 2) MFMA with FP32 accumulation; products of
-// these formats are exact in FP32. Tiles of 64 queries x 64 vectors, K steps
-// of 4 slabs (128 coordinates).
+// these formats are exact in FP32. This kernel serves the coarse step (every
+// query against the centroids, stored as one slab-layout list): tiles of 64
+// queries x 64 centroids, K steps of 4 slabs (128 coordinates). The scan uses
+// k_tile_q_scan.
 template <int FMT>
 __global__ __launch_bounds__(256) void k_tile_dist_q(TileQArgs a) {
   constexpr int EB = FMT == 1 ? 2 : 1;
@@ -2074,63 +2075,27 @@ __global__ __launch_bounds__(256) void k_tile_dist_q(TileQArgs a) {
   __shared__ float rsc[TILE_Q], csc[TILE_V], cn[TILE_V];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int total = a.coarse ? a.total_host : a.tile_off[a.nlist];
+  const int total = a.total_host;
   const int G = gridDim.x;
   const int rb = (wv >> 1) * 32, cb = (wv & 1) * 32;
   const int fr = lane & 15, fg = lane >> 4;
   const int nslab_dot = (a.d_dot + SLAB - 1) / SLAB;
   const int nsteps = (nslab_dot + KS - 1) / KS;
 
-  // work items as in k_tile_multi: coarse, a contiguous run per XCD; scan,
-  // chunks of SCAN_CHUNK items dealt to the XCDs and taken one at a time
-  // from the XCD's counter
-  const int xcd = blockIdx.x & 7;
-  __shared__ int s_item;
-  for (int w = a.coarse ? xcd * (G >> 3) + (blockIdx.x >> 3) : 0;; w += G) {
-    if (!a.coarse) {
-      __syncthreads();  // every thread has read the previous s_item
-      if (tid == 0) {
-        const int k = atomicAdd(&a.work[xcd], 1);
-        s_item = ((k / SCAN_CHUNK) * 8 + xcd) * SCAN_CHUNK + k % SCAN_CHUNK;
-      }
-      __syncthreads();
-      w = s_item;
-    }
-    if (w >= total) break;
-    int h, qt, vt, m, nvec;
-    int64_t npad, p0;
-    if (a.coarse) {
-      h = 0;
-      qt = w % a.qtiles;
-      vt = w / a.qtiles;
-      m = (int)a.nq;
-      nvec = a.nl;
-      npad = a.nl_pad;
-      p0 = 0;
-    } else {
-      int lo = 0, hi = a.nlist - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (a.tile_off[mid] <= w) lo = mid; else hi = mid - 1;
-      }
-      h = lo;
-      m = a.cnt[h];
-      nvec = a.len[h];
-      p0 = a.poff[h];
-      npad = a.poff[h + 1] - p0;
-      const int qts = (m + TILE_Q - 1) / TILE_Q;
-      const int rem = w - a.tile_off[h];
-      qt = rem % qts;
-      vt = rem / qts;
-    }
+  // XCD-aware order: workgroup b runs on XCD b % 8; each XCD gets a
+  // contiguous run of work items
+  const int L = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  for (int w = L; w < total; w += G) {
+    const int qt = w % a.qtiles, vt = w / a.qtiles;
+    const int m = (int)a.nq, nvec = a.nl;
+    const int64_t npad = a.nl_pad, p0 = 0;
     __syncthreads();
     if (tid < TILE_Q) {
       const int i = qt * TILE_Q + tid;
       if (i < m) {
-        const int32_t pair = a.coarse ? i : a.bucket[a.bkt_off[h] + i];
-        const int32_t qq = pair / a.pair_div;
+        const int32_t qq = i;
         rq[tid] = qq;
-        rbase[tid] = a.coarse ? (int64_t)i * a.nl : a.pair_base[pair];
+        rbase[tid] = (int64_t)i * a.nl;
         rsc[tid] = FMT == 2 ? a.qscale[qq] : 1.f;
       } else {
         rq[tid] = -1;
@@ -3015,7 +2980,6 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   t.d_pad = ix->d_cb_pad;
   t.pair_div = 1;
   t.out = b.S;
-  t.coarse = 1;
   t.nq = nq;
   t.nl = ix->nlist;
   t.nl_pad = ix->nl_pad;
