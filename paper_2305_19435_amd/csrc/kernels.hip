@@ -1008,6 +1008,32 @@ __device__ __forceinline__ void measureB(const SelArgs &a, bool coarse, const Ca
   }
 }
 
+// measureB's vector case (d_B <= 2048) with this lane's query coordinates
+// 4l + 256u .. 4l + 256u + 3 already in registers (q4[u]); the same order of
+// accumulation, so the same bits.
+__device__ __forceinline__ void measureB_vec_rq(const SelArgs &a, const CandLoc &L,
+                                                const float4 *q4, int lane, float &S,
+                                                float &C) {
+  const int d = a.d_B;
+  const float *base = a.rows ? a.rows + L.row * a.d_pad
+                             : a.vec + L.p0 * a.d_pad + (L.row - L.p0) * SLAB;
+  const int64_t np = a.rows ? 1 : L.npad;
+  float4 xv[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int dim = 4 * lane + 256 * u;
+    xv[u] = dim < d ? ldg4(base + (int64_t)(dim / SLAB) * np * SLAB + dim % SLAB)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int dim = 4 * lane + 256 * u + e;
+      if (dim < d) acc_sq_diff(f4(q4[u], e), f4(xv[u], e), S, C);
+    }
+}
+
 __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
   extern __shared__ __attribute__((aligned(16))) unsigned char sel_smem[];
   uint32_t *hist = (uint32_t *)sel_smem;
@@ -1455,10 +1481,29 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
       myid = INT64_MAX;
       mygp = -1;
     }
+    // vectors up to 2048 coordinates: this lane's query coordinates are
+    // read once into registers
+    const bool rq = !coarse && a.d_B <= 2048;
+    float4 q4[8];
+    if (rq) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int dim = 4 * lane + 256 * u + e;
+          v[e] = dim < a.d_B ? qglob[dim] : 0.f;
+        }
+        q4[u] = make_float4(v[0], v[1], v[2], v[3]);
+      }
+    }
     for (int cc = 0; cc < nres; ++cc) {
       const int64_t gp = (int64_t)readlane64((uint64_t)mygp, cc);
       float S = 0.f, C = 0.f;
-      measureB(a, coarse, locate_packed(a, coarse, gp), qglob, lane, S, C);
+      if (rq)
+        measureB_vec_rq(a, locate_packed(a, false, gp), q4, lane, S, C);
+      else
+        measureB(a, coarse, locate_packed(a, coarse, gp), qglob, lane, S, C);
       wave_reduce_pair(S, C);
       if (lane == cc) {
         myS = S;
