@@ -1,17 +1,27 @@
-// Device kernels of the AdANNS-IVF search path for gfx950 (CDNA4) and their
+// Device kernels of the AdANNS search paths for gfx950 (CDNA4) and their
 // host-side launch wrappers.
 //
-//   k_stage_queries  query prefix staging (zero-padded, 16-byte aligned rows)
-//   k_tile_dist      first-pass distances |x|^2 - 2 q.x for tiles of
-//                    64 queries x 64 vectors on FP32 MFMA; one kernel serves
-//                    the coarse step (all queries against the centroids) and
-//                    the list scan (each list against the queries probing it)
-//   k_select_refine  per query: radix selection of the shortlist, exact
-//                    re-measurement of the shortlist in compensated FP32,
-//                    bitonic sort by (distance, id), top-k / top-nprobe out
+//   k_stage_multi    query prefix staging (zero-padded, 16-byte aligned rows)
+//   k_tile_multi     first-pass distances |x|^2 - 2 q.x on FP32 MFMA over a
+//                    batch of configurations, persistent: the coarse step
+//                    (all queries against the centroids) and the list scan
+//                    (each list against the queries probing it; TQ x TV
+//                    tiles, operands copied global -> LDS, per-XCD work
+//                    counters)
+//   k_select_wave / k_select_multi / k_select_refine(_wave)
+//                    per query: the shortlist by first-pass value, exact
+//                    re-measurement in compensated FP32, sort by (distance,
+//                    id), top-k / top-nprobe out (one wave or one workgroup
+//                    per query)
 //   k_count / k_list_scan / k_scatter / k_seg_len / k_pair_base
 //                    probe bucketing: (query, probe) pairs grouped per list,
 //                    tile counts per list and the output segment of each pair
+//   k_rotate / k_pq_lut / k_adc_scan
+//                    IVF-PQ: query rotation (FP64 MFMA), distance tables,
+//                    table-lookup scan with the tables in LDS
+//   k_quant_* / k_tile_dist_q / k_tile_q_scan
+//                    precision form: BF16 / e4m3 copies and their first pass
+//                    on BF16 / FP8 MFMA (coarse, scan)
 //
 // The coarse step follows Algorithm 1's inference loop (distances to every
 // centroid on the d_c prefix, then the nprobe nearest); the scan is its
