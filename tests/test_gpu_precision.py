@@ -87,3 +87,40 @@ def test_precision_chunked_equals_whole(prec, lib):
         lib.set_search_scratch_cap(0)
     for x, y in zip(whole, parts):
         assert torch.equal(x, y)
+
+
+@pytest.fixture(scope="module")
+def prec_wide(lib):
+    """d = 200: several 128-byte stages per row for both formats, the last one
+    partial; three queries repeated 100 times fill 128-row query tiles."""
+    import synth
+    m = synth.Mixture(200, 300, seed=57)
+    X = m.database(30_000)
+    Qr = m.queries(63)
+    Q = np.concatenate([np.repeat(Qr[:3], 100, axis=0), Qr[3:]])
+    C32, a, off, ids = oracle_index(X, 48, 24, 6, 57)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    index.set_precision("bf16")
+    index.set_precision("fp8")
+    yield X, Q, C32, off, ids, index
+    index.free()
+
+
+@pytest.mark.parametrize("fmt,d_s", [("bf16", 200), ("fp8", 200), ("bf16", 130), ("fp8", 128)])
+def test_precision_parity_wide(prec_wide, fmt, d_s):
+    X, Q, C32, off, ids, index = prec_wide
+    d_c, nprobe, k, rerank, margin = 24, 4, 10, 32, 8
+    dist, gid, probes = index.search_precision(torch.from_numpy(Q).cuda(), d_c, d_s, nprobe, k,
+                                               fmt, rerank, margin, return_probes=True)
+    torch.cuda.synchronize()
+    dist, gid, probes = dist.cpu().numpy(), gid.cpu().numpy(), probes.cpu().numpy()
+    sel = list(range(0, len(Q), 9))
+    rd, ri, rp, shortlists = precision.precision_search64(
+        X, Q[sel], C32.astype(np.float64), off, ids, d_c, d_s, nprobe, k, fmt, rerank, margin,
+        return_shortlist=True)
+    assert np.array_equal(probes[sel], rp)
+    rep = check.Report()
+    for j, qi in enumerate(sel):
+        check.compare_knn(Q[qi], X, shortlists[j], dist[qi], gid[qi], rd[j], ri[j], d_s,
+                          report=rep, tag=f"q{qi}")
+    assert rep.ok, rep.problems
