@@ -99,7 +99,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
+        print(json.dumps({"error": "this library runs on one GPU only; multi-GPU sharding is a "
                                    "design (see DESIGN.md), --gpus must be 1"}), flush=True)
         sys.exit(2)
 

@@ -47,7 +47,7 @@ typedef enum adanns_status {
   ADANNS_EINVAL = -1,      /* invalid argument */
   ADANNS_ENOMEM = -2,      /* device or host allocation failed */
   ADANNS_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
-  ADANNS_EUNSUPPORTED = -4,/* valid request this build does not support */
+  ADANNS_EUNSUPPORTED = -4,/* valid request this library does not support */
   ADANNS_EBUDGET = -5,     /* request exceeds an admission budget */
   ADANNS_EIO = -6          /* a file could not be opened, read or written, or is malformed */
 } adanns_status;
