@@ -391,8 +391,9 @@ adanns_status adanns_index_centroids(const adanns_index *index, float *centroids
  * their list layout and every PQ codec). adanns_index_save waits for the
  * device, then writes ``path`` (created or truncated). adanns_index_load
  * reads such a file onto the current device on ``stream`` and returns a new
- * index in *out (release with adanns_index_free). Low-precision copies are
- * not stored: call adanns_set_precision again after a load. A file that is
+ * index in *out (release with adanns_index_free). Low-precision copies and
+ * the row-major re-measure copy are not stored: call adanns_set_precision /
+ * adanns_index_add_row_copy again after a load. A file that is
  * not a complete index of this format version gives ADANNS_EIO and leaves
  * *out untouched. */
 adanns_status adanns_index_save(const adanns_index *index, const char *path);
