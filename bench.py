@@ -63,7 +63,7 @@ def parse():
                     help="run one 1 GiB device-to-device copy first (HBM counter calibration)")
     ap.add_argument("--form", default="ivf",
                     choices=["ivf", "precision", "batching", "pq", "serving", "diagnostics",
-                             "sweep"],
+                             "sweep", "latency"],
                     help="ivf: the headline FP32 search; the others measure the other forms")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile-shape autotuner")
     ap.add_argument("--row-copy", action="store_true",
@@ -99,8 +99,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this library runs on one GPU only; multi-GPU sharding is a "
-                                   "design (see DESIGN.md), --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "this library runs on one GPU only (multi-GPU sharding is "
+                                   "designed, not built); --gpus must be 1"}), flush=True)
         sys.exit(2)
 
     import torch

@@ -41,7 +41,7 @@ def _kernel_ms(lib, names):
 def run(args, lib, torch, log):
     {"precision": precision_form, "batching": batching_form, "pq": pq_form,
      "serving": serving_form, "diagnostics": diagnostics_form,
-     "sweep": sweep_form}[args.form](args, lib, torch, log)
+     "sweep": sweep_form, "latency": latency_form}[args.form](args, lib, torch, log)
 
 
 # ---------------------------------------------------------------------------
@@ -487,4 +487,81 @@ def sweep_form(args, lib, torch, log):
            "config": {"workload": f"imagenet1k: N={n} d={w.d} nq={nq} nlist={nlist} d_s={d_s} "
                                   f"k={k}; one index per d_c; value = best QPS at recall@10 >= 0.69"},
            "scan_shapes": shapes, "grid": grid}
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+def latency_form(args, lib, torch, log):
+    """Small-batch latency of the FP32 search on the image-retrieval shape
+    (d_c 64, d_s 2048, nprobe 8, k 10): per batch size, p50 / p99 of the
+    device time of one whole search (HIP events around it, after warm-up),
+    and the share of it that one read of the probed lists' prefixes takes
+    at 8 TB/s (the HBM floor of the query-major regime)."""
+    import numpy as np
+    w = synth.WORKLOADS["imagenet1k"]
+    n = args.n or w.n
+    mix = w.mixture()
+    X = mix.database(n)
+    Q = mix.queries(4096)
+    Xd = torch.from_numpy(X).cuda()
+    n_train = min(n, 64 * w.nlist)
+    rows = synth.subsample_rows(n, n_train, w.seed)
+    index = lib.IvfIndex.build_ivf(Xd, w.nlist, w.d_c, args.iters,
+                                   synth.init_rows(n_train, w.nlist, w.seed), train_rows=rows)
+    del Xd
+    torch.cuda.empty_cache()
+    lens = np.diff(index.lists()[0])
+    reps = 50
+    res = {}
+    for nq in (1, 8, 64, 512, 4096):
+        Qd = torch.from_numpy(Q[:nq]).cuda()
+        dist = torch.empty((nq, w.k), dtype=torch.float32, device="cuda")
+        ids = torch.empty((nq, w.k), dtype=torch.int64, device="cuda")
+        probes = None
+        for _ in range(3):
+            _, _, probes = index.search(Qd, w.d_c, w.d_s, w.nprobe, w.k, return_probes=True)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            index.search(Qd, w.d_c, w.d_s, w.nprobe, w.k, out=(dist, ids))
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        # the same search as one replayed hipGraph (batching form, one
+        # configuration): launch overheads leave the host's path
+        gb = lib.Batch([(index, nq, w.d_c, w.d_s, w.nprobe, w.k)], ldq=w.d, ldk=w.k)
+        for _ in range(3):
+            gb.run(Qd, out=(dist, ids), graph=True)
+        torch.cuda.synchronize()
+        gms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            gb.run(Qd, out=(dist, ids), graph=True)
+            e1.record()
+            torch.cuda.synchronize()
+            gms.append(e0.elapsed_time(e1))
+        gb.free()
+        p = probes.cpu().numpy()
+        # bytes of one read of every distinct probed list's prefix
+        lists = np.unique(p)
+        floor_bytes = float(lens[lists].sum()) * w.d_s * 4
+        p50, p99 = float(np.percentile(ms, 50)), float(np.percentile(ms, 99))
+        res[f"nq={nq}"] = {"p50_ms": round(p50, 4), "p99_ms": round(p99, 4),
+                           "qps_at_p50": round(nq / (p50 * 1e-3), 1),
+                           "graph_p50_ms": round(float(np.percentile(gms, 50)), 4),
+                           "graph_p99_ms": round(float(np.percentile(gms, 99)), 4),
+                           "distinct_lists": int(len(lists)),
+                           "hbm_floor_ms": round(floor_bytes / (HBM_PEAK_GBS * 1e9) * 1e3, 4),
+                           "hbm_floor_frac": round(floor_bytes / (HBM_PEAK_GBS * 1e9) / (p50 * 1e-3), 4)}
+        log(f"nq={nq}: p50 {p50:.3f} ms, p99 {p99:.3f} ms")
+    index.free()
+    out = {"metric": "p50/p99 latency of one FP32 search per batch size", "value": res["nq=1"]["p50_ms"],
+           "unit": "ms (p50, one query)", "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
+           "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": f"imagenet1k: N={n} d={w.d} nlist={w.nlist} d_c={w.d_c} "
+                                  f"d_s={w.d_s} nprobe={w.nprobe} k={w.k}; {reps} searches per size"},
+           "batches": res}
     print(json.dumps(out), flush=True)

@@ -244,6 +244,8 @@ SearchBufs carve(char *base, const adanns_index *ix, int64_t nq, int32_t dq_pad,
   b.max_nprobe = nprobe;
   b.max_k = MAX_SHORTLIST - REFINE_MARGIN;
   b.max_nlist = ix->nlist;
+  // items <= sum over lists of (its pairs) x (its 64-vector tiles)
+  b.max_items = nq * nprobe * cdiv(std::max<int64_t>(ix->max_len, 1), 64);
   b.ldqs = dq_pad;
   b.Qs = c.take<float>((size_t)nq * dq_pad);
   b.S = coarse ? c.take<float>((size_t)nq * ix->nlist) : nullptr;

@@ -103,6 +103,7 @@ adanns_status adanns_batch_create(const adanns_batch_config *cfgs, int32_t ncfg,
   int64_t q0 = 0, S0 = 0, pair0 = 0, D = 0;
   int32_t vl0 = 0, ct0 = 0, dq = 1, kmax = 1;
   double probed = 0, lists = 0;
+  int64_t max_items = 0;  // upper bound on the scan's work items
   for (int32_t c = 0; c < ncfg; ++c) {
     const adanns_batch_config &u = cfgs[c];
     const adanns_index *ix = u.index;
@@ -119,6 +120,7 @@ adanns_status adanns_batch_create(const adanns_batch_config *cfgs, int32_t ncfg,
     if (u.nprobe < 1 || u.nprobe > ix->nlist) return bad("nprobe outside [1, nlist]");
     if (u.k < 1 || u.k > MAX_SHORTLIST) return bad("k outside [1, 1024]");
     CfgDev g = make_cfg(ix, u.d_c, u.d_s, u.nprobe, u.k, u.nq);
+    max_items += u.nq * u.nprobe * cdiv(std::max<int64_t>(ix->max_len, 1), 64);
     g.q0 = q0;
     g.S0 = S0;
     g.pair0 = pair0;
@@ -169,6 +171,7 @@ adanns_status adanns_batch_create(const adanns_batch_config *cfgs, int32_t ncfg,
     b.max_k = kmax;
     b.max_nlist = 1;
     for (const CfgDev &g : p->cfg) b.max_nlist = std::max(b.max_nlist, g.nlist);
+    b.max_items = max_items;
     b.Qs = cv.take<float>((size_t)q0 * dq_pad);
     b.S = cv.take<float>((size_t)S0);
     b.probes = cv.take<int32_t>((size_t)pair0);

@@ -178,6 +178,7 @@ struct SearchBufs {
   int64_t Qtot;       // query rows over configurations
   int64_t pairs;      // pairs over configurations
   int32_t max_nprobe, max_k, max_nlist;  // maxima over configurations (LDS sizing)
+  int64_t max_items;  // upper bound on the scan's work items (caps its grid); 0 = none
   float *Qs;          // [nq][dq_pad]
   int64_t ldqs;
   float *S;           // [nq][nlist] coarse first-pass scores

@@ -2916,6 +2916,8 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
   t.D = b.D;
   t.work = b.work;
   grid = (int)round_up(std::max(8, grid), 8);
+  // no more workgroups than the work items can occupy (small batches)
+  if (b.max_items > 0) grid = (int)std::min<int64_t>(grid, round_up(std::max<int64_t>(8, b.max_items), 8));
   {
     KernelTimer tm("tile_dist_scan", st);
     if (tv == 128) {
@@ -3102,10 +3104,12 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   u.out = b.D;
   {
     KernelTimer tm("tile_q_scan", st);
+    const int qgrid = (int)(b.max_items > 0 ? std::min<int64_t>(PERSIST_WG, round_up(std::max<int64_t>(8, b.max_items), 8))
+                                            : PERSIST_WG);
     if (fmt == 1)
-      hipLaunchKernelGGL((k_tile_q_scan<1, QTILE_Q, QTILE_V>), dim3(PERSIST_WG), dim3(256), 0, st, u);
+      hipLaunchKernelGGL((k_tile_q_scan<1, QTILE_Q, QTILE_V>), dim3(qgrid), dim3(256), 0, st, u);
     else
-      hipLaunchKernelGGL((k_tile_q_scan<2, QTILE_Q, QTILE_V>), dim3(PERSIST_WG), dim3(256), 0, st, u);
+      hipLaunchKernelGGL((k_tile_q_scan<2, QTILE_Q, QTILE_V>), dim3(qgrid), dim3(256), 0, st, u);
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
