@@ -115,7 +115,8 @@ adanns_status dmalloc(adanns_index *ix, void **p, size_t bytes) {
 }
 
 void free_index_memory(adanns_index *ix) {
-  void *ptrs[] = {ix->vec, ix->rows, ix->poff, ix->len, ix->rowid, ix->cent, ix->cent_slab};
+  void *ptrs[] = {ix->vec,  ix->rows, ix->poff,      ix->len,
+                  ix->rowid, ix->cent, ix->cent_slab, ix->xmax2};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &qsv : ix->quant) {
@@ -133,6 +134,15 @@ void free_index_memory(adanns_index *ix) {
   for (auto &kv : ix->scratch)
     if (kv.second.base) (void)hipFree(kv.second.base);
   ix->scratch.clear();
+}
+
+// The largest squared row norm of the filled vector layout, which bounds the
+// rounding error of the FP32 first pass (allocated on first use).
+adanns_status vector_norm_bound(adanns_index *ix, hipStream_t st) {
+  adanns_status s;
+  if (!ix->xmax2 && (s = dmalloc(ix, (void **)&ix->xmax2, sizeof(float)))) return s;
+  ADANNS_HIP(launch_row_norm_max(ix, st));
+  return ADANNS_OK;
 }
 
 // Lays out lists, ids and vectors for a validated assignment (host array).
@@ -188,9 +198,11 @@ adanns_status build_layout(adanns_index *ix, const Mat &X, const std::vector<int
                             hipMemcpyHostToDevice, st));
   ADANNS_HIP(hipMemcpyAsync(d_row_list, row_list.data(), ix->rows_pad * sizeof(int32_t),
                             hipMemcpyHostToDevice, st));
-  if (X.p)
+  if (X.p) {
     ADANNS_HIP(launch_layout(X, ix->d, ix->rowid, d_row_list, ix->poff, ix->rows_pad, ix->d_pad,
                              ix->vec, st));
+    if ((s = vector_norm_bound(ix, st))) return s;
+  }
   ADANNS_HIP(hipStreamSynchronize(st));
   return ADANNS_OK;
 }
@@ -1286,7 +1298,8 @@ adanns_status adanns_index_load(const char *path, void *stream, adanns_index **o
     }
     if ((s = build_centroids(ix, dc, d_cb, st))) return fail(s);
   }
-  if ((s = file_to_dev(fl, ix->vec, (size_t)rows_pad * ix->d_pad * sizeof(float), st)))
+  if ((s = file_to_dev(fl, ix->vec, (size_t)rows_pad * ix->d_pad * sizeof(float), st)) ||
+      (s = vector_norm_bound(ix, st)))
     return fail(s);
   int32_t npq = 0;
   if (!fl.get(&npq, 4) || npq < 0 || npq > 16) return fail(bad("codec count"));

@@ -1594,7 +1594,36 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
       }
     }
   }
-  const int ncand = (int)min64(L, (int64_t)K1);
+  int ncand = (int)min64(L, (int64_t)K1);
+  const float ADANNS_GLOBAL_AS *qrow =
+      (const float ADANNS_GLOBAL_AS *)(m.Qs + r * m.ldqs);
+
+  // 1b. vectors: the first-pass value |x|^2 - 2 q.x of a d_s-prefix is off
+  // its exact value by at most B = c (X^2 + 2 |q| X), X the largest row norm
+  // of the index and c = 4 (d_s + 2) 2^-24: four times the classical bound
+  // for a length-d_s dot product and sum of squares in FP32 plus the final
+  // rounding. A candidate whose first-pass value exceeds the k-th smallest by
+  // more than 2B is farther than k others in exact arithmetic, so only the
+  // shortlist's prefix within 2B of the k-th smallest is re-measured.
+  if (!coarse && g.xmax2 != nullptr && ncand > kout) {
+    float qq = 0.f;
+    for (int d0 = 4 * lane; d0 < d_dot; d0 += 256) {
+      const float4 v = ldg4((const float *)qrow + d0);
+      qq += (d0 < d_dot ? v.x * v.x : 0.f) + (d0 + 1 < d_dot ? v.y * v.y : 0.f) +
+            (d0 + 2 < d_dot ? v.z * v.z : 0.f) + (d0 + 3 < d_dot ? v.w * v.w : 0.f);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o);
+    const float X2 = ldg(g.xmax2), X = sqrtf(X2), qn = sqrtf(qq);
+    const float B = 4.f * (float)(d_dot + 2) * 0x1p-24f * (X2 + 2.f * qn * X);
+    const uint32_t kk = (uint32_t)(readlane64(best, kout - 1) >> 32);
+    const float vk = __uint_as_float((kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk);
+    const float T = vk + 2.f * B;
+    if (T <= __FLT_MAX__) {
+      const uint64_t tcomp = ((uint64_t)order_key(T) << 32) | 0xFFFFFFFFull;
+      ncand = __popcll(__ballot(lane < ncand && best <= tcomp));
+    }
+  }
 
   // 2. where each candidate lives (lane j < ncand holds candidate j)
   int64_t my_id = INT64_MAX, my_npad = 0;
@@ -1623,8 +1652,6 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
   }
 
   // 3. exact re-measurement over the lanes
-  const float ADANNS_GLOBAL_AS *qrow =
-      (const float ADANNS_GLOBAL_AS *)(m.Qs + r * m.ldqs);
   float myS = __builtin_inff(), myC = 0.f;
   // vectors: SELW_G candidates at a time, lane l taking coordinates
   // 4l + 256u + e in that order (as measure1), up to 2048 coordinates per
@@ -2711,6 +2738,7 @@ CfgDev make_cfg(const adanns_index *ix, int32_t d_c, int32_t d_s, int32_t nprobe
   CfgDev c{};
   c.vec = ix->vec;
   c.rows = ix->rows;
+  c.xmax2 = ix->xmax2;
   c.poff = ix->poff;
   c.len = ix->len;
   c.rowid = ix->rowid;
@@ -2980,6 +3008,45 @@ hipError_t launch_slab_to_rows(const adanns_index *ix, float *rows, hipStream_t 
   const unsigned bx = (unsigned)std::min<int64_t>(64, cdiv(per_list, 256));
   hipLaunchKernelGGL(k_slab_to_rows, dim3(bx, (unsigned)ix->nlist), dim3(256), 0, st, ix->vec,
                      ix->poff, ix->d_pad, rows);
+  return hipGetLastError();
+}
+
+// Largest squared norm over the rows of the slab layout (padding rows are
+// zero): block h covers list h, each half-wave one row at a time with its 32
+// lanes across the slab width. Non-negative floats order as their bit
+// patterns, so the maximum is taken with an integer atomic.
+__global__ __launch_bounds__(256) void k_row_norm_max(const float *__restrict__ vec,
+                                                      const int64_t *__restrict__ poff,
+                                                      int32_t d_pad, uint32_t *__restrict__ out) {
+  __shared__ float sh[8];
+  const int h = blockIdx.x, half = threadIdx.x >> 5, l = threadIdx.x & 31;
+  const int64_t p0 = poff[h], np = poff[h + 1] - p0;
+  const float *src = vec + p0 * d_pad;
+  const int nslab = d_pad / SLAB;
+  float best = 0.f;
+  for (int64_t r = half; r < np; r += 8) {
+    float s = 0.f;
+    for (int k = 0; k < nslab; ++k) {
+      const float x = src[((int64_t)k * np + r) * SLAB + l];
+      s = fmaf(x, x, s);
+    }
+    for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
+    best = fmaxf(best, s);
+  }
+  if (l == 0) sh[half] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = sh[0];
+    for (int i = 1; i < 8; ++i) m = fmaxf(m, sh[i]);
+    atomicMax(out, __float_as_uint(m));
+  }
+}
+
+hipError_t launch_row_norm_max(const adanns_index *ix, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(ix->xmax2, 0, sizeof(float), st);
+  if (e != hipSuccess || ix->nlist == 0) return e;
+  hipLaunchKernelGGL(k_row_norm_max, dim3((unsigned)ix->nlist), dim3(256), 0, st, ix->vec,
+                     ix->poff, ix->d_pad, (uint32_t *)ix->xmax2);
   return hipGetLastError();
 }
 

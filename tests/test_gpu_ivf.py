@@ -190,3 +190,49 @@ def test_chunked_search_equals_whole(small, lib):
     for x, y in zip(whole, parts):
         assert np.array_equal(x, y)
     assert np.array_equal(d2.cpu().numpy(), whole[0]) and np.array_equal(g2.cpu().numpy(), whole[1])
+
+
+def test_large_offset_shortlist(lib):
+    """Vectors and queries share an offset of norm 100, so the FP32 first pass
+    (|x|^2 - 2 q.x near -1e4) errs by ~1e-2 while the nearest candidates of a
+    query lie at squared distances 1 + 0.0005 j: the first pass misorders
+    them, and the result is right only if the exact re-measure covers every
+    shortlisted candidate within the first pass's error bound of the k-th."""
+    rng = np.random.default_rng(2305)
+    d, nq, per, k, nlist = 64, 16, 12, 5, 4
+    o = rng.standard_normal(d)
+    o *= 100.0 / np.linalg.norm(o)
+    Q = (o + 0.1 * rng.standard_normal((nq, d))).astype(np.float32)
+    rows = []
+    for i in range(nq):
+        u = rng.standard_normal((per, d))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        s = np.sqrt(1.0 + 0.0005 * rng.permutation(per))
+        rows.append(Q[i].astype(np.float64) + s[:, None] * u)
+    rows.append(o + 3.0 * rng.standard_normal((400, d)))
+    X = np.concatenate(rows).astype(np.float32)
+    # the case is meaningful: FP32 accumulation in one order puts a member
+    # of the exact top k above the k-th smallest FP32 value for most queries
+    X64 = X.astype(np.float64)
+    misordered = 0
+    for q in Q:
+        nx = np.zeros(len(X), np.float32)
+        dot = np.zeros(len(X), np.float32)
+        for j in range(d):
+            nx = nx + X[:, j] * X[:, j]
+            dot = dot + X[:, j] * q[j]
+        f = nx - np.float32(2) * dot
+        top = np.argsort(((X64 - q.astype(np.float64)) ** 2).sum(1), kind="stable")[:k]
+        misordered += int((f[top] > np.sort(f)[k - 1]).any())
+    assert misordered >= nq // 2
+    C32, a, off, ids = oracle_index(X, nlist, 16, 10, 7)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    try:
+        dist, gid, probes = index.search(torch.from_numpy(Q).cuda(), 16, d, nlist, k,
+                                         return_probes=True)
+        torch.cuda.synchronize()
+        rep = check_search(X, Q, C32, off, ids, 16, d, nlist, k, dist.cpu().numpy(),
+                           gid.cpu().numpy(), got_p=probes.cpu().numpy())
+        assert rep.ok, rep.problems
+    finally:
+        index.free()
