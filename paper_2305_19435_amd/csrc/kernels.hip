@@ -1569,14 +1569,15 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
   // 1. the K1 smallest (key, position) composites, sorted over lanes
   const float ADANNS_GLOBAL_AS *sg = (const float ADANNS_GLOBAL_AS *)seg;
   uint64_t best = ~0ull, thr = ~0ull;
-  constexpr int U = COARSE ? 16 : 32;  // loads in flight per lane
-  for (int64_t base = 0; base < L; base += 64 * U) {
-    float v[U];
+  constexpr int U = COARSE ? 16 : 32;  // loads in flight per lane and batch
+  // batches of 64 U values, the next batch loading while one is merged
+  // (positions past the segment re-read its last value, so that the loads
+  // carry no branches and the merge waits for its own batch only)
+  auto load = [&](float (&v)[U], int64_t base) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = base + 64 * u + lane;
-      v[u] = i < L ? sg[i] : 0.f;
-    }
+    for (int u = 0; u < U; ++u) v[u] = sg[min64(base + 64 * u + lane, L - 1)];
+  };
+  auto merge = [&](const float (&v)[U], int64_t base) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = base + 64 * u + lane;
@@ -1592,6 +1593,20 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
           thr = readlane64(best, K1 - 1);
         }
       }
+    }
+  };
+  if (L > 0) {
+    float va[U], vb[U];
+    load(va, 0);
+    // (the prefetch is unconditional: a batch past the end re-reads the
+    // last value, and the wait counts stay exact on every path)
+    for (int64_t base = 0;; base += 128 * U) {
+      load(vb, base + 64 * U);
+      merge(va, base);
+      if (base + 64 * U >= L) break;
+      load(va, base + 128 * U);
+      merge(vb, base + 64 * U);
+      if (base + 128 * U >= L) break;
     }
   }
   int ncand = (int)min64(L, (int64_t)K1);
