@@ -1595,7 +1595,19 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
       }
     }
   };
-  if (L > 0) {
+  if constexpr (COARSE) {
+    // one score row per query (nlist values, often a single batch): no
+    // prefetch
+    for (int64_t base = 0; base < L; base += 64 * U) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = base + 64 * u + lane;
+        v[u] = i < L ? sg[i] : 0.f;
+      }
+      merge(v, base);
+    }
+  } else if (L > 0) {
     float va[U], vb[U];
     load(va, 0);
     // (the prefetch is unconditional: a batch past the end re-reads the
