@@ -2585,6 +2585,71 @@ __global__ void k_count(const int32_t *__restrict__ probes, int64_t npairs, cons
   atomicAdd(&cnt[cfg[c].vl0 + probes[p]], 1);
 }
 
+// The same two passes with the counting done per workgroup in LDS first
+// (BKT_CHUNK pairs per workgroup), so that each workgroup makes one global
+// atomic per list it touches instead of one per pair: the list counters
+// share few cache lines, and per-pair atomics on them serialise.
+constexpr int BKT_CHUNK = 8192;       // pairs per workgroup
+constexpr int BKT_LDS_BINS = 8192;    // virtual lists an LDS histogram holds (32 KB)
+
+__global__ __launch_bounds__(1024) void k_count_lds(const int32_t *__restrict__ probes,
+                                                    int64_t npairs, const CfgDev *cfg,
+                                                    int32_t ncfg, int32_t V,
+                                                    int32_t *__restrict__ cnt) {
+  extern __shared__ int32_t hist[];  // [V]
+  const int tid = threadIdx.x;
+  for (int i = tid; i < V; i += 1024) hist[i] = 0;
+  __syncthreads();
+  const int64_t p0 = (int64_t)blockIdx.x * BKT_CHUNK, p1 = min64(npairs, p0 + BKT_CHUNK);
+  for (int64_t p = p0 + tid; p < p1; p += 1024) {
+    const int c = cfg_of(cfg, ncfg, &CfgDev::pair0, p);
+    atomicAdd(&hist[cfg[c].vl0 + probes[p]], 1);
+  }
+  __syncthreads();
+  for (int i = tid; i < V; i += 1024) {
+    const int32_t h = hist[i];
+    if (h) atomicAdd(&cnt[i], h);
+  }
+}
+
+// bucket[bkt_off[v] + slot] = p for the pairs p of virtual list v: a
+// workgroup ranks its pairs per list in LDS, reserves one run of slots per
+// list with one atomic on cursor[v], then writes.
+__global__ __launch_bounds__(1024) void k_scatter_lds(const int32_t *__restrict__ probes,
+                                                      int64_t npairs, const CfgDev *cfg,
+                                                      int32_t ncfg, int32_t V,
+                                                      const int32_t *__restrict__ bkt_off,
+                                                      int32_t *__restrict__ cursor,
+                                                      int32_t *__restrict__ bucket) {
+  extern __shared__ int32_t hist[];  // [V]: counts, then each list's run start
+  constexpr int PER = BKT_CHUNK / 1024;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < V; i += 1024) hist[i] = 0;
+  __syncthreads();
+  const int64_t p0 = (int64_t)blockIdx.x * BKT_CHUNK, p1 = min64(npairs, p0 + BKT_CHUNK);
+  int32_t vv[PER], rk[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int64_t p = p0 + tid + 1024 * j;
+    vv[j] = -1;
+    rk[j] = 0;
+    if (p < p1) {
+      const int c = cfg_of(cfg, ncfg, &CfgDev::pair0, p);
+      vv[j] = cfg[c].vl0 + probes[p];
+      rk[j] = atomicAdd(&hist[vv[j]], 1);
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < V; i += 1024) {
+    const int32_t h = hist[i];
+    if (h) hist[i] = atomicAdd(&cursor[i], h);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PER; ++j)
+    if (vv[j] >= 0) bucket[bkt_off[vv[j]] + hist[vv[j]] + rk[j]] = (int32_t)(p0 + tid + 1024 * j);
+}
+
 // One workgroup of 1024 threads: bucket offsets, tile prefix (query tiles of
 // height tq x tv-vector tiles per virtual list), cursor and scan work counter
 // reset.
@@ -2649,21 +2714,31 @@ __global__ void k_seg_len(const int32_t *__restrict__ probes, int64_t Qtot, cons
 // One workgroup: out[0..n] = exclusive prefix of in[0..n).
 __global__ __launch_bounds__(1024) void k_scan_i64(const int64_t *__restrict__ in, int64_t n,
                                                    int64_t *__restrict__ out) {
+  // tiles of 1024 x R values: thread t holds R consecutive values of a tile
+  // (coalesced across the block, every load of a tile in flight at once)
   __shared__ int64_t sh[16];
+  constexpr int R = 8;
   const int tid = threadIdx.x;
-  const int64_t chunk = (n + blockDim.x - 1) / blockDim.x;
-  const int64_t a0 = tid * chunk, a1 = min64(n, a0 + chunk);
-  int64_t s = 0;
-  for (int64_t i = a0; i < a1; ++i) s += in[i];
-  int64_t tot;
-  int64_t e = block_excl_scan<int64_t>(s, sh, &tot);
-  __syncthreads();  // every thread has read ``in`` (which may alias scratch) before writes
-  for (int64_t i = a0; i < a1; ++i) {
-    int64_t v = in[i];
-    out[i] = e;
-    e += v;
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += 1024 * R) {
+    int64_t v[R], s = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = base + (int64_t)tid * R + r;
+      v[r] = i < n ? in[i] : 0;
+      s += v[r];
+    }
+    int64_t tot;
+    int64_t e = carry + block_excl_scan<int64_t>(s, sh, &tot);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = base + (int64_t)tid * R + r;
+      if (i < n) out[i] = e;
+      e += v[r];
+    }
+    carry += tot;
   }
-  if (tid == 0) out[n] = tot;
+  if (tid == 0) out[n] = carry;
 }
 
 __global__ void k_pair_base(const int32_t *__restrict__ probes, int64_t Qtot, const CfgDev *cfg,
@@ -2887,12 +2962,23 @@ static hipError_t bucketing_multi(const SearchBufs &b, int32_t tq, int32_t tv, h
   KernelTimer tmb("bucketing", st);
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks_for(b.V, 256)), dim3(256), 0, st, b.cnt,
                      (int64_t)b.V, 0);
-  hipLaunchKernelGGL(k_count, dim3(blocks_for(b.pairs, 256)), dim3(256), 0, st, b.probes, b.pairs,
-                     b.cfg, b.ncfg, b.cnt);
+  const bool lds = b.V <= BKT_LDS_BINS;
+  const unsigned gl = (unsigned)std::max<int64_t>(1, cdiv(b.pairs, BKT_CHUNK));
+  const size_t hb = (size_t)b.V * sizeof(int32_t);
+  if (lds)
+    hipLaunchKernelGGL(k_count_lds, dim3(gl), dim3(1024), hb, st, b.probes, b.pairs, b.cfg, b.ncfg,
+                       b.V, b.cnt);
+  else
+    hipLaunchKernelGGL(k_count, dim3(blocks_for(b.pairs, 256)), dim3(256), 0, st, b.probes,
+                       b.pairs, b.cfg, b.ncfg, b.cnt);
   hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, st, b.cnt, b.cfg, b.ncfg, b.V, tq, tv,
                      b.bkt_off, b.tile_off, b.cursor, b.work);
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(b.pairs, 256)), dim3(256), 0, st, b.probes,
-                     b.pairs, b.cfg, b.ncfg, b.bkt_off, b.cursor, b.bucket);
+  if (lds)
+    hipLaunchKernelGGL(k_scatter_lds, dim3(gl), dim3(1024), hb, st, b.probes, b.pairs, b.cfg,
+                       b.ncfg, b.V, b.bkt_off, b.cursor, b.bucket);
+  else
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(b.pairs, 256)), dim3(256), 0, st, b.probes,
+                       b.pairs, b.cfg, b.ncfg, b.bkt_off, b.cursor, b.bucket);
   // per-query segment lengths go to pair_base as a temporary, then the scan
   hipLaunchKernelGGL(k_seg_len, dim3(blocks_for(b.Qtot, 256)), dim3(256), 0, st, b.probes, b.Qtot,
                      b.cfg, b.ncfg, b.pair_base);
