@@ -79,6 +79,28 @@ def test_batch_equals_alone_all_shapes(lib, setup):
     batch.free()
 
 
+def test_many_configurations_beyond_lds_histogram(lib, setup):
+    """136 configurations of 64 lists each: more virtual lists (8704) than the
+    bucketing's LDS histogram holds, so it takes its per-pair atomic path;
+    every configuration still equals its search alone, bit for bit."""
+    X, indices, _, _ = setup
+    k = 10
+    rng = np.random.default_rng(9)
+    many = []
+    for _ in range(136):
+        many.append((int(rng.choice([16, 32, 64])), int(rng.choice([32, 64, 128])),
+                     int(rng.choice([2, 4, 8])), int(rng.integers(1, 6))))
+    Q = rng.standard_normal((sum(c[3] for c in many), 128)).astype(np.float32)
+    alone = _alone(indices, many, Q, k)
+    batch = lib.Batch([(indices[c[0]][0], c[3], c[0], c[1], c[2], k) for c in many], ldq=128)
+    dist, ids = batch.run(torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    got = _split(dist.cpu().numpy(), ids.cpu().numpy(), many, k)
+    for (gd, gi), (ad, ai) in zip(got, alone):
+        assert np.array_equal(gi, ai) and np.array_equal(gd, ad)
+    batch.free()
+
+
 def test_graph_replays_equal_eager(lib, setup):
     X, indices, configs, Qall = setup
     k = 10
