@@ -1290,7 +1290,9 @@ __global__ __launch_bounds__(512) void k_select_refine(SelArgs a) { select_body(
 // mechanics). Results equal select_body's.
 __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane);
 
-__global__ __launch_bounds__(256) void k_select_refine_wave(SelArgs a, int64_t nq) {
+// (four waves per SIMD: its steps wait on memory latency, so waves in flight
+// count more than the two registers the limit spills)
+__global__ __launch_bounds__(256, 4) void k_select_refine_wave(SelArgs a, int64_t nq) {
   const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (q >= nq) return;  // whole waves leave; nothing synchronises the block
   wave_select(a, q, threadIdx.x & 63);
@@ -1373,9 +1375,11 @@ __global__ __launch_bounds__(512) void k_select_multi(SelMultiArgs m) {
 // same order of accumulation as select_body) and sorted across lanes by
 // (distance pair, id). Results are identical to k_select_multi's.
 constexpr int WSEL_K = 64;
-// candidates re-measured together by k_select_wave (three keep two waves
-// per SIMD; four need more than 256 registers)
-constexpr int SELW_G = 3;
+// candidates re-measured together by k_select_wave: two, with 1024
+// coordinates per pass, keep the kernel within 128 registers, four waves per
+// SIMD (the selection waits on memory latency, so waves in flight count more
+// than loads per wave)
+constexpr int SELW_G = 2;
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -1538,9 +1542,9 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
 
 // COARSE: the coarse step's selection (m.coarse set), else the scan's; two
 // instantiations, so that the coarse one does not carry the registers of the
-// scan's three-candidate re-measure.
+// scan's two-candidate re-measure.
 template <bool COARSE>
-__global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qtot) {
+__global__ __launch_bounds__(256, 3) void k_select_wave(SelMultiArgs m, int64_t Qtot) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= Qtot) return;  // whole waves leave; nothing below synchronises the block
@@ -1569,8 +1573,8 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
   // 1. the K1 smallest (key, position) composites, sorted over lanes
   const float ADANNS_GLOBAL_AS *sg = (const float ADANNS_GLOBAL_AS *)seg;
   uint64_t best = ~0ull, thr = ~0ull;
-  constexpr int U = COARSE ? 16 : 32;  // loads in flight per lane and batch
-  // batches of 64 U values, the next batch loading while one is merged
+  constexpr int U = 16;  // loads in flight per lane and batch
+  // scan: batches of 64 U values, the next batch loading while one is merged
   // (positions past the segment re-read its last value, so that the loads
   // carry no branches and the merge waits for its own batch only)
   auto load = [&](float (&v)[U], int64_t base) {
@@ -1681,8 +1685,8 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
   // 3. exact re-measurement over the lanes
   float myS = __builtin_inff(), myC = 0.f;
   // vectors: SELW_G candidates at a time, lane l taking coordinates
-  // 4l + 256u + e in that order (as measure1), up to 2048 coordinates per
-  // pass read as 16-byte pieces, so that SELW_G x 8 + 8 loads are in flight
+  // 4l + 256u + e in that order (as measure1), up to 1024 coordinates per
+  // pass read as 16-byte pieces, so that SELW_G x 4 + 4 loads are in flight
   // per lane; the query row's rows are 16-byte aligned and padded to the
   // slab width.
   if (!coarse)
@@ -1698,24 +1702,24 @@ __global__ __launch_bounds__(256) void k_select_wave(SelMultiArgs m, int64_t Qto
     float S[SELW_G], C[SELW_G];
 #pragma unroll
     for (int gi = 0; gi < SELW_G; ++gi) S[gi] = C[gi] = 0.f;
-    for (int d0 = 4 * lane; d0 < d_dot; d0 += 256 * 8) {
-      float4 qv[8], xv[SELW_G][8];
+    for (int d0 = 4 * lane; d0 < d_dot; d0 += 256 * 4) {
+      float4 qv[4], xv[SELW_G][4];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 4; ++u) {
         const int dim = d0 + 256 * u;
         qv[u] = dim < d_dot ? ldg4((const float *)qrow + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
 #pragma unroll
       for (int gi = 0; gi < SELW_G; ++gi)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 4; ++u) {
           const int dim = d0 + 256 * u;
           xv[gi][u] = dim < d_dot
                           ? ldg4((const float *)xp[gi] + (int64_t)(dim / SLAB) * np[gi] * SLAB + dim % SLAB)
                           : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           if (d0 + 256 * u + e < d_dot)
