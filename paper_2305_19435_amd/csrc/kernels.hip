@@ -849,6 +849,75 @@ __device__ __forceinline__ CandLoc locate_packed(const SelArgs &a, bool coarse, 
 // row in LDS, or NULL to read it from global memory. Each lane accumulates
 // its coordinates lane, lane + 64, ... in increasing order; loads are
 // issued in batches so that several are in flight.
+// Exact distance between the quantised query and G quantised stored rows
+// (SEL_QUANT), the rows' loads in flight together: lane l takes 16-byte
+// chunks l, l + 64, ... of each row inside its slabs, QB chunks per row
+// loaded before any is used; each row accumulates its coordinates in the
+// same order as with G = 1, so the results do not depend on G.
+template <int G>
+__device__ __forceinline__ void measure_quant_rows(const SelArgs &a, int64_t q, const CandLoc *L,
+                                                   const uint8_t *qq_lds, int lane, float *S,
+                                                   float *C) {
+  const int d = a.d_dot;
+  const float qs = a.qfmt == 2 ? ldg(a.qQscale + q) : 1.f;
+  const int qeb = a.qfmt == 1 ? 2 : 1;
+  const int per = 16 / qeb;
+  float xs[G];
+  const uint8_t *vb[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    xs[g] = a.qfmt == 2 ? ldg(a.qscale + L[g].row) : 1.f;
+    vb[g] = (const uint8_t *)a.qvec + (L[g].p0 * a.qd_pad + (L[g].row - L[g].p0) * SLAB) * qeb;
+  }
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  constexpr int QB = 4;
+  for (int e00 = lane * per; e00 < d; e00 += 64 * per * QB) {
+    u32x4 w4s[G][QB], q4s[QB];
+#pragma unroll
+    for (int b = 0; b < QB; ++b) {
+      const int e0 = e00 + 64 * per * b;
+      if (e0 < d) {
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          w4s[g][b] = ldg((const u32x4 *)(vb[g] + ((int64_t)(e0 / SLAB) * L[g].npad * SLAB +
+                                                   e0 % SLAB) * qeb));
+        // the query's bytes at the same coordinates (rows are 16-byte aligned)
+        q4s[b] = qq_lds ? *(const u32x4 *)(qq_lds + (int64_t)e0 * qeb)
+                        : ldg((const u32x4 *)((const uint8_t *)a.qQ + (q * a.ldqq + e0) * qeb));
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < QB; ++b) {
+      const int e0 = e00 + 64 * per * b;
+      if (e0 >= d) break;
+      const u32x4 q4 = q4s[b];
+      const uint32_t qds[4] = {q4[0], q4[1], q4[2], q4[3]};
+      const uint32_t msk = qeb == 2 ? 0xffffu : 0xffu;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const u32x4 w4 = w4s[g][b];
+        const uint32_t wds[4] = {w4[0], w4[1], w4[2], w4[3]};
+        for (int u = 0; u < per && e0 + u < d; ++u) {
+          const int sh = ((u * qeb) % 4) * 8;
+          const uint32_t bits = (wds[(u * qeb) / 4] >> sh) & msk;
+          const uint32_t qbits = (qds[(u * qeb) / 4] >> sh) & msk;
+          float qh, ql, xh, xl;
+          if (a.qfmt == 1) {
+            qh = bf16_to_float((uint16_t)qbits);
+            ql = 0.f;
+            xh = bf16_to_float((uint16_t)bits);
+            xl = 0.f;
+          } else {
+            two_prod(qs, e4m3_to_float(qbits), qh, ql);
+            two_prod(xs[g], e4m3_to_float(bits), xh, xl);
+          }
+          acc_sq_diff2(qh, ql - xl, xh, S[g], C[g]);
+        }
+      }
+    }
+  }
+}
+
 template <class QP>
 __device__ __forceinline__ void measure1(const SelArgs &a, int64_t q, const CandLoc &L, QP qrow,
                                          const uint8_t *qq_lds, int lane, float &S, float &C) {
@@ -915,53 +984,8 @@ __device__ __forceinline__ void measure1(const SelArgs &a, int64_t q, const Cand
     const bool cq = a.mode == SEL_COARSE_QUANT;
     const float xs = a.qfmt == 2 ? ldg(a.qscale + L.row) : 1.f;
     const float qs = a.qfmt == 2 ? ldg(a.qQscale + q) : 1.f;
-    const int qeb = a.qfmt == 1 ? 2 : 1;
     if (!cq) {  // 16-byte chunks of the stored row, inside one slab
-      const int per = 16 / qeb;
-      const uint8_t *vb =
-          (const uint8_t *)a.qvec + (L.p0 * a.qd_pad + (L.row - L.p0) * SLAB) * qeb;
-      // QB chunks per lane are loaded before any is used (the same order of
-      // accumulation as one chunk at a time)
-      typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-      constexpr int QB = 4;
-      for (int e00 = lane * per; e00 < d; e00 += 64 * per * QB) {
-        u32x4 w4s[QB], q4s[QB];
-#pragma unroll
-        for (int b = 0; b < QB; ++b) {
-          const int e0 = e00 + 64 * per * b;
-          if (e0 < d) {
-            w4s[b] = ldg((const u32x4 *)(vb + ((int64_t)(e0 / SLAB) * L.npad * SLAB + e0 % SLAB) * qeb));
-            // the query's bytes at the same coordinates (rows are 16-byte aligned)
-            q4s[b] = qq_lds ? *(const u32x4 *)(qq_lds + (int64_t)e0 * qeb)
-                            : ldg((const u32x4 *)((const uint8_t *)a.qQ + (q * a.ldqq + e0) * qeb));
-          }
-        }
-#pragma unroll
-        for (int b = 0; b < QB; ++b) {
-          const int e0 = e00 + 64 * per * b;
-          if (e0 >= d) break;
-          const u32x4 w4 = w4s[b], q4 = q4s[b];
-          const uint32_t wds[4] = {w4[0], w4[1], w4[2], w4[3]};
-          const uint32_t qds[4] = {q4[0], q4[1], q4[2], q4[3]};
-          const uint32_t msk = qeb == 2 ? 0xffffu : 0xffu;
-          for (int u = 0; u < per && e0 + u < d; ++u) {
-            const int sh = ((u * qeb) % 4) * 8;
-            const uint32_t bits = (wds[(u * qeb) / 4] >> sh) & msk;
-            const uint32_t qbits = (qds[(u * qeb) / 4] >> sh) & msk;
-            float qh, ql, xh, xl;
-            if (a.qfmt == 1) {
-              qh = bf16_to_float((uint16_t)qbits);
-              ql = 0.f;
-              xh = bf16_to_float((uint16_t)bits);
-              xl = 0.f;
-            } else {
-              two_prod(qs, e4m3_to_float(qbits), qh, ql);
-              two_prod(xs, e4m3_to_float(bits), xh, xl);
-            }
-            acc_sq_diff2(qh, ql - xl, xh, S, C);
-          }
-        }
-      }
+      measure_quant_rows<1>(a, q, &L, qq_lds, lane, &S, &C);
     } else {
       for (int dim = lane; dim < d; dim += 64) {
         float qh, ql, xh, xl;
@@ -1465,22 +1489,47 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
   // 2. lane j < ncand locates candidate j
   CandLoc mine{INT64_MAX, -1, 0, 0, 0};
   if (lane < ncand) mine = locate(a, coarse, q, seg0, (int64_t)(uint32_t)best);
-  // 3. first exact measure, one candidate at a time over the lanes
+  // 3. first exact measure over the lanes: quantised rows two at a time,
+  // other measures one candidate at a time
   const float ADANNS_GLOBAL_AS *qglob = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
   float myS = __builtin_inff(), myC = 0.f;
-  for (int cc = 0; cc < ncand; ++cc) {
+  auto cand = [&](int cc) {
     CandLoc Lc;
     Lc.id = (int64_t)readlane64((uint64_t)mine.id, cc);
     Lc.gpack = (int64_t)readlane64((uint64_t)mine.gpack, cc);
     Lc.row = (int64_t)readlane64((uint64_t)mine.row, cc);
     Lc.p0 = (int64_t)readlane64((uint64_t)mine.p0, cc);
     Lc.npad = (int64_t)readlane64((uint64_t)mine.npad, cc);
-    float S = 0.f, C = 0.f;
-    measure1(a, q, Lc, qglob, nullptr, lane, S, C);
-    wave_reduce_pair(S, C);
-    if (lane == cc) {
-      myS = S;
-      myC = C;
+    return Lc;
+  };
+  if (a.mode == SEL_QUANT) {
+    for (int cc = 0; cc < ncand; cc += 2) {
+      // an odd last candidate is measured twice, the copy discarded
+      const int c1 = cc + 1 < ncand ? cc + 1 : cc;
+      const CandLoc Lp[2] = {cand(cc), cand(c1)};
+      float S[2] = {0.f, 0.f}, C[2] = {0.f, 0.f};
+      measure_quant_rows<2>(a, q, Lp, nullptr, lane, S, C);
+      wave_reduce_pair(S[0], C[0]);
+      wave_reduce_pair(S[1], C[1]);
+      if (lane == cc) {
+        myS = S[0];
+        myC = C[0];
+      }
+      if (lane == c1 && c1 != cc) {
+        myS = S[1];
+        myC = C[1];
+      }
+    }
+  } else {
+    for (int cc = 0; cc < ncand; ++cc) {
+      const CandLoc Lc = cand(cc);
+      float S = 0.f, C = 0.f;
+      measure1(a, q, Lc, qglob, nullptr, lane, S, C);
+      wave_reduce_pair(S, C);
+      if (lane == cc) {
+        myS = S;
+        myC = C;
+      }
     }
   }
   int64_t myid = mine.id, mygp = mine.gpack;
