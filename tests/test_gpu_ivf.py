@@ -236,3 +236,19 @@ def test_large_offset_shortlist(lib):
         assert rep.ok, rep.problems
     finally:
         index.free()
+
+
+def test_many_queries_equal_their_first_copy(small):
+    """20,000 queries (the small query set repeated): more per-query output
+    segments than one tile of the segment scan (8192) and many work items per
+    list; every copy of a query returns the same bits as the first copy."""
+    w, X, Q, C32, off, ids, index = small
+    n = 20_000
+    Qn = np.concatenate([Q] * (n // len(Q) + 1))[:n]
+    d, g, p = _run(index, Qn, w.d_c, w.d_s, w.nprobe, w.k)
+    base = _run(index, Q, w.d_c, w.d_s, w.nprobe, w.k)
+    for r0 in range(0, n, len(Q)):
+        m = min(len(Q), n - r0)
+        assert np.array_equal(g[r0:r0 + m], base[1][:m]), r0
+        assert np.array_equal(d[r0:r0 + m], base[0][:m]), r0
+        assert np.array_equal(p[r0:r0 + m], base[2][:m]), r0
