@@ -115,8 +115,8 @@ adanns_status dmalloc(adanns_index *ix, void **p, size_t bytes) {
 }
 
 void free_index_memory(adanns_index *ix) {
-  void *ptrs[] = {ix->vec,  ix->rows, ix->poff,      ix->len,
-                  ix->rowid, ix->cent, ix->cent_slab, ix->xmax2};
+  void *ptrs[] = {ix->vec,  ix->rows, ix->poff,      ix->len,      ix->rowid,
+                  ix->cent, ix->cent_slab, ix->xmax2, ix->cmax2};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &qsv : ix->quant) {
@@ -141,7 +141,7 @@ void free_index_memory(adanns_index *ix) {
 adanns_status vector_norm_bound(adanns_index *ix, hipStream_t st) {
   adanns_status s;
   if (!ix->xmax2 && (s = dmalloc(ix, (void **)&ix->xmax2, sizeof(float)))) return s;
-  ADANNS_HIP(launch_row_norm_max(ix, st));
+  ADANNS_HIP(launch_row_norm_max(ix->vec, ix->poff, ix->nlist, ix->d_pad, ix->xmax2, st));
   return ADANNS_OK;
 }
 
@@ -238,6 +238,9 @@ adanns_status build_centroids(adanns_index *ix, const float *centroids, int64_t 
                             hipMemcpyHostToDevice, st));
   ADANNS_HIP(launch_layout(f32mat(ix->cent, ix->d_cb_pad), ix->d_cb, d_src, d_rl, d_poff, ix->nl_pad,
                            ix->d_cb_pad, ix->cent_slab, st));
+  // the largest centroid norm bounds the coarse first pass's rounding error
+  if ((s = dmalloc(ix, (void **)&ix->cmax2, sizeof(float)))) return s;
+  ADANNS_HIP(launch_row_norm_max(ix->cent_slab, d_poff, 1, ix->d_cb_pad, ix->cmax2, st));
   ADANNS_HIP(hipStreamSynchronize(st));
   return ADANNS_OK;
 }

@@ -119,6 +119,7 @@ struct adanns_index {
   float *cent_slab = nullptr;          // centroids as one slab-layout list of nl_pad rows
   float *xmax2 = nullptr;              // [1] largest squared row norm of vec, once vec is
                                        // filled (bounds the first pass's rounding error)
+  float *cmax2 = nullptr;              // [1] largest squared norm of the centroids
   std::map<int32_t, adanns::PqCodec> pq;   // keyed by M
   adanns::QuantStore quant[3];             // indexed by adanns_format (1 bf16, 2 e4m3)
   size_t own_bytes = 0;
@@ -153,6 +154,7 @@ struct CfgDev {
   const float *vec;        // the configuration's index
   const float *rows;       // its row-major copy, or NULL
   const float *xmax2;      // its largest squared row norm, or NULL
+  const float *cmax2;      // its largest squared centroid norm, or NULL
   const int64_t *poff;
   const int32_t *len;
   const int64_t *rowid;
@@ -249,8 +251,10 @@ hipError_t launch_gather_codes(const uint8_t *codes, int32_t M, const int64_t *r
 // Precision form: quantised copies, quantised queries, first passes, selection.
 // Row-major copy of the index's slab layout into rows [rows_pad][d_pad].
 hipError_t launch_slab_to_rows(const adanns_index *ix, float *rows, hipStream_t st);
-// Largest squared row norm of the index's slab layout into ix->xmax2.
-hipError_t launch_row_norm_max(const adanns_index *ix, hipStream_t st);
+// Largest squared row norm of a slab layout of nlists lists (offsets poff)
+// into *out.
+hipError_t launch_row_norm_max(const float *vec, const int64_t *poff, int32_t nlists,
+                               int32_t d_pad, float *out, hipStream_t st);
 hipError_t launch_quantize_store(const adanns_index *ix, int32_t fmt, QuantStore &qs,
                                  hipStream_t st);
 hipError_t launch_quantize_cent_fp8(const adanns_index *ix, const int64_t *poff2, QuantStore &qs,

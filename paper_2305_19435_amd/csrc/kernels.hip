@@ -1678,14 +1678,16 @@ __global__ __launch_bounds__(256, 3) void k_select_wave(SelMultiArgs m, int64_t 
   const float ADANNS_GLOBAL_AS *qrow =
       (const float ADANNS_GLOBAL_AS *)(m.Qs + r * m.ldqs);
 
-  // 1b. vectors: the first-pass value |x|^2 - 2 q.x of a d_s-prefix is off
-  // its exact value by at most B = c (X^2 + 2 |q| X), X the largest row norm
-  // of the index and c = 4 (d_s + 2) 2^-24: four times the classical bound
-  // for a length-d_s dot product and sum of squares in FP32 plus the final
-  // rounding. A candidate whose first-pass value exceeds the k-th smallest by
-  // more than 2B is farther than k others in exact arithmetic, so only the
-  // shortlist's prefix within 2B of the k-th smallest is re-measured.
-  if (!coarse && g.xmax2 != nullptr && ncand > kout) {
+  // 1b. the first-pass value |x|^2 - 2 q.x on a prefix of d coordinates
+  // (d_s for vectors, d_c for centroids) is off its exact value by at most
+  // B = c (X^2 + 2 |q| X), X the largest norm of the index's rows (or
+  // centroids) and c = 4 (d + 2) 2^-24: four times the classical bound for a
+  // length-d dot product and sum of squares in FP32 plus the final rounding.
+  // A candidate whose first-pass value exceeds the k-th smallest by more than
+  // 2B is farther than k others in exact arithmetic, so only the shortlist's
+  // prefix within 2B of the k-th smallest is re-measured.
+  const float *xm = coarse ? g.cmax2 : g.xmax2;
+  if (xm != nullptr && ncand > kout) {
     float qq = 0.f;
     for (int d0 = 4 * lane; d0 < d_dot; d0 += 256) {
       const float4 v = ldg4((const float *)qrow + d0);
@@ -1694,7 +1696,7 @@ __global__ __launch_bounds__(256, 3) void k_select_wave(SelMultiArgs m, int64_t 
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o);
-    const float X2 = ldg(g.xmax2), X = sqrtf(X2), qn = sqrtf(qq);
+    const float X2 = ldg(xm), X = sqrtf(X2), qn = sqrtf(qq);
     const float B = 4.f * (float)(d_dot + 2) * 0x1p-24f * (X2 + 2.f * qn * X);
     const uint32_t kk = (uint32_t)(readlane64(best, kout - 1) >> 32);
     const float vk = __uint_as_float((kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk);
@@ -2894,6 +2896,7 @@ CfgDev make_cfg(const adanns_index *ix, int32_t d_c, int32_t d_s, int32_t nprobe
   c.vec = ix->vec;
   c.rows = ix->rows;
   c.xmax2 = ix->xmax2;
+  c.cmax2 = ix->cmax2;
   c.poff = ix->poff;
   c.len = ix->len;
   c.rowid = ix->rowid;
@@ -3208,11 +3211,12 @@ __global__ __launch_bounds__(256) void k_row_norm_max(const float *__restrict__ 
   }
 }
 
-hipError_t launch_row_norm_max(const adanns_index *ix, hipStream_t st) {
-  hipError_t e = hipMemsetAsync(ix->xmax2, 0, sizeof(float), st);
-  if (e != hipSuccess || ix->nlist == 0) return e;
-  hipLaunchKernelGGL(k_row_norm_max, dim3((unsigned)ix->nlist), dim3(256), 0, st, ix->vec,
-                     ix->poff, ix->d_pad, (uint32_t *)ix->xmax2);
+hipError_t launch_row_norm_max(const float *vec, const int64_t *poff, int32_t nlists,
+                               int32_t d_pad, float *out, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(out, 0, sizeof(float), st);
+  if (e != hipSuccess || nlists == 0) return e;
+  hipLaunchKernelGGL(k_row_norm_max, dim3((unsigned)nlists), dim3(256), 0, st, vec, poff, d_pad,
+                     (uint32_t *)out);
   return hipGetLastError();
 }
 
