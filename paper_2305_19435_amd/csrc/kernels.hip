@@ -1404,6 +1404,9 @@ constexpr int WSEL_K = 64;
 // SIMD (the selection waits on memory latency, so waves in flight count more
 // than loads per wave)
 constexpr int SELW_G = 2;
+// batches of at most this many queries take k_select_wave's WIDE form (two
+// waves per SIMD on every SIMD: the chip is not filled either way)
+constexpr int64_t SELW_WIDE_MAX = 2048;
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -1591,9 +1594,13 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
 
 // COARSE: the coarse step's selection (m.coarse set), else the scan's; two
 // instantiations, so that the coarse one does not carry the registers of the
-// scan's two-candidate re-measure.
-template <bool COARSE>
-__global__ __launch_bounds__(256, 3) void k_select_wave(SelMultiArgs m, int64_t Qtot) {
+// scan's re-measure. WIDE (batches too small to fill the chip, where each
+// query's own latency counts): more loads per wave, three candidates per
+// pass of 2048 coordinates and 32 first-pass values per lane, at two waves
+// per SIMD; otherwise two candidates per pass of 1024 coordinates and 16
+// first-pass values per lane, at four waves per SIMD.
+template <bool COARSE, bool WIDE = false>
+__global__ __launch_bounds__(256, WIDE ? 2 : 3) void k_select_wave(SelMultiArgs m, int64_t Qtot) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= Qtot) return;  // whole waves leave; nothing below synchronises the block
@@ -1622,7 +1629,7 @@ __global__ __launch_bounds__(256, 3) void k_select_wave(SelMultiArgs m, int64_t 
   // 1. the K1 smallest (key, position) composites, sorted over lanes
   const float ADANNS_GLOBAL_AS *sg = (const float ADANNS_GLOBAL_AS *)seg;
   uint64_t best = ~0ull, thr = ~0ull;
-  constexpr int U = 16;  // loads in flight per lane and batch
+  constexpr int U = !COARSE && WIDE ? 32 : 16;  // loads in flight per lane and batch
   // scan: batches of 64 U values, the next batch loading while one is merged
   // (positions past the segment re-read its last value, so that the loads
   // carry no branches and the merge waits for its own batch only)
@@ -1735,51 +1742,51 @@ __global__ __launch_bounds__(256, 3) void k_select_wave(SelMultiArgs m, int64_t 
 
   // 3. exact re-measurement over the lanes
   float myS = __builtin_inff(), myC = 0.f;
-  // vectors: SELW_G candidates at a time, lane l taking coordinates
-  // 4l + 256u + e in that order (as measure1), up to 1024 coordinates per
-  // pass read as 16-byte pieces, so that SELW_G x 4 + 4 loads are in flight
-  // per lane; the query row's rows are 16-byte aligned and padded to the
-  // slab width.
+  // vectors: G candidates at a time, lane l taking coordinates
+  // 4l + 256u + e in that order (as measure1), 256 PP coordinates per pass
+  // read as 16-byte pieces, so that G x PP + PP loads are in flight per lane;
+  // the query row's rows are 16-byte aligned and padded to the slab width.
+  constexpr int G = WIDE ? 3 : SELW_G, PP = WIDE ? 8 : 4;
   if (!coarse)
-  for (int cc = 0; cc < ncand; cc += SELW_G) {
-    const float ADANNS_GLOBAL_AS *xp[SELW_G];
-    int64_t np[SELW_G];
+  for (int cc = 0; cc < ncand; cc += G) {
+    const float ADANNS_GLOBAL_AS *xp[G];
+    int64_t np[G];
 #pragma unroll
-    for (int gi = 0; gi < SELW_G; ++gi) {
+    for (int gi = 0; gi < G; ++gi) {
       const int c = cc + gi < ncand ? cc + gi : ncand - 1;
       xp[gi] = (const float ADANNS_GLOBAL_AS *)readlane64((uint64_t)my_base, c);
       np[gi] = (int64_t)readlane64((uint64_t)my_npad, c);
     }
-    float S[SELW_G], C[SELW_G];
+    float S[G], C[G];
 #pragma unroll
-    for (int gi = 0; gi < SELW_G; ++gi) S[gi] = C[gi] = 0.f;
-    for (int d0 = 4 * lane; d0 < d_dot; d0 += 256 * 4) {
-      float4 qv[4], xv[SELW_G][4];
+    for (int gi = 0; gi < G; ++gi) S[gi] = C[gi] = 0.f;
+    for (int d0 = 4 * lane; d0 < d_dot; d0 += 256 * PP) {
+      float4 qv[PP], xv[G][PP];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < PP; ++u) {
         const int dim = d0 + 256 * u;
         qv[u] = dim < d_dot ? ldg4((const float *)qrow + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
 #pragma unroll
-      for (int gi = 0; gi < SELW_G; ++gi)
+      for (int gi = 0; gi < G; ++gi)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < PP; ++u) {
           const int dim = d0 + 256 * u;
           xv[gi][u] = dim < d_dot
                           ? ldg4((const float *)xp[gi] + (int64_t)(dim / SLAB) * np[gi] * SLAB + dim % SLAB)
                           : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < PP; ++u)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           if (d0 + 256 * u + e < d_dot)
 #pragma unroll
-            for (int gi = 0; gi < SELW_G; ++gi)
+            for (int gi = 0; gi < G; ++gi)
               acc_sq_diff(f4(qv[u], e), f4(xv[gi][u], e), S[gi], C[gi]);
     }
 #pragma unroll
-    for (int gi = 0; gi < SELW_G; ++gi) {
+    for (int gi = 0; gi < G; ++gi) {
       wave_reduce_pair(S[gi], C[gi]);
       if (cc + gi < ncand && lane == cc + gi) {
         myS = S[gi];
@@ -3145,7 +3152,10 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
   m.lcap = seg_cap(m.kcap, SEG_LDS_CAP);
   {
     KernelTimer tm("select_scan", st);
-    if (b.max_k + REFINE_MARGIN <= WSEL_K)
+    if (b.max_k + REFINE_MARGIN <= WSEL_K && b.Qtot <= SELW_WIDE_MAX)
+      hipLaunchKernelGGL((k_select_wave<false, true>), dim3((unsigned)cdiv(b.Qtot, 4)), dim3(256),
+                         0, st, m, b.Qtot);
+    else if (b.max_k + REFINE_MARGIN <= WSEL_K)
       hipLaunchKernelGGL(k_select_wave<false>, dim3((unsigned)cdiv(b.Qtot, 4)), dim3(256), 0, st, m,
                          b.Qtot);
     else
