@@ -1404,8 +1404,9 @@ constexpr int WSEL_K = 64;
 // SIMD (the selection waits on memory latency, so waves in flight count more
 // than loads per wave)
 constexpr int SELW_G = 2;
-// batches of at most this many queries take k_select_wave's WIDE form (two
-// waves per SIMD on every SIMD: the chip is not filled either way)
+// batches of at most this many queries take k_select_wave's WIDE form: one
+// wave per query puts at most two waves on each of the 1024 SIMDs, which the
+// WIDE form holds, so the four-wave form would gain nothing there
 constexpr int64_t SELW_WIDE_MAX = 2048;
 
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
