@@ -120,7 +120,7 @@ void free_index_memory(adanns_index *ix) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &qsv : ix->quant) {
-    void *pp[] = {qsv.vec, qsv.scale, qsv.cent, qsv.cent_scale};
+    void *pp[] = {qsv.vec, qsv.scale, qsv.cent, qsv.cent_scale, qsv.emax};
     for (void *p : pp)
       if (p) (void)hipFree(p);
     qsv = QuantStore{};
@@ -909,7 +909,7 @@ adanns_status adanns_set_precision(adanns_index *ix, int32_t fmt, void *stream) 
   QuantStore q;
   const size_t eb = fmt == ADANNS_BF16 ? 2 : 1;
   auto fail = [&](adanns_status e) {
-    void *pp[] = {q.vec, q.scale, q.cent, q.cent_scale};
+    void *pp[] = {q.vec, q.scale, q.cent, q.cent_scale, q.emax};
     for (void *p : pp)
       if (p) (void)hipFree(p);
     return e;
@@ -921,7 +921,8 @@ adanns_status adanns_set_precision(adanns_index *ix, int32_t fmt, void *stream) 
     if ((s = dmalloc(ix, (void **)&q.cent_scale, (size_t)ix->nl_pad * sizeof(float))))
       return fail(s);
   }
-  if (launch_quantize_store(ix, fmt, q, st)) {
+  if ((s = dmalloc(ix, (void **)&q.emax, sizeof(float)))) return fail(s);
+  if (launch_quantize_store(ix, fmt, q, st) || launch_quant_err_max(ix, fmt, q, st)) {
     set_error("HIP error while quantising the vectors");
     return fail(ADANNS_EHIP);
   }

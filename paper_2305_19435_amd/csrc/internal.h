@@ -95,6 +95,7 @@ struct QuantStore {
   float *scale = nullptr;       // [rows_pad] (e4m3 only)
   void *cent = nullptr;         // one-list slab layout of nl_pad rows
   float *cent_scale = nullptr;  // [nl_pad] (e4m3 only)
+  float *emax = nullptr;        // [1] largest |x - dequantised x| over the rows
 };
 }  // namespace adanns
 
@@ -251,6 +252,10 @@ hipError_t launch_gather_codes(const uint8_t *codes, int32_t M, const int64_t *r
 // Precision form: quantised copies, quantised queries, first passes, selection.
 // Row-major copy of the index's slab layout into rows [rows_pad][d_pad].
 hipError_t launch_slab_to_rows(const adanns_index *ix, float *rows, hipStream_t st);
+// Largest |x - dequantised x| over the rows of the index's quantised copy
+// (fmt 1 bf16, 2 e4m3) into qs.emax.
+hipError_t launch_quant_err_max(const adanns_index *ix, int32_t fmt, const QuantStore &qs,
+                                hipStream_t st);
 // Largest squared row norm of a slab layout of nlists lists (offsets poff)
 // into *out.
 hipError_t launch_row_norm_max(const float *vec, const int64_t *poff, int32_t nlists,

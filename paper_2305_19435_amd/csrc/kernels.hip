@@ -702,6 +702,7 @@ struct SelArgs {
   const void *qQ;          // quantised queries [nq][ldqq]
   const float *qQscale;    // per query (fp8)
   int64_t ldqq;
+  const float *qemax;      // largest |x - dequantised x| of the stored rows, or NULL
   int64_t qnpad;           // coarse-quant: rows of the one-list layout
   float *out_dist;
   int64_t *out_ids;
@@ -1542,6 +1543,28 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
   if (a.stageB) {
     // second exact measure (FP32 L2 on d_B coordinates) of the K2 best
     nres = ncand < a.K2 ? ncand : a.K2;
+    // Quantised rows: |‖q - x‖ - ‖q^ - x^‖| <= ‖q - q^‖ + ‖x - x^‖ <= e,
+    // e = ‖q - q^‖ + (largest ‖x - x^‖ of the rows). A candidate whose
+    // quantised distance lies beyond (sqrt(D^_k) + 2e)^2 is farther than k
+    // others in FP32, so only the prefix within it is re-measured.
+    if (a.mode == SEL_QUANT && a.qemax != nullptr && nres > a.kout) {
+      float eq = 0.f;
+      for (int dim = lane; dim < a.d_B; dim += 64) {
+        const int64_t qi = q * a.ldqq + dim;
+        const float qh = a.qfmt == 1 ? bf16_to_float(ldg((const uint16_t *)a.qQ + qi))
+                                     : ldg(a.qQscale + q) * e4m3_to_float(ldg((const uint8_t *)a.qQ + qi));
+        const float df = qglob[dim] - qh;
+        eq = fmaf(df, df, eq);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) eq += __shfl_xor(eq, o);
+      // a margin of 1e-3 relative covers the FP32 rounding of these bounds
+      const float e = (sqrtf(eq) + ldg(a.qemax)) * 1.001f;
+      const float sk = __shfl(myS, a.kout - 1);
+      const float up = sqrtf(fmaxf(sk, 0.f)) + 2.f * e;
+      const bool keep = lane < nres && sqrtf(fmaxf(myS, 0.f)) <= up * 1.001f;
+      nres = __popcll(__ballot(keep));
+    }
     if (lane >= nres) {
       myS = __builtin_inff();
       myC = 0.f;
@@ -3256,6 +3279,50 @@ hipError_t launch_quantize_cent_fp8(const adanns_index *ix, const int64_t *poff2
   return hipGetLastError();
 }
 
+// Largest |x - dequantised x| over the rows of the quantised slab layout
+// (as k_row_norm_max: block h covers list h, a half-wave per row). The
+// dequantised value is the bf16 value, or scale x e4m3 value.
+__global__ __launch_bounds__(256) void k_quant_err_max(const float *__restrict__ vec,
+                                                       const void *__restrict__ qvec,
+                                                       const float *__restrict__ qscale,
+                                                       int32_t fmt, const int64_t *__restrict__ poff,
+                                                       int32_t d_pad, uint32_t *__restrict__ out) {
+  __shared__ float sh[8];
+  const int h = blockIdx.x, half = threadIdx.x >> 5, l = threadIdx.x & 31;
+  const int64_t p0 = poff[h], np = poff[h + 1] - p0;
+  const int nslab = d_pad / SLAB;
+  float best = 0.f;
+  for (int64_t r = half; r < np; r += 8) {
+    const float xs = fmt == 2 ? qscale[p0 + r] : 1.f;
+    float s = 0.f;
+    for (int k = 0; k < nslab; ++k) {
+      const int64_t i = p0 * d_pad + ((int64_t)k * np + r) * SLAB + l;
+      const float xq = fmt == 1 ? bf16_to_float(((const uint16_t *)qvec)[i])
+                                : xs * e4m3_to_float(((const uint8_t *)qvec)[i]);
+      const float df = vec[i] - xq;
+      s = fmaf(df, df, s);
+    }
+    for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
+    best = fmaxf(best, sqrtf(s));
+  }
+  if (l == 0) sh[half] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = sh[0];
+    for (int i = 1; i < 8; ++i) m = fmaxf(m, sh[i]);
+    atomicMax(out, __float_as_uint(m));
+  }
+}
+
+hipError_t launch_quant_err_max(const adanns_index *ix, int32_t fmt, const QuantStore &qs,
+                                hipStream_t st) {
+  hipError_t e = hipMemsetAsync(qs.emax, 0, sizeof(float), st);
+  if (e != hipSuccess || ix->nlist == 0) return e;
+  hipLaunchKernelGGL(k_quant_err_max, dim3((unsigned)ix->nlist), dim3(256), 0, st, ix->vec,
+                     qs.vec, qs.scale, fmt, ix->poff, ix->d_pad, (uint32_t *)qs.emax);
+  return hipGetLastError();
+}
+
 hipError_t launch_quantize_queries(const float *Q, int64_t nq, int64_t ldq, int32_t d,
                                    int32_t fmt, void *Qq, int64_t ldqq, float *qscale,
                                    hipStream_t st) {
@@ -3388,6 +3455,8 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   r.qQ = Qq;
   r.qQscale = qscale;
   r.ldqq = ldqq;
+  // (e4m3's quantisation error spans the whole shortlist: no bound)
+  r.qemax = fmt == 1 ? qs.emax : nullptr;
   r.out_dist = dist;
   r.out_ids = ids;
   {
