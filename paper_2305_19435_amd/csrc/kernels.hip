@@ -703,6 +703,9 @@ struct SelArgs {
   const float *qQscale;    // per query (fp8)
   int64_t ldqq;
   const float *qemax;      // largest |x - dequantised x| of the stored rows, or NULL
+                           // (enables the FP32 re-rank's quantisation bound)
+  const float *qerr;       // the same, for the first pass's rounding bound, or NULL
+  const float *xmax2;      // largest squared FP32 row norm (with qerr), or NULL
   int64_t qnpad;           // coarse-quant: rows of the one-list layout
   float *out_dist;
   int64_t *out_ids;
@@ -1490,13 +1493,49 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
       }
     }
   }
-  const int ncand = (int)min64(L, (int64_t)K1);
+  int ncand = (int)min64(L, (int64_t)K1);
+  const float ADANNS_GLOBAL_AS *qglob = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
+  // 1b. quantised scan (precision form): the first pass |x^|^2 - 2 q^.x^ of
+  // the dequantised operands on d coordinates is off by at most
+  // B = 4 (d + 2) 2^-24 (X^2 + 2 |q^| X), X >= every |x^| (the largest FP32
+  // row norm plus the largest |x - x^|), as on the FP32 path; only the
+  // shortlist's prefix within 2B of the K2-th smallest can hold the K2
+  // nearest by exact quantised distance, so only it is measured. |q - q^|
+  // is kept for the re-rank's bound below.
+  float eqn = -1.f;
+  if (a.mode == SEL_QUANT && a.qerr != nullptr && a.xmax2 != nullptr) {
+    float qq = 0.f, ee = 0.f;
+    for (int dim = lane; dim < a.d_dot; dim += 64) {
+      const int64_t qi = q * a.ldqq + dim;
+      const float qh = a.qfmt == 1 ? bf16_to_float(ldg((const uint16_t *)a.qQ + qi))
+                                   : ldg(a.qQscale + q) * e4m3_to_float(ldg((const uint8_t *)a.qQ + qi));
+      const float df = qglob[dim] - qh;
+      qq = fmaf(qh, qh, qq);
+      ee = fmaf(df, df, ee);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      qq += __shfl_xor(qq, o);
+      ee += __shfl_xor(ee, o);
+    }
+    eqn = sqrtf(ee);
+    if (ncand > a.K2) {
+      const float X = (sqrtf(ldg(a.xmax2)) + ldg(a.qerr)) * 1.001f, qn = sqrtf(qq) * 1.001f;
+      const float B = 4.f * (float)(a.d_dot + 2) * 0x1p-24f * (X * X + 2.f * qn * X);
+      const uint32_t kk = (uint32_t)(readlane64(best, a.K2 - 1) >> 32);
+      const float vk = __uint_as_float((kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk);
+      const float T = vk + 2.f * B;
+      if (T <= __FLT_MAX__) {
+        const uint64_t tcomp = ((uint64_t)order_key(T) << 32) | 0xFFFFFFFFull;
+        ncand = __popcll(__ballot(lane < ncand && best <= tcomp));
+      }
+    }
+  }
   // 2. lane j < ncand locates candidate j
   CandLoc mine{INT64_MAX, -1, 0, 0, 0};
   if (lane < ncand) mine = locate(a, coarse, q, seg0, (int64_t)(uint32_t)best);
   // 3. first exact measure over the lanes: quantised rows two at a time,
   // other measures one candidate at a time
-  const float ADANNS_GLOBAL_AS *qglob = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
   float myS = __builtin_inff(), myC = 0.f;
   auto cand = [&](int cc) {
     CandLoc Lc;
@@ -1548,18 +1587,21 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
     // quantised distance lies beyond (sqrt(D^_k) + 2e)^2 is farther than k
     // others in FP32, so only the prefix within it is re-measured.
     if (a.mode == SEL_QUANT && a.qemax != nullptr && nres > a.kout) {
-      float eq = 0.f;
-      for (int dim = lane; dim < a.d_B; dim += 64) {
-        const int64_t qi = q * a.ldqq + dim;
-        const float qh = a.qfmt == 1 ? bf16_to_float(ldg((const uint16_t *)a.qQ + qi))
-                                     : ldg(a.qQscale + q) * e4m3_to_float(ldg((const uint8_t *)a.qQ + qi));
-        const float df = qglob[dim] - qh;
-        eq = fmaf(df, df, eq);
-      }
+      if (eqn < 0.f || a.d_B != a.d_dot) {
+        float eq = 0.f;
+        for (int dim = lane; dim < a.d_B; dim += 64) {
+          const int64_t qi = q * a.ldqq + dim;
+          const float qh = a.qfmt == 1 ? bf16_to_float(ldg((const uint16_t *)a.qQ + qi))
+                                       : ldg(a.qQscale + q) * e4m3_to_float(ldg((const uint8_t *)a.qQ + qi));
+          const float df = qglob[dim] - qh;
+          eq = fmaf(df, df, eq);
+        }
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) eq += __shfl_xor(eq, o);
+        for (int o = 32; o > 0; o >>= 1) eq += __shfl_xor(eq, o);
+        eqn = sqrtf(eq);
+      }
       // a margin of 1e-3 relative covers the FP32 rounding of these bounds
-      const float e = (sqrtf(eq) + ldg(a.qemax)) * 1.001f;
+      const float e = (eqn + ldg(a.qemax)) * 1.001f;
       const float sk = __shfl(myS, a.kout - 1);
       const float up = sqrtf(fmaxf(sk, 0.f)) + 2.f * e;
       const bool keep = lane < nres && sqrtf(fmaxf(myS, 0.f)) <= up * 1.001f;
@@ -3457,6 +3499,8 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   r.ldqq = ldqq;
   // (e4m3's quantisation error spans the whole shortlist: no bound)
   r.qemax = fmt == 1 ? qs.emax : nullptr;
+  r.qerr = qs.emax;
+  r.xmax2 = ix->xmax2;
   r.out_dist = dist;
   r.out_ids = ids;
   {
