@@ -120,7 +120,7 @@ void free_index_memory(adanns_index *ix) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &qsv : ix->quant) {
-    void *pp[] = {qsv.vec, qsv.scale, qsv.cent, qsv.cent_scale, qsv.emax};
+    void *pp[] = {qsv.vec, qsv.scale, qsv.cent, qsv.cent_scale, qsv.emax, qsv.cent_emax};
     for (void *p : pp)
       if (p) (void)hipFree(p);
     qsv = QuantStore{};
@@ -909,7 +909,7 @@ adanns_status adanns_set_precision(adanns_index *ix, int32_t fmt, void *stream) 
   QuantStore q;
   const size_t eb = fmt == ADANNS_BF16 ? 2 : 1;
   auto fail = [&](adanns_status e) {
-    void *pp[] = {q.vec, q.scale, q.cent, q.cent_scale, q.emax};
+    void *pp[] = {q.vec, q.scale, q.cent, q.cent_scale, q.emax, q.cent_emax};
     for (void *p : pp)
       if (p) (void)hipFree(p);
     return e;
@@ -921,17 +921,22 @@ adanns_status adanns_set_precision(adanns_index *ix, int32_t fmt, void *stream) 
     if ((s = dmalloc(ix, (void **)&q.cent_scale, (size_t)ix->nl_pad * sizeof(float))))
       return fail(s);
   }
-  if ((s = dmalloc(ix, (void **)&q.emax, sizeof(float)))) return fail(s);
+  if ((s = dmalloc(ix, (void **)&q.emax, sizeof(float))) ||
+      (s = dmalloc(ix, (void **)&q.cent_emax, sizeof(float))))
+    return fail(s);
   if (launch_quantize_store(ix, fmt, q, st) || launch_quant_err_max(ix, fmt, q, st)) {
     set_error("HIP error while quantising the vectors");
     return fail(ADANNS_EHIP);
   }
-  if (fmt == ADANNS_FP8_E4M3) {
+  {
+    // the centroids as one list: e4m3 copies (the BF16 copy is made with the
+    // vectors), then the largest quantisation error
     int64_t *d_poff2 = nullptr;
     const int64_t h_poff2[2] = {0, ix->nl_pad};
     if (hipMalloc(&d_poff2, 2 * sizeof(int64_t)) ||
         hipMemcpyAsync(d_poff2, h_poff2, 2 * sizeof(int64_t), hipMemcpyHostToDevice, st) ||
-        launch_quantize_cent_fp8(ix, d_poff2, q, st) || hipStreamSynchronize(st)) {
+        (fmt == ADANNS_FP8_E4M3 && launch_quantize_cent_fp8(ix, d_poff2, q, st)) ||
+        launch_quant_err_max_cent(ix, fmt, d_poff2, q, st) || hipStreamSynchronize(st)) {
       if (d_poff2) (void)hipFree(d_poff2);
       set_error("HIP error while quantising the centroids");
       return fail(ADANNS_EHIP);

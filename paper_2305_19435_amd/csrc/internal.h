@@ -96,6 +96,7 @@ struct QuantStore {
   void *cent = nullptr;         // one-list slab layout of nl_pad rows
   float *cent_scale = nullptr;  // [nl_pad] (e4m3 only)
   float *emax = nullptr;        // [1] largest |x - dequantised x| over the rows
+  float *cent_emax = nullptr;   // [1] the same over the centroids
 };
 }  // namespace adanns
 
@@ -256,6 +257,10 @@ hipError_t launch_slab_to_rows(const adanns_index *ix, float *rows, hipStream_t 
 // (fmt 1 bf16, 2 e4m3) into qs.emax.
 hipError_t launch_quant_err_max(const adanns_index *ix, int32_t fmt, const QuantStore &qs,
                                 hipStream_t st);
+// The same over the quantised centroids (one-list layout, offsets poff2) into
+// qs.cent_emax.
+hipError_t launch_quant_err_max_cent(const adanns_index *ix, int32_t fmt, const int64_t *poff2,
+                                     const QuantStore &qs, hipStream_t st);
 // Largest squared row norm of a slab layout of nlists lists (offsets poff)
 // into *out.
 hipError_t launch_row_norm_max(const float *vec, const int64_t *poff, int32_t nlists,

@@ -1503,7 +1503,8 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
   // nearest by exact quantised distance, so only it is measured. |q - q^|
   // is kept for the re-rank's bound below.
   float eqn = -1.f;
-  if (a.mode == SEL_QUANT && a.qerr != nullptr && a.xmax2 != nullptr) {
+  const bool quant = a.mode == SEL_QUANT || a.mode == SEL_COARSE_QUANT;
+  if (quant && a.qerr != nullptr && a.xmax2 != nullptr) {
     float qq = 0.f, ee = 0.f;
     for (int dim = lane; dim < a.d_dot; dim += 64) {
       const int64_t qi = q * a.ldqq + dim;
@@ -1586,7 +1587,7 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
     // e = ‖q - q^‖ + (largest ‖x - x^‖ of the rows). A candidate whose
     // quantised distance lies beyond (sqrt(D^_k) + 2e)^2 is farther than k
     // others in FP32, so only the prefix within it is re-measured.
-    if (a.mode == SEL_QUANT && a.qemax != nullptr && nres > a.kout) {
+    if (quant && a.qemax != nullptr && nres > a.kout) {
       if (eqn < 0.f || a.d_B != a.d_dot) {
         float eq = 0.f;
         for (int dim = lane; dim < a.d_B; dim += 64) {
@@ -3365,6 +3366,15 @@ hipError_t launch_quant_err_max(const adanns_index *ix, int32_t fmt, const Quant
   return hipGetLastError();
 }
 
+hipError_t launch_quant_err_max_cent(const adanns_index *ix, int32_t fmt, const int64_t *poff2,
+                                     const QuantStore &qs, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(qs.cent_emax, 0, sizeof(float), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_quant_err_max, dim3(1), dim3(256), 0, st, ix->cent_slab, qs.cent,
+                     qs.cent_scale, fmt, poff2, ix->d_cb_pad, (uint32_t *)qs.cent_emax);
+  return hipGetLastError();
+}
+
 hipError_t launch_quantize_queries(const float *Q, int64_t nq, int64_t ldq, int32_t d,
                                    int32_t fmt, void *Qq, int64_t ldqq, float *qscale,
                                    hipStream_t st) {
@@ -3430,6 +3440,9 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   s.qQscale = qscale;
   s.ldqq = ldqq;
   s.qnpad = ix->nl_pad;
+  s.qemax = fmt == 1 ? qs.cent_emax : nullptr;
+  s.qerr = qs.cent_emax;
+  s.xmax2 = ix->cmax2;
   s.out_probes = b.probes;
   s.out_probes2 = user_probes;
   {
