@@ -1270,6 +1270,40 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
   if (a.stageB) {
     // second exact measure (FP32 L2 on d_B coordinates) of the K2 best
     nres = ncand < a.K2 ? ncand : a.K2;
+    // quantised rows: as in wave_select, only the prefix within
+    // (sqrt(D^_k) + 2e)^2, e = |q - q^| + the largest |x - x^|, is re-measured
+    if ((a.mode == SEL_QUANT || a.mode == SEL_COARSE_QUANT) && a.qemax != nullptr &&
+        nres > a.kout) {
+      __shared__ float s_eq[16];
+      __shared__ int s_nres;
+      float eq = 0.f;
+      for (int dim = tid; dim < a.d_B; dim += blockDim.x) {
+        const int64_t qi = q * a.ldqq + dim;
+        const float qh = a.qfmt == 1 ? bf16_to_float(ldg((const uint16_t *)a.qQ + qi))
+                                     : ldg(a.qQscale + q) * e4m3_to_float(ldg((const uint8_t *)a.qQ + qi));
+        const float df = ldg(a.Qs + q * a.ldqs + dim) - qh;
+        eq = fmaf(df, df, eq);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) eq += __shfl_xor(eq, o);
+      if (lane == 0) s_eq[wv] = eq;
+      __syncthreads();
+      if (tid == 0) {
+        float t = 0.f;
+        for (int w = 0; w < nwv; ++w) t += s_eq[w];
+        // a margin of 1e-3 relative covers the FP32 rounding of these bounds
+        const float e = (sqrtf(t) + ldg(a.qemax)) * 1.001f;
+        const float up = (sqrtf(fmaxf(chi[a.kout - 1], 0.f)) + 2.f * e) * 1.001f;
+        int lo = a.kout, hi = nres;  // the first position past the bound
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (sqrtf(fmaxf(chi[mid], 0.f)) <= up) lo = mid + 1; else hi = mid;
+        }
+        s_nres = lo;
+      }
+      __syncthreads();
+      nres = s_nres;
+    }
     auto run2 = [&](auto qrow) {
       for (int c = wv; c < nres; c += nwv) {
         float S = 0.f, C = 0.f;
