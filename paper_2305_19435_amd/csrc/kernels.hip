@@ -1566,6 +1566,38 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
       }
     }
   }
+  // 1c. IVF-PQ: the first pass sums M table entries, each the FP32 sum over
+  // dsub coordinates of (q'_hi - c)^2. Against the exact asymmetric distance
+  // (rotated query q'_hi + q'_lo) it is off by at most
+  // B(f) = 4 (dsub + M + 4) 2^-24 f + 4 2^-24 |q'| (2 sqrt(f) + 2^-24 |q'|):
+  // four times the classical bounds for the entries and their sum, plus the
+  // dropped q'_lo (|q'_lo| <= 2^-24 |q'_hi|). B(f) and f - B(f) increase
+  // with f, so the candidates whose lower bound exceeds the upper bound of
+  // the nsel-th value form a suffix of the shortlist and are not measured.
+  if (a.mode == SEL_ADC) {
+    const int nsel = a.stageB ? a.K2 : a.kout;
+    if (ncand > nsel) {
+      const float ADANNS_GLOBAL_AS *qh = (const float ADANNS_GLOBAL_AS *)(a.qr_hi + q * a.ldqr);
+      float qq = 0.f;
+      for (int dim = lane; dim < a.d_dot; dim += 64) qq = fmaf(qh[dim], qh[dim], qq);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o);
+      const float qn = sqrtf(qq) * 1.001f;
+      const float c1 = 4.f * (float)(a.dsub + a.M + 4) * 0x1p-24f, c2 = 4.f * 0x1p-24f * qn;
+      auto bound = [&](float f) {
+        f = fmaxf(f, 0.f);
+        return c1 * f + c2 * (2.f * sqrtf(f) + 0x1p-24f * qn);
+      };
+      auto kval = [](uint64_t comp) {
+        const uint32_t kk = (uint32_t)(comp >> 32);
+        return __uint_as_float((kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk);
+      };
+      const float vk = kval(readlane64(best, nsel - 1));
+      const float up = vk + bound(vk);
+      const float fi = kval(best);
+      if (up <= __FLT_MAX__) ncand = __popcll(__ballot(lane < ncand && fi - bound(fi) <= up));
+    }
+  }
   // 2. lane j < ncand locates candidate j
   CandLoc mine{INT64_MAX, -1, 0, 0, 0};
   if (lane < ncand) mine = locate(a, coarse, q, seg0, (int64_t)(uint32_t)best);
