@@ -15,7 +15,8 @@
   scored against the ranking at the highest d.
 
 Pins: tests/test_oracle_metrics.py (hand-built overlaps, the cost optimum at
-sqrt(nprobe * d_s * N / d_c), C_r of a hand-built set).
+sqrt(nprobe * d_s * N / d_c), C_r of a hand-built set, centroid recall of a
+hand-built layout for k < N and k = N).
 """
 from __future__ import annotations
 

@@ -26,7 +26,9 @@ Pins (tests/test_oracle_pq.py): the table decomposition equals the distance
 to the decoded vector; with at most 256 training rows and init on all rows
 the codebooks reproduce the data and ADC equals exact search; R^T R = I;
 distances are invariant under R; OPQ distortion never increases across
-alternations.
+alternations; with a random orthonormal R and every row its own codeword in
+the rotated space, IVF-OPQ over one list equals exact search (rotation
+invariance), while the same codes searched with R^T do not.
 """
 from __future__ import annotations
 

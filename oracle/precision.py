@@ -27,7 +27,10 @@ Pins (tests/test_oracle_precision.py): every e4m3 byte decodes to the value
 the definition gives and re-encodes to itself; values exactly representable
 pass through unchanged; rounding picks the nearest neighbour with ties to the
 even code; BF16 agrees with a pure-Python bit rounding; with the shortlist as
-long as the candidate list, the form reduces exactly to IVF search.
+long as the candidate list, the form reduces exactly to IVF search; on a
+hand-built four-centroid layout whose BF16 / e4m3 rounding swaps the two
+nearest centroids, the coarse step's probes for nprobe 1..3 and margins 0
+and 1 are the ones worked out by hand from the definition.
 """
 from __future__ import annotations
 

@@ -79,3 +79,19 @@ def test_probe_validity_band():
     assert check.probes_valid(c, [0, 2], 2)        # inside the tie band
     assert not check.probes_valid(c, [0, 3], 2)
     assert not check.probes_valid(c, [1, 2], 2)    # left out a strictly nearer one
+
+
+def test_centroid_recall_hand_built():
+    """k-Recall@N of centroids ranked on a one-coordinate prefix against the
+    full width (Appendix E.2), distances worked out by hand."""
+    C = np.array([[0.1, 5.0], [1.0, 0.0], [2.0, 0.0], [-3.0, 0.0]])
+    # q = (0, 0): full 25.01, 1, 4, 9 -> order 1, 2, 3, 0; prefix 0.01, 1, 4, 9 -> 0, 1, 2, 3
+    q0 = np.array([[0.0, 0.0]])
+    assert metrics.centroid_recall(q0, C, 1, 1, 1) == 0.0
+    assert metrics.centroid_recall(q0, C, 1, 1, 2) == 1.0
+    assert metrics.centroid_recall(q0, C, 1, 2, 2) == 0.5
+    assert metrics.centroid_recall(q0, C, 1, 2, 3) == 1.0
+    # q = (3, 0): full 33.41, 4, 1, 36 -> 2, 1, 0, 3; prefix 8.41, 4, 1, 36 -> 2, 1, 0, 3
+    Q = np.array([[0.0, 0.0], [3.0, 0.0]])
+    assert metrics.centroid_recall(Q, C, 1, 2, 2) == (1 + 2) / 4
+    assert metrics.centroid_recall(Q, C, 2, 2, 2) == 1.0

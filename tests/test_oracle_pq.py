@@ -78,3 +78,32 @@ def test_ivfpq_rerank_full_is_ivf(small_data):
     D2, I2, P2 = ivf.ivf_search64(X, Q[:20], C, off, ids, w.d_c, w.d_s, w.nprobe, w.k)
     assert np.array_equal(P, P2) and np.array_equal(I, I2)
     np.testing.assert_allclose(D, D2, rtol=1e-13)
+
+
+def test_rotated_adc_is_exact_under_rotation_invariance():
+    """Every row its own codeword in the rotated space: the decoded rotated
+    rows equal X R, and |q R - x R| = |q - x| for orthonormal R (Section 3,
+    OPQ; Appendix D), so IVF-OPQ over one list equals exact search. The same
+    codes searched with R^T (a transposed rotation of the query) do not."""
+    d, M, n = 16, 4, 256
+    m = synth.Mixture(d, 7, seed=23)
+    X = m.database(n).astype(np.float64)
+    Q = m.queries(12).astype(np.float64)
+    # the float32 draw re-orthonormalised in float64 (QR, signs fixed)
+    R, r = np.linalg.qr(synth.random_rotation(d, seed=23).astype(np.float64))
+    R = R * np.sign(np.diag(r))[None, :]
+    np.testing.assert_allclose(R.T @ R, np.eye(d), atol=1e-13)
+    assert not np.allclose(R, R.T)
+    Y = X @ R
+    cbs = pq.pq_train64(Y, M, 2, init_rows=np.arange(n))
+    codes = pq.pq_encode64(Y, cbs)
+    np.testing.assert_allclose(pq.pq_decode64(codes, cbs), Y, rtol=0, atol=1e-12)
+    off = np.array([0, n])
+    ids = np.arange(n)
+    D, I, _ = pq.ivfpq_search64(Q, np.zeros((1, d)), off, ids, codes, R, cbs, 4, 1, 10)
+    De, Ie = exact.exact_knn64(X, Q, 10)
+    assert np.array_equal(I, Ie)
+    np.testing.assert_allclose(D, De, rtol=1e-10, atol=1e-12)
+    # a query rotated by R^T instead of R misses neighbours
+    Dt, It, _ = pq.ivfpq_search64(Q, np.zeros((1, d)), off, ids, codes, R.T.copy(), cbs, 4, 1, 10)
+    assert not np.array_equal(It, Ie)

@@ -93,3 +93,43 @@ def test_full_rerank_reduces_to_ivf(small_data):
                                            fmt, rerank=w.n, coarse_margin=w.nlist)
         assert np.array_equal(got[2], ref[2]) and np.array_equal(got[1], ref[1])
         np.testing.assert_allclose(got[0], ref[0], rtol=1e-13)
+
+
+def _two_list_index(C):
+    """Two database rows per centroid (lists 0..3), d = 2."""
+    X = np.repeat(np.asarray(C, dtype=np.float32), 2, axis=0) + np.float32(0.01)
+    a = np.repeat(np.arange(len(C)), 2)
+    off, ids = kmeans.build_lists(a, len(C))
+    return X, off, ids
+
+
+def test_coarse_first_pass_reorders_by_hand():
+    """Coarse step of the precision form with a small margin: the quantised
+    first pass picks the nprobe + coarse_margin best by quantised distance,
+    exact FP64 distances order that shortlist. Centroids are built so that
+    rounding swaps the two nearest (values worked out by hand; d_c = 1)."""
+    q = np.array([[1.0, 0.0]], dtype=np.float32)
+    # BF16: 1 + 2^-8 is a tie between 1 and 1 + 2^-7 and rounds to the even
+    # 1.0 (quantised distance 0, exact 2^-16); 0.997 rounds to 1 - 2^-8
+    # (quantised distance 2^-16, exact 9e-6 < 2^-16)
+    cb = [[1.0 + 2.0 ** -8, 1.75], [0.997, 1.75], [3.0, 1.75], [-2.0, 1.75]]
+    # e4m3: the 1.75 sets the scale 1/256, so a coordinate a becomes
+    # round_e4m3(256 a) / 256; 1.06 -> 256/256 = 1 (exact distance 0.0036),
+    # 0.96 -> 240/256 = 0.9375 (exact 0.0016 < 0.0036, quantised 0.0039 > 0)
+    cf = [[1.06, 1.75], [0.96, 1.75], [3.0, 1.75], [-2.0, 1.75]]
+    for fmt, C in (("bf16", cb), ("fp8", cf)):
+        C = np.asarray(C, dtype=np.float32)
+        X, off, ids = _two_list_index(C)
+        deq = precision.dequantized(C, fmt)[:, 0]
+        # the construction does what the comments say
+        assert abs(deq[0] - 1.0) < 1e-6 and deq[1] < 0.9999
+        assert abs(C[1, 0] - 1.0) < abs(C[0, 0] - 1.0)
+
+        def probes(nprobe, margin):
+            return precision.precision_search64(X, q, C, off, ids, 1, 2, nprobe, 1, fmt,
+                                                rerank=4, coarse_margin=margin)[2][0].tolist()
+
+        assert probes(1, 0) == [0]        # quantised pass keeps only centroid 0
+        assert probes(1, 1) == [1]        # margin 1 lets the exact step pick 1
+        assert probes(2, 0) == [1, 0]     # both shortlisted, exact order
+        assert probes(3, 0) == [1, 0, 2]
