@@ -276,6 +276,26 @@ adanns_status adanns_timing_reset(void);
 adanns_status adanns_timing_read(const char *kernel, int64_t *launches, double *total_ms);
 
 /*
+ * Certificate counters of the shortlists (Algorithm 1's linear scan returns
+ * the exact k nearest of the candidates; here a cheaper first pass orders
+ * them and only a shortlist is re-measured exactly). Every selection keeps
+ * the candidates whose first-pass value, widened by the first pass's
+ * rounding-error bound (or IVF-PQ's table-sum bound), can still reach the
+ * k nearest (the nprobe nearest centroids, the rerank_k nearest by the
+ * quantised measure), however many there are; a query whose band outgrows
+ * the one-wave list is selected again by a re-selection launch with up to
+ * 4096 slots (LDS permitting). Counts since the last reset, over every search
+ * on the current device:
+ *   reselected   host out, queries handed to the re-selection launch (or NULL);
+ *   uncertified  host out, queries whose band held more candidates than the
+ *                largest shortlist (those results are the nearest of the
+ *                first-pass best only), or NULL.
+ * reset != 0 zeroes both after reading. Synchronises the current device.
+ * Errors: ADANNS_EHIP.
+ */
+adanns_status adanns_selection_stats(int64_t *reselected, int64_t *uncertified, int32_t reset);
+
+/*
  * Batching form: many search configurations, each with its own index,
  * (d_c, d_s, nprobe, k) and query batch, run as one set of persistent
  * launches over a descriptor table (coarse tiles of every configuration in

@@ -19,8 +19,9 @@ if not os.path.exists(LIB_PATH):
                       "(python -c 'import __graft_entry__ as g; g.build()')")
 lib = C.CDLL(LIB_PATH)
 
-OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, EBUDGET = 0, -1, -2, -3, -4, -5
-STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED", -5: "EBUDGET"}
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, EBUDGET, EIO = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EUNSUPPORTED", -5: "EBUDGET",
+                -6: "EIO"}
 
 vp = C.c_void_p
 i32 = C.c_int32
@@ -55,6 +56,7 @@ _SIGS = {
     "adanns_timing_enable": (C.c_int, [i32]),
     "adanns_timing_reset": (C.c_int, []),
     "adanns_timing_read": (C.c_int, [C.c_char_p, vp, vp]),
+    "adanns_selection_stats": (C.c_int, [vp, vp, i32]),
     "adanns_search": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, vp, vp, vp, vp]),
     "adanns_search_probes": (C.c_int, [vp, vp, i64, i64, i32, i32, vp, i32, vp, vp, vp]),
     "adanns_index_info": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -118,6 +120,15 @@ def timing_read(kernel: str):
     ms = C.c_double()
     check(lib.adanns_timing_read(kernel.encode(), C.addressof(n), C.addressof(ms)))
     return n.value, ms.value
+
+
+def selection_stats(reset: bool = False):
+    """adanns_selection_stats: (queries re-selected with a wider shortlist,
+    queries left uncertified) since the last reset, current device."""
+    a = C.c_int64()
+    b = C.c_int64()
+    check(lib.adanns_selection_stats(C.addressof(a), C.addressof(b), 1 if reset else 0))
+    return a.value, b.value
 
 
 def set_search_scratch_cap(nbytes: int = 0):

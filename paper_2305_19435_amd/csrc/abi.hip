@@ -274,6 +274,7 @@ SearchBufs carve(char *base, const adanns_index *ix, int64_t nq, int32_t dq_pad,
   b.seg_off = c.take<int64_t>(nq + 1);
   b.pair_base = c.take<int64_t>((size_t)nq * nprobe);
   b.D = c.take<float>((size_t)nq * ix->top_prefix[nprobe]);
+  b.redo = c.take<int32_t>((size_t)nq + 2);
   *total = c.off + 256;
   return b;
 }
@@ -346,6 +347,13 @@ static adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t 
   float *Xc = nullptr;  // staged chunk for the final assignment of all rows
   ADANNS_HIP(hipMalloc(&Xc, (size_t)std::min(n, chunk) * dcp * sizeof(float)));
   tmp.ptrs.push_back(Xc);
+  // re-selection list of the assignment searches, and the largest squared
+  // centroid norm that bounds their first pass's rounding error
+  int32_t *redo = nullptr;
+  ADANNS_HIP(hipMalloc(&redo, (size_t)(chunk + 2) * sizeof(int32_t)));
+  tmp.ptrs.push_back(redo);
+  ADANNS_HIP(hipMalloc(&cix.cmax2, sizeof(float)));
+  tmp.ptrs.push_back(cix.cmax2);
   if (train_rows) {
     ADANNS_HIP(hipMalloc(&d_rows, (size_t)nt * sizeof(int64_t)));
     tmp.ptrs.push_back(d_rows);
@@ -379,10 +387,12 @@ static adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t 
                          float *out_min) -> adanns_status {
     ADANNS_HIP(launch_layout(f32mat(C, dcp), d_c, d_src, d_rl, d_poff1, cix.nl_pad, dcp,
                              cix.cent_slab, st));
+    ADANNS_HIP(launch_row_norm_max(cix.cent_slab, d_poff1, 1, dcp, cix.cmax2, st));
     for (int64_t a0 = 0; a0 < count; a0 += chunk) {
       const int64_t m = std::min(chunk, count - a0);
       SearchBufs b{};
       b.cfg = d_cfg;
+      b.redo = redo;
       b.Qs = const_cast<float *>(rows) + a0 * ldr;
       b.ldqs = ldr;
       b.S = S;
@@ -415,6 +425,7 @@ static adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t 
   if (!final_all_rows) {  // centroids only (the caller encodes the rows itself)
     cix.cent = nullptr;
     cix.cent_slab = nullptr;
+    cix.cmax2 = nullptr;
     *C_out = C;
     return ADANNS_OK;
   }
@@ -422,11 +433,13 @@ static adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t 
   assign_all.assign(n, 0);
   ADANNS_HIP(launch_layout(f32mat(C, dcp), d_c, d_src, d_rl, d_poff1, cix.nl_pad, dcp,
                            cix.cent_slab, st));
+  ADANNS_HIP(launch_row_norm_max(cix.cent_slab, d_poff1, 1, dcp, cix.cmax2, st));
   for (int64_t a0 = 0; a0 < n; a0 += chunk) {
     const int64_t m = std::min(chunk, n - a0);
     ADANNS_HIP(launch_stage_rows(X.rows(a0), nullptr, nullptr, m, d_c, Xc, dcp, st));
     SearchBufs b{};
     b.cfg = d_cfg;
+    b.redo = redo;
     b.Qs = Xc;
     b.ldqs = dcp;
     b.S = S;
@@ -446,6 +459,7 @@ static adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t 
   }
   cix.cent = nullptr;
   cix.cent_slab = nullptr;  // freed by tmp
+  cix.cmax2 = nullptr;
   *C_out = C;
   return ADANNS_OK;
 }
@@ -1094,6 +1108,17 @@ adanns_status adanns_timing_read(const char *kernel, int64_t *launches, double *
   auto it = g_totals.find(kernel);
   if (launches) *launches = it == g_totals.end() ? 0 : it->second.first;
   if (total_ms) *total_ms = it == g_totals.end() ? 0.0 : it->second.second;
+  return ADANNS_OK;
+}
+
+adanns_status adanns_selection_stats(int64_t *reselected, int64_t *uncertified, int32_t reset) {
+  clear_error();
+  adanns_status s = check_async();
+  if (s) return s;
+  unsigned long long v[2] = {0ull, 0ull};
+  ADANNS_HIP(read_selection_stats(v, reset != 0));
+  if (reselected) *reselected = (int64_t)v[0];
+  if (uncertified) *uncertified = (int64_t)v[1];
   return ADANNS_OK;
 }
 

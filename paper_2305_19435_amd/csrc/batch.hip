@@ -184,6 +184,7 @@ adanns_status adanns_batch_create(const adanns_batch_config *cfgs, int32_t ncfg,
     b.seg_off = cv.take<int64_t>(q0 + 1);
     b.pair_base = cv.take<int64_t>((size_t)pair0);
     b.D = cv.take<float>((size_t)D);
+    b.redo = cv.take<int32_t>((size_t)q0 + 2);
     if (pass == 0) {
       p->scratch_bytes = cv.off + 256;
       if (hipMalloc(&p->scratch, p->scratch_bytes) != hipSuccess) {

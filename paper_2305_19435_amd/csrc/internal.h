@@ -176,6 +176,10 @@ struct CfgDev {
 CfgDev make_cfg(const adanns_index *ix, int32_t d_c, int32_t d_s, int32_t nprobe, int32_t k,
                 int64_t nq);
 
+// Selection counters of the current device (synchronises it): [0] queries
+// re-selected with a wider shortlist, [1] queries left uncertified.
+hipError_t read_selection_stats(unsigned long long out[2], bool reset);
+
 // ---- launch wrappers (kernels.hip) -----------------------------------------
 struct SearchBufs {
   CfgDev *cfg;        // device descriptors (one for an ordinary search)
@@ -199,6 +203,7 @@ struct SearchBufs {
   int64_t *seg_off;   // [nq + 1]
   int64_t *pair_base; // [nq * nprobe]
   float *D;           // first-pass distances, query-segmented
+  int32_t *redo;      // [2 + Qtot] re-selection counters (coarse, scan) and list, or NULL
 };
 
 // A row-major matrix of FP32 or IEEE-half elements (the caller's database,

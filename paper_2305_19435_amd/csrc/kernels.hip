@@ -714,7 +714,44 @@ struct SelArgs {
   int64_t ldo;             // output row stride (0 = kout)
   int32_t lcap;            // segment floats staged in LDS (0 = none)
   int32_t kcap;            // candidate slots in LDS (power of two >= K1)
+  // Queries whose shortlist cannot be certified here are appended to
+  // redo_list (count in *redo_cnt) and left for the re-selection launch; NULL
+  // in that launch itself.
+  int32_t *redo_cnt;
+  int32_t *redo_list;
+  int64_t redo_q0;         // added to a query's index in redo_list
 };
+
+// Process-wide selection counters (per device): [0] queries handed to the
+// re-selection launch, [1] queries whose band of possible nearest candidates
+// held more than the largest shortlist (result not certified exact).
+__device__ unsigned long long g_sel_stats[2];
+
+// Bound on |first-pass value - exact value| of a candidate, as a function of
+// the first-pass value f. kind 0: none known; 1: a constant B; 2: IVF-PQ's
+// B(f) = c1 f + c2 (2 sqrt(f) + 2^-24 |q'|) (see wave_fp_bound). Both grow
+// with f no faster than f, so f - B(f) is non-decreasing and a candidate that
+// can still reach the kv nearest is one with f - B(f) <= v_kv + B(v_kv),
+// v_kv the kv-th smallest first-pass value: every other one is farther than
+// kv candidates in exact arithmetic.
+struct FpBound {
+  int32_t kind;
+  float B, c1, c2, qn;
+  float eq;  // quantised modes: |q - q^| over the first measure's prefix, else -1
+  __device__ float of(float f) const {
+    if (kind == 1) return B;
+    f = fmaxf(f, 0.f);
+    return c1 * f + c2 * (2.f * sqrtf(f) + 0x1p-24f * qn);
+  }
+  __device__ float upper(float v) const { return v + of(v); }
+  __device__ bool keep(float f, float up) const { return f - of(f) <= up; }
+};
+
+// First-pass value of a (order_key << 32 | position) composite.
+__device__ __forceinline__ float comp_value(uint64_t comp) {
+  const uint32_t kk = (uint32_t)(comp >> 32);
+  return __uint_as_float((kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk);
+}
 
 __device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
 
@@ -1072,6 +1109,82 @@ __device__ __forceinline__ void measureB_vec_rq(const SelArgs &a, const CandLoc 
     }
 }
 
+// The first-pass error bound of query q's candidates (one wave; every lane
+// gets the same value).
+//  * FP32 first pass |x|^2 - 2 q.x on d coordinates (SEL_COARSE, SEL_L2):
+//    off its exact value by at most B = 4 (d + 2) 2^-24 (X^2 + 2 |q| X), X the
+//    largest norm of the stored rows (xmax2 = X^2): four times the classical
+//    bound of a length-d dot product and sum of squares in FP32 plus the final
+//    rounding (the factor covers the matrix cores' undocumented internal
+//    accumulation order).
+//  * quantised first pass (SEL_QUANT, SEL_COARSE_QUANT): the same expression
+//    for the dequantised operands, X = (largest FP32 norm) + (largest
+//    |x - x^|), |q| replaced by |q^|.
+//  * ADC (SEL_ADC): the first pass sums M table entries, each the FP32 sum over
+//    dsub coordinates of (q'_hi - c)^2; against the exact asymmetric distance
+//    (rotated query q'_hi + q'_lo) it is off by at most
+//    B(f) = 4 (dsub + M + 4) 2^-24 f + 4 2^-24 |q'| (2 sqrt(f) + 2^-24 |q'|):
+//    four times the classical bounds for the entries and their sum, plus the
+//    dropped q'_lo (|q'_lo| <= 2^-24 |q'_hi|).
+// Norms are rounded up by 1e-3 relative where the bound is not already four
+// times the classical one.
+__device__ FpBound wave_fp_bound(const SelArgs &a, int64_t q, int lane) {
+  FpBound fb{0, 0.f, 0.f, 0.f, 0.f, -1.f};
+  const int d = a.d_dot;
+  if (a.mode == SEL_ADC) {
+    const float ADANNS_GLOBAL_AS *qh = (const float ADANNS_GLOBAL_AS *)(a.qr_hi + q * a.ldqr);
+    float qq = 0.f;
+    for (int dim = lane; dim < d; dim += 64) qq = fmaf(qh[dim], qh[dim], qq);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o);
+    fb.qn = sqrtf(qq) * 1.001f;
+    fb.c1 = 4.f * (float)(a.dsub + a.M + 4) * 0x1p-24f;
+    fb.c2 = 4.f * 0x1p-24f * fb.qn;
+    fb.kind = 2;
+  } else if (a.mode == SEL_QUANT || a.mode == SEL_COARSE_QUANT) {
+    const float ADANNS_GLOBAL_AS *qrow = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
+    float qq = 0.f, ee = 0.f;
+    for (int dim = lane; dim < d; dim += 64) {
+      const int64_t qi = q * a.ldqq + dim;
+      const float qh = a.qfmt == 1
+                           ? bf16_to_float(ldg((const uint16_t *)a.qQ + qi))
+                           : ldg(a.qQscale + q) * e4m3_to_float(ldg((const uint8_t *)a.qQ + qi));
+      const float df = qrow[dim] - qh;
+      qq = fmaf(qh, qh, qq);
+      ee = fmaf(df, df, ee);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      qq += __shfl_xor(qq, o);
+      ee += __shfl_xor(ee, o);
+    }
+    fb.eq = sqrtf(ee);
+    if (a.qerr != nullptr && a.xmax2 != nullptr) {
+      const float X = (sqrtf(ldg(a.xmax2)) + ldg(a.qerr)) * 1.001f, qn = sqrtf(qq) * 1.001f;
+      fb.B = 4.f * (float)(d + 2) * 0x1p-24f * (X * X + 2.f * qn * X);
+      fb.kind = 1;
+    }
+  } else if (a.xmax2 != nullptr) {  // FP32 first pass
+    const float ADANNS_GLOBAL_AS *qrow = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
+    float qq = 0.f;
+    for (int dim = lane; dim < d; dim += 64) qq = fmaf(qrow[dim], qrow[dim], qq);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o);
+    const float X2 = ldg(a.xmax2), X = sqrtf(X2), qn = sqrtf(qq);
+    fb.B = 4.f * (float)(d + 2) * 0x1p-24f * (X2 + 2.f * qn * X);
+    fb.kind = 1;
+  }
+  if (!(fb.B <= __FLT_MAX__) || !(fb.qn <= __FLT_MAX__)) fb.kind = 0;  // overflowed
+  return fb;
+}
+
+// Hands query q to the re-selection launch (one lane / thread calls this).
+__device__ __forceinline__ void push_redo(int32_t *cnt, int32_t *list, int64_t q) {
+  const int slot = atomicAdd(cnt, 1);
+  list[slot] = (int32_t)q;
+  atomicAdd(&g_sel_stats[0], 1ull);
+}
+
 __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
   extern __shared__ __attribute__((aligned(16))) unsigned char sel_smem[];
   uint32_t *hist = (uint32_t *)sel_smem;
@@ -1100,14 +1213,22 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
     seg = a.D + seg0;
     L = a.seg_off[q + 1] - seg0;
   }
+  __shared__ FpBound s_fb;
+  __shared__ int s_ncand, s_nkeep;
+  __shared__ float s_up;
   int ncand;
+  // the segment is staged in LDS when it fits: every pass below reads it
+  const bool staged = L > a.K1 && L <= a.lcap;
+  bool rounds = false;  // band wider than the slots: measured in rounds
   if (L <= a.K1) {
     ncand = (int)L;
     for (int i = tid; i < ncand; i += blockDim.x) cpos[i] = i;
   } else {
-    ncand = a.K1;
-    // stage the segment in LDS when it fits: every pass below reads it
-    const bool staged = L <= a.lcap;
+    // the first-pass error bound of this query (one wave computes it)
+    if (wv == 0) {
+      const FpBound fb = wave_fp_bound(a, q, lane);
+      if (lane == 0) s_fb = fb;
+    }
     if (staged) {  // eight independent loads in flight per thread
       for (int64_t base = tid; base < L; base += (int64_t)blockDim.x * 8) {
         float v[8];
@@ -1141,84 +1262,151 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
       atomicMin(&s_min, kmin);
       atomicMax(&s_max, kmax);
       __syncthreads();
-      // radix selection of the K1-th smallest key over an adaptive window
+      // radix selection of the K-th smallest key over an adaptive window
       // [lo, hi): each pass splits the window into at most 2048 bins; the
-      // last pass has unit bins, so T is exact and hist[s_bin] counts the
-      // keys equal to T
-      uint64_t lo = s_min, hi = (uint64_t)s_max + 1;
-      uint32_t need = (uint32_t)a.K1;
-      for (int pass = 0; pass < 4; ++pass) {
-        const uint64_t width = hi - lo;
-        const int shift = width <= 2048 ? 0 : (64 - __clzll((long long)(width - 1))) - 11;
-        for (int i = tid; i < 2048; i += blockDim.x) hist[i] = 0;
-        __syncthreads();
-        for (int64_t i = tid; i < L; i += blockDim.x) {
-          const uint64_t kk = order_key(src[i]);
-          if (kk >= lo && kk < hi) atomicAdd(&hist[(uint32_t)((kk - lo) >> shift)], 1u);
-        }
-        __syncthreads();
-        const int per = 2048 / blockDim.x;
-        uint32_t local = 0;
-        for (int e = 0; e < per; ++e) local += hist[tid * per + e];
-        uint32_t excl = block_excl_scan<uint32_t>(local, sh32, nullptr);
-        if (excl < need && need <= excl + local) {
-          uint32_t c = excl;
-          for (int e = 0; e < per; ++e) {
-            uint32_t hb = hist[tid * per + e];
-            if (c + hb >= need) {
-              s_bin = (uint32_t)(tid * per + e);
-              s_before = c;
-              break;
+      // last pass has unit bins, so T is exact; on return need counts the
+      // keys equal to T that belong to the K smallest and n_eq all of them
+      auto radix = [&](uint32_t K, uint32_t &T, uint32_t &need, uint32_t &n_eq) {
+        uint64_t lo = s_min, hi = (uint64_t)s_max + 1;
+        need = K;
+        for (int pass = 0; pass < 4; ++pass) {
+          const uint64_t width = hi - lo;
+          const int shift = width <= 2048 ? 0 : (64 - __clzll((long long)(width - 1))) - 11;
+          for (int i = tid; i < 2048; i += blockDim.x) hist[i] = 0;
+          __syncthreads();
+          for (int64_t i = tid; i < L; i += blockDim.x) {
+            const uint64_t kk = order_key(src[i]);
+            if (kk >= lo && kk < hi) atomicAdd(&hist[(uint32_t)((kk - lo) >> shift)], 1u);
+          }
+          __syncthreads();
+          const int per = 2048 / blockDim.x;
+          uint32_t local = 0;
+          for (int e = 0; e < per; ++e) local += hist[tid * per + e];
+          uint32_t excl = block_excl_scan<uint32_t>(local, sh32, nullptr);
+          if (excl < need && need <= excl + local) {
+            uint32_t c = excl;
+            for (int e = 0; e < per; ++e) {
+              uint32_t hb = hist[tid * per + e];
+              if (c + hb >= need) {
+                s_bin = (uint32_t)(tid * per + e);
+                s_before = c;
+                break;
+              }
+              c += hb;
             }
-            c += hb;
+          }
+          __syncthreads();
+          const uint64_t nlo = lo + ((uint64_t)s_bin << shift);
+          const uint64_t nhi = nlo + ((uint64_t)1 << shift);
+          need -= s_before;
+          lo = nlo;
+          hi = nhi < hi ? nhi : hi;
+          __syncthreads();
+          if (shift == 0) break;
+        }
+        T = (uint32_t)lo;
+        n_eq = hist[s_bin];
+        __syncthreads();
+      };
+      // the K smallest (key, position) composites, in slots 0..K-1
+      auto take_smallest = [&](int K) {
+        uint32_t T, need, n_eq;
+        radix((uint32_t)K, T, need, n_eq);
+        if (tid == 0) s_slot = 0;
+        __syncthreads();
+        if (n_eq == need) {
+          // every key equal to T is taken: one coalesced pass, any slot order
+          for (int64_t i = tid; i < L; i += blockDim.x) {
+            if (order_key(src[i]) <= T) {
+              const int slot = atomicAdd(&s_slot, 1);
+              cpos[slot] = i;
+            }
+          }
+        } else {
+          // take every key below T and the first ``need`` equal ones in
+          // position order
+          const int64_t chunk = (L + blockDim.x - 1) / blockDim.x;
+          const int64_t a0 = tid * chunk, a1 = min64(L, a0 + chunk);
+          uint32_t ne = 0;
+          for (int64_t i = a0; i < a1; ++i) ne += order_key(src[i]) == T;
+          uint32_t eq_before = block_excl_scan<uint32_t>(ne, sh32, nullptr);
+          const int nlt = K - (int)need;
+          for (int64_t i = a0; i < a1; ++i) {
+            uint32_t kk = order_key(src[i]);
+            if (kk < T) {
+              int slot = atomicAdd(&s_slot, 1);
+              cpos[slot] = i;
+            } else if (kk == T) {
+              if (eq_before < need) cpos[nlt + eq_before] = i;
+              ++eq_before;
+            }
           }
         }
-        __syncthreads();
-        const uint64_t nlo = lo + ((uint64_t)s_bin << shift);
-        const uint64_t nhi = nlo + ((uint64_t)1 << shift);
-        need -= s_before;
-        lo = nlo;
-        hi = nhi < hi ? nhi : hi;
-        __syncthreads();
-        if (shift == 0) break;
+      };
+      const FpBound fb = s_fb;
+      if (fb.kind == 0) {
+        // no error bound known: the plain margin, not certified
+        take_smallest(a.K1);
+        if (tid == 0) {
+          s_ncand = a.K1;
+          atomicAdd(&g_sel_stats[1], 1ull);
+        }
+        return;
       }
-      const uint32_t T = (uint32_t)lo;
-      const uint32_t n_eq = hist[s_bin];
+      // Certified shortlist: every candidate whose first-pass value can still
+      // reach the kv nearest (FpBound::keep against the kv-th smallest value),
+      // however many there are.
+      const int kv = a.stageB ? a.K2 : a.kout;
+      uint32_t T, need, n_eq;
+      radix((uint32_t)kv, T, need, n_eq);
+      const float up = fb.upper(comp_value((uint64_t)T << 32));
       if (tid == 0) s_slot = 0;
       __syncthreads();
-      if (n_eq == need) {
-        // every key equal to T is taken: one coalesced pass, any slot order
-        for (int64_t i = tid; i < L; i += blockDim.x) {
-          if (order_key(src[i]) <= T) {
-            const int slot = atomicAdd(&s_slot, 1);
-            cpos[slot] = i;
-          }
+      int nk = 0;
+      for (int64_t i = tid; i < L; i += blockDim.x) nk += fb.keep(src[i], up);
+      atomicAdd(&s_slot, nk);
+      __syncthreads();
+      const int n_keep = s_slot;
+      __syncthreads();
+      if (n_keep <= a.kcap) {
+        if (tid == 0) s_slot = 0;
+        __syncthreads();
+        for (int64_t i = tid; i < L; i += blockDim.x)
+          if (fb.keep(src[i], up)) cpos[atomicAdd(&s_slot, 1)] = i;
+        if (tid == 0) s_ncand = n_keep;
+      } else if (a.redo_list != nullptr) {
+        // more than this launch's slots: the re-selection launch takes it
+        if (tid == 0) {
+          push_redo(a.redo_cnt, a.redo_list, q + a.redo_q0);
+          s_ncand = -1;
+        }
+      } else if (a.kcap - kv >= 1) {
+        // more than this launch's slots: the band is measured in rounds of
+        // kcap - kv candidates, keeping the kv best (see below)
+        if (tid == 0) {
+          s_ncand = -2;
+          s_nkeep = n_keep;
+          s_up = up;
         }
       } else {
-        // take every key below T and the first ``need`` equal ones in
-        // position order
-        const int64_t chunk = (L + blockDim.x - 1) / blockDim.x;
-        const int64_t a0 = tid * chunk, a1 = min64(L, a0 + chunk);
-        uint32_t ne = 0;
-        for (int64_t i = a0; i < a1; ++i) ne += order_key(src[i]) == T;
-        uint32_t eq_before = block_excl_scan<uint32_t>(ne, sh32, nullptr);
-        const int nlt = a.K1 - (int)need;
-        for (int64_t i = a0; i < a1; ++i) {
-          uint32_t kk = order_key(src[i]);
-          if (kk < T) {
-            int slot = atomicAdd(&s_slot, 1);
-            cpos[slot] = i;
-          } else if (kk == T) {
-            if (eq_before < need) cpos[nlt + eq_before] = i;
-            ++eq_before;
-          }
+        // no room for rounds (kv fills the slots): the kcap nearest by first
+        // pass, counted as not certified
+        take_smallest(a.kcap);
+        if (tid == 0) {
+          s_ncand = a.kcap;
+          atomicAdd(&g_sel_stats[1], 1ull);
         }
       }
     };
+    __syncthreads();  // s_fb
     if (staged)
       select_from(segbuf);
     else
       select_from((const float ADANNS_GLOBAL_AS *)seg);
+    __syncthreads();
+    ncand = s_ncand;
+    if (ncand == -1) return;  // handed over (uniform over the block)
+    rounds = ncand == -2;
   }
   __syncthreads();
   // stage the query row (coordinates of both measures) in LDS
@@ -1238,8 +1426,8 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
   // first exact measure, one wave per candidate; the query row is read from
   // LDS when staged, else from global memory (one instantiation each)
   const float ADANNS_GLOBAL_AS *qglob = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
-  auto run1 = [&](auto qrow) {
-    for (int c = wv; c < ncand; c += nwv) {
+  auto run1 = [&](auto qrow, int c0, int c1) {
+    for (int c = c0 + wv; c < c1; c += nwv) {
       const CandLoc Lc = locate(a, coarse, q, seg0, cpos[c]);
       float S = 0.f, C = 0.f;
       measure1(a, q, Lc, qrow, qqstaged ? qqstage : nullptr, lane, S, C);
@@ -1252,19 +1440,62 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
       }
     }
   };
-  if (qstaged)
-    run1(qstage);
-  else
-    run1(qglob);
-  int P2 = 1;
-  while (P2 < ncand) P2 <<= 1;
-  for (int c = ncand + tid; c < P2; c += blockDim.x) {
-    chi[c] = __builtin_inff();
-    clo[c] = 0.f;
-    cid[c] = INT64_MAX;
-    cg[c] = -1;
+  auto sort_first = [&](int n) {  // sorts slots [0, n) by (distance pair, id)
+    int P2 = 1;
+    while (P2 < n) P2 <<= 1;
+    for (int c = n + tid; c < P2; c += blockDim.x) {
+      chi[c] = __builtin_inff();
+      clo[c] = 0.f;
+      cid[c] = INT64_MAX;
+      cg[c] = -1;
+    }
+    bitonic_sort(chi, clo, cid, cg, P2);
+  };
+  if (!rounds) {
+    if (qstaged)
+      run1(qstage, 0, ncand);
+    else
+      run1(qglob, 0, ncand);
+    sort_first(ncand);
+  } else {
+    // The band holds n_keep > kcap candidates: in position order, rounds of
+    // kcap - kv of them are measured into the slots after the kv best so
+    // far, and the slots re-sorted, so that the kv best of the whole band
+    // remain. Every candidate of the band is measured exactly once.
+    const int kv = a.stageB ? a.K2 : a.kout;
+    const int C = a.kcap - kv;
+    const int nk = s_nkeep;
+    auto band_rounds = [&](auto src) {
+      const FpBound fb = s_fb;
+      const float up = s_up;
+      const int64_t chunk = (L + blockDim.x - 1) / blockDim.x;
+      const int64_t a0 = tid * chunk, a1 = min64(L, a0 + chunk);
+      int have = 0;
+      for (int lo = 0; lo < nk; lo += C) {
+        const int cnt = min(C, nk - lo);
+        uint32_t ne = 0;
+        for (int64_t i = a0; i < a1; ++i) ne += fb.keep(src[i], up);
+        uint32_t r = block_excl_scan<uint32_t>(ne, sh32, nullptr);
+        for (int64_t i = a0; i < a1 && r < (uint32_t)(lo + cnt); ++i)
+          if (fb.keep(src[i], up)) {
+            if (r >= (uint32_t)lo) cpos[have + (r - lo)] = i;
+            ++r;
+          }
+        __syncthreads();
+        if (qstaged)
+          run1(qstage, have, have + cnt);
+        else
+          run1(qglob, have, have + cnt);
+        sort_first(have + cnt);
+        have = min(kv, have + cnt);
+      }
+      ncand = have;
+    };
+    if (staged)
+      band_rounds(segbuf);
+    else
+      band_rounds((const float ADANNS_GLOBAL_AS *)seg);
   }
-  bitonic_sort(chi, clo, cid, cg, P2);
 
   int nres = ncand;
   if (a.stageB) {
@@ -1272,8 +1503,10 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
     nres = ncand < a.K2 ? ncand : a.K2;
     // quantised rows: as in wave_select, only the prefix within
     // (sqrt(D^_k) + 2e)^2, e = |q - q^| + the largest |x - x^|, is re-measured
+    // (both measures on the same prefix: distances on different prefixes do
+    // not bound each other)
     if ((a.mode == SEL_QUANT || a.mode == SEL_COARSE_QUANT) && a.qemax != nullptr &&
-        nres > a.kout) {
+        a.d_B == a.d_dot && nres > a.kout) {
       __shared__ float s_eq[16];
       __shared__ int s_nres;
       float eq = 0.f;
@@ -1347,6 +1580,23 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
 
 __global__ __launch_bounds__(512) void k_select_refine(SelArgs a) { select_body(a, blockIdx.x); }
 
+// Re-selection of the queries a previous selection launch handed over (their
+// first shortlist could not be certified): the certified band selection of
+// select_body with this launch's larger candidate capacity. The grid strides
+// over the list; its length is read from device memory, so the launch needs
+// no host synchronisation.
+__global__ __launch_bounds__(512) void k_select_refine_redo(SelArgs a) {
+  const int32_t n = *(volatile const int32_t *)a.redo_cnt;
+  const int32_t *list = a.redo_list;
+  SelArgs b = a;
+  b.redo_cnt = nullptr;
+  b.redo_list = nullptr;
+  for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    select_body(b, list[i]);
+    __syncthreads();  // LDS reused by the next query
+  }
+}
+
 // The same selection and measures for one query on one wave, without LDS
 // or barriers, when K1 <= 64 (see k_select_wave below for the list
 // mechanics). Results equal select_body's.
@@ -1378,10 +1628,13 @@ struct SelMultiArgs {
   int64_t *ids;
   int64_t ldk;
   int32_t lcap, kcap;
+  // [2 + Qtot]: counts of queries handed to re-selection by the coarse ([0])
+  // and scan ([1]) selections, then the list of them; NULL in the
+  // re-selection launch itself
+  int32_t *redo;
 };
 
-__global__ __launch_bounds__(512) void k_select_multi(SelMultiArgs m) {
-  const int64_t r = blockIdx.x;
+__device__ __forceinline__ void select_multi_row(const SelMultiArgs &m, int64_t r) {
   const int c = cfg_of(m.cfg, m.ncfg, &CfgDev::q0, r);
   const CfgDev &g = m.cfg[c];
   const int64_t q = r - g.q0;
@@ -1404,6 +1657,7 @@ __global__ __launch_bounds__(512) void k_select_multi(SelMultiArgs m) {
     a.out_probes2 = m.user_probes ? m.user_probes + g.pair0 : nullptr;
     a.out_dist = m.dist ? m.dist + g.q0 : nullptr;
     a.ldo = 1;
+    a.xmax2 = g.cmax2;
   } else {
     a.mode = SEL_L2;
     a.D = m.D;
@@ -1423,8 +1677,31 @@ __global__ __launch_bounds__(512) void k_select_multi(SelMultiArgs m) {
     a.pair_base = m.pair_base + g.pair0;
     a.out_dist = m.dist + g.q0 * m.ldk;
     a.out_ids = m.ids + g.q0 * m.ldk;
+    a.xmax2 = g.xmax2;
+  }
+  if (m.redo) {
+    a.redo_cnt = m.redo + (m.coarse ? 0 : 1);
+    a.redo_list = m.redo + 2;  // batch rows
+    a.redo_q0 = g.q0;
   }
   select_body(a, q);
+}
+
+__global__ __launch_bounds__(512) void k_select_multi(SelMultiArgs m) {
+  select_multi_row(m, blockIdx.x);
+}
+
+// Re-selection of the batch rows handed over by the coarse (m.coarse) or scan
+// selection: as k_select_refine_redo.
+__global__ __launch_bounds__(512) void k_select_multi_redo(SelMultiArgs m) {
+  const int32_t n = *(volatile const int32_t *)(m.redo + (m.coarse ? 0 : 1));
+  const int32_t *list = m.redo + 2;
+  SelMultiArgs b = m;
+  b.redo = nullptr;
+  for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    select_multi_row(b, list[i]);
+    __syncthreads();  // LDS reused by the next row
+  }
 }
 
 // Per-query selection when at most WSEL_K candidates are kept (K1 <= 64):
@@ -1437,6 +1714,9 @@ __global__ __launch_bounds__(512) void k_select_multi(SelMultiArgs m) {
 // same order of accumulation as select_body) and sorted across lanes by
 // (distance pair, id). Results are identical to k_select_multi's.
 constexpr int WSEL_K = 64;
+// the one-wave selections keep up to kv + WAVE_MARGIN first-pass candidates
+// (within WSEL_K), kv the number of exact values the query needs
+constexpr int WAVE_MARGIN = 24;
 // candidates re-measured together by k_select_wave: two, with 1024
 // coordinates per pass, keep the kernel within 128 registers, four waves per
 // SIMD (the selection waits on memory latency, so waves in flight count more
@@ -1498,8 +1778,12 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
     seg = a.D + seg0;
     L = a.seg_off[q + 1] - seg0;
   }
-  // 1. the K1 smallest (key, position) composites, sorted over the lanes
-  const int K1 = a.K1;
+  // 1. the K1 smallest (key, position) composites, sorted over the lanes;
+  // K1 as wide as the lanes allow up to kv + WAVE_MARGIN, so that the
+  // certificate below rarely fails (only the band within the error bound is
+  // measured, so a wider list costs insertions, not measures)
+  const int kv = a.stageB ? a.K2 : a.kout;
+  const int K1 = max(a.K1, min(WSEL_K, kv + WAVE_MARGIN));
   const float ADANNS_GLOBAL_AS *sg = (const float ADANNS_GLOBAL_AS *)seg;
   uint64_t best = ~0ull, thr = ~0ull;
   constexpr int U = 16;
@@ -1529,74 +1813,29 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
   }
   int ncand = (int)min64(L, (int64_t)K1);
   const float ADANNS_GLOBAL_AS *qglob = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
-  // 1b. quantised scan (precision form): the first pass |x^|^2 - 2 q^.x^ of
-  // the dequantised operands on d coordinates is off by at most
-  // B = 4 (d + 2) 2^-24 (X^2 + 2 |q^| X), X >= every |x^| (the largest FP32
-  // row norm plus the largest |x - x^|), as on the FP32 path; only the
-  // shortlist's prefix within 2B of the K2-th smallest can hold the K2
-  // nearest by exact quantised distance, so only it is measured. |q - q^|
-  // is kept for the re-rank's bound below.
-  float eqn = -1.f;
+  // 1b. certificate: with B the first pass's error bound (wave_fp_bound),
+  // only candidates whose value can still reach the kv nearest are measured
+  // (for the quantised first pass: the kv nearest by exact quantised
+  // distance). If the list holds fewer than all candidates and its last
+  // entry can still reach them, candidates beyond it might too: the query is
+  // handed to the re-selection launch (workgroup path, certified band).
+  const FpBound fb = wave_fp_bound(a, q, lane);
   const bool quant = a.mode == SEL_QUANT || a.mode == SEL_COARSE_QUANT;
-  if (quant && a.qerr != nullptr && a.xmax2 != nullptr) {
-    float qq = 0.f, ee = 0.f;
-    for (int dim = lane; dim < a.d_dot; dim += 64) {
-      const int64_t qi = q * a.ldqq + dim;
-      const float qh = a.qfmt == 1 ? bf16_to_float(ldg((const uint16_t *)a.qQ + qi))
-                                   : ldg(a.qQscale + q) * e4m3_to_float(ldg((const uint8_t *)a.qQ + qi));
-      const float df = qglob[dim] - qh;
-      qq = fmaf(qh, qh, qq);
-      ee = fmaf(df, df, ee);
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      qq += __shfl_xor(qq, o);
-      ee += __shfl_xor(ee, o);
-    }
-    eqn = sqrtf(ee);
-    if (ncand > a.K2) {
-      const float X = (sqrtf(ldg(a.xmax2)) + ldg(a.qerr)) * 1.001f, qn = sqrtf(qq) * 1.001f;
-      const float B = 4.f * (float)(a.d_dot + 2) * 0x1p-24f * (X * X + 2.f * qn * X);
-      const uint32_t kk = (uint32_t)(readlane64(best, a.K2 - 1) >> 32);
-      const float vk = __uint_as_float((kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk);
-      const float T = vk + 2.f * B;
-      if (T <= __FLT_MAX__) {
-        const uint64_t tcomp = ((uint64_t)order_key(T) << 32) | 0xFFFFFFFFull;
-        ncand = __popcll(__ballot(lane < ncand && best <= tcomp));
+  const float eqn = fb.eq;
+  if (fb.kind != 0 && ncand > kv) {
+    const float up = fb.upper(comp_value(readlane64(best, kv - 1)));
+    if (L > K1 && fb.keep(comp_value(readlane64(best, K1 - 1)), up)) {
+      if (a.redo_list != nullptr) {
+        if (lane == 0) push_redo(a.redo_cnt, a.redo_list, q + a.redo_q0);
+        return;
       }
+      if (lane == 0) atomicAdd(&g_sel_stats[1], 1ull);
     }
-  }
-  // 1c. IVF-PQ: the first pass sums M table entries, each the FP32 sum over
-  // dsub coordinates of (q'_hi - c)^2. Against the exact asymmetric distance
-  // (rotated query q'_hi + q'_lo) it is off by at most
-  // B(f) = 4 (dsub + M + 4) 2^-24 f + 4 2^-24 |q'| (2 sqrt(f) + 2^-24 |q'|):
-  // four times the classical bounds for the entries and their sum, plus the
-  // dropped q'_lo (|q'_lo| <= 2^-24 |q'_hi|). B(f) and f - B(f) increase
-  // with f, so the candidates whose lower bound exceeds the upper bound of
-  // the nsel-th value form a suffix of the shortlist and are not measured.
-  if (a.mode == SEL_ADC) {
-    const int nsel = a.stageB ? a.K2 : a.kout;
-    if (ncand > nsel) {
-      const float ADANNS_GLOBAL_AS *qh = (const float ADANNS_GLOBAL_AS *)(a.qr_hi + q * a.ldqr);
-      float qq = 0.f;
-      for (int dim = lane; dim < a.d_dot; dim += 64) qq = fmaf(qh[dim], qh[dim], qq);
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o);
-      const float qn = sqrtf(qq) * 1.001f;
-      const float c1 = 4.f * (float)(a.dsub + a.M + 4) * 0x1p-24f, c2 = 4.f * 0x1p-24f * qn;
-      auto bound = [&](float f) {
-        f = fmaxf(f, 0.f);
-        return c1 * f + c2 * (2.f * sqrtf(f) + 0x1p-24f * qn);
-      };
-      auto kval = [](uint64_t comp) {
-        const uint32_t kk = (uint32_t)(comp >> 32);
-        return __uint_as_float((kk & 0x80000000u) ? (kk & 0x7FFFFFFFu) : ~kk);
-      };
-      const float vk = kval(readlane64(best, nsel - 1));
-      const float up = vk + bound(vk);
-      const float fi = kval(best);
-      if (up <= __FLT_MAX__) ncand = __popcll(__ballot(lane < ncand && fi - bound(fi) <= up));
-    }
+    ncand = __popcll(__ballot(lane < ncand && fb.keep(comp_value(best), up)));
+  } else if (fb.kind == 0 && L > K1) {
+    // no bound known (never the case for the library's launches): the plain
+    // list, not certified
+    if (lane == 0) atomicAdd(&g_sel_stats[1], 1ull);
   }
   // 2. lane j < ncand locates candidate j
   CandLoc mine{INT64_MAX, -1, 0, 0, 0};
@@ -1653,20 +1892,9 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
     // e = ‖q - q^‖ + (largest ‖x - x^‖ of the rows). A candidate whose
     // quantised distance lies beyond (sqrt(D^_k) + 2e)^2 is farther than k
     // others in FP32, so only the prefix within it is re-measured.
-    if (quant && a.qemax != nullptr && nres > a.kout) {
-      if (eqn < 0.f || a.d_B != a.d_dot) {
-        float eq = 0.f;
-        for (int dim = lane; dim < a.d_B; dim += 64) {
-          const int64_t qi = q * a.ldqq + dim;
-          const float qh = a.qfmt == 1 ? bf16_to_float(ldg((const uint16_t *)a.qQ + qi))
-                                       : ldg(a.qQscale + q) * e4m3_to_float(ldg((const uint8_t *)a.qQ + qi));
-          const float df = qglob[dim] - qh;
-          eq = fmaf(df, df, eq);
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) eq += __shfl_xor(eq, o);
-        eqn = sqrtf(eq);
-      }
+    // (both measures on the same prefix: distances on different prefixes do
+    // not bound each other)
+    if (quant && a.qemax != nullptr && a.d_B == a.d_dot && eqn >= 0.f && nres > a.kout) {
       // a margin of 1e-3 relative covers the FP32 rounding of these bounds
       const float e = (eqn + ldg(a.qemax)) * 1.001f;
       const float sk = __shfl(myS, a.kout - 1);
@@ -1747,17 +1975,18 @@ __global__ __launch_bounds__(256, WIDE ? 2 : 3) void k_select_wave(SelMultiArgs 
   if (coarse) {
     seg = m.S + g.S0 + q * g.nlist;
     L = g.nlist;
-    K1 = min(g.nlist, min(g.nprobe + REFINE_MARGIN, MAX_SHORTLIST));
     kout = g.nprobe;
     d_dot = g.d_c;
   } else {
     seg0 = m.seg_off[r];
     seg = m.D + seg0;
     L = m.seg_off[r + 1] - seg0;
-    K1 = min(g.k + REFINE_MARGIN, MAX_SHORTLIST);
     kout = g.k;
     d_dot = g.d_s;
   }
+  // the launch guarantees kout + REFINE_MARGIN <= WSEL_K; a wider list (see
+  // WAVE_MARGIN) lets the certificate below fail rarely
+  K1 = min(WSEL_K, kout + WAVE_MARGIN);
 
   // 1. the K1 smallest (key, position) composites, sorted over lanes
   const float ADANNS_GLOBAL_AS *sg = (const float ADANNS_GLOBAL_AS *)seg;
@@ -1826,7 +2055,11 @@ __global__ __launch_bounds__(256, WIDE ? 2 : 3) void k_select_wave(SelMultiArgs 
   // A candidate whose first-pass value exceeds the k-th smallest by more than
   // 2B is farther than k others in exact arithmetic, so only the shortlist's
   // prefix within 2B of the k-th smallest is re-measured.
+  // Certificate: if the list holds fewer than all L candidates and its last
+  // entry is within the 2B band too, candidates beyond it might be among the
+  // kout nearest; the query then goes to the re-selection launch.
   const float *xm = coarse ? g.cmax2 : g.xmax2;
+  bool certain = L <= K1;
   if (xm != nullptr && ncand > kout) {
     float qq = 0.f;
     for (int d0 = 4 * lane; d0 < d_dot; d0 += 256) {
@@ -1843,8 +2076,16 @@ __global__ __launch_bounds__(256, WIDE ? 2 : 3) void k_select_wave(SelMultiArgs 
     const float T = vk + 2.f * B;
     if (T <= __FLT_MAX__) {
       const uint64_t tcomp = ((uint64_t)order_key(T) << 32) | 0xFFFFFFFFull;
+      certain = certain || readlane64(best, K1 - 1) > tcomp;
       ncand = __popcll(__ballot(lane < ncand && best <= tcomp));
     }
+  }
+  if (!certain) {
+    if (m.redo != nullptr) {
+      if (lane == 0) push_redo(m.redo + (COARSE ? 0 : 1), m.redo + 2, r);
+      return;  // whole waves leave
+    }
+    if (lane == 0) atomicAdd(&g_sel_stats[1], 1ull);
   }
 
   // 2. where each candidate lives (lane j < ncand holds candidate j)
@@ -2974,26 +3215,36 @@ static int32_t next_pow2(int32_t v) {
 
 constexpr int32_t SEG_LDS_CAP = 16384;   // at most this many first-pass distances staged
 
-// LDS a selection workgroup may use: the device's per-workgroup limit (the
-// function attribute is raised to it when it exceeds the 64 KB default).
+// Dynamic LDS a selection workgroup may use: the device's per-workgroup limit
+// less the kernels' static LDS (the function attribute is raised to it when it
+// exceeds the 64 KB default; if that fails, 64 KB less the static LDS).
 static size_t sel_smem_budget() {
   static std::once_flag once;
-  static size_t budget = 64 * 1024;
+  static size_t budget = 48 * 1024;
   std::call_once(once, [] {
+    const void *fns[] = {(const void *)k_select_refine, (const void *)k_select_multi,
+                         (const void *)k_select_refine_redo, (const void *)k_select_multi_redo};
     int dev = 0, v = 0;
+    size_t per_block = 64 * 1024, stat = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
         v > 0)
-      budget = (size_t)v;
-    if (budget > 64 * 1024) {
-      if (hipFuncSetAttribute((const void *)k_select_refine,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget) != hipSuccess ||
-          hipFuncSetAttribute((const void *)k_select_multi,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)budget) != hipSuccess) {
-        (void)hipGetLastError();
-        budget = 64 * 1024;
-      }
+      per_block = (size_t)v;
+    for (const void *f : fns) {
+      hipFuncAttributes fa;
+      if (hipFuncGetAttributes(&fa, f) == hipSuccess) stat = std::max(stat, fa.sharedSizeBytes);
     }
+    stat = (stat + 255) / 256 * 256;
+    const size_t dflt = 64 * 1024 - stat;
+    size_t dyn = per_block > stat ? per_block - stat : 0;
+    if (dyn > dflt) {
+      bool ok = true;
+      for (const void *f : fns)
+        ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) ==
+                       hipSuccess;
+      if (!ok) dyn = dflt;
+    }
+    budget = dyn;
     (void)hipGetLastError();
   });
   return budget;
@@ -3006,21 +3257,62 @@ static int32_t seg_cap(int32_t kcap, int64_t max_len) {
   return (int32_t)std::max<int64_t>(cap, 0);
 }
 
+// Candidate slots of the re-selection launches: the most that fit the LDS
+// budget (up to 4096), so that only a band of more candidates than that
+// leaves a result uncertified.
+static int32_t redo_kcap() {
+  int32_t k = 4096;
+  while (k > 64 && sel_smem_bytes(0, k) > sel_smem_budget()) k >>= 1;
+  return k;
+}
+
+hipError_t read_selection_stats(unsigned long long out[2], bool reset) {
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_sel_stats), 2 * sizeof(unsigned long long));
+  if (e == hipSuccess && reset) {
+    const unsigned long long z[2] = {0ull, 0ull};
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_sel_stats), z, sizeof(z));
+  }
+  return e;
+}
+
+// Workgroups of a re-selection launch (it strides over its list).
+static unsigned redo_grid(int64_t nq) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(nq, 512)); }
+
+// Zeroes the two re-selection counters of a search (a fill kernel, not a
+// memset: searches may be captured into graphs).
+static void reset_redo(int32_t *redo, hipStream_t st) {
+  if (redo) hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, redo, (int64_t)2, 0);
+}
+
 // One query per wave when the first shortlist fits the lanes and either the
 // exact measures are short (one wave measures the candidates one after
 // another) or the batch holds enough queries to give every SIMD two waves
 // (measured: the precision form's re-rank of 32 at d_s 2048, 147k
 // coordinates per query, 24 % faster than one workgroup per query on 50k
 // queries); else one workgroup of eight waves per query.
-static void launch_select(const SelArgs &s, int64_t nq, size_t smem, hipStream_t st) {
+// ``redo_cnt`` / ``redo_list`` (nq entries) collect the queries whose
+// shortlist the first launch cannot certify; the re-selection launch that
+// follows takes them with the widest shortlist. NULL: no re-selection.
+static void launch_select(SelArgs s, int64_t nq, size_t smem, int32_t *redo_cnt,
+                          int32_t *redo_list, hipStream_t st) {
   if (nq == 0) return;
   const int64_t measure = (int64_t)s.K1 * s.d_dot + (s.stageB ? (int64_t)s.K2 * s.d_B : 0);
   const bool many = nq >= 2048;
+  s.redo_cnt = redo_cnt;
+  s.redo_list = redo_cnt ? redo_list : nullptr;
+  s.redo_q0 = 0;
   if (s.K1 <= WSEL_K && s.kout <= WSEL_K &&
       (measure <= 96 * 1024 || (many && measure <= 512 * 1024)))
     hipLaunchKernelGGL(k_select_refine_wave, dim3((unsigned)cdiv(nq, 4)), dim3(256), 0, st, s, nq);
   else
     hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(512), smem, st, s);
+  if (redo_cnt) {
+    s.kcap = redo_kcap();
+    s.lcap = seg_cap(s.kcap, SEG_LDS_CAP);
+    hipLaunchKernelGGL(k_select_refine_redo, dim3(redo_grid(nq)), dim3(512),
+                       sel_smem_bytes(s.lcap, s.kcap), st, s);
+  }
 }
 
 // Sets the LDS caps of a single-configuration selection; returns its bytes.
@@ -3142,6 +3434,7 @@ static hipError_t coarse_multi(const SearchBufs &b, int32_t *user_probes, float 
   m.dist = out_min_dist;
   m.kcap = next_pow2(std::min(b.max_nlist, std::min(b.max_nprobe + REFINE_MARGIN, MAX_SHORTLIST)));
   m.lcap = seg_cap(m.kcap, b.max_nlist);
+  m.redo = b.redo;
   {
     KernelTimer tm("select_coarse", st);
     if (b.max_nprobe + REFINE_MARGIN <= WSEL_K)
@@ -3150,6 +3443,12 @@ static hipError_t coarse_multi(const SearchBufs &b, int32_t *user_probes, float 
     else
       hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(512),
                          sel_smem_bytes(m.lcap, m.kcap), st, m);
+    if (b.redo) {
+      m.kcap = redo_kcap();
+      m.lcap = seg_cap(m.kcap, b.max_nlist);
+      hipLaunchKernelGGL(k_select_multi_redo, dim3(redo_grid(b.Qtot)), dim3(512),
+                         sel_smem_bytes(m.lcap, m.kcap), st, m);
+    }
   }
   return hipGetLastError();
 }
@@ -3191,6 +3490,7 @@ hipError_t launch_coarse(const adanns_index *ix, const SearchBufs &b, int64_t nq
   const CfgDev c = make_cfg(ix, d_c, 0, nprobe, 0, nq);
   hipError_t e = launch_store_cfg(c, b.cfg, st);
   if (e != hipSuccess) return e;
+  reset_redo(b.redo, st);
   SearchBufs bb = b;
   bb.ncfg = 1;
   bb.Qtot = nq;
@@ -3220,6 +3520,7 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
                                int32_t tv, int32_t grid, hipStream_t st, bool do_coarse) {
   if (tq != 32 && tq != 128) tq = 64;
   if (tv != 128) tv = 64;
+  reset_redo(b.redo, st);
   // The kernels read query rows through 16-byte loads up to the 32-coordinate
   // slab that holds the last coordinate they use, and mask what lies past it;
   // rows that are 16-byte aligned and at least that wide are read in place,
@@ -3283,6 +3584,7 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
   m.ldk = ldk;
   m.kcap = next_pow2(std::min(b.max_k + REFINE_MARGIN, MAX_SHORTLIST));
   m.lcap = seg_cap(m.kcap, SEG_LDS_CAP);
+  m.redo = b.redo;
   {
     KernelTimer tm("select_scan", st);
     if (b.max_k + REFINE_MARGIN <= WSEL_K && b.Qtot <= SELW_WIDE_MAX)
@@ -3294,6 +3596,13 @@ hipError_t launch_search_multi(const SearchBufs &b, const float *Q, int64_t ldq,
     else
       hipLaunchKernelGGL(k_select_multi, dim3((unsigned)b.Qtot), dim3(512),
                          sel_smem_bytes(m.lcap, m.kcap), st, m);
+  }
+  if (b.redo) {
+    KernelTimer tm("select_redo", st);
+    m.kcap = redo_kcap();
+    m.lcap = seg_cap(m.kcap, SEG_LDS_CAP);
+    hipLaunchKernelGGL(k_select_multi_redo, dim3(redo_grid(b.Qtot)), dim3(512),
+                       sel_smem_bytes(m.lcap, m.kcap), st, m);
   }
   return hipGetLastError();
 }
@@ -3459,6 +3768,7 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   const QuantStore &qs = ix->quant[fmt];
   hipError_t e0 = launch_store_cfg(make_cfg(ix, d_c, d_s, nprobe, k, nq), b.cfg, st);
   if (e0 != hipSuccess) return e0;
+  reset_redo(b.redo, st);
   // coarse first pass on the quantised centroids
   TileQArgs t{};
   t.Qq = (const uint8_t *)Qq;
@@ -3514,7 +3824,7 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   {
     const size_t smem = sel_caps(s, ix->nlist);
     KernelTimer tm("select_q_coarse", st);
-    launch_select(s, nq, smem, st);
+    launch_select(s, nq, smem, b.redo, b.redo ? b.redo + 2 : nullptr, st);
   }
   e = launch_bucketing(ix, b, nq, nprobe, st, QTILE_Q, QTILE_V);
   if (e != hipSuccess) return e;
@@ -3585,7 +3895,7 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   {
     const size_t smem = sel_caps(r, SEG_LDS_CAP);
     KernelTimer tm("select_q_scan", st);
-    launch_select(r, nq, smem, st);
+    launch_select(r, nq, smem, b.redo ? b.redo + 1 : nullptr, b.redo ? b.redo + 2 : nullptr, st);
   }
   return hipGetLastError();
 }
@@ -3625,6 +3935,7 @@ hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const Sea
                             int64_t nq, int32_t nprobe, int32_t k, int32_t rerank_k,
                             int32_t d_rerank, float *qr_hi, float *qr_lo, float *lut, float *dist,
                             int64_t *ids, hipStream_t st) {
+  reset_redo(b.redo, st);
   hipError_t e = launch_bucketing(ix, b, nq, nprobe, st);
   if (e != hipSuccess) return e;
   const int64_t ldqr = pq.d_s;
@@ -3680,7 +3991,7 @@ hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const Sea
   {
     const size_t smem = sel_caps(s, SEG_LDS_CAP);
     KernelTimer tm("select_adc", st);
-    launch_select(s, nq, smem, st);
+    launch_select(s, nq, smem, b.redo ? b.redo + 1 : nullptr, b.redo ? b.redo + 2 : nullptr, st);
   }
   return hipGetLastError();
 }

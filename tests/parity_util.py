@@ -5,7 +5,7 @@ from __future__ import annotations
 import numpy as np
 
 import synth
-from oracle import check, ivf, kmeans
+from oracle import check, ivf, kmeans, pq
 
 
 def oracle_index(X, nlist, d_c, iters, seed, n_train=None):
@@ -60,3 +60,17 @@ def check_search(X, Q, C32, off, ids, d_c, d_s, nprobe, k, got_d, got_i, got_p=N
         check.compare_knn(Q[qi], X, cands[j], got_d[qi], got_i[qi], rd[j], ri[j], d_s,
                           report=rep, tag=f"q{qi}", dist_tol=dist_tol)
     return rep
+
+
+def make_codec(X, M, d_s, opq, seed):
+    """Oracle-trained PQ (or OPQ) codec on X[:, :d_s], rounded to the FP32
+    values the library holds. Returns (R32, codebooks32, codes)."""
+    X64 = X[:, :d_s].astype(np.float64)
+    init = synth.init_rows(len(X), 256, seed, synth.STREAM_PQ)
+    if opq:
+        R, cbs, _ = pq.opq_train64(X64[:4000], M, 3, 3, synth.init_rows(4000, 256, seed, synth.STREAM_PQ))
+    else:
+        R, cbs = np.eye(d_s), pq.pq_train64(X64, M, 4, init_rows=init)
+    R32, cb32 = R.astype(np.float32), cbs.astype(np.float32)
+    codes = pq.pq_encode64(X64 @ R32.astype(np.float64), cb32.astype(np.float64))
+    return R32, cb32, codes

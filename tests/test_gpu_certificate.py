@@ -1,0 +1,188 @@
+"""Certified shortlists (Algorithm 1's linear scan returns the exact k nearest
+of the candidates). Every selection re-measures exactly the candidates whose
+first-pass value, widened by the first pass's error bound, can still reach
+the k nearest. These cases put more such candidates in the band than the
+one-wave list (or the workgroup's slots) holds, so the query must go to the
+re-selection launch; the results must still equal the FP64 oracle's and
+none may be left uncertified."""
+import numpy as np
+import pytest
+
+from oracle import check, ivf, kmeans, pq, precision
+from parity_util import check_search, make_codec, oracle_index
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2305_19435_amd as p
+    return p
+
+
+def offset_rows(seed, d, nq, per, nfar=400):
+    """Queries and, per query, ``per`` rows at squared distances
+    1 + 0.0005 j (j a permutation), all sharing an offset of norm 100, so the
+    FP32 first pass |x|^2 - 2 q.x (near -1e4) errs by ~1e-2 and every near row
+    lies inside the error band of the k-th; plus ``nfar`` far rows."""
+    rng = np.random.default_rng(seed)
+    o = rng.standard_normal(d)
+    o *= 100.0 / np.linalg.norm(o)
+    Q = (o + 0.1 * rng.standard_normal((nq, d))).astype(np.float32)
+    rows = []
+    for i in range(nq):
+        u = rng.standard_normal((per, d))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        s = np.sqrt(1.0 + 0.0005 * rng.permutation(per))
+        rows.append(Q[i].astype(np.float64) + s[:, None] * u)
+    rows.append(o + 3.0 * rng.standard_normal((nfar, d)))
+    return np.concatenate(rows).astype(np.float32), Q
+
+
+def _search(index, Q, d_c, d_s, nprobe, k):
+    dist, gid, probes = index.search(torch.from_numpy(Q).cuda(), d_c, d_s, nprobe, k,
+                                     return_probes=True)
+    torch.cuda.synchronize()
+    return dist.cpu().numpy(), gid.cpu().numpy(), probes.cpu().numpy()
+
+
+@pytest.mark.parametrize("per,k", [(48, 5),      # band of 48 > the one-wave list of 29
+                                   (40, 60),     # workgroup path (k + 8 > 64)
+                                   (200, 60)])   # workgroup path, band past its 128 slots
+def test_scan_band_overflow(lib, per, k):
+    d, nq, nlist = 64, 16, 4
+    X, Q = offset_rows(2305 + per, d, nq, per)
+    C32, a, off, ids = oracle_index(X, nlist, 16, 10, 7)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    try:
+        lib.selection_stats(reset=True)
+        dist, gid, probes = _search(index, Q, 16, d, nlist, k)
+        resel, uncert = lib.selection_stats(reset=True)
+        rep = check_search(X, Q, C32, off, ids, 16, d, nlist, k, dist, gid, got_p=probes)
+        assert rep.ok, rep.problems
+        assert uncert == 0
+        if per != 40:
+            assert resel >= nq // 2    # handed to the re-selection launch
+    finally:
+        index.free()
+
+
+def test_coarse_band_overflow(lib):
+    """64 centroids at squared distances 1 + 0.0005 j from every query, all
+    offset by a norm-100 vector: the coarse first pass cannot separate them,
+    so the nprobe = 4 probes need every centroid re-measured."""
+    rng = np.random.default_rng(19435)
+    d, nq, nlist, nprobe, k = 64, 24, 64, 4, 5
+    o = rng.standard_normal(d)
+    o *= 100.0 / np.linalg.norm(o)
+    base = o + 0.01 * rng.standard_normal(d)
+    u = rng.standard_normal((nlist, d))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    C = (base + np.sqrt(1.0 + 0.0005 * rng.permutation(nlist))[:, None] * u).astype(np.float32)
+    Q = (base + 0.002 * rng.standard_normal((nq, d))).astype(np.float32)
+    X = (np.repeat(C.astype(np.float64), 10, axis=0) +
+         0.05 * rng.standard_normal((nlist * 10, d))).astype(np.float32)
+    a = np.repeat(np.arange(nlist), 10).astype(np.int32)
+    off, ids = kmeans.build_lists(a, nlist)
+    index = lib.IvfIndex.import_ivf(X, C, a)
+    try:
+        lib.selection_stats(reset=True)
+        dist, gid, probes = _search(index, Q, d, d, nprobe, k)
+        resel, uncert = lib.selection_stats(reset=True)
+        rep = check_search(X, Q, C, off, ids, d, d, nprobe, k, dist, gid, got_p=probes)
+        assert rep.ok, rep.problems
+        assert rep.probe_diffs == 0
+        assert uncert == 0 and resel >= nq // 2
+    finally:
+        index.free()
+
+
+def test_precision_band_overflow(lib):
+    """BF16 first pass on offset rows: the quantisation error (~0.1 per
+    vector) and the FP32 rounding bound put all 48 near rows of a query in
+    the band of the re-rank's 8th value."""
+    d, nq, per, nlist, k, rerank = 64, 16, 48, 4, 5, 8
+    X, Q = offset_rows(77, d, nq, per)
+    C32, a, off, ids = oracle_index(X, nlist, 16, 10, 7)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    try:
+        for fmt in ("bf16", "fp8"):
+            index.set_precision(fmt)
+            lib.selection_stats(reset=True)
+            dist, gid, probes = index.search_precision(torch.from_numpy(Q).cuda(), 16, d, nlist,
+                                                       k, fmt, rerank, 0, return_probes=True)
+            torch.cuda.synchronize()
+            resel, uncert = lib.selection_stats(reset=True)
+            dist, gid, probes = dist.cpu().numpy(), gid.cpu().numpy(), probes.cpu().numpy()
+            rd, ri, rp, shortlists = precision.precision_search64(
+                X, Q, C32.astype(np.float64), off, ids, 16, d, nlist, k, fmt, rerank, 0,
+                return_shortlist=True)
+            assert np.array_equal(np.sort(probes, 1), np.sort(rp, 1))
+            rep = check.Report()
+            for qi in range(nq):
+                check.compare_knn(Q[qi], X, shortlists[qi], dist[qi], gid[qi], rd[qi], ri[qi], d,
+                                  report=rep, tag=f"{fmt} q{qi}")
+            assert rep.ok, rep.problems
+            assert uncert == 0 and resel >= nq // 2, (fmt, resel, uncert)
+    finally:
+        index.free()
+
+
+@pytest.mark.parametrize("rerank", [0, 8])
+def test_pq_identical_codes(lib, small_data, rerank):
+    """48 copies of one row next to query 0 share their codes, so their ADC
+    values tie and all lie in the band of the k-th: the result is the
+    copies with the smallest ids, as in the oracle's (distance, id) order."""
+    w, X0, Q = small_data
+    X0 = X0[:3000]
+    dup = np.repeat((Q[0] + np.float32(1e-3)).astype(np.float32)[None, :], 48, axis=0)
+    X = np.concatenate([X0[:1000], dup, X0[1000:]])
+    C32, a, off, ids = oracle_index(X, 8, w.d_c, 6, 3)
+    M = 8
+    R32, cb32, codes = make_codec(X, M, w.d, False, 11)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    index.pq_import(M, w.d, None, cb32, codes)
+    k, nprobe = 5, 2
+    Qs = Q[:8]
+    try:
+        lib.selection_stats(reset=True)
+        dist, gid, probes = index.search_pq(torch.from_numpy(Qs).cuda(), w.d_c, nprobe, M, k,
+                                            rerank_k=rerank, d_rerank=w.d, return_probes=True)
+        torch.cuda.synchronize()
+        resel, uncert = lib.selection_stats(reset=True)
+        dist, gid, probes = dist.cpu().numpy(), gid.cpu().numpy(), probes.cpu().numpy()
+        rd, ri, _, cands, luts = pq.ivfpq_search64(
+            Qs, C32.astype(np.float64), off, ids, codes, R32.astype(np.float64),
+            cb32.astype(np.float64), w.d_c, nprobe, k, rerank_k=rerank, X=X, d_rerank=w.d,
+            forced_probes=probes, return_candidates=True)
+        rep = check.Report()
+        for qi in range(len(Qs)):
+            fn = None if rerank else (
+                lambda lut: (lambda idx: pq.adc_dist64(lut, codes[np.asarray(idx)])))(luts[qi])
+            check.compare_knn(Qs[qi], X, cands[qi], dist[qi], gid[qi], rd[qi], ri[qi], w.d,
+                              report=rep, tag=f"q{qi}", dist64=fn)
+        assert rep.ok, rep.problems
+        assert np.array_equal(gid[0], np.arange(1000, 1000 + k))
+        assert uncert == 0 and resel >= 1
+    finally:
+        index.free()
+
+
+def test_certified_results_unchanged_when_band_is_narrow(lib, small_data):
+    """On ordinary data no query needs re-selection and the counters stay 0."""
+    w, X, Q = small_data
+    C32, a, off, ids = oracle_index(X, w.nlist, w.d_c, 10, w.seed)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    try:
+        lib.selection_stats(reset=True)
+        dist, gid, probes = _search(index, Q, w.d_c, w.d_s, w.nprobe, w.k)
+        resel, uncert = lib.selection_stats(reset=True)
+        rep = check_search(X, Q, C32, off, ids, w.d_c, w.d_s, w.nprobe, w.k, dist, gid,
+                           got_p=probes)
+        assert rep.ok, rep.problems
+        assert uncert == 0
+    finally:
+        index.free()

@@ -4,7 +4,7 @@ import pytest
 
 import synth
 from oracle import check, ivf, pq
-from parity_util import oracle_index
+from parity_util import make_codec, oracle_index
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -16,19 +16,6 @@ def lib():
         pytest.skip("no GPU")
     import paper_2305_19435_amd as p
     return p
-
-
-def make_codec(X, M, d_s, opq, seed):
-    """Oracle-trained codec, rounded to the FP32 values the library holds."""
-    X64 = X[:, :d_s].astype(np.float64)
-    init = synth.init_rows(len(X), 256, seed, synth.STREAM_PQ)
-    if opq:
-        R, cbs, _ = pq.opq_train64(X64[:4000], M, 3, 3, synth.init_rows(4000, 256, seed, synth.STREAM_PQ))
-    else:
-        R, cbs = np.eye(d_s), pq.pq_train64(X64, M, 4, init_rows=init)
-    R32, cb32 = R.astype(np.float32), cbs.astype(np.float32)
-    codes = pq.pq_encode64(X64 @ R32.astype(np.float64), cb32.astype(np.float64))
-    return R32, cb32, codes
 
 
 @pytest.fixture(scope="module")
