@@ -296,6 +296,18 @@ adanns_status adanns_timing_read(const char *kernel, int64_t *launches, double *
 adanns_status adanns_selection_stats(int64_t *reselected, int64_t *uncertified, int32_t reset);
 
 /*
+ * Measurement utility (not part of the method): reads ``bytes`` of device
+ * memory ``buf`` once with 16-byte loads and writes one partial sum per
+ * workgroup to ``partial`` (device, [grid] FP32), the achievable read-only
+ * bandwidth to set beside the scans' rates. Timed under the name
+ * "stream_read" when kernel timing is on (adanns_timing_*).
+ * Requirements: buf 16-byte aligned, bytes a multiple of 16, 1 <= grid <= 65536.
+ * Asynchronous on ``stream``. Errors: ADANNS_EINVAL, ADANNS_EHIP.
+ */
+adanns_status adanns_stream_read(const void *buf, size_t bytes, float *partial, int32_t grid,
+                                 void *stream);
+
+/*
  * Batching form: many search configurations, each with its own index,
  * (d_c, d_s, nprobe, k) and query batch, run as one set of persistent
  * launches over a descriptor table (coarse tiles of every configuration in

@@ -1111,6 +1111,21 @@ adanns_status adanns_timing_read(const char *kernel, int64_t *launches, double *
   return ADANNS_OK;
 }
 
+adanns_status adanns_stream_read(const void *buf, size_t bytes, float *partial, int32_t grid,
+                                 void *stream) {
+  clear_error();
+  ADANNS_REQUIRE(buf != nullptr && partial != nullptr, "buf and partial must be non-NULL");
+  ADANNS_REQUIRE(bytes % 16 == 0 && ((uintptr_t)buf & 15) == 0,
+                 "buf must be 16-byte aligned and bytes a multiple of 16");
+  ADANNS_REQUIRE(grid >= 1 && grid <= 65536, "grid must be in [1, 65536], got %d", grid);
+  adanns_status s = check_async();
+  if (s) return s;
+  if (bytes == 0) return ADANNS_OK;
+  KernelTimer tm("stream_read", (hipStream_t)stream);
+  ADANNS_HIP(launch_stream_read(buf, bytes, partial, grid, (hipStream_t)stream));
+  return ADANNS_OK;
+}
+
 adanns_status adanns_selection_stats(int64_t *reselected, int64_t *uncertified, int32_t reset) {
   clear_error();
   adanns_status s = check_async();

@@ -180,6 +180,11 @@ CfgDev make_cfg(const adanns_index *ix, int32_t d_c, int32_t d_s, int32_t nprobe
 // re-selected with a wider shortlist, [1] queries left uncertified.
 hipError_t read_selection_stats(unsigned long long out[2], bool reset);
 
+// Read-only streaming probe over bytes (a multiple of 16) of buf; out holds
+// one float per workgroup of the grid.
+hipError_t launch_stream_read(const void *buf, size_t bytes, float *out, int32_t grid,
+                              hipStream_t st);
+
 // ---- launch wrappers (kernels.hip) -----------------------------------------
 struct SearchBufs {
   CfgDev *cfg;        // device descriptors (one for an ordinary search)

@@ -1716,7 +1716,7 @@ __global__ __launch_bounds__(512) void k_select_multi_redo(SelMultiArgs m) {
 constexpr int WSEL_K = 64;
 // the one-wave selections keep up to kv + WAVE_MARGIN first-pass candidates
 // (within WSEL_K), kv the number of exact values the query needs
-constexpr int WAVE_MARGIN = 24;
+constexpr int WAVE_MARGIN = 12;
 // candidates re-measured together by k_select_wave: two, with 1024
 // coordinates per pass, keep the kernel within 128 registers, four waves per
 // SIMD (the selection waits on memory latency, so waves in flight count more
@@ -3661,6 +3661,45 @@ __global__ __launch_bounds__(256) void k_row_norm_max(const float *__restrict__ 
     for (int i = 1; i < 8; ++i) m = fmaxf(m, sh[i]);
     atomicMax(out, __float_as_uint(m));
   }
+}
+
+// Read-only streaming probe: every byte of buf read once with 16-byte loads,
+// four in flight per thread, consecutive threads on consecutive 16-byte
+// pieces (each wave reads 1 KB contiguous per load); each workgroup writes
+// the sum of what it read, so that no load can be dropped.
+__global__ __launch_bounds__(256) void k_stream_read(const float4 *__restrict__ buf, int64_t n4,
+                                                     float *__restrict__ out) {
+  __shared__ float sh[4];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (; i + 3 * stride < n4; i += 4 * stride) {
+    const float4 a = buf[i], b = buf[i + stride], c = buf[i + 2 * stride], d = buf[i + 3 * stride];
+    acc.x += (a.x + b.x) + (c.x + d.x);
+    acc.y += (a.y + b.y) + (c.y + d.y);
+    acc.z += (a.z + b.z) + (c.z + d.z);
+    acc.w += (a.w + b.w) + (c.w + d.w);
+  }
+  for (; i < n4; i += stride) {
+    const float4 a = buf[i];
+    acc.x += a.x;
+    acc.y += a.y;
+    acc.z += a.z;
+    acc.w += a.w;
+  }
+  float v = (acc.x + acc.y) + (acc.z + acc.w);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+hipError_t launch_stream_read(const void *buf, size_t bytes, float *out, int32_t grid,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_stream_read, dim3((unsigned)grid), dim3(256), 0, st, (const float4 *)buf,
+                     (int64_t)(bytes / 16), out);
+  return hipGetLastError();
 }
 
 hipError_t launch_row_norm_max(const float *vec, const int64_t *poff, int32_t nlists,
