@@ -139,6 +139,34 @@ adanns_status adanns_search(const adanns_index *index, const float *Q, int64_t n
                             float *dist, int64_t *ids, int32_t *probes, void *stream);
 
 /*
+ * adanns_search for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, bit for bit, but the search scratch (staged
+ * queries, coarse scores, probes, buckets, first-pass values, re-selection
+ * list) lives in a fixed device array of adanns_search_noalloc_max_bytes()
+ * = 64 MiB that the library holds on every GPU it runs on until the process
+ * ends, instead of the index's per-stream workspace. The call allocates
+ * nothing (no hipMalloc / hipFree, no torch allocation, no events: kernel
+ * timing is suspended for it); its first call on a device looks up the
+ * array's device address once.
+ *   Arguments, limits and result conventions: as adanns_search.
+ * Errors: as adanns_search, and ADANNS_EBUDGET (outputs untouched) when the
+ * batch needs more scratch than the array holds (about nq * (top-nprobe list
+ * lengths + nlist + max(d_c, d_s)) * 4 bytes): search fewer queries per call.
+ * Every call on a GPU shares that GPU's array, so calls that overlap on one
+ * GPU (several streams or threads at once) race and must be serialised by
+ * the caller; the array keeps the last call's contents, and every search
+ * clears what it needs cleared itself.
+ */
+adanns_status adanns_search_noalloc(const adanns_index *index, const float *Q, int64_t nq,
+                                    int64_t ldq, int32_t d_c, int32_t d_s, int32_t nprobe,
+                                    int32_t k, float *dist, int64_t *ids, int32_t *probes,
+                                    void *stream);
+
+/* Bytes of the fixed scratch array of adanns_search_noalloc (64 MiB). */
+size_t adanns_search_noalloc_max_bytes(void);
+
+/*
  * Same as adanns_search with the probe lists given instead of computed:
  *   probes device, [nq x nprobe] int32, each in [0, nlist), no repeats
  *          within a row; both are checked (ADANNS_EINVAL), which copies the

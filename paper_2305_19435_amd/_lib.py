@@ -59,6 +59,8 @@ _SIGS = {
     "adanns_selection_stats": (C.c_int, [vp, vp, i32]),
     "adanns_stream_read": (C.c_int, [vp, C.c_size_t, vp, i32, vp]),
     "adanns_search": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, vp, vp, vp, vp]),
+    "adanns_search_noalloc": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, vp, vp, vp, vp]),
+    "adanns_search_noalloc_max_bytes": (C.c_size_t, []),
     "adanns_search_probes": (C.c_int, [vp, vp, i64, i64, i32, i32, vp, i32, vp, vp, vp]),
     "adanns_index_info": (C.c_int, [vp, vp, vp, vp, vp]),
     "adanns_index_lists": (C.c_int, [vp, vp, vp]),

@@ -56,7 +56,16 @@ struct PendingTimer {
 static std::vector<PendingTimer> g_pending;
 static std::map<std::string, std::pair<int64_t, double>> g_totals;
 
-bool timing_on() { return g_timing.load(std::memory_order_relaxed); }
+static thread_local bool t_timers_off = false;
+
+bool timing_on() { return !t_timers_off && g_timing.load(std::memory_order_relaxed); }
+
+// Suspends kernel timing on this thread for its scope.
+struct TimersOff {
+  bool prev;
+  TimersOff() : prev(t_timers_off) { t_timers_off = true; }
+  ~TimersOff() { t_timers_off = prev; }
+};
 
 KernelTimer::KernelTimer(const char *n, hipStream_t s) : name(n), st(s) {
   if (!timing_on()) return;
@@ -512,10 +521,39 @@ adanns_status adanns_ivf_import(const void *X, int64_t n, int32_t d, int64_t ldx
 
 static std::atomic<size_t> g_scratch_cap{kSearchScratchCap};
 
+// Scratch of adanns_search_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends. Host code must not use its name as an
+// address (that is a host-side stand-in): the device address comes from
+// hipGetSymbolAddress, once per device, kept in g_noalloc_ptr.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[kMaxDevices];
+
+// Device address of ``scratch`` on the current device.
+static adanns_status noalloc_scratch(void **out) {
+  int dev = 0;
+  ADANNS_HIP(hipGetDevice(&dev));
+  ADANNS_REQUIRE(dev >= 0 && dev < kMaxDevices, "device %d is beyond the %d supported", dev,
+                 kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *p = nullptr;
+    ADANNS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return ADANNS_OK;
+}
+
+// fixed_base != NULL: the search runs in that caller-fixed scratch of
+// fixed_cap bytes (no allocation, no chunking; a larger need is EBUDGET).
 static adanns_status search_common(const adanns_index *cix, const float *Q, int64_t nq,
                                    int64_t ldq, int32_t d_c, int32_t d_s, int32_t nprobe,
                                    const int32_t *given_probes, int32_t k, float *dist,
-                                   int64_t *ids, int32_t *probes_out, void *stream) {
+                                   int64_t *ids, int32_t *probes_out, void *stream,
+                                   void *fixed_base = nullptr, size_t fixed_cap = 0) {
   adanns_index *ix = const_cast<adanns_index *>(cix);
   const bool coarse = given_probes == nullptr;
   ADANNS_REQUIRE(ix != nullptr, "index is NULL");
@@ -546,12 +584,21 @@ static adanns_status search_common(const adanns_index *cix, const float *Q, int6
     return t;
   };
   int64_t chunk = nq;
-  while (chunk > 1 && scratch_of(chunk) > cap) chunk = (chunk + 1) / 2;
+  if (fixed_base) {
+    const size_t need = scratch_of(nq);
+    if (need > fixed_cap) {
+      set_error("the search needs %zu bytes of scratch, more than the %zu of the allocation-free "
+                "entry point: search fewer queries per call", need, fixed_cap);
+      return ADANNS_EBUDGET;
+    }
+  } else {
+    while (chunk > 1 && scratch_of(chunk) > cap) chunk = (chunk + 1) / 2;
+  }
   for (int64_t r0 = 0; r0 < nq; r0 += chunk) {
     const int64_t m = std::min(chunk, nq - r0);
     size_t total = scratch_of(m);
-    void *base = nullptr;
-    if ((s = get_scratch(ix, st, total, &base))) return s;
+    void *base = fixed_base;
+    if (!fixed_base && (s = get_scratch(ix, st, total, &base))) return s;
     SearchBufs b = carve((char *)base, ix, m, dq_pad, nprobe, coarse, &total);
     b.max_k = k;
     ADANNS_HIP(launch_store_cfg(make_cfg(ix, coarse ? d_c : 1, d_s, nprobe, k, m), b.cfg, st));
@@ -579,6 +626,21 @@ adanns_status adanns_search(const adanns_index *index, const float *Q, int64_t n
   clear_error();
   return search_common(index, Q, nq, ldq, d_c, d_s, nprobe, nullptr, k, dist, ids, probes, stream);
 }
+
+adanns_status adanns_search_noalloc(const adanns_index *index, const float *Q, int64_t nq,
+                                    int64_t ldq, int32_t d_c, int32_t d_s, int32_t nprobe,
+                                    int32_t k, float *dist, int64_t *ids, int32_t *probes,
+                                    void *stream) {
+  clear_error();
+  void *base = nullptr;
+  adanns_status s = noalloc_scratch(&base);
+  if (s) return s;
+  TimersOff no_events;  // kernel timing would create events
+  return search_common(index, Q, nq, ldq, d_c, d_s, nprobe, nullptr, k, dist, ids, probes, stream,
+                       base, kNoAllocScratchBytes);
+}
+
+size_t adanns_search_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
 
 adanns_status adanns_search_probes(const adanns_index *index, const float *Q, int64_t nq,
                                    int64_t ldq, int32_t d_s, int32_t nprobe,
