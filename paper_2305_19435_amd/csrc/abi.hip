@@ -129,7 +129,8 @@ void free_index_memory(adanns_index *ix) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &qsv : ix->quant) {
-    void *pp[] = {qsv.vec, qsv.scale, qsv.cent, qsv.cent_scale, qsv.emax, qsv.cent_emax};
+    void *pp[] = {qsv.vec, qsv.scale, qsv.cent, qsv.cent_scale, qsv.emax, qsv.cent_emax,
+                  qsv.rerr};
     for (void *p : pp)
       if (p) (void)hipFree(p);
     qsv = QuantStore{};
@@ -985,7 +986,7 @@ adanns_status adanns_set_precision(adanns_index *ix, int32_t fmt, void *stream) 
   QuantStore q;
   const size_t eb = fmt == ADANNS_BF16 ? 2 : 1;
   auto fail = [&](adanns_status e) {
-    void *pp[] = {q.vec, q.scale, q.cent, q.cent_scale, q.emax, q.cent_emax};
+    void *pp[] = {q.vec, q.scale, q.cent, q.cent_scale, q.emax, q.cent_emax, q.rerr};
     for (void *p : pp)
       if (p) (void)hipFree(p);
     return e;
@@ -998,7 +999,8 @@ adanns_status adanns_set_precision(adanns_index *ix, int32_t fmt, void *stream) 
       return fail(s);
   }
   if ((s = dmalloc(ix, (void **)&q.emax, sizeof(float))) ||
-      (s = dmalloc(ix, (void **)&q.cent_emax, sizeof(float))))
+      (s = dmalloc(ix, (void **)&q.cent_emax, sizeof(float))) ||
+      (s = dmalloc(ix, (void **)&q.rerr, (size_t)ix->rows_pad * sizeof(float))))
     return fail(s);
   if (launch_quantize_store(ix, fmt, q, st) || launch_quant_err_max(ix, fmt, q, st)) {
     set_error("HIP error while quantising the vectors");

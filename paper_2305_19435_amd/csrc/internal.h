@@ -96,6 +96,7 @@ struct QuantStore {
   void *cent = nullptr;         // one-list slab layout of nl_pad rows
   float *cent_scale = nullptr;  // [nl_pad] (e4m3 only)
   float *emax = nullptr;        // [1] largest |x - dequantised x| over the rows
+  float *rerr = nullptr;        // [rows_pad] |x - dequantised x| of each row (layout order)
   float *cent_emax = nullptr;   // [1] the same over the centroids
 };
 }  // namespace adanns

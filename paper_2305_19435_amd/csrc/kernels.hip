@@ -704,6 +704,7 @@ struct SelArgs {
   int64_t ldqq;
   const float *qemax;      // largest |x - dequantised x| of the stored rows, or NULL
                            // (enables the FP32 re-rank's quantisation bound)
+  const float *qrerr;      // |x - dequantised x| of each stored row (layout order), or NULL
   const float *qerr;       // the same, for the first pass's rounding bound, or NULL
   const float *xmax2;      // largest squared FP32 row norm (with qerr), or NULL
   int64_t qnpad;           // coarse-quant: rows of the one-list layout
@@ -738,6 +739,7 @@ struct FpBound {
   int32_t kind;
   float B, c1, c2, qn;
   float eq;  // quantised modes: |q - q^| over the first measure's prefix, else -1
+  float qq;  // quantised modes: |q^|^2 over that prefix (FP32; the first pass omits it)
   __device__ float of(float f) const {
     if (kind == 1) return B;
     f = fmaxf(f, 0.f);
@@ -1129,7 +1131,7 @@ __device__ __forceinline__ void measureB_vec_rq(const SelArgs &a, const CandLoc 
 // Norms are rounded up by 1e-3 relative where the bound is not already four
 // times the classical one.
 __device__ FpBound wave_fp_bound(const SelArgs &a, int64_t q, int lane) {
-  FpBound fb{0, 0.f, 0.f, 0.f, 0.f, -1.f};
+  FpBound fb{0, 0.f, 0.f, 0.f, 0.f, -1.f, 0.f};
   const int d = a.d_dot;
   if (a.mode == SEL_ADC) {
     const float ADANNS_GLOBAL_AS *qh = (const float ADANNS_GLOBAL_AS *)(a.qr_hi + q * a.ldqr);
@@ -1159,6 +1161,7 @@ __device__ FpBound wave_fp_bound(const SelArgs &a, int64_t q, int lane) {
       ee += __shfl_xor(ee, o);
     }
     fb.eq = sqrtf(ee);
+    fb.qq = qq;
     if (a.qerr != nullptr && a.xmax2 != nullptr) {
       const float X = (sqrtf(ldg(a.xmax2)) + ldg(a.qerr)) * 1.001f, qn = sqrtf(qq) * 1.001f;
       fb.B = 4.f * (float)(d + 2) * 0x1p-24f * (X * X + 2.f * qn * X);
@@ -1344,6 +1347,119 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
         }
       };
       const FpBound fb = s_fb;
+      // Precision form (quantised first pass, then the exact FP32 distance
+      // re-ranks the K2 nearest by exact quantised distance): the final k
+      // are found without materialising that shortlist S*. With B the first
+      // pass's bound, a candidate with f < v_{K2+1} - 2B is surely in S*
+      // (nearer than every candidate outside the first pass's K2 smallest)
+      // and one with f > v_K2 + 2B surely not. Its FP32 distance is at least
+      // (sqrt(f - B) - |q - q^| - |x - x^|)^2 (triangle inequality; the
+      // second norm is the candidate's own row's quantisation error). The k
+      // nearest by first pass (surely in S*) are measured in FP32; U, the
+      // largest of those, bounds the k-th FP32 distance of S* from above, so
+      // only sure candidates whose lower bound reaches U are measured. If a
+      // candidate that is not surely in S* could reach U, the general path
+      // below decides S* exactly instead.
+      if (a.mode == SEL_QUANT && a.stageB && a.qrerr != nullptr && a.qerr != nullptr &&
+          a.d_B == a.d_dot && fb.kind == 1 && L > a.K2 && a.kout <= a.K2 && a.kout <= a.kcap) {
+        __shared__ int s_qr;
+        __shared__ uint32_t s_above;
+        const float B = fb.B;
+        uint32_t T2, need2, neq2;
+        radix((uint32_t)a.K2, T2, need2, neq2);
+        const float vK2 = comp_value((uint64_t)T2 << 32);
+        if (tid == 0) s_above = 0xffffffffu;
+        __syncthreads();
+        if (neq2 <= need2) {  // the smallest key above T2 is v_{K2+1}
+          uint32_t mk = 0xffffffffu;
+          for (int64_t i = tid; i < L; i += blockDim.x) {
+            const uint32_t kk = order_key(src[i]);
+            if (kk > T2 && kk < mk) mk = kk;
+          }
+          atomicMin(&s_above, mk);
+        }
+        __syncthreads();
+        const float vK2p1 = neq2 > need2 ? vK2 : comp_value((uint64_t)s_above << 32);
+        const float sure_thr = vK2p1 - 2.f * B, amb_hi = vK2 + 2.f * B;
+        // the k nearest by first pass, measured in FP32
+        take_smallest(a.kout);
+        if (tid == 0) s_qr = 1;
+        __syncthreads();
+        const float ADANNS_GLOBAL_AS *qg = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
+        for (int c = wv; c < a.kout; c += nwv) {
+          const CandLoc Lc = locate(a, false, q, seg0, cpos[c]);
+          float S = 0.f, C = 0.f;
+          measureB(a, false, Lc, qg, lane, S, C);
+          wave_reduce_pair(S, C);
+          if (lane == 0) {
+            chi[c] = S;
+            clo[c] = C;
+            if (!(src[cpos[c]] < sure_thr)) s_qr = 0;  // not surely in S*: general path
+          }
+        }
+        __syncthreads();
+        if (tid == 0) {
+          float u = 0.f;
+          for (int c = 0; c < a.kout; ++c) u = fmaxf(u, chi[c] + clo[c]);
+          s_up = u * (1.f + 0x1p-20f);
+          s_slot = 0;
+        }
+        __syncthreads();
+        if (s_qr) {
+          // the first pass omits |q^|^2: the exact quantised distance is at
+          // least f - B + |q^|^2, the FP32 sum of squares |q^|^2 being off by
+          // at most 4 (d + 2) 2^-24 of itself
+          const float qlo = fb.qq * (1.f - 4.f * (float)(a.d_dot + 2) * 0x1p-24f);
+          const float sU = sqrtf(s_up);
+          const float eq = fb.eq * 1.001f;
+          const float reach = sU + eq + ldg(a.qerr) * 1.001f;
+          const float fmax = fminf(amb_hi, reach * reach * 1.001f + B - qlo);
+          for (int64_t i = tid; i < L; i += blockDim.x) {
+            const float f = src[i];
+            if (!(f <= fmax)) continue;
+            const CandLoc Lc = locate(a, false, q, seg0, i);
+            const float lo = sqrtf(fmaxf(f - B + qlo, 0.f)) - eq - ldg(a.qrerr + Lc.row) * 1.001f;
+            if (lo <= sU) {
+              const int slot = atomicAdd(&s_slot, 1);
+              if (slot < a.kcap) cpos[slot] = i;
+              if (!(f < sure_thr)) s_qr = 0;
+            }
+          }
+        }
+        __syncthreads();
+        const int nM = s_slot;
+        if (s_qr && nM <= a.kcap && nM >= a.kout) {
+          for (int c = wv; c < nM; c += nwv) {
+            const CandLoc Lc = locate(a, false, q, seg0, cpos[c]);
+            float S = 0.f, C = 0.f;
+            measureB(a, false, Lc, qg, lane, S, C);
+            wave_reduce_pair(S, C);
+            if (lane == 0) {
+              chi[c] = S;
+              clo[c] = C;
+              cid[c] = Lc.id;
+              cg[c] = Lc.gpack;
+            }
+          }
+          int P2 = 1;
+          while (P2 < nM) P2 <<= 1;
+          for (int c = nM + tid; c < P2; c += blockDim.x) {
+            chi[c] = __builtin_inff();
+            clo[c] = 0.f;
+            cid[c] = INT64_MAX;
+            cg[c] = -1;
+          }
+          bitonic_sort(chi, clo, cid, cg, P2);
+          const int64_t ldo_ = a.ldo ? a.ldo : a.kout;
+          for (int j = tid; j < a.kout; j += blockDim.x) {
+            a.out_dist[q * ldo_ + j] = chi[j];
+            a.out_ids[q * ldo_ + j] = cid[j];
+          }
+          if (tid == 0) s_ncand = -4;  // done
+          return;
+        }
+        __syncthreads();
+      }
       if (fb.kind == 0) {
         // no error bound known: the plain margin, not certified
         take_smallest(a.K1);
@@ -1405,7 +1521,7 @@ __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
       select_from((const float ADANNS_GLOBAL_AS *)seg);
     __syncthreads();
     ncand = s_ncand;
-    if (ncand == -1) return;  // handed over (uniform over the block)
+    if (ncand == -1 || ncand == -4) return;  // handed over / done (uniform over the block)
     rounds = ncand == -2;
   }
   __syncthreads();
@@ -1594,6 +1710,197 @@ __global__ __launch_bounds__(512) void k_select_refine_redo(SelArgs a) {
   for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
     select_body(b, list[i]);
     __syncthreads();  // LDS reused by the next query
+  }
+}
+
+// Precision-form re-rank of a deep shortlist (SEL_QUANT with the FP32
+// re-rank, K2 > the one-wave list), one 256-thread workgroup per query, in
+// the common case; every other case is handed to the re-selection launch
+// (select_body: the same reasoning with exact order statistics, else the
+// shortlist decided exactly). With f the quantised first-pass values of the
+// query's candidates and B their error bound (wave_fp_bound):
+//  * one 2048-bin histogram of f (equal widths between the segment's min and
+//    max) places ranks kout, K2 and K2 + 1 in bins; bin edges widened by one
+//    bin on each side give v_{K2+1} >= lo and v_K2 <= hi, so a candidate with
+//    f < lo - 2B is surely in the shortlist S* (the K2 nearest by exact
+//    quantised distance) and one with f > hi + 2B surely not;
+//  * the candidates in the bins up to rank kout (all surely in S*, else the
+//    query is handed over) are measured in FP32; U, their kout-th smallest
+//    distance, bounds the kout-th FP32 distance of S* from above;
+//  * a candidate's FP32 distance is at least
+//    (sqrt(f - B + |q^|^2) - |q - q^| - |x - x^|)^2, so only those whose
+//    bound reaches U are measured (all must be surely in S*), and the kout
+//    nearest of them are the result.
+constexpr int QRR_BINS = 2048;
+constexpr int QRR_CAP = 256;
+
+__global__ __launch_bounds__(256) void k_select_qrerank(SelArgs a) {
+  __shared__ uint32_t hist[QRR_BINS];
+  __shared__ int64_t cpos[QRR_CAP], cid[QRR_CAP], cg[QRR_CAP];
+  __shared__ float chi[QRR_CAP], clo[QRR_CAP];
+  __shared__ uint32_t sh32[16];
+  __shared__ FpBound s_fb;
+  __shared__ uint32_t s_kmin, s_kmax;
+  __shared__ int s_cnt, s_bad, s_bk, s_b2, s_b3;
+  __shared__ float s_U;
+  const int64_t q = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+  const int kout = a.kout, K2 = a.K2;
+  const int64_t seg0 = a.seg_off[q], L = a.seg_off[q + 1] - seg0;
+  const float ADANNS_GLOBAL_AS *src = (const float ADANNS_GLOBAL_AS *)(a.D + seg0);
+  const int64_t ldo = a.ldo ? a.ldo : a.kout;
+  auto hand_over = [&]() {
+    if (tid == 0) push_redo(a.redo_cnt, a.redo_list, q + a.redo_q0);
+  };
+  if (L <= (int64_t)K2 + REFINE_MARGIN) {  // short segments: the general path
+    hand_over();
+    return;
+  }
+  if (wv == 0) {
+    const FpBound fb = wave_fp_bound(a, q, lane);
+    if (lane == 0) s_fb = fb;
+  }
+  if (tid == 0) {
+    s_kmin = 0xffffffffu;
+    s_kmax = 0u;
+    s_cnt = 0;
+    s_bad = 0;
+  }
+  for (int i = tid; i < QRR_BINS; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const FpBound fb = s_fb;
+  if (fb.kind != 1) {
+    hand_over();
+    return;
+  }
+  {
+    uint32_t kmin = 0xffffffffu, kmax = 0u;
+    for (int64_t i = tid; i < L; i += blockDim.x) {
+      const uint32_t kk = order_key(src[i]);
+      kmin = kk < kmin ? kk : kmin;
+      kmax = kk > kmax ? kk : kmax;
+    }
+    atomicMin(&s_kmin, kmin);
+    atomicMax(&s_kmax, kmax);
+  }
+  __syncthreads();
+  const float fmin = comp_value((uint64_t)s_kmin << 32), fmax = comp_value((uint64_t)s_kmax << 32);
+  const float w = (fmax - fmin) / (float)QRR_BINS;
+  const float inv = fmax > fmin ? (float)QRR_BINS / (fmax - fmin) : 0.f;
+  auto bin_of = [&](float f) { return min(QRR_BINS - 1, max(0, (int)((f - fmin) * inv))); };
+  for (int64_t i = tid; i < L; i += blockDim.x) atomicAdd(&hist[bin_of(src[i])], 1u);
+  __syncthreads();
+  {
+    constexpr int per = QRR_BINS / 256;
+    uint32_t local = 0;
+    for (int e = 0; e < per; ++e) local += hist[tid * per + e];
+    uint32_t c = block_excl_scan<uint32_t>(local, sh32, nullptr);
+    for (int e = 0; e < per; ++e) {
+      const uint32_t hb = hist[tid * per + e], b = tid * per + e;
+      if (c < (uint32_t)kout && (uint32_t)kout <= c + hb) s_bk = b;
+      if (c < (uint32_t)K2 && (uint32_t)K2 <= c + hb) s_b2 = b;
+      if (c < (uint32_t)K2 + 1 && (uint32_t)K2 + 1 <= c + hb) s_b3 = b;
+      c += hb;
+    }
+  }
+  __syncthreads();
+  const float B = fb.B;
+  const float sure_thr = (fmin + (float)(s_b3 - 1) * w) - 2.f * B;  // below: surely in S*
+  const float amb_hi = (fmin + (float)(s_b2 + 2) * w) + 2.f * B;    // above: surely not
+  const int bk = s_bk;
+  // the candidates of the bins up to rank kout
+  for (int64_t i = tid; i < L; i += blockDim.x) {
+    const float f = src[i];
+    if (bin_of(f) <= bk) {
+      const int slot = atomicAdd(&s_cnt, 1);
+      if (slot < QRR_CAP) cpos[slot] = i;
+      if (!(f < sure_thr)) s_bad = 1;
+    }
+  }
+  __syncthreads();
+  const int c0 = s_cnt;
+  if (s_bad || c0 > QRR_CAP || c0 < kout) {
+    hand_over();
+    return;
+  }
+  const float ADANNS_GLOBAL_AS *qg = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
+  // this lane's query coordinates 4 lane + 256 u (+0..3), read once
+  const bool rq = a.d_B <= 2048;
+  float4 q4[8];
+  if (rq) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int dim = 4 * lane + 256 * u + e;
+        v[e] = dim < a.d_B ? qg[dim] : 0.f;
+      }
+      q4[u] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  }
+  auto measure = [&](int n) {  // FP32 distances of slots [0, n), sorted
+    for (int c = wv; c < n; c += nwv) {
+      const CandLoc Lc = locate(a, false, q, seg0, cpos[c]);
+      float S = 0.f, C = 0.f;
+      if (rq)
+        measureB_vec_rq(a, Lc, q4, lane, S, C);
+      else
+        measureB(a, false, Lc, qg, lane, S, C);
+      wave_reduce_pair(S, C);
+      if (lane == 0) {
+        chi[c] = S;
+        clo[c] = C;
+        cid[c] = Lc.id;
+        cg[c] = Lc.gpack;
+      }
+    }
+    int P2 = 1;
+    while (P2 < n) P2 <<= 1;
+    __syncthreads();
+    for (int c = n + tid; c < P2; c += blockDim.x) {
+      chi[c] = __builtin_inff();
+      clo[c] = 0.f;
+      cid[c] = INT64_MAX;
+      cg[c] = -1;
+    }
+    bitonic_sort(chi, clo, cid, cg, P2);
+  };
+  measure(c0);
+  if (tid == 0) {
+    s_U = (chi[kout - 1] + clo[kout - 1]) * (1.f + 0x1p-20f);
+    s_cnt = 0;
+  }
+  __syncthreads();
+  // the candidates whose FP32 lower bound reaches U
+  {
+    const float qlo = fb.qq * (1.f - 4.f * (float)(a.d_dot + 2) * 0x1p-24f);
+    const float sU = sqrtf(s_U);
+    const float eq = fb.eq * 1.001f;
+    const float reach = sU + eq + ldg(a.qerr) * 1.001f;
+    const float flim = fminf(amb_hi, reach * reach * 1.001f + B - qlo);
+    for (int64_t i = tid; i < L; i += blockDim.x) {
+      const float f = src[i];
+      if (!(f <= flim)) continue;
+      const CandLoc Lc = locate(a, false, q, seg0, i);
+      const float lo = sqrtf(fmaxf(f - B + qlo, 0.f)) - eq - ldg(a.qrerr + Lc.row) * 1.001f;
+      if (lo <= sU) {
+        const int slot = atomicAdd(&s_cnt, 1);
+        if (slot < QRR_CAP) cpos[slot] = i;
+        if (!(f < sure_thr)) s_bad = 1;
+      }
+    }
+  }
+  __syncthreads();
+  const int nM = s_cnt;
+  if (s_bad || nM > QRR_CAP || nM < kout) {
+    hand_over();
+    return;
+  }
+  measure(nM);
+  for (int j = tid; j < kout; j += blockDim.x) {
+    a.out_dist[q * ldo + j] = chi[j];
+    a.out_ids[q * ldo + j] = cid[j];
   }
 }
 
@@ -3305,6 +3612,9 @@ static void launch_select(SelArgs s, int64_t nq, size_t smem, int32_t *redo_cnt,
   if (s.K1 <= WSEL_K && s.kout <= WSEL_K &&
       (measure <= 96 * 1024 || (many && measure <= 512 * 1024)))
     hipLaunchKernelGGL(k_select_refine_wave, dim3((unsigned)cdiv(nq, 4)), dim3(256), 0, st, s, nq);
+  else if (s.mode == SEL_QUANT && s.stageB && s.qrerr != nullptr && s.qerr != nullptr &&
+           s.d_B == s.d_dot && s.kout <= s.K2 && s.kout <= QRR_CAP && redo_cnt != nullptr)
+    hipLaunchKernelGGL(k_select_qrerank, dim3((unsigned)nq), dim3(256), 0, st, s);
   else
     hipLaunchKernelGGL(k_select_refine, dim3((unsigned)nq), dim3(512), smem, st, s);
   if (redo_cnt) {
@@ -3743,7 +4053,8 @@ __global__ __launch_bounds__(256) void k_quant_err_max(const float *__restrict__
                                                        const void *__restrict__ qvec,
                                                        const float *__restrict__ qscale,
                                                        int32_t fmt, const int64_t *__restrict__ poff,
-                                                       int32_t d_pad, uint32_t *__restrict__ out) {
+                                                       int32_t d_pad, uint32_t *__restrict__ out,
+                                                       float *__restrict__ rerr) {
   __shared__ float sh[8];
   const int h = blockIdx.x, half = threadIdx.x >> 5, l = threadIdx.x & 31;
   const int64_t p0 = poff[h], np = poff[h + 1] - p0;
@@ -3761,6 +4072,7 @@ __global__ __launch_bounds__(256) void k_quant_err_max(const float *__restrict__
     }
     for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
     best = fmaxf(best, sqrtf(s));
+    if (rerr != nullptr && l == 0) rerr[p0 + r] = sqrtf(s);
   }
   if (l == 0) sh[half] = best;
   __syncthreads();
@@ -3776,7 +4088,7 @@ hipError_t launch_quant_err_max(const adanns_index *ix, int32_t fmt, const Quant
   hipError_t e = hipMemsetAsync(qs.emax, 0, sizeof(float), st);
   if (e != hipSuccess || ix->nlist == 0) return e;
   hipLaunchKernelGGL(k_quant_err_max, dim3((unsigned)ix->nlist), dim3(256), 0, st, ix->vec,
-                     qs.vec, qs.scale, fmt, ix->poff, ix->d_pad, (uint32_t *)qs.emax);
+                     qs.vec, qs.scale, fmt, ix->poff, ix->d_pad, (uint32_t *)qs.emax, qs.rerr);
   return hipGetLastError();
 }
 
@@ -3785,7 +4097,8 @@ hipError_t launch_quant_err_max_cent(const adanns_index *ix, int32_t fmt, const 
   hipError_t e = hipMemsetAsync(qs.cent_emax, 0, sizeof(float), st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_quant_err_max, dim3(1), dim3(256), 0, st, ix->cent_slab, qs.cent,
-                     qs.cent_scale, fmt, poff2, ix->d_cb_pad, (uint32_t *)qs.cent_emax);
+                     qs.cent_scale, fmt, poff2, ix->d_cb_pad, (uint32_t *)qs.cent_emax,
+                     (float *)nullptr);
   return hipGetLastError();
 }
 
@@ -3928,6 +4241,7 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   // (e4m3's quantisation error spans the whole shortlist: no bound)
   r.qemax = fmt == 1 ? qs.emax : nullptr;
   r.qerr = qs.emax;
+  r.qrerr = qs.rerr;
   r.xmax2 = ix->xmax2;
   r.out_dist = dist;
   r.out_ids = ids;

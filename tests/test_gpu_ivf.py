@@ -69,13 +69,18 @@ def test_search_parity(small, d_c, d_s, nprobe, k):
 
 
 def test_exhaustive_equals_exact(small):
-    from oracle import exact
+    """nprobe = nlist and d_s = d: the search is exact k-NN (Section 3), so
+    the result must equal brute force under the tie-aware rules."""
+    from oracle import check, exact
     w, X, Q, C32, off, ids, index = small
     dist, gid, _ = _run(index, Q, w.d_c, w.d, w.nlist, w.k)
     De, Ie = exact.exact_knn64(X, Q, w.k)
-    mism = (gid != Ie).sum()
-    assert mism == 0 or np.all(np.abs(De[gid != Ie] - De[gid != Ie]) == 0)
-    np.testing.assert_allclose(dist, De, rtol=1e-5)
+    rep = check.Report()
+    every = np.arange(len(X))
+    for qi in range(len(Q)):
+        check.compare_knn(Q[qi], X, every, dist[qi], gid[qi], De[qi], Ie[qi], w.d, report=rep,
+                          tag=f"q{qi}")
+    assert rep.ok, rep.problems
 
 
 def test_edge_query_counts(small):

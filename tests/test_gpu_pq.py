@@ -82,10 +82,13 @@ def test_pq_train_matches_oracle(lib, small_data):
     R, cb, codes = index.pq_codec(M, w.d)
     assert np.array_equal(R, np.eye(w.d, dtype=np.float32))
     ref_cb = pq.pq_train64(X, M, iters, init_rows=init)
-    # Lloyd in FP32 vs FP64 may assign a near-tie point differently, which
-    # moves the two codewords involved; every other codeword must agree
-    close = np.all(np.abs(cb - ref_cb) <= 2e-5, axis=2)
-    assert close.mean() >= 0.98, close.mean()
+    # after several rounds a near-tie assignment (FP32 vs FP64) may have
+    # moved codewords apart; the training objective must agree regardless
+    # (the exact one-round comparison is test_pq_train_one_round_traced)
+    Xf = X.astype(np.float64)
+    got_j = pq.distortion64(Xf, pq.pq_encode64(Xf, cb.astype(np.float64)), cb.astype(np.float64))
+    ref_j = pq.distortion64(Xf, pq.pq_encode64(Xf, ref_cb), ref_cb)
+    assert abs(got_j - ref_j) <= 1e-3 * ref_j, (got_j, ref_j)
     ref_codes = pq.pq_encode64(X, cb.astype(np.float64))
     diff = np.argwhere(codes != ref_codes)
     dsub = w.d // M
@@ -117,8 +120,10 @@ def test_pq_train_with_rotation(lib, small_data):
     assert np.array_equal(R2, R)
     Y = X.astype(np.float64) @ R.astype(np.float64)
     ref_cb = pq.pq_train64(Y[rows], M, iters, init_rows=init)
-    close = np.all(np.abs(cb - ref_cb) <= 2e-5, axis=2)
-    assert close.mean() >= 0.98, close.mean()
+    got_j = pq.distortion64(Y[rows], pq.pq_encode64(Y[rows], cb.astype(np.float64)),
+                            cb.astype(np.float64))
+    ref_j = pq.distortion64(Y[rows], pq.pq_encode64(Y[rows], ref_cb), ref_cb)
+    assert abs(got_j - ref_j) <= 1e-3 * ref_j, (got_j, ref_j)
     ref_codes = pq.pq_encode64(Y, cb.astype(np.float64))
     diff = np.argwhere(codes != ref_codes)
     dsub = w.d // M
@@ -128,6 +133,44 @@ def test_pq_train_with_rotation(lib, small_data):
         dr = ((y - cb[m, ref_codes[j, m]]) ** 2).sum()
         assert abs(dg - dr) <= 1e-5 * max(dr, 1e-12)
     assert len(diff) <= 0.001 * codes.size
+    index.free()
+
+
+@pytest.mark.parametrize("rotate", [False, True])
+def test_pq_train_one_round_traced(lib, small_data, rotate):
+    """One Lloyd round per block from the same initial codewords (the
+    training rows' sub-vectors given by init_rows): every GPU codeword equals
+    the oracle's mean to FP32 rounding, except the codewords of clusters that
+    a near-tie row (best two squared distances within 1e-5 relative, where
+    FP32 and FP64 may choose differently) joins or leaves."""
+    w, X, Q = small_data
+    C32, a, off, ids = oracle_index(X, w.nlist, w.d_c, 5, w.seed)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    M = 8
+    dsub = w.d // M
+    R = synth.random_rotation(w.d, w.seed, tag=5) if rotate else None
+    rows = synth.subsample_rows(w.n, 5000, w.seed, tag=6)
+    init = synth.init_rows(len(rows), 256, w.seed, synth.STREAM_PQ, tag=7)
+    index.pq_train(torch.from_numpy(X).cuda(), M, w.d, 1, init, train_rows=rows, R=R)
+    _, cb, _ = index.pq_codec(M, w.d)
+    Y = X[rows].astype(np.float64)
+    if rotate:
+        Y = Y @ R.astype(np.float64)
+    ref_cb = pq.pq_train64(Y, M, 1, init_rows=init)
+    traced = 0
+    for m in range(M):
+        ym = Y[:, m * dsub:(m + 1) * dsub]
+        c0 = ym[init]                                   # the common initial codewords
+        dd = ((ym[:, None, :] - c0[None, :, :]) ** 2).sum(-1)
+        two = np.sort(dd, axis=1)[:, :2]
+        near = (two[:, 1] - two[:, 0]) <= 1e-5 * np.maximum(two[:, 1], 1e-30)
+        touched = set()
+        for j in np.flatnonzero(near):                  # codewords a near-tie row may choose
+            touched |= set(np.flatnonzero(dd[j] <= two[j, 0] * (1 + 1e-5) + 1e-30).tolist())
+        bad = np.flatnonzero(np.any(np.abs(cb[m] - ref_cb[m]) > 2e-6, axis=1))
+        assert set(bad.tolist()) <= touched, (m, sorted(set(bad.tolist()) - touched))
+        traced += len(bad)
+    assert traced <= 0.01 * M * 256
     index.free()
 
 
