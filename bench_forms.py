@@ -70,11 +70,15 @@ def precision_form(args, lib, torch, log):
     torch.cuda.empty_cache()
     res = {}
     k = w.k
-    sample = np.arange(min(args.cpu_sample, nq))
+    # recall over a sample large enough to resolve 0.2 percentage points
+    # (one missed neighbour in 2,000 queries is 0.005 pp)
+    sample = np.unique(np.linspace(0, nq - 1, min(max(args.cpu_sample, 2000), nq))
+                       .round().astype(np.int64))
+    Qs_d = Qd[torch.from_numpy(sample).cuda()]
     lib.timing_reset()
     lib.timing_enable(True)
     t = _timed(torch, lambda: index.search(Qd, d_c, w.d_s, nprobe, k), args.steps, args.warmup)
-    _, ids32 = index.search(Qd[: len(sample)], d_c, w.d_s, nprobe, k)
+    _, ids32 = index.search(Qs_d, d_c, w.d_s, nprobe, k)
     res["fp32"] = {"qps": nq / t, "ms_per_step": t * 1e3,
                    "kernels_ms": _kernel_ms(lib, ["tile_dist_scan", "select_scan"])}
     gpu_ids = {"fp32": ids32.cpu().numpy()}
@@ -84,12 +88,16 @@ def precision_form(args, lib, torch, log):
         for R in reranks:
             fmt = f"{fmt0}_rerank{R}"
             lib.timing_reset()
+            lib.selection_stats(reset=True)
             t = _timed(torch, lambda: index.search_precision(Qd, d_c, w.d_s, nprobe, k, fmt0, R),
                        args.steps, args.warmup)
-            dd, ii = index.search_precision(Qd[: len(sample)], d_c, w.d_s, nprobe, k, fmt0, R)
+            resel, uncert = lib.selection_stats(reset=True)
+            dd, ii = index.search_precision(Qs_d, d_c, w.d_s, nprobe, k, fmt0, R)
             res[fmt] = {"qps": nq / t, "ms_per_step": t * 1e3, "rerank": R,
                         "kernels_ms": _kernel_ms(lib, ["tile_q_coarse", "select_q_coarse",
-                                                       "tile_q_scan", "select_q_scan"])}
+                                                       "tile_q_scan", "select_q_scan"]),
+                        "reselected_per_step": resel / (args.steps + args.warmup),
+                        "uncertified": uncert}
             gpu_ids[fmt] = ii.cpu().numpy()
             res[fmt]["dist_sample"] = dd.cpu().numpy()
     lib.timing_enable(False)
@@ -107,13 +115,20 @@ def precision_form(args, lib, torch, log):
             err = max(err, float(np.max(np.abs(dd[r][ok] - d64) / d64)))
         res[fmt]["max_rel_dist_err"] = err
         res[fmt]["recall_minus_fp32_pp"] = 100 * (res[fmt]["recall_at_10"] - res["fp32"]["recall_at_10"])
-    ok = [f for f in res if f != "fp32" and res[f]["recall_minus_fp32_pp"] >= -0.2]
-    best = max(ok or [f for f in res if f != "fp32"], key=lambda f: res[f]["qps"])
+    # the headline is the configured re-rank depth (the top-256 of the
+    # image-retrieval precision workload); other depths are reported beside it
+    at_depth = [f for f in res if f != "fp32" and res[f]["rerank"] == args.rerank]
+    ok = [f for f in at_depth if res[f]["recall_minus_fp32_pp"] >= -0.2]
+    best = max(ok or at_depth, key=lambda f: res[f]["qps"])
     out = {"metric": "QPS of the precision form (first pass BF16 / FP8-e4m3, FP32 re-rank)",
            "value": round(res[best]["qps"], 1), "unit": "queries/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
            "dtype": best.split("_")[0], "data": "synthetic", "vs_baseline": None,
            "best_setting": best,
+           "fp32_qps": round(res["fp32"]["qps"], 1),
+           "beats_fp32_at_depth": {f: bool(res[f]["qps"] > res["fp32"]["qps"] and
+                                           res[f]["recall_minus_fp32_pp"] >= -0.2)
+                                   for f in at_depth},
            "config": {"workload": f"imagenet1k precision form: N={n} d={w.d} nq={nq} nlist={w.nlist} "
                                   f"d_c={d_c} d_s={w.d_s} nprobe={nprobe} k={k} rerank={args.rerank}",
                       "recall_sample_queries": int(len(sample))},

@@ -1188,6 +1188,39 @@ __device__ __forceinline__ void push_redo(int32_t *cnt, int32_t *list, int64_t q
   atomicAdd(&g_sel_stats[0], 1ull);
 }
 
+// measureB_vec_rq for two candidates at once (both rows' loads in flight);
+// each row's order of accumulation as in measureB_vec_rq, so the same bits.
+__device__ __forceinline__ void measureB_vec_rq2(const SelArgs &a, const CandLoc &L0,
+                                                 const CandLoc &L1, const float4 *q4, int lane,
+                                                 float &S0, float &C0, float &S1, float &C1) {
+  const int d = a.d_B;
+  const float *b0 = a.rows ? a.rows + L0.row * a.d_pad
+                           : a.vec + L0.p0 * a.d_pad + (L0.row - L0.p0) * SLAB;
+  const float *b1 = a.rows ? a.rows + L1.row * a.d_pad
+                           : a.vec + L1.p0 * a.d_pad + (L1.row - L1.p0) * SLAB;
+  const int64_t n0 = a.rows ? 1 : L0.npad, n1 = a.rows ? 1 : L1.npad;
+  float4 x0[8], x1[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int dim = 4 * lane + 256 * u;
+    const bool in = dim < d;
+    x0[u] = in ? ldg4(b0 + (int64_t)(dim / SLAB) * n0 * SLAB + dim % SLAB)
+               : make_float4(0.f, 0.f, 0.f, 0.f);
+    x1[u] = in ? ldg4(b1 + (int64_t)(dim / SLAB) * n1 * SLAB + dim % SLAB)
+               : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int dim = 4 * lane + 256 * u + e;
+      if (dim < d) {
+        acc_sq_diff(f4(q4[u], e), f4(x0[u], e), S0, C0);
+        acc_sq_diff(f4(q4[u], e), f4(x1[u], e), S1, C1);
+      }
+    }
+}
+
 __device__ __forceinline__ void select_body(const SelArgs &a, const int64_t q) {
   extern __shared__ __attribute__((aligned(16))) unsigned char sel_smem[];
   uint32_t *hist = (uint32_t *)sel_smem;
@@ -1773,13 +1806,27 @@ __global__ __launch_bounds__(256) void k_select_qrerank(SelArgs a) {
     hand_over();
     return;
   }
+  // passes over the segment: eight loads in flight per thread (positions
+  // past the end re-read the last value and are not visited)
+  auto each_f = [&](auto fn) {
+    for (int64_t base = tid; base < L; base += (int64_t)blockDim.x * 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[min64(base + (int64_t)blockDim.x * u, L - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t i = base + (int64_t)blockDim.x * u;
+        if (i < L) fn(i, v[u]);
+      }
+    }
+  };
   {
     uint32_t kmin = 0xffffffffu, kmax = 0u;
-    for (int64_t i = tid; i < L; i += blockDim.x) {
-      const uint32_t kk = order_key(src[i]);
+    each_f([&](int64_t, float f) {
+      const uint32_t kk = order_key(f);
       kmin = kk < kmin ? kk : kmin;
       kmax = kk > kmax ? kk : kmax;
-    }
+    });
     atomicMin(&s_kmin, kmin);
     atomicMax(&s_kmax, kmax);
   }
@@ -1788,7 +1835,7 @@ __global__ __launch_bounds__(256) void k_select_qrerank(SelArgs a) {
   const float w = (fmax - fmin) / (float)QRR_BINS;
   const float inv = fmax > fmin ? (float)QRR_BINS / (fmax - fmin) : 0.f;
   auto bin_of = [&](float f) { return min(QRR_BINS - 1, max(0, (int)((f - fmin) * inv))); };
-  for (int64_t i = tid; i < L; i += blockDim.x) atomicAdd(&hist[bin_of(src[i])], 1u);
+  each_f([&](int64_t, float f) { atomicAdd(&hist[bin_of(f)], 1u); });
   __syncthreads();
   {
     constexpr int per = QRR_BINS / 256;
@@ -1809,14 +1856,13 @@ __global__ __launch_bounds__(256) void k_select_qrerank(SelArgs a) {
   const float amb_hi = (fmin + (float)(s_b2 + 2) * w) + 2.f * B;    // above: surely not
   const int bk = s_bk;
   // the candidates of the bins up to rank kout
-  for (int64_t i = tid; i < L; i += blockDim.x) {
-    const float f = src[i];
+  each_f([&](int64_t i, float f) {
     if (bin_of(f) <= bk) {
       const int slot = atomicAdd(&s_cnt, 1);
       if (slot < QRR_CAP) cpos[slot] = i;
       if (!(f < sure_thr)) s_bad = 1;
     }
-  }
+  });
   __syncthreads();
   const int c0 = s_cnt;
   if (s_bad || c0 > QRR_CAP || c0 < kout) {
@@ -1840,19 +1886,40 @@ __global__ __launch_bounds__(256) void k_select_qrerank(SelArgs a) {
     }
   }
   auto measure = [&](int n) {  // FP32 distances of slots [0, n), sorted
-    for (int c = wv; c < n; c += nwv) {
-      const CandLoc Lc = locate(a, false, q, seg0, cpos[c]);
-      float S = 0.f, C = 0.f;
-      if (rq)
-        measureB_vec_rq(a, Lc, q4, lane, S, C);
-      else
+    if (rq) {  // two candidates per wave at a time
+      for (int c = 2 * wv; c < n; c += 2 * nwv) {
+        const int c1 = c + 1 < n ? c + 1 : c;
+        const CandLoc L0 = locate(a, false, q, seg0, cpos[c]);
+        const CandLoc L1 = locate(a, false, q, seg0, cpos[c1]);
+        float S0 = 0.f, C0 = 0.f, S1 = 0.f, C1 = 0.f;
+        measureB_vec_rq2(a, L0, L1, q4, lane, S0, C0, S1, C1);
+        wave_reduce_pair(S0, C0);
+        wave_reduce_pair(S1, C1);
+        if (lane == 0) {
+          chi[c] = S0;
+          clo[c] = C0;
+          cid[c] = L0.id;
+          cg[c] = L0.gpack;
+          if (c1 != c) {
+            chi[c1] = S1;
+            clo[c1] = C1;
+            cid[c1] = L1.id;
+            cg[c1] = L1.gpack;
+          }
+        }
+      }
+    } else {
+      for (int c = wv; c < n; c += nwv) {
+        const CandLoc Lc = locate(a, false, q, seg0, cpos[c]);
+        float S = 0.f, C = 0.f;
         measureB(a, false, Lc, qg, lane, S, C);
-      wave_reduce_pair(S, C);
-      if (lane == 0) {
-        chi[c] = S;
-        clo[c] = C;
-        cid[c] = Lc.id;
-        cg[c] = Lc.gpack;
+        wave_reduce_pair(S, C);
+        if (lane == 0) {
+          chi[c] = S;
+          clo[c] = C;
+          cid[c] = Lc.id;
+          cg[c] = Lc.gpack;
+        }
       }
     }
     int P2 = 1;
@@ -1879,9 +1946,8 @@ __global__ __launch_bounds__(256) void k_select_qrerank(SelArgs a) {
     const float eq = fb.eq * 1.001f;
     const float reach = sU + eq + ldg(a.qerr) * 1.001f;
     const float flim = fminf(amb_hi, reach * reach * 1.001f + B - qlo);
-    for (int64_t i = tid; i < L; i += blockDim.x) {
-      const float f = src[i];
-      if (!(f <= flim)) continue;
+    each_f([&](int64_t i, float f) {
+      if (!(f <= flim)) return;
       const CandLoc Lc = locate(a, false, q, seg0, i);
       const float lo = sqrtf(fmaxf(f - B + qlo, 0.f)) - eq - ldg(a.qrerr + Lc.row) * 1.001f;
       if (lo <= sU) {
@@ -1889,7 +1955,7 @@ __global__ __launch_bounds__(256) void k_select_qrerank(SelArgs a) {
         if (slot < QRR_CAP) cpos[slot] = i;
         if (!(f < sure_thr)) s_bad = 1;
       }
-    }
+    });
   }
   __syncthreads();
   const int nM = s_cnt;
