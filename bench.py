@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--row-copy", action="store_true",
                     help="add the row-major copy of the vectors that the exact re-measures read")
     ap.add_argument("--rerank", type=int, default=256, help="precision form shortlist")
+    ap.add_argument("--pq-rotation", default="opq", choices=["opq", "random"],
+                    help="IVF-PQ forms: learned OPQ rotation or a seeded random one")
     return ap.parse_args()
 
 

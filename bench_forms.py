@@ -225,8 +225,9 @@ def batching_form(args, lib, torch, log):
 def _nq_index(args, lib, torch, log):
     """The NQ-shaped IVF-PQ index: N x 768 vectors stored FP16 (handed to the
     library as FP16; the index converts them to FP32 in its layout), nlist
-    16384 on the d_c = 64 prefix, GPU-trained PQ codecs with M = 32 and 64
-    after a seeded random rotation."""
+    16384 on the d_c = 64 prefix, GPU-trained OPQ codecs (learned 768 x 768
+    rotation) with M = 32 and 64, or PQ after a seeded random rotation
+    (--pq-rotation random)."""
     w = synth.WORKLOADS["nq21m"]
     n = args.n or w.n
     mix = w.mixture()
@@ -245,13 +246,23 @@ def _nq_index(args, lib, torch, log):
     log(f"IVF built (nlist {nlist}) in {time.time() - t0:.1f}s")
     pq_rows = synth.subsample_rows(n, min(n, 65536), w.seed, tag=7)
     t0 = time.time()
+    args.opq_distortion = {}
     for M in (32, 64):
-        # a seeded random orthonormal rotation spreads the decaying spectrum's
-        # energy over the M blocks before PQ (the rotation is not learned)
-        index.pq_train(Xd, M, w.d, 8, synth.init_rows(len(pq_rows), 256, w.seed, synth.STREAM_PQ, M),
-                       train_rows=pq_rows, R=synth.random_rotation(w.d, w.seed, tag=M))
+        init = synth.init_rows(len(pq_rows), 256, w.seed, synth.STREAM_PQ, M)
+        if args.pq_rotation == "opq":
+            # the rotation learned with the codebooks from the seeded random
+            # one: 4 alternations of PQ training (4 Lloyd rounds) and
+            # rotation, then a last PQ training
+            hist = index.opq_train(Xd, M, w.d, 4, 4, init, train_rows=pq_rows,
+                                   R_init=synth.random_rotation(w.d, w.seed, tag=M))
+            args.opq_distortion[f"M{M}"] = [float(h) for h in hist]
+        else:
+            # a seeded random orthonormal rotation spreads the decaying
+            # spectrum's energy over the M blocks before PQ
+            index.pq_train(Xd, M, w.d, 8, init, train_rows=pq_rows,
+                           R=synth.random_rotation(w.d, w.seed, tag=M))
     torch.cuda.synchronize()
-    log(f"PQ codecs trained and encoded in {time.time() - t0:.1f}s")
+    log(f"{args.pq_rotation} codecs trained and encoded in {time.time() - t0:.1f}s")
     del Xd
     torch.cuda.empty_cache()
     Q = mix.queries(w.nq).astype(np.float16).astype(np.float32)
@@ -310,6 +321,8 @@ def pq_form(args, lib, torch, log):
                                   f"nq={nq} k=10; value at nprobe=64 M=64"},
            "settings": {k_: {kk: (float(f"{v:.6g}") if isinstance(v, float) else v)
                              for kk, v in r.items()} for k_, r in res.items()},
+           "rotation": args.pq_rotation,
+           "opq_training_distortion": getattr(args, "opq_distortion", {}),
            "recall_at_10": rec}
     index.free()
     print(json.dumps(out), flush=True)

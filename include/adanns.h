@@ -215,6 +215,55 @@ adanns_status adanns_pq_train(adanns_index *index, const void *X, int64_t ldx, i
                               const int32_t *init_rows, const int64_t *train_rows,
                               int64_t n_train, void *stream);
 
+/*
+ * Optimized product quantisation trained on the GPU (Section 3, "Optimized
+ * Product Quantization": a learned orthonormal rotation before PQ, the
+ * non-parametric method of Ge et al. that the paper names; Section 4.3
+ * AdANNS-IVFOPQ). On the training rows' first d_s coordinates X:
+ *   R = R_init; then ``outer`` times { Y = X R; PQ k-means on Y (pq_iters Lloyd
+ *   rounds per block, from init_rows the first time, then from the previous
+ *   codebooks); Yhat = the decoded codes of Y; R = the orthonormal R that
+ *   minimises |X R - Yhat|_F, the orthogonal polar factor of X^T Yhat
+ *   (adanns_polar_factor) }; then a last PQ k-means on X R from the previous
+ *   codebooks. Every row of the index is then rotated and encoded and the
+ *   codec attached as by adanns_pq_import (R, codebooks, codes).
+ *   X          device, the index's database [n x d] of element type ``dtype``
+ *              (row j = id j), stride ldx elements.
+ *   R_init     device [d_s x d_s] FP32 orthonormal starting rotation, or NULL
+ *              for the identity (the alternation only lowers the distortion
+ *              from where it starts, so a start that spreads the variance
+ *              over the blocks, e.g. a random rotation, matters).
+ *   init_rows  host [256] int32, indices into the training rows.
+ *   train_rows host [n_train] int64 rows of X to train on, or NULL (all).
+ *   distortion host [outer + 1] or NULL: sum over the training rows of
+ *              |Y - Yhat|^2 after each PQ training (non-increasing: each step
+ *              minimises it with the other held fixed).
+ * Rotations and products accumulate in FP64; codebooks are FP32.
+ * Limits: as adanns_pq_train; 0 <= outer <= 100; 0 <= pq_iters <= 1000.
+ * Errors: ADANNS_EINVAL, ADANNS_ENOMEM, ADANNS_EHIP, ADANNS_EUNSUPPORTED (the
+ * rotation step met a singular X^T Yhat). Synchronises ``stream``.
+ */
+adanns_status adanns_opq_train(adanns_index *index, const void *X, int64_t ldx, int32_t dtype,
+                               int32_t M, int32_t d_s, const float *R_init, int32_t outer,
+                               int32_t pq_iters, const int32_t *init_rows,
+                               const int64_t *train_rows, int64_t n_train, double *distortion,
+                               void *stream);
+
+/*
+ * The orthogonal polar factor of a square matrix (the solution of the
+ * orthogonal Procrustes problem inside OPQ training): for A = U S V^T
+ * (S > 0), R = U V^T, the orthonormal matrix nearest to A.
+ *   A, R       device, [d x d] FP64 row-major (A unchanged).
+ *   iterations host out or NULL: Newton-Schulz steps taken.
+ * Computed by the Newton-Schulz iteration Z <- 1.5 Z - 0.5 Z Z^T Z from
+ * A / |A|_F in FP64 until a step changes Z by less than 1e-13 |Z|_F (at most
+ * 200 steps). Limits: 1 <= d <= 4096. Errors: ADANNS_EINVAL, ADANNS_ENOMEM,
+ * ADANNS_EHIP, ADANNS_EUNSUPPORTED (Z^T Z not the identity to 1e-9 at the end:
+ * A singular or too ill-conditioned). Synchronises ``stream``.
+ */
+adanns_status adanns_polar_factor(const double *A, int32_t d, double *R, int32_t *iterations,
+                                  void *stream);
+
 /* A codec as stored: R host [d_s x d_s], codebooks host [M x 256 x d_s/M],
  * codes host [n x M] in database-id order. Any may be NULL. Synchronous. */
 adanns_status adanns_pq_codec(const adanns_index *index, int32_t M, float *R, float *codebooks,
@@ -407,24 +456,30 @@ adanns_status adanns_autotune_clear(void);
  * (search as adanns_search_pq). Request i (query row i of Q, device
  * [n x ldq]) arrives arrival_s[i] seconds after the call starts (host clock;
  * non-decreasing) with its own budget (d_c[i], nprobe[i], M[i]) (host
- * arrays). A host loop admits arrived requests while the device memory their
- * searches need (staged query, coarse scores, probes, candidate distances,
- * tables) fits in hbm_budget bytes together with the requests in flight,
- * batches admitted requests of one budget into a step (the oldest pending
- * request's budget first, at most max_batch requests), runs up to nstreams
- * steps concurrently on streams of their own, and on each step's completion
- * event records the latency of its requests and frees their budget, while
- * newer requests keep being admitted (continuous batching). A request that
- * alone exceeds the budget is rejected (latency -1). Results go to row i of
- * dist / ids (device [n x k]); latency_s (host [n]) is completion minus
- * arrival. Each stream's scratch memory is grown before the clock starts.
- * Blocks until every request completed; synchronises the device.
+ * arrays). hbm_budget bytes of device memory are allocated once, as one
+ * region; every search step's scratch (staged queries, coarse scores,
+ * probes, buckets, candidate distances, rotated queries, tables: exactly what
+ * the search carves) is a piece of it. A host loop admits arrived requests
+ * while their step's scratch fits a free piece of the region, batches
+ * admitted requests of one budget into a step (the oldest pending request's
+ * budget first, at most max_batch requests, as many as the largest free
+ * piece holds), runs up to nstreams steps concurrently on streams of their
+ * own, and on each step's completion event records the latency of its
+ * requests and returns its piece, while newer requests keep being admitted
+ * (continuous batching). The memory in use by searches therefore never
+ * exceeds hbm_budget (the per-stream step buffers for max_batch staged
+ * queries and results, max_batch * (ldq + 3k + 2) * 4 bytes per stream, are
+ * outside it). A request whose step alone exceeds the budget is rejected
+ * (latency -1). Results go to row i of dist / ids (device [n x k]); latency_s
+ * (host [n]) is completion minus arrival. Before the clock starts one request
+ * of each budget runs on every stream (kernel loading). Blocks until every
+ * request completed; synchronises the device.
  */
 typedef struct adanns_serve_stats {
   double wall_s;               /* first arrival window start to last completion */
   int64_t steps;               /* search steps launched */
   double mean_batch;           /* requests per step */
-  size_t max_inflight_bytes;   /* peak admitted bytes (never above hbm_budget) */
+  size_t max_inflight_bytes;   /* peak search scratch in use (never above hbm_budget) */
   int32_t max_streams_busy;    /* peak concurrent steps */
   int64_t rejected;            /* requests larger than the budget */
 } adanns_serve_stats;

@@ -13,7 +13,8 @@ the high-dimensional vectors (Section 4.3).
 Readings:
 
 * OPQ is the non-parametric alternation of Ge et al. (named in Section 3):
-  R = I; repeat { PQ on Y = X R (warm-started k-means), then
+  R = R0 (a given orthonormal start, the identity by default); repeat { PQ
+  on Y = X R (warm-started k-means), then
   R = U V^T from the SVD of X^T Y_hat (orthogonal Procrustes) };
 * the scan compares the *unquantised* rotated query with the codes
   (asymmetric distance): LUT_m[c] = |q'_m - C_m[c]|^2 and
@@ -91,11 +92,12 @@ def procrustes64(X, Yhat) -> np.ndarray:
     return U @ Vt
 
 
-def opq_train64(X, M: int, outer: int, pq_iters: int, init_rows):
-    """Returns (R [d,d], codebooks [M,256,d/M], distortion after each PQ step)."""
+def opq_train64(X, M: int, outer: int, pq_iters: int, init_rows, R0=None):
+    """Returns (R [d,d], codebooks [M,256,d/M], distortion after each PQ step).
+    The alternation starts from the orthonormal R0 (identity if None)."""
     X = np.asarray(X, dtype=np.float64)
     d = X.shape[1]
-    R = np.eye(d)
+    R = np.eye(d) if R0 is None else np.asarray(R0, dtype=np.float64)
     cbs = None
     hist = []
     for _ in range(outer):

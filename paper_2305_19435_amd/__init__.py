@@ -6,7 +6,7 @@ loudly when the shared library has not been built.
 """
 from ._lib import (AdannsError, check, last_error, lib, selection_stats,  # noqa: F401
                    set_search_scratch_cap, timing_enable, timing_read, timing_reset, version)
-from .index import IvfIndex  # noqa: F401
+from .index import IvfIndex, polar_factor  # noqa: F401
 from .batch import Batch, autotune_clear  # noqa: F401
 
 __all__ = ["IvfIndex", "Batch", "AdannsError", "version", "last_error", "lib"]

@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libadanns.so")
-SOURCES = ["kernels.hip", "abi.hip", "batch.hip", "serve.hip"]
+SOURCES = ["kernels.hip", "abi.hip", "batch.hip", "serve.hip", "opq.hip"]
 
 # Packed FP32 instructions are turned off for all device code: they have
 # produced silently wrong results on this hardware generation.

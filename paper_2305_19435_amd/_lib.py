@@ -37,6 +37,9 @@ _SIGS = {
     "adanns_pq_import": (C.c_int, [vp, i32, i32, vp, vp, vp, vp]),
     "adanns_pq_codec": (C.c_int, [vp, i32, vp, vp, vp]),
     "adanns_pq_train": (C.c_int, [vp, vp, i64, i32, i32, i32, vp, i32, vp, vp, i64, vp]),
+    "adanns_opq_train": (C.c_int, [vp, vp, i64, i32, i32, i32, vp, i32, i32, vp, vp, i64, vp,
+                                   vp]),
+    "adanns_polar_factor": (C.c_int, [vp, i32, vp, vp, vp]),
     "adanns_search_pq": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp]),
     "adanns_set_precision": (C.c_int, [vp, i32, vp]),
     "adanns_index_add_row_copy": (C.c_int, [vp, vp]),

@@ -319,11 +319,11 @@ static adanns_status init_index_shape(adanns_index *ix, int64_t n, int32_t d, in
 // Lloyd's k-means on the GPU. Assignment = the coarse step with one probe
 // (first-pass MFMA scores, exact re-measurement of the best few, ties to the
 // smaller index); update = per-centroid mean in a fixed summation order.
-static adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t d_c,
-                                int32_t iters, const int32_t *init_rows, const int64_t *train_rows,
-                                int64_t n_train, double *objective, hipStream_t st,
-                                std::vector<int32_t> &assign_all, float **C_out,
-                                bool final_all_rows = true) {
+namespace adanns {
+adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t d_c, int32_t iters,
+                         const int32_t *init_rows, const int64_t *train_rows, int64_t n_train,
+                         double *objective, hipStream_t st, std::vector<int32_t> &assign_all,
+                         float **C_out, bool final_all_rows, const float *init_centroids) {
   const int32_t dcp = (int32_t)round_up(d_c, SLAB);
   const int64_t nt = train_rows ? n_train : n;
   DevFree tmp;
@@ -370,8 +370,15 @@ static adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t 
     ADANNS_HIP(hipMemcpyAsync(d_rows, train_rows, nt * sizeof(int64_t), hipMemcpyHostToDevice, st));
   }
   ADANNS_HIP(launch_stage_rows(X, d_rows, nullptr, nt, d_c, Xt, dcp, st));
-  ADANNS_HIP(hipMemcpyAsync(d_init, init_rows, nlist * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  ADANNS_HIP(launch_stage_rows(f32mat(Xt, dcp), nullptr, d_init, nlist, d_c, C, dcp, st));
+  if (init_centroids) {  // given starting centroids (warm start), row stride d_c
+    ADANNS_HIP(hipMemsetAsync(C, 0, (size_t)nlist * dcp * sizeof(float), st));
+    ADANNS_HIP(hipMemcpy2DAsync(C, dcp * sizeof(float), init_centroids, d_c * sizeof(float),
+                                d_c * sizeof(float), nlist, hipMemcpyDeviceToDevice, st));
+  } else {
+    ADANNS_HIP(hipMemcpyAsync(d_init, init_rows, nlist * sizeof(int32_t), hipMemcpyHostToDevice,
+                              st));
+    ADANNS_HIP(launch_stage_rows(f32mat(Xt, dcp), nullptr, d_init, nlist, d_c, C, dcp, st));
+  }
   cix.cent = C;
 
   std::vector<int32_t> h_asg(nt);
@@ -473,6 +480,7 @@ static adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t 
   *C_out = C;
   return ADANNS_OK;
 }
+}  // namespace adanns
 
 extern "C" {
 
@@ -702,7 +710,7 @@ adanns_status adanns_build_ivf(const void *X, int64_t n, int32_t d, int64_t ldx,
   float *C = nullptr;
   const Mat Xm{X, ldx, dtype};
   if ((s = kmeans_gpu(Xm, n, nlist, d_c, iters, init_rows, train_rows, nt, objective, st, assign,
-                      &C))) {
+                      &C, true, nullptr))) {
     if (C) (void)hipFree(C);
     return s;
   }
@@ -844,7 +852,7 @@ adanns_status adanns_pq_train(adanns_index *ix, const void *X, int64_t ldx, int3
     float *C = nullptr;
     // Lloyd's k-means with 256 codewords on the m-th block of coordinates
     if ((s = kmeans_gpu(Tx.cols((int64_t)m * dsub), nT, 256, dsub, iters, init_rows, trows, nt,
-                        nullptr, st, unused, &C, false))) {
+                        nullptr, st, unused, &C, false, nullptr))) {
       if (C) (void)hipFree(C);
       return s;
     }
@@ -907,11 +915,29 @@ adanns_status adanns_pq_codec(const adanns_index *ix, int32_t M, float *R, float
   return ADANNS_OK;
 }
 
-adanns_status adanns_search_pq(const adanns_index *cix, const float *Q, int64_t nq, int64_t ldq,
-                               int32_t d_c, int32_t nprobe, int32_t M, int32_t k,
-                               int32_t rerank_k, int32_t d_rerank, float *dist, int64_t *ids,
-                               int32_t *probes, void *stream) {
-  clear_error();
+}  // extern "C"
+
+namespace adanns {
+// Scratch bytes of one IVF-PQ search of nq queries (0 if the budget is invalid).
+size_t pq_search_scratch_bytes(const adanns_index *ix, int64_t nq, int32_t d_c, int32_t nprobe,
+                               int32_t M, int32_t rerank_k, int32_t d_rerank) {
+  auto it = ix->pq.find(M);
+  if (it == ix->pq.end() || nprobe < 1 || nprobe > ix->nlist) return 0;
+  const PqCodec &pq = it->second;
+  const int32_t dq = std::max(std::max(d_c, pq.d_s), rerank_k > 0 ? d_rerank : 0);
+  const int32_t dq_pad = (int32_t)round_up(dq, SLAB);
+  size_t t = 0;
+  carve(nullptr, ix, nq, dq_pad, nprobe, true, &t);
+  return t + (size_t)round_up((size_t)nq * pq.d_s * 4, 256) * 2 +
+         (size_t)round_up((size_t)nq * M * 256 * 4, 256) + 1024;
+}
+
+// adanns_search_pq; with fixed_base the scratch is that caller-owned region
+// of fixed_cap bytes (no allocation, no chunking; a larger need is EBUDGET).
+adanns_status search_pq_impl(const adanns_index *cix, const float *Q, int64_t nq, int64_t ldq,
+                             int32_t d_c, int32_t nprobe, int32_t M, int32_t k, int32_t rerank_k,
+                             int32_t d_rerank, float *dist, int64_t *ids, int32_t *probes,
+                             void *stream, void *fixed_base, size_t fixed_cap) {
   adanns_index *ix = const_cast<adanns_index *>(cix);
   ADANNS_REQUIRE(ix != nullptr, "index is NULL");
   auto it = ix->pq.find(M);
@@ -942,10 +968,14 @@ adanns_status adanns_search_pq(const adanns_index *cix, const float *Q, int64_t 
     size_t t = 0;
     carve(nullptr, ix, m, dq_pad, nprobe, true, &t);
     if (carved) *carved = t;
-    return t + (size_t)round_up((size_t)m * pq.d_s * 4, 256) * 2 +
-           (size_t)round_up((size_t)m * M * 256 * 4, 256) + 1024;
+    return pq_search_scratch_bytes(ix, m, d_c, nprobe, M, rerank_k, d_rerank);
   };
-  if (nq > 1 && bytes_of(nq, nullptr) > g_scratch_cap.load()) {  // query chunks
+  if (fixed_base && bytes_of(nq, nullptr) > fixed_cap) {
+    set_error("the search needs %zu bytes of scratch, more than the %zu given",
+              bytes_of(nq, nullptr), fixed_cap);
+    return ADANNS_EBUDGET;
+  }
+  if (!fixed_base && nq > 1 && bytes_of(nq, nullptr) > g_scratch_cap.load()) {  // query chunks
     int64_t chunk = nq;
     while (chunk > 1 && bytes_of(chunk, nullptr) > g_scratch_cap.load()) chunk = (chunk + 1) / 2;
     for (int64_t r0 = 0; r0 < nq; r0 += chunk) {
@@ -959,8 +989,8 @@ adanns_status adanns_search_pq(const adanns_index *cix, const float *Q, int64_t 
   }
   size_t total = 0;
   const size_t extra = bytes_of(nq, &total) - total;
-  void *base = nullptr;
-  if ((s = get_scratch(ix, st, total + extra, &base))) return s;
+  void *base = fixed_base;
+  if (!fixed_base && (s = get_scratch(ix, st, total + extra, &base))) return s;
   SearchBufs b = carve((char *)base, ix, nq, dq_pad, nprobe, true, &total);
   Carver c{(char *)base, total, 0};
   float *qr_hi = c.take<float>((size_t)nq * pq.d_s);
@@ -971,6 +1001,18 @@ adanns_status adanns_search_pq(const adanns_index *cix, const float *Q, int64_t 
   ADANNS_HIP(launch_pq_search(ix, pq, b, nq, nprobe, k, rerank_k, d_rerank, qr_hi, qr_lo, lut,
                               dist, ids, st));
   return ADANNS_OK;
+}
+}  // namespace adanns
+
+extern "C" {
+
+adanns_status adanns_search_pq(const adanns_index *cix, const float *Q, int64_t nq, int64_t ldq,
+                               int32_t d_c, int32_t nprobe, int32_t M, int32_t k,
+                               int32_t rerank_k, int32_t d_rerank, float *dist, int64_t *ids,
+                               int32_t *probes, void *stream) {
+  clear_error();
+  return search_pq_impl(cix, Q, nq, ldq, d_c, nprobe, M, k, rerank_k, d_rerank, dist, ids, probes,
+                        stream, nullptr, 0);
 }
 
 adanns_status adanns_set_precision(adanns_index *ix, int32_t fmt, void *stream) {

@@ -181,6 +181,17 @@ CfgDev make_cfg(const adanns_index *ix, int32_t d_c, int32_t d_s, int32_t nprobe
 // re-selected with a wider shortlist, [1] queries left uncertified.
 hipError_t read_selection_stats(unsigned long long out[2], bool reset);
 
+// IVF-PQ search (adanns_search_pq) and the scratch bytes it needs for nq
+// queries of one budget (0 for an invalid budget). With fixed_base the
+// scratch is that caller-owned region of fixed_cap bytes: no allocation, no
+// query chunks, ADANNS_EBUDGET if it does not fit.
+size_t pq_search_scratch_bytes(const adanns_index *ix, int64_t nq, int32_t d_c, int32_t nprobe,
+                               int32_t M, int32_t rerank_k, int32_t d_rerank);
+adanns_status search_pq_impl(const adanns_index *ix, const float *Q, int64_t nq, int64_t ldq,
+                             int32_t d_c, int32_t nprobe, int32_t M, int32_t k, int32_t rerank_k,
+                             int32_t d_rerank, float *dist, int64_t *ids, int32_t *probes,
+                             void *stream, void *fixed_base, size_t fixed_cap);
+
 // Read-only streaming probe over bytes (a multiple of 16) of buf; out holds
 // one float per workgroup of the grid.
 hipError_t launch_stream_read(const void *buf, size_t bytes, float *out, int32_t grid,
@@ -223,6 +234,18 @@ struct Mat {
   Mat cols(int64_t c0) const { return Mat{(const char *)p + c0 * esize(), ld, type}; }
 };
 inline Mat f32mat(const float *p, int64_t ld) { return Mat{p, ld, 0}; }
+
+// Lloyd's k-means on the GPU (abi.hip): nlist centroids of the first d_c
+// columns of X's training rows (all n, or train_rows), from init_rows (indices
+// into the training rows) or, if init_centroids (device [nlist x d_c]) is
+// given, from those; iters rounds. *C_out (device, [nlist x round_up(d_c, 32)],
+// caller frees) holds the centroids; with final_all_rows every row of X is
+// then assigned (assign_all) and objective gets the objective per round.
+adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t d_c, int32_t iters,
+                         const int32_t *init_rows, const int64_t *train_rows, int64_t n_train,
+                         double *objective, hipStream_t st, std::vector<int32_t> &assign_all,
+                         float **C_out, bool final_all_rows, const float *init_centroids);
+
 
 hipError_t launch_stage_queries(const float *Q, int64_t nq, int64_t ldq, int32_t dq,
                                 float *Qs, int64_t ldqs, hipStream_t st);

@@ -22,6 +22,44 @@ __global__ void k_scatter_rows(const float *__restrict__ sd, const int64_t *__re
   di[rows[r] * k + j] = si[i];
 }
 
+// First-fit allocator over one device region (offsets only; 256-byte units).
+struct Pool {
+  std::vector<std::pair<size_t, size_t>> free_;  // (offset, size), by offset
+  explicit Pool(size_t cap) { free_.push_back({0, cap / 256 * 256}); }
+  static size_t unit(size_t b) { return (b + 255) / 256 * 256; }
+  size_t largest() const {
+    size_t m = 0;
+    for (const auto &f : free_) m = std::max(m, f.second);
+    return m;
+  }
+  bool alloc(size_t bytes, size_t *off) {
+    bytes = unit(bytes);
+    for (size_t i = 0; i < free_.size(); ++i)
+      if (free_[i].second >= bytes) {
+        *off = free_[i].first;
+        free_[i].first += bytes;
+        free_[i].second -= bytes;
+        if (free_[i].second == 0) free_.erase(free_.begin() + i);
+        return true;
+      }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = unit(bytes);
+    size_t i = 0;
+    while (i < free_.size() && free_[i].first < off) ++i;
+    free_.insert(free_.begin() + i, {off, bytes});
+    if (i + 1 < free_.size() && free_[i].first + free_[i].second == free_[i + 1].first) {
+      free_[i].second += free_[i + 1].second;
+      free_.erase(free_.begin() + i + 1);
+    }
+    if (i > 0 && free_[i - 1].first + free_[i - 1].second == free_[i].first) {
+      free_[i - 1].second += free_[i].second;
+      free_.erase(free_.begin() + i);
+    }
+  }
+};
+
 struct Slot {
   hipStream_t st = nullptr;
   hipEvent_t done = nullptr;
@@ -31,16 +69,10 @@ struct Slot {
   int64_t *rows_dev = nullptr;
   int64_t *rows_host = nullptr;  // pinned
   std::vector<int64_t> reqs;     // requests of the step in flight
-  size_t bytes = 0;              // admitted bytes of the step
+  size_t bytes = 0;              // its search scratch: a region of the pool
+  size_t off = 0;
   bool busy = false;
 };
-
-// Device bytes one request of this budget adds to a search step.
-size_t request_bytes(const adanns_index *ix, int32_t d_s, int32_t nprobe, int32_t M,
-                     int32_t dq_pad) {
-  return (size_t)dq_pad * 4 + (size_t)ix->nlist * 4 + (size_t)nprobe * 20 +
-         (size_t)ix->top_prefix[nprobe] * 4 + (size_t)M * 256 * 4 + (size_t)d_s * 8 + 64;
-}
 
 }  // namespace
 }  // namespace adanns
@@ -79,7 +111,6 @@ adanns_status adanns_serve(const adanns_index *index, const float *Q, int64_t ld
   }
   if (rerank_k > 0) dq = std::max(dq, d_rerank);
   ADANNS_REQUIRE(ldq >= dq, "ldq (%lld) is smaller than the widest prefix (%d)", (long long)ldq, dq);
-  const int32_t dq_pad = (int32_t)round_up(dq, SLAB);
   adanns_status s = ADANNS_OK;
   {
     hipError_t e = hipGetLastError();
@@ -89,6 +120,15 @@ adanns_status adanns_serve(const adanns_index *index, const float *Q, int64_t ld
     }
   }
 
+  // step bytes of ``cnt`` requests of request r's budget: the search scratch
+  // exactly as the search carves it
+  auto step_bytes = [&](int64_t r, int64_t cnt) {
+    return pq_search_scratch_bytes(ix, cnt, d_c[r], nprobe[r], M[r], rerank_k, d_rerank);
+  };
+  // the budget is one device region: every step's search scratch is carved
+  // out of it, so the admitted bytes are the bytes in use
+  void *pool_base = nullptr;
+  Pool pool(hbm_budget);
   std::vector<Slot> slots(nstreams);
   auto cleanup = [&]() {
     for (Slot &sl : slots) {
@@ -100,7 +140,14 @@ adanns_status adanns_serve(const adanns_index *index, const float *Q, int64_t ld
       if (sl.rows_host) (void)hipHostFree(sl.rows_host);
       if (sl.st) (void)hipStreamDestroy(sl.st);
     }
+    if (pool_base) (void)hipFree(pool_base);
   };
+  if (hbm_budget >= 256 && hipMalloc(&pool_base, hbm_budget / 256 * 256) != hipSuccess) {
+    (void)hipGetLastError();
+    pool_base = nullptr;
+    set_error("could not allocate the %zu-byte serving budget", hbm_budget);
+    return ADANNS_ENOMEM;
+  }
   for (Slot &sl : slots) {
     if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) ||
         hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) ||
@@ -115,8 +162,10 @@ adanns_status adanns_serve(const adanns_index *index, const float *Q, int64_t ld
       return ADANNS_ENOMEM;
     }
   }
-  // launch one step of ``cnt`` requests (same budget) on a slot
-  auto launch = [&](Slot &sl, const std::vector<int64_t> &reqs) -> adanns_status {
+  // launch one step of ``cnt`` requests (same budget) on a slot, its search
+  // scratch the pool region [off, off + bytes)
+  auto launch = [&](Slot &sl, const std::vector<int64_t> &reqs, size_t off,
+                    size_t bytes) -> adanns_status {
     const int64_t cnt = (int64_t)reqs.size();
     std::memcpy(sl.rows_host, reqs.data(), cnt * sizeof(int64_t));
     ADANNS_HIP(hipMemcpyAsync(sl.rows_dev, sl.rows_host, cnt * sizeof(int64_t),
@@ -124,8 +173,9 @@ adanns_status adanns_serve(const adanns_index *index, const float *Q, int64_t ld
     ADANNS_HIP(launch_stage_rows(f32mat(Q, ldq), sl.rows_dev, nullptr, cnt, (int32_t)ldq, sl.Qstep,
                                  ldq, sl.st));
     const int64_t r0 = reqs[0];
-    adanns_status e = adanns_search_pq(ix, sl.Qstep, cnt, ldq, d_c[r0], nprobe[r0], M[r0], k,
-                                       rerank_k, d_rerank, sl.dstep, sl.istep, nullptr, sl.st);
+    adanns_status e = search_pq_impl(ix, sl.Qstep, cnt, ldq, d_c[r0], nprobe[r0], M[r0], k,
+                                     rerank_k, d_rerank, sl.dstep, sl.istep, nullptr, sl.st,
+                                     (char *)pool_base + off, bytes);
     if (e) return e;
     hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)cdiv(cnt * k, 256)), dim3(256), 0, sl.st,
                        sl.dstep, sl.istep, cnt, k, sl.rows_dev, dist, ids);
@@ -133,24 +183,30 @@ adanns_status adanns_serve(const adanns_index *index, const float *Q, int64_t ld
     ADANNS_HIP(hipEventRecord(sl.done, sl.st));
     return ADANNS_OK;
   };
-  // warm-up: grow every stream's scratch to the largest step before timing
+  // warm-up (kernels loaded before the clock starts): one request of each
+  // budget that fits, on every stream; results are overwritten later
   {
-    int64_t widest = 0;
-    for (int64_t i = 1; i < n; ++i)
-      if ((int64_t)nprobe[i] * M[i] > (int64_t)nprobe[widest] * M[widest]) widest = i;
-    std::vector<int64_t> w(std::min<int64_t>(max_batch, n), widest);
-    for (Slot &sl : slots) {
-      if ((s = launch(sl, w))) {
-        cleanup();
-        return s;
+    std::vector<int64_t> seen;
+    for (int64_t i = 0; i < n; ++i) {
+      bool dup = false;
+      for (int64_t j : seen)
+        dup = dup || (d_c[j] == d_c[i] && nprobe[j] == nprobe[i] && M[j] == M[i]);
+      if (dup) continue;
+      seen.push_back(i);
+      const size_t b = step_bytes(i, 1);
+      if (b > hbm_budget / 256 * 256) continue;
+      for (Slot &sl : slots) {
+        if ((s = launch(sl, std::vector<int64_t>{i}, 0, b))) {
+          cleanup();
+          return s;
+        }
+        (void)hipStreamSynchronize(sl.st);
       }
     }
-    for (Slot &sl : slots) (void)hipStreamSynchronize(sl.st);
   }
 
   std::vector<size_t> need(n);
-  for (int64_t i = 0; i < n; ++i)
-    need[i] = request_bytes(ix, ix->pq[M[i]].d_s, nprobe[i], M[i], dq_pad);
+  for (int64_t i = 0; i < n; ++i) need[i] = step_bytes(i, 1);
   for (int64_t i = 0; i < n; ++i) latency_s[i] = -1.0;
   std::deque<int64_t> pending;
   int64_t next = 0, done_cnt = 0, steps = 0, batched = 0, rejected = 0;
@@ -176,6 +232,7 @@ adanns_status adanns_serve(const adanns_index *index, const float *Q, int64_t ld
       for (int64_t r : sl.reqs) latency_s[r] = t - arrival_s[r];
       done_cnt += (int64_t)sl.reqs.size();
       inflight -= sl.bytes;
+      pool.release(sl.off, sl.bytes);
       sl.busy = false;
       sl.reqs.clear();
       progress = true;
@@ -188,32 +245,40 @@ adanns_status adanns_serve(const adanns_index *index, const float *Q, int64_t ld
     for (Slot &sl : slots) {
       if (sl.busy || pending.empty()) continue;
       const int64_t head = pending.front();
-      if (need[head] > hbm_budget) {  // can never be admitted
+      if (Pool::unit(need[head]) > hbm_budget / 256 * 256) {  // can never be admitted
         pending.pop_front();
         ++rejected;
         progress = true;
         continue;
       }
-      if (inflight + need[head] > hbm_budget) break;  // wait for memory to free up
+      const size_t avail = pool.largest();
+      if (Pool::unit(need[head]) > avail) break;  // wait for memory to free up
+      // the head's budget group, as many as the largest free region holds
       std::vector<int64_t> take;
-      size_t bytes = 0;
       for (auto it = pending.begin(); it != pending.end() && (int64_t)take.size() < max_batch;) {
         const int64_t r = *it;
         if (d_c[r] == d_c[head] && nprobe[r] == nprobe[head] && M[r] == M[head] &&
-            inflight + bytes + need[r] <= hbm_budget) {
+            Pool::unit(step_bytes(head, (int64_t)take.size() + 1)) <= avail) {
           take.push_back(r);
-          bytes += need[r];
           it = pending.erase(it);
         } else {
           ++it;
         }
       }
-      if ((s = launch(sl, take))) {
+      const size_t bytes = Pool::unit(step_bytes(head, (int64_t)take.size()));
+      size_t off = 0;
+      if (!pool.alloc(bytes, &off)) {  // cannot happen: bytes <= the largest free region
+        cleanup();
+        set_error("serving pool allocation failed");
+        return ADANNS_EBUDGET;
+      }
+      if ((s = launch(sl, take, off, bytes))) {
         cleanup();
         return s;
       }
       sl.reqs = std::move(take);
       sl.bytes = bytes;
+      sl.off = off;
       sl.busy = true;
       inflight += bytes;
       max_inflight = std::max(max_inflight, inflight);

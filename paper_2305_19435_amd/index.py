@@ -150,6 +150,23 @@ class IvfIndex:
                                   init.ctypes.data, None if tr is None else tr.ctypes.data,
                                   0 if tr is None else len(tr), _stream(stream)))
 
+    def opq_train(self, X, M: int, d_s: int, outer: int, pq_iters: int, init_rows,
+                  train_rows=None, R_init=None, stream=None):
+        """adanns_opq_train: GPU-trained OPQ codec (rotation learned from R_init,
+        default the identity). Returns the distortion after each PQ training
+        [outer + 1]."""
+        Xd, xt = _dev_x(X)
+        init = np.ascontiguousarray(init_rows, dtype=np.int32)
+        tr = None if train_rows is None else np.ascontiguousarray(train_rows, dtype=np.int64)
+        Rd = None if R_init is None else _dev_f32(R_init, Xd.device)
+        dist = np.zeros(outer + 1, dtype=np.float64)
+        check(lib.adanns_opq_train(self._h, Xd.data_ptr(), Xd.stride(0), xt, M, d_s, _ptr(Rd),
+                                   outer, pq_iters, init.ctypes.data,
+                                   None if tr is None else tr.ctypes.data,
+                                   0 if tr is None else len(tr), dist.ctypes.data,
+                                   _stream(stream)))
+        return dist
+
     def pq_codec(self, M: int, d_s: int):
         """(R [d_s, d_s], codebooks [M, 256, d_s/M], codes [n, M]) as stored."""
         R = np.empty((d_s, d_s), dtype=np.float32)
@@ -269,3 +286,15 @@ class IvfIndex:
             self.free()
         except Exception:
             pass
+
+
+def polar_factor(A, stream=None):
+    """adanns_polar_factor of a square FP64 matrix (a CUDA tensor or an array).
+    Returns (R as a CUDA FP64 tensor, Newton-Schulz steps taken)."""
+    Ad = A if isinstance(A, torch.Tensor) and A.is_cuda else torch.from_numpy(np.asarray(A))
+    Ad = Ad.to(device="cuda", dtype=torch.float64).contiguous()
+    d = Ad.shape[0]
+    R = torch.empty_like(Ad)
+    it = C.c_int32()
+    check(lib.adanns_polar_factor(Ad.data_ptr(), d, R.data_ptr(), C.byref(it), _stream(stream)))
+    return R, it.value

@@ -5,8 +5,7 @@ import numpy as np
 import pytest
 
 import synth
-from parity_util import oracle_index
-from test_gpu_pq import make_codec
+from parity_util import make_codec, oracle_index
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu

@@ -107,3 +107,20 @@ def test_rotated_adc_is_exact_under_rotation_invariance():
     # a query rotated by R^T instead of R misses neighbours
     Dt, It, _ = pq.ivfpq_search64(Q, np.zeros((1, d)), off, ids, codes, R.T.copy(), cbs, 4, 1, 10)
     assert not np.array_equal(It, Ie)
+
+
+def test_opq_from_a_given_rotation():
+    """Started from an orthonormal R0, the alternation's first PQ step is PQ
+    on X R0, the distortion never increases, and R stays orthonormal."""
+    m = synth.Mixture(16, 6, seed=31)
+    X = m.database(1500).astype(np.float64)
+    init = synth.init_rows(1500, 256, 31, synth.STREAM_PQ)
+    R0 = synth.random_rotation(16, seed=31).astype(np.float64)
+    R0, r = np.linalg.qr(R0)
+    R0 = R0 * np.sign(np.diag(r))[None, :]
+    R, cbs, hist = pq.opq_train64(X, 4, 3, 2, init, R0=R0)
+    first = pq.pq_train64(X @ R0, 4, 2, init_rows=init)
+    codes = pq.pq_encode64(X @ R0, first)
+    assert hist[0] == pytest.approx(pq.distortion64(X @ R0, codes, first), rel=1e-12)
+    assert np.all(hist[1:] <= hist[:-1] * (1 + 1e-10))
+    np.testing.assert_allclose(R.T @ R, np.eye(16), atol=1e-10)
