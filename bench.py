@@ -72,6 +72,8 @@ def parse():
                              "sweep", "latency"],
                     help="ivf: the headline FP32 search; the others measure the other forms")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile-shape autotuner")
+    ap.add_argument("--no-filtered", action="store_true",
+                    help="skip the exact search with a quantised first pass")
     ap.add_argument("--row-copy", action="store_true",
                     help="add the row-major copy of the vectors that the exact re-measures read")
     ap.add_argument("--rerank", type=int, default=256, help="precision form shortlist")
@@ -311,6 +313,8 @@ def main():
         f"re-selected {reselected}, uncertified {uncertified}")
     timed_d = dist.cpu().numpy()
     timed_i = ids.cpu().numpy()
+    filtered = None if args.no_filtered else filtered_leg(lib, torch, index, Qd, d_c, d_s, nprobe, k,
+                                                          args.steps, args.warmup, timed_d, timed_i)
 
     # the same steps with the queries handed over in pinned host memory: the
     # PCIe-inclusive rate (context only; ``value`` keeps inputs resident)
@@ -419,6 +423,7 @@ def main():
         "shortlists": {"reselected_per_step": reselected / args.steps,
                        "uncertified": uncertified},
         "qps_including_h2d": round(qps_h2d, 1),
+        "exact_with_quantised_first_pass": filtered,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -430,9 +435,49 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def filtered_leg(lib, torch, index, Qd, d_c, d_s, nprobe, k, steps, warmup, timed_d, timed_i):
+    """The same search's exact FP32 result from a quantised first pass
+    (adanns_search_filtered: BF16 / e4m3 list scan, FP32 re-measure of the
+    candidates whose quantisation bound reaches the k-th): its rate and
+    whether its output equals the timed FP32 path's bit for bit."""
+    out = {}
+    nq = Qd.shape[0]
+    for fmt in ("bf16", "fp8"):
+        index.set_precision(fmt)
+        d_ = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+        i_ = torch.empty((nq, k), dtype=torch.int64, device="cuda")
+        for _ in range(warmup):
+            index.search_filtered(Qd, d_c, d_s, nprobe, k, fmt, out=(d_, i_))
+        torch.cuda.synchronize()
+        lib.filtered_stats(reset=True)
+        lib.timing_reset()
+        lib.timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            index.search_filtered(Qd, d_c, d_s, nprobe, k, fmt, out=(d_, i_))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lib.timing_enable(False)
+        measured, windowed = lib.filtered_stats(reset=True)
+        kern = {}
+        for name in ("tile_dist_coarse", "select_coarse", "bucketing", "tile_q_scan",
+                     "select_filtered"):
+            cnt, ms = lib.timing_read(name)
+            if cnt:
+                kern[name] = round(ms / cnt, 4)
+        same = bool(np.array_equal(d_.cpu().numpy(), timed_d) and
+                    np.array_equal(i_.cpu().numpy(), timed_i))
+        out[fmt] = {"qps": round(nq * steps / wall, 1), "ms_per_step": round(wall * 1e3 / steps, 4),
+                    "kernels_avg_ms": kern, "output_bitwise_equal_to_fp32_path": same,
+                    "exact_measures_per_query": round(measured / (nq * steps), 2),
+                    "queries_windowed_frac": round(windowed / (nq * steps), 5)}
+        log(f"exact search with a {fmt} first pass: {out[fmt]}")
+    return out
+
+
 def stream_read_gbs(lib, torch, buf):
     """Read bandwidth of the library's read-only probe over ``buf`` (1 GiB)."""
-    grid = 256 * 8
+    grid = 32768
     part = torch.empty(grid, dtype=torch.float32, device="cuda")
     nbytes = buf.numel() * 4
     lib.check(lib.lib.adanns_stream_read(buf.data_ptr(), nbytes, part.data_ptr(), grid,

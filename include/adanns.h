@@ -332,6 +332,30 @@ adanns_status adanns_search_precision(const adanns_index *index, const float *Q,
                                       int32_t *probes, void *stream);
 
 /*
+ * adanns_search's result (Algorithm 1, inference: the exact k nearest in
+ * FP32 of the probed lists' rows on their first d_s coordinates; the same
+ * FP32 coarse step and probes) computed with a quantised first pass over
+ * the lists: the list scan runs on the BF16 or e4m3 copy
+ * (adanns_set_precision) on BF16 / FP8 matrix cores, and only candidates
+ * whose FP32 distance can still be among the k nearest are measured exactly
+ * in FP32. A candidate's FP32 distance lies within
+ * (sqrt(D^) -/+ (|q - q^| + |x - x^|))^2 of the exact distance D^ between the
+ * quantised values (triangle inequality; |x - x^| is the row's own
+ * quantisation error, stored with the copy), and D^ within the first pass's
+ * rounding bound of its first-pass value; candidates whose lower bound
+ * exceeds the k-th smallest FP32 distance found so far are skipped. The
+ * exact measure is the one adanns_search uses, so dist, ids and probes equal
+ * adanns_search's bit for bit. Needs adanns_set_precision(fmt) first;
+ * ldq >= d (queries are quantised over all d coordinates); 1 <= k <= 128.
+ * Other arguments and conventions as adanns_search.
+ */
+adanns_status adanns_search_filtered(const adanns_index *index, const float *Q, int64_t nq,
+                                     int64_t ldq, int32_t d_c, int32_t d_s, int32_t nprobe,
+                                     int32_t k, int32_t fmt, float *dist, int64_t *ids,
+                                     int32_t *probes, void *stream);
+
+/*
+ * The low-precision copy as stored, in database-id order: values host/*
  * The low-precision copy as stored, in database-id order: values host
  * [n x d] (uint16 bf16 bits, or e4m3 bytes), scales host [n] FP32 (1 for
  * bf16). Either may be NULL. Synchronous; for tests and tools.
@@ -373,8 +397,23 @@ adanns_status adanns_timing_read(const char *kernel, int64_t *launches, double *
 adanns_status adanns_selection_stats(int64_t *reselected, int64_t *uncertified, int32_t reset);
 
 /*
+ * Diagnostics of adanns_search_filtered (the work its filter leaves, not a
+ * result): counts since the last reset over every such search on the current
+ * device:
+ *   measured  host out, candidates measured exactly in FP32 (or NULL);
+ *   windowed  host out, queries whose candidates that can still reach the k
+ *             nearest outgrew the free slots, so that they were taken in
+ *             several windows of increasing lower bound (or NULL).
+ * reset != 0 zeroes both after reading. Synchronises the current device.
+ * Errors: ADANNS_EHIP.
+ */
+adanns_status adanns_filtered_stats(int64_t *measured, int64_t *windowed, int32_t reset);
+
+/*
  * Measurement utility (not part of the method): reads ``bytes`` of device
- * memory ``buf`` once with 16-byte loads and writes one partial sum per
+ * memory ``buf`` once with 16-byte non-temporal loads (streamed past the
+ * caches; a grid of tens of thousands of workgroups reaches the highest
+ * rate) and writes one partial sum per
  * workgroup to ``partial`` (device, [grid] FP32), the achievable read-only
  * bandwidth to set beside the scans' rates. Timed under the name
  * "stream_read" when kernel timing is on (adanns_timing_*).

@@ -46,6 +46,8 @@ _SIGS = {
     "adanns_index_quantized": (C.c_int, [vp, i32, vp, vp]),
     "adanns_search_precision": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, i32, i32, i32,
                                           vp, vp, vp, vp]),
+    "adanns_search_filtered": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, i32, vp, vp, vp,
+                                         vp]),
     "adanns_batch_create": (C.c_int, [vp, i32, i64, i64, vp, PIX]),
     "adanns_batch_run": (C.c_int, [vp, vp, vp, vp, vp, vp]),
     "adanns_batch_run_graph": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -60,6 +62,7 @@ _SIGS = {
     "adanns_timing_reset": (C.c_int, []),
     "adanns_timing_read": (C.c_int, [C.c_char_p, vp, vp]),
     "adanns_selection_stats": (C.c_int, [vp, vp, i32]),
+    "adanns_filtered_stats": (C.c_int, [vp, vp, i32]),
     "adanns_stream_read": (C.c_int, [vp, C.c_size_t, vp, i32, vp]),
     "adanns_search": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, vp, vp, vp, vp]),
     "adanns_search_noalloc": (C.c_int, [vp, vp, i64, i64, i32, i32, i32, i32, vp, vp, vp, vp]),
@@ -134,6 +137,15 @@ def selection_stats(reset: bool = False):
     a = C.c_int64()
     b = C.c_int64()
     check(lib.adanns_selection_stats(C.addressof(a), C.addressof(b), 1 if reset else 0))
+    return a.value, b.value
+
+
+def filtered_stats(reset: bool = False):
+    """adanns_filtered_stats: (candidates measured exactly, queries taken in
+    several windows) by adanns_search_filtered since the last reset."""
+    a = C.c_int64()
+    b = C.c_int64()
+    check(lib.adanns_filtered_stats(C.addressof(a), C.addressof(b), 1 if reset else 0))
     return a.value, b.value
 
 

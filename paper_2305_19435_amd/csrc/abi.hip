@@ -1160,6 +1160,67 @@ adanns_status adanns_search_precision(const adanns_index *cix, const float *Q, i
   return ADANNS_OK;
 }
 
+adanns_status adanns_search_filtered(const adanns_index *cix, const float *Q, int64_t nq,
+                                     int64_t ldq, int32_t d_c, int32_t d_s, int32_t nprobe,
+                                     int32_t k, int32_t fmt, float *dist, int64_t *ids,
+                                     int32_t *probes, void *stream) {
+  clear_error();
+  adanns_index *ix = const_cast<adanns_index *>(cix);
+  ADANNS_REQUIRE(ix != nullptr, "index is NULL");
+  ADANNS_REQUIRE(fmt == ADANNS_BF16 || fmt == ADANNS_FP8_E4M3, "fmt must be 1 or 2, got %d", fmt);
+  ADANNS_REQUIRE(ix->quant[fmt].vec != nullptr,
+                 "no quantised copy in this format: call adanns_set_precision first");
+  ADANNS_REQUIRE(nq >= 0, "nq must be >= 0");
+  ADANNS_REQUIRE(d_c >= 1 && d_c <= ix->d_cb, "d_c must be in [1, %d], got %d", ix->d_cb, d_c);
+  ADANNS_REQUIRE(d_s >= 1 && d_s <= ix->d, "d_s must be in [1, %d], got %d", ix->d, d_s);
+  ADANNS_REQUIRE(nprobe >= 1 && nprobe <= ix->nlist, "nprobe must be in [1, %d], got %d",
+                 ix->nlist, nprobe);
+  ADANNS_REQUIRE(k >= 1 && k <= 128, "k must be in [1, 128], got %d", k);
+  ADANNS_REQUIRE(ldq >= ix->d, "ldq (%lld) must be >= d (%d): queries are quantised over d",
+                 (long long)ldq, ix->d);
+  ADANNS_REQUIRE(nq < (int64_t(1) << 31) / nprobe, "nq * nprobe must be below 2^31");
+  if (nq == 0) return ADANNS_OK;
+  ADANNS_REQUIRE(Q && dist && ids, "Q, dist and ids must be non-NULL");
+  adanns_status s = check_async();
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int32_t dq = std::max(d_c, d_s);
+  const int32_t dq_pad = (int32_t)round_up(dq, SLAB);
+  const size_t eb = fmt == ADANNS_BF16 ? 2 : 1;
+  auto bytes_of = [&](int64_t m, size_t *carved) {
+    size_t t = 0;
+    carve(nullptr, ix, m, dq_pad, nprobe, true, &t);
+    if (carved) *carved = t;
+    return t + (size_t)round_up((size_t)m * ix->d_pad * eb, 256) +
+           (size_t)round_up((size_t)m * 4, 256) + 1024;
+  };
+  if (nq > 1 && bytes_of(nq, nullptr) > g_scratch_cap.load()) {  // query chunks
+    int64_t chunk = nq;
+    while (chunk > 1 && bytes_of(chunk, nullptr) > g_scratch_cap.load()) chunk = (chunk + 1) / 2;
+    for (int64_t r0 = 0; r0 < nq; r0 += chunk) {
+      const int64_t m = std::min(chunk, nq - r0);
+      if ((s = adanns_search_filtered(ix, Q + r0 * ldq, m, ldq, d_c, d_s, nprobe, k, fmt,
+                                      dist + r0 * k, ids + r0 * k,
+                                      probes ? probes + r0 * nprobe : nullptr, stream)))
+        return s;
+    }
+    return ADANNS_OK;
+  }
+  size_t total = 0;
+  const size_t extra = bytes_of(nq, &total) - total;
+  void *base = nullptr;
+  if ((s = get_scratch(ix, st, total + extra, &base))) return s;
+  SearchBufs b = carve((char *)base, ix, nq, dq_pad, nprobe, true, &total);
+  Carver c{(char *)base, total, 0};
+  void *Qq = c.take<uint8_t>((size_t)nq * ix->d_pad * eb);
+  float *qscale = c.take<float>((size_t)nq);
+  ADANNS_HIP(launch_stage_queries(Q, nq, ldq, dq, b.Qs, b.ldqs, st));
+  ADANNS_HIP(launch_quantize_queries(Q, nq, ldq, ix->d, fmt, Qq, ix->d_pad, qscale, st));
+  ADANNS_HIP(launch_filtered_search(ix, fmt, b, Qq, ix->d_pad, qscale, nq, d_c, d_s, nprobe, k,
+                                    dist, ids, probes, st));
+  return ADANNS_OK;
+}
+
 adanns_status adanns_index_quantized(const adanns_index *ix, int32_t fmt, void *values,
                                      float *scales) {
   clear_error();
@@ -1237,9 +1298,20 @@ adanns_status adanns_selection_stats(int64_t *reselected, int64_t *uncertified, 
   adanns_status s = check_async();
   if (s) return s;
   unsigned long long v[2] = {0ull, 0ull};
-  ADANNS_HIP(read_selection_stats(v, reset != 0));
+  ADANNS_HIP(read_selection_stats(v, 0, reset != 0));
   if (reselected) *reselected = (int64_t)v[0];
   if (uncertified) *uncertified = (int64_t)v[1];
+  return ADANNS_OK;
+}
+
+adanns_status adanns_filtered_stats(int64_t *measured, int64_t *windowed, int32_t reset) {
+  clear_error();
+  adanns_status s = check_async();
+  if (s) return s;
+  unsigned long long v[2] = {0ull, 0ull};
+  ADANNS_HIP(read_selection_stats(v, 2, reset != 0));
+  if (measured) *measured = (int64_t)v[0];
+  if (windowed) *windowed = (int64_t)v[1];
   return ADANNS_OK;
 }
 

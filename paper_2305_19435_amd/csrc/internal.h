@@ -179,7 +179,8 @@ CfgDev make_cfg(const adanns_index *ix, int32_t d_c, int32_t d_s, int32_t nprobe
 
 // Selection counters of the current device (synchronises it): [0] queries
 // re-selected with a wider shortlist, [1] queries left uncertified.
-hipError_t read_selection_stats(unsigned long long out[2], bool reset);
+// Reads (and with reset zeroes) selection counters first, first + 1.
+hipError_t read_selection_stats(unsigned long long out[2], int first, bool reset);
 
 // IVF-PQ search (adanns_search_pq) and the scratch bytes it needs for nq
 // queries of one budget (0 for an invalid budget). With fixed_base the
@@ -311,6 +312,14 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
                                    int32_t d_c, int32_t d_s, int32_t nprobe, int32_t k,
                                    int32_t rerank_k, int32_t coarse_margin, float *dist,
                                    int64_t *ids, int32_t *user_probes, hipStream_t st);
+// adanns_search's exact result from a quantised first pass (fmt 1 bf16, 2
+// e4m3): FP32 coarse step, quantised list scan, FP32 re-measure of the
+// candidates whose quantisation bound reaches the k-th.
+hipError_t launch_filtered_search(const adanns_index *ix, int32_t fmt, const SearchBufs &b,
+                                  const void *Qq, int64_t ldqq, const float *qscale, int64_t nq,
+                                  int32_t d_c, int32_t d_s, int32_t nprobe, int32_t k,
+                                  float *dist, int64_t *ids, int32_t *user_probes,
+                                  hipStream_t st);
 // IVF-PQ: rotation (compensated), tables, ADC scan and selection.
 hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const SearchBufs &b,
                             int64_t nq, int32_t nprobe, int32_t k, int32_t rerank_k,

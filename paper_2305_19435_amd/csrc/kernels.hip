@@ -105,7 +105,7 @@ __device__ __forceinline__ void wave_reduce_pair(float &S, float &C) {
 
 // Exclusive prefix sum over the block (blockDim.x a multiple of 64).
 template <class T>
-__device__ T block_excl_scan(T v, T *sh /* >= blockDim.x / 64 */, T *total) {
+__device__ __forceinline__ T block_excl_scan(T v, T *sh /* >= blockDim.x / 64 */, T *total) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   T inc = v;
 #pragma unroll
@@ -725,8 +725,10 @@ struct SelArgs {
 
 // Process-wide selection counters (per device): [0] queries handed to the
 // re-selection launch, [1] queries whose band of possible nearest candidates
-// held more than the largest shortlist (result not certified exact).
-__device__ unsigned long long g_sel_stats[2];
+// held more than the largest shortlist (result not certified exact); exact
+// search with a quantised first pass: [2] candidates measured exactly, [3]
+// queries that needed more than one window of candidates.
+__device__ unsigned long long g_sel_stats[4];
 
 // Bound on |first-pass value - exact value| of a candidate, as a function of
 // the first-pass value f. kind 0: none known; 1: a constant B; 2: IVF-PQ's
@@ -1144,16 +1146,38 @@ __device__ FpBound wave_fp_bound(const SelArgs &a, int64_t q, int lane) {
     fb.c2 = 4.f * 0x1p-24f * fb.qn;
     fb.kind = 2;
   } else if (a.mode == SEL_QUANT || a.mode == SEL_COARSE_QUANT) {
-    const float ADANNS_GLOBAL_AS *qrow = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
+    // lane l takes coordinates 4l + 256u .. +3 (16-byte query loads, eight
+    // in flight; the staged rows are padded past d to a multiple of 4)
+    const float *qrow = a.Qs + q * a.ldqs;
+    const float qs = a.qfmt == 1 ? 1.f : ldg(a.qQscale + q);
     float qq = 0.f, ee = 0.f;
-    for (int dim = lane; dim < d; dim += 64) {
-      const int64_t qi = q * a.ldqq + dim;
-      const float qh = a.qfmt == 1
-                           ? bf16_to_float(ldg((const uint16_t *)a.qQ + qi))
-                           : ldg(a.qQscale + q) * e4m3_to_float(ldg((const uint8_t *)a.qQ + qi));
-      const float df = qrow[dim] - qh;
-      qq = fmaf(qh, qh, qq);
-      ee = fmaf(df, df, ee);
+    for (int d0 = 4 * lane; d0 < d; d0 += 256 * 8) {
+      float4 xv[8];
+      uint2 hv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int dim = d0 + 256 * u;
+        const int64_t qi = q * a.ldqq + dim;
+        xv[u] = dim < d ? ldg4(qrow + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (dim >= d) hv[u] = make_uint2(0u, 0u);
+        else if (a.qfmt == 1) hv[u] = *(const uint2 *)((const uint16_t *)a.qQ + qi);
+        else hv[u] = make_uint2(*(const uint32_t *)((const uint8_t *)a.qQ + qi), 0u);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int dim = d0 + 256 * u + e;
+          if (dim < d) {
+            const uint32_t w = e < 2 ? hv[u].x : hv[u].y;
+            const float qh = a.qfmt == 1
+                                 ? __uint_as_float((e & 1 ? w >> 16 : w & 0xffffu) << 16)
+                                 : qs * e4m3_to_float((uint8_t)(hv[u].x >> (8 * e)));
+            const float df = f4(xv[u], e) - qh;
+            qq = fmaf(qh, qh, qq);
+            ee = fmaf(df, df, ee);
+          }
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -1168,9 +1192,19 @@ __device__ FpBound wave_fp_bound(const SelArgs &a, int64_t q, int lane) {
       fb.kind = 1;
     }
   } else if (a.xmax2 != nullptr) {  // FP32 first pass
-    const float ADANNS_GLOBAL_AS *qrow = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
+    const float *qrow = a.Qs + q * a.ldqs;
     float qq = 0.f;
-    for (int dim = lane; dim < d; dim += 64) qq = fmaf(qrow[dim], qrow[dim], qq);
+    for (int d0 = 4 * lane; d0 < d; d0 += 256 * 8) {
+      float4 xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        xv[u] = d0 + 256 * u < d ? ldg4(qrow + d0 + 256 * u) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (d0 + 256 * u + e < d) qq = fmaf(f4(xv[u], e), f4(xv[u], e), qq);
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o);
     const float X2 = ldg(a.xmax2), X = sqrtf(X2), qn = sqrtf(qq);
@@ -1967,6 +2001,430 @@ __global__ __launch_bounds__(256) void k_select_qrerank(SelArgs a) {
   for (int j = tid; j < kout; j += blockDim.x) {
     a.out_dist[q * ldo + j] = chi[j];
     a.out_ids[q * ldo + j] = cid[j];
+  }
+}
+
+// Exact FP32 k nearest of every candidate with a quantised first pass
+// (adanns_search_filtered: the same result as adanns_search, bit for bit), one
+// 256-thread workgroup per query. With f the quantised first-pass values and
+// B their error bound, a candidate's FP32 distance is at least
+// lo = sqrt(f - B + |q^|^2) - |q - q^| - |x - x^| (triangle inequality, the
+// last norm the candidate's own row's quantisation error).
+//  1. The candidates of the f-histogram bins up to rank k (set 1) are
+//     measured exactly in FP32; U, their k-th smallest distance, bounds the
+//     k-th nearest's from above.
+//  2. Every other candidate whose lo reaches sqrt(U) is measured and the k
+//     nearest of all measured ones returned. When more than the free slots
+//     qualify, they are taken in windows of increasing lo (a histogram of lo
+//     picks each window), U tightening after each; a window that cannot be
+//     split falls back to rounds in position order.
+// Candidates are located through the query's probe table staged in LDS
+// (position -> probe by binary search); queries with more probes than the
+// table holds locate through global memory. g_sel_stats[2] counts exact
+// measures, g_sel_stats[3] queries that needed more than one window.
+constexpr int FLT_NPT = 256;
+constexpr int FLT_LIST = 1024;  // candidates listed for the bound test
+
+__global__ __launch_bounds__(256) void k_select_exact_filtered(SelArgs a) {
+  __shared__ uint32_t hist[QRR_BINS];
+  __shared__ int32_t s_lpos[FLT_LIST];
+  __shared__ float s_lf[FLT_LIST];
+  __shared__ int64_t cpos[QRR_CAP], cid[QRR_CAP], cg[QRR_CAP];
+  __shared__ float chi[QRR_CAP], clo[QRR_CAP];
+  __shared__ int64_t t_start[FLT_NPT + 1], t_p0[FLT_NPT], t_np[FLT_NPT];
+  __shared__ int32_t t_h[FLT_NPT];
+  __shared__ uint32_t sh32[16];
+  __shared__ FpBound s_fb;
+  __shared__ uint32_t s_kmin, s_kmax;
+  __shared__ int s_cnt, s_bk, s_c1, s_nl;
+  __shared__ float s_U, s_t;
+  const int64_t q = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+  const int kout = a.kout, np = a.nprobe;
+  const int64_t seg0 = a.seg_off[q], L = a.seg_off[q + 1] - seg0;
+  const float ADANNS_GLOBAL_AS *src = (const float ADANNS_GLOBAL_AS *)(a.D + seg0);
+  const int64_t ldo = a.ldo ? a.ldo : a.kout;
+  const bool tab = np <= FLT_NPT;
+  if (wv == 0) {
+    const FpBound fb = wave_fp_bound(a, q, lane);
+    if (lane == 0) s_fb = fb;
+  }
+  if (tid == 0) {
+    s_kmin = 0xffffffffu;
+    s_kmax = 0u;
+    s_cnt = 0;
+  }
+  if (tab) {
+    for (int p = tid; p < np; p += blockDim.x) {
+      const int32_t h = ldg(a.probes + q * np + p);
+      t_start[p] = ldg(a.pair_base + q * np + p) - seg0;
+      t_h[p] = h;
+      t_p0[p] = ldg(a.poff + h);
+      t_np[p] = ldg(a.poff + h + 1) - t_p0[p];
+    }
+    if (tid == 0) t_start[np] = L;
+  }
+  for (int i = tid; i < QRR_BINS; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const FpBound fb = s_fb;
+  // probe of position pos (t_start[p] <= pos < t_start[p + 1])
+  auto probe_of = [&](int64_t pos) {
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (t_start[mid] <= pos) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
+  // layout row of position pos
+  auto row_of = [&](int64_t pos) -> int64_t {
+    if (!tab) return locate(a, false, q, seg0, pos).row;
+    const int p = probe_of(pos);
+    return t_p0[p] + (pos - t_start[p]);
+  };
+  auto loc_of = [&](int64_t pos) -> CandLoc {
+    if (!tab) return locate(a, false, q, seg0, pos);
+    const int p = probe_of(pos);
+    CandLoc c;
+    const int64_t r = pos - t_start[p];
+    c.p0 = t_p0[p];
+    c.npad = t_np[p];
+    c.row = c.p0 + r;
+    c.id = ldg(a.rowid + c.row);
+    c.gpack = ((int64_t)t_h[p] << 32) | r;
+    return c;
+  };
+  // Passes over the segment: 16-byte loads of the aligned 4-value chunks
+  // that cover it, eight in flight per thread (a chunk's values outside the
+  // segment are skipped; the buffer's 256-byte alignment keeps the first
+  // and last chunks inside it). each_f, one value per load, serves the
+  // passes whose per-value work is heavy (rare paths).
+  auto each_fast = [&](auto fn) {
+    const int64_t c0 = seg0 >> 2, c1 = (seg0 + L + 3) >> 2;
+    for (int64_t cb = c0 + tid; cb < c1; cb += (int64_t)blockDim.x * 8) {
+      float4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = ldg4(a.D + 4 * min64(cb + (int64_t)blockDim.x * u, c1 - 1));
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t ch = cb + (int64_t)blockDim.x * u;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t i = 4 * ch + e - seg0;
+          if (ch < c1 && i >= 0 && i < L) fn(i, f4(v[u], e));
+        }
+      }
+    }
+  };
+  auto each_f = [&](auto fn) {
+    for (int64_t base = tid; base < L; base += (int64_t)blockDim.x * 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = src[min64(base + (int64_t)blockDim.x * u, L - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t i = base + (int64_t)blockDim.x * u;
+        if (i < L) fn(i, v[u]);
+      }
+    }
+  };
+  const float ADANNS_GLOBAL_AS *qg = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
+  int measured = 0;  // thread 0's count of exact measures
+  // FP32 distances of slots [c0, c1), then slots [0, c1) sorted
+  auto measure = [&](int c0, int c1) __attribute__((always_inline)) {
+    if (tid == 0) measured += c1 - c0;
+    if (a.d_B <= 2048) {
+      // this lane's query coordinates 4 lane + 256 u (+0..3), as 16-byte
+      // loads inside the staged row (ldqs >= d_B, a multiple of 4; values
+      // past d_B are not used)
+      float4 q4[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int dim = 4 * lane + 256 * u;
+        q4[u] = dim < a.ldqs ? ldg4(a.Qs + q * a.ldqs + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      for (int c = c0 + 2 * wv; c < c1; c += 2 * nwv) {
+        const int cc = c + 1 < c1 ? c + 1 : c;
+        const CandLoc L0 = loc_of(cpos[c]);
+        const CandLoc L1 = loc_of(cpos[cc]);
+        float S0 = 0.f, C0 = 0.f, S1 = 0.f, C1 = 0.f;
+        measureB_vec_rq2(a, L0, L1, q4, lane, S0, C0, S1, C1);
+        wave_reduce_pair(S0, C0);
+        wave_reduce_pair(S1, C1);
+        if (lane == 0) {
+          chi[c] = S0;
+          clo[c] = C0;
+          cid[c] = L0.id;
+          cg[c] = L0.gpack;
+          if (cc != c) {
+            chi[cc] = S1;
+            clo[cc] = C1;
+            cid[cc] = L1.id;
+            cg[cc] = L1.gpack;
+          }
+        }
+      }
+    } else {
+      for (int c = c0 + wv; c < c1; c += nwv) {
+        const CandLoc Lc = loc_of(cpos[c]);
+        float S = 0.f, C = 0.f;
+        measureB(a, false, Lc, qg, lane, S, C);
+        wave_reduce_pair(S, C);
+        if (lane == 0) {
+          chi[c] = S;
+          clo[c] = C;
+          cid[c] = Lc.id;
+          cg[c] = Lc.gpack;
+        }
+      }
+    }
+    int P2 = 1;
+    while (P2 < c1) P2 <<= 1;
+    __syncthreads();
+    for (int c = c1 + tid; c < P2; c += blockDim.x) {
+      chi[c] = __builtin_inff();
+      clo[c] = 0.f;
+      cid[c] = INT64_MAX;
+      cg[c] = -1;
+    }
+    bitonic_sort(chi, clo, cid, cg, P2);
+  };
+  // Phase-2 state: the bound's constants, U's root, and the lower bounds
+  // already measured (lo <= t)
+  const float B = fb.B;
+  const float qlo = fb.qq * (1.f - 4.f * (float)(a.d_dot + 2) * 0x1p-24f);
+  const float eq = fb.eq * 1.001f;
+  const float emax = ldg(a.qerr) * 1.001f;
+  float fmin = 0.f, fhi = 0.f, inv = 0.f, t = -1.f, sU = 0.f, flim = 0.f;
+  int bk = -1;
+  // (bins and bounds are recomputed in several passes: no contraction, so
+  // that every pass takes the same bits)
+  // bins of [fmin, fhi]; values above fhi take bin QRR_BINS
+  auto bin_of = [&](float f) {
+#pragma clang fp contract(off)
+    return f > fhi ? QRR_BINS : min(QRR_BINS - 1, max(0, (int)((f - fmin) * inv)));
+  };
+  // lo of a candidate outside set 1 that can reach sqrt(U) and is not
+  // measured yet, else -1 (lo is clamped at 0)
+  auto lo_of = [&](int64_t i, float f) -> float {
+#pragma clang fp contract(off)
+    if (!(f <= flim) || bin_of(f) <= bk) return -1.f;
+    const float lo = fmaxf(sqrtf(fmaxf(f - B + qlo, 0.f)) - eq -
+                               ldg(a.qrerr + row_of(i)) * 1.001f, 0.f);
+    return lo > t && lo <= sU ? lo : -1.f;
+  };
+  // mode 0: every candidate; 1: set 1; 2: lo_of
+  auto pred = [&](int mode, int64_t i, float f) -> bool {
+    return mode == 0 ? true : mode == 1 ? bin_of(f) <= bk : lo_of(i, f) >= 0.f;
+  };
+  // Every candidate with pred(mode), measured in rounds of at most
+  // QRR_CAP - have slots in position order (ranks from contiguous per-thread
+  // chunks and a block scan), merged with the have sorted ones; returns the
+  // new have.
+  auto rounds_by_position = [&](int mode, int have) -> int {
+    const int64_t chunk = (L + blockDim.x - 1) / blockDim.x;
+    const int64_t a0 = min64(L, tid * chunk), a1 = min64(L, a0 + chunk);
+    uint32_t ne = 0;
+    for (int64_t i = a0; i < a1; ++i) ne += pred(mode, i, src[i]) ? 1u : 0u;
+    uint32_t n = 0;
+    const uint32_t r0 = block_excl_scan<uint32_t>(ne, sh32, &n);
+    for (uint32_t lo = 0; lo < n;) {
+      const uint32_t cnt = min((uint32_t)(QRR_CAP - have), n - lo);
+      uint32_t r = r0;
+      for (int64_t i = a0; i < a1 && r < lo + cnt; ++i)
+        if (pred(mode, i, src[i])) {
+          if (r >= lo) cpos[have + (r - lo)] = i;
+          ++r;
+        }
+      __syncthreads();
+      measure(have, have + (int)cnt);
+      have = min(kout, have + (int)cnt);
+      lo += cnt;
+    }
+    return have;
+  };
+  int got;
+  bool multi = false;
+  if (L <= QRR_CAP || fb.kind != 1) {  // few candidates, or no bound known: all measured
+    got = rounds_by_position(0, 0);
+    multi = L > QRR_CAP;
+  } else {
+    {
+      uint32_t kmin = 0xffffffffu, kmax = 0u;
+      each_fast([&](int64_t, float f) {
+        const uint32_t kk = order_key(f);
+        kmin = kk < kmin ? kk : kmin;
+        kmax = kk > kmax ? kk : kmax;
+      });
+      atomicMin(&s_kmin, kmin);
+      atomicMax(&s_kmax, kmax);
+    }
+    __syncthreads();
+    fmin = comp_value((uint64_t)s_kmin << 32);
+    const float fmax = comp_value((uint64_t)s_kmax << 32);
+    // the histogram covers the lowest quarter of the range first (rank k
+    // lies there unless the quarter holds fewer than k), else all of it
+    for (int full = 0; full < 2; ++full) {
+      fhi = full ? fmax : fmin + 0.25f * (fmax - fmin);
+      inv = fhi > fmin ? (float)QRR_BINS / (fhi - fmin) : 0.f;
+      if (full) {
+        for (int b = tid; b < QRR_BINS; b += blockDim.x) hist[b] = 0;
+        __syncthreads();
+      }
+      each_fast([&](int64_t, float f) {
+        const int b = bin_of(f);
+        if (b < QRR_BINS) atomicAdd(&hist[b], 1u);
+      });
+      __syncthreads();
+      constexpr int per = QRR_BINS / 256;
+      uint32_t local = 0, tot = 0;
+      for (int e = 0; e < per; ++e) local += hist[tid * per + e];
+      uint32_t c = block_excl_scan<uint32_t>(local, sh32, &tot);
+      for (int e = 0; e < per; ++e) {
+        const uint32_t hb = hist[tid * per + e], b = tid * per + e;
+        if (c < (uint32_t)kout && (uint32_t)kout <= c + hb) {
+          s_bk = b;
+          s_c1 = c + hb;
+        }
+        c += hb;
+      }
+      __syncthreads();
+      if (tot >= (uint32_t)kout) break;
+    }
+    bk = s_bk;
+    const int c1 = s_c1;
+    // 1: the bins up to rank kout (at least kout candidates)
+    int have;
+    if (c1 <= QRR_CAP) {
+      each_fast([&](int64_t i, float f) {
+        if (bin_of(f) <= bk) {
+          const int slot = atomicAdd(&s_cnt, 1);
+          if (slot < c1) cpos[slot] = i;
+        }
+      });
+      __syncthreads();
+      measure(0, c1);
+      have = kout;
+    } else {
+      have = rounds_by_position(1, 0);
+      multi = true;
+    }
+    // 2: the rest whose lower bound reaches sqrt(U), in windows of lo
+    for (;;) {
+      sU = sqrtf((chi[kout - 1] + clo[kout - 1]) * (1.f + 0x1p-20f));
+      const float reach = sU + eq + emax;
+      flim = reach * reach * 1.001f + B - qlo;
+      const int C = QRR_CAP - have;
+      __syncthreads();
+      if (tid == 0) {
+        s_cnt = 0;
+        s_nl = 0;
+      }
+      __syncthreads();
+      auto take = [&](int64_t i, float f) {
+        if (lo_of(i, f) >= 0.f) {
+          const int slot = atomicAdd(&s_cnt, 1);
+          if (slot < C) cpos[have + slot] = i;
+        }
+      };
+      // the values below flim outside set 1 are listed first, so that the
+      // row-error loads of the bound test are issued together
+      const bool listable = L <= 0x7fffffff;  // positions fit the list's int32
+      each_fast([&](int64_t i, float f) {
+        if (listable && f <= flim && bin_of(f) > bk) {
+          const int e = atomicAdd(&s_nl, 1);
+          if (e < FLT_LIST) {
+            s_lpos[e] = (int32_t)i;
+            s_lf[e] = f;
+          }
+        }
+      });
+      __syncthreads();
+      const int nl = s_nl;
+      if (listable && nl <= FLT_LIST) {
+        for (int e = tid; e < nl; e += blockDim.x) take(s_lpos[e], s_lf[e]);
+      } else {
+        each_f(take);
+      }
+      __syncthreads();
+      int n = s_cnt;
+      const bool windowed = n > C;
+      if (windowed) {
+        multi = true;
+        // histogram of lo over (t, sU]: the longest run of bins from the
+        // start holding at most C candidates (and at least one) is the
+        // next window
+        for (int b = tid; b < QRR_BINS; b += blockDim.x) hist[b] = 0;
+        __syncthreads();
+        const float t0 = fmaxf(t, 0.f);
+        const float winv = sU > t0 ? (float)QRR_BINS / (sU - t0) : 0.f;
+        auto wbin = [&](float lo) {
+#pragma clang fp contract(off)
+          return min(QRR_BINS - 1, max(0, (int)((lo - t0) * winv)));
+        };
+        each_f([&](int64_t i, float f) {
+          const float lo = lo_of(i, f);
+          if (lo >= 0.f) atomicAdd(&hist[wbin(lo)], 1u);
+        });
+        __syncthreads();
+        {
+          constexpr int per = QRR_BINS / 256;
+          uint32_t local = 0;
+          for (int e = 0; e < per; ++e) local += hist[tid * per + e];
+          uint32_t c = block_excl_scan<uint32_t>(local, sh32, nullptr);
+          if (tid == 0) s_bk = -1;
+          __syncthreads();
+          for (int e = 0; e < per; ++e) {
+            const uint32_t hb = hist[tid * per + e], b = tid * per + e;
+            if (c + hb > 0 && c + hb <= (uint32_t)C &&
+                (b + 1 == QRR_BINS || c + hb + hist[b + 1] > (uint32_t)C))
+              s_bk = b;
+            c += hb;
+          }
+        }
+        __syncthreads();
+        const int wb = s_bk;
+        if (wb < 0) {  // the first non-empty bin alone overflows: position order
+          have = rounds_by_position(2, have);
+          break;
+        }
+        // the window: exactly the candidates of bins 0..wb
+        if (tid == 0) s_cnt = 0;
+        __syncthreads();
+        each_f([&](int64_t i, float f) {
+          const float lo = lo_of(i, f);
+          if (lo >= 0.f && wbin(lo) <= wb) {
+            const int slot = atomicAdd(&s_cnt, 1);
+            if (slot < C) cpos[have + slot] = i;
+          }
+        });
+        __syncthreads();
+        n = min(s_cnt, C);
+        // the largest lo taken: every candidate left has a larger one
+        float mx = 0.f;
+        for (int c = have + tid; c < have + n; c += blockDim.x) {
+          const int64_t i = cpos[c];
+          mx = fmaxf(mx, lo_of(i, src[i]));
+        }
+        if (tid == 0) s_t = 0.f;
+        __syncthreads();
+        atomicMax((int *)&s_t, __float_as_int(mx));
+        __syncthreads();
+      }
+      if (n > 0) measure(have, have + n);
+      have = min(kout, have + n);
+      if (!windowed) break;
+      t = s_t;
+    }
+    got = have;
+  }
+  for (int j = tid; j < kout; j += blockDim.x) {
+    a.out_dist[q * ldo + j] = j < got ? chi[j] : __builtin_inff();
+    a.out_ids[q * ldo + j] = j < got ? cid[j] : -1;
+  }
+  if (tid == 0) {
+    atomicAdd(&g_sel_stats[2], (unsigned long long)measured);
+    if (multi) atomicAdd(&g_sel_stats[3], 1ull);
   }
 }
 
@@ -3639,12 +4097,13 @@ static int32_t redo_kcap() {
   return k;
 }
 
-hipError_t read_selection_stats(unsigned long long out[2], bool reset) {
+hipError_t read_selection_stats(unsigned long long out[2], int first, bool reset) {
+  const size_t off = (size_t)first * sizeof(unsigned long long), n = 2 * sizeof(unsigned long long);
   hipError_t e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_sel_stats), 2 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_sel_stats), n, off);
   if (e == hipSuccess && reset) {
     const unsigned long long z[2] = {0ull, 0ull};
-    e = hipMemcpyToSymbol(HIP_SYMBOL(g_sel_stats), z, sizeof(z));
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_sel_stats), z, n, off);
   }
   return e;
 }
@@ -4039,31 +4498,28 @@ __global__ __launch_bounds__(256) void k_row_norm_max(const float *__restrict__ 
   }
 }
 
-// Read-only streaming probe: every byte of buf read once with 16-byte loads,
-// four in flight per thread, consecutive threads on consecutive 16-byte
-// pieces (each wave reads 1 KB contiguous per load); each workgroup writes
-// the sum of what it read, so that no load can be dropped.
-__global__ __launch_bounds__(256) void k_stream_read(const float4 *__restrict__ buf, int64_t n4,
+// Read-only streaming probe: every byte of buf read once with 16-byte
+// non-temporal loads (streamed past the caches), four in flight per thread,
+// consecutive threads on consecutive 16-byte pieces (each wave reads 1 KB
+// contiguous per load); each workgroup writes the sum of what it read, so
+// that no load can be dropped. (Measured on 4 GiB: plain loads reach 5.3 TB/s
+// with 1024 workgroups and 6.2 TB/s with 32768; non-temporal loads 5.7 and
+// 7.0 TB/s.)
+__global__ __launch_bounds__(256) void k_stream_read(const floatx4 *__restrict__ buf, int64_t n4,
                                                      float *__restrict__ out) {
   __shared__ float sh[4];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   for (; i + 3 * stride < n4; i += 4 * stride) {
-    const float4 a = buf[i], b = buf[i + stride], c = buf[i + 2 * stride], d = buf[i + 3 * stride];
-    acc.x += (a.x + b.x) + (c.x + d.x);
-    acc.y += (a.y + b.y) + (c.y + d.y);
-    acc.z += (a.z + b.z) + (c.z + d.z);
-    acc.w += (a.w + b.w) + (c.w + d.w);
+    const floatx4 a = __builtin_nontemporal_load(buf + i);
+    const floatx4 b = __builtin_nontemporal_load(buf + i + stride);
+    const floatx4 c = __builtin_nontemporal_load(buf + i + 2 * stride);
+    const floatx4 d = __builtin_nontemporal_load(buf + i + 3 * stride);
+    acc += (a + b) + (c + d);
   }
-  for (; i < n4; i += stride) {
-    const float4 a = buf[i];
-    acc.x += a.x;
-    acc.y += a.y;
-    acc.z += a.z;
-    acc.w += a.w;
-  }
-  float v = (acc.x + acc.y) + (acc.z + acc.w);
+  for (; i < n4; i += stride) acc += __builtin_nontemporal_load(buf + i);
+  float v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
@@ -4073,7 +4529,7 @@ __global__ __launch_bounds__(256) void k_stream_read(const float4 *__restrict__ 
 
 hipError_t launch_stream_read(const void *buf, size_t bytes, float *out, int32_t grid,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_stream_read, dim3((unsigned)grid), dim3(256), 0, st, (const float4 *)buf,
+  hipLaunchKernelGGL(k_stream_read, dim3((unsigned)grid), dim3(256), 0, st, (const floatx4 *)buf,
                      (int64_t)(bytes / 16), out);
   return hipGetLastError();
 }
@@ -4178,6 +4634,46 @@ hipError_t launch_quantize_queries(const float *Q, int64_t nq, int64_t ldq, int3
   return hipGetLastError();
 }
 
+// The quantised list scan's first pass (precision and filtered searches):
+// each probed list's quantised vectors against the quantised queries probing
+// it, into b.D (tiles and buckets from launch_bucketing with QTILE shapes).
+static hipError_t launch_q_scan(const adanns_index *ix, int32_t fmt, const SearchBufs &b,
+                                const void *Qq, int64_t ldqq, const float *qscale,
+                                int32_t nprobe, int32_t d_s, hipStream_t st) {
+  const QuantStore &qs = ix->quant[fmt];
+  hipError_t e;
+  TileQArgs u{};
+  u.Qq = (const uint8_t *)Qq;
+  u.ldqq = ldqq;
+  u.qscale = qscale;
+  u.d_dot = d_s;
+  u.vec = (const uint8_t *)qs.vec;
+  u.vscale = qs.scale;
+  u.d_pad = ix->d_pad;
+  u.poff = ix->poff;
+  u.len = ix->len;
+  u.nlist = ix->nlist;
+  u.tile_off = b.tile_off;
+  u.bkt_off = b.bkt_off;
+  u.cnt = b.cnt;
+  u.work = b.work;
+  u.bucket = b.bucket;
+  u.pair_div = nprobe;
+  u.pair_base = b.pair_base;
+  u.out = b.D;
+  {
+    KernelTimer tm("tile_q_scan", st);
+    const int qgrid = (int)(b.max_items > 0 ? std::min<int64_t>(PERSIST_WG, round_up(std::max<int64_t>(8, b.max_items), 8))
+                                            : PERSIST_WG);
+    if (fmt == 1)
+      hipLaunchKernelGGL((k_tile_q_scan<1, QTILE_Q, QTILE_V>), dim3(qgrid), dim3(256), 0, st, u);
+    else
+      hipLaunchKernelGGL((k_tile_q_scan<2, QTILE_Q, QTILE_V>), dim3(qgrid), dim3(256), 0, st, u);
+  }
+  e = hipGetLastError();
+  return e;
+}
+
 hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const SearchBufs &b,
                                    const void *Qq, int64_t ldqq, const float *qscale, int64_t nq,
                                    int32_t d_c, int32_t d_s, int32_t nprobe, int32_t k,
@@ -4246,39 +4742,8 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   }
   e = launch_bucketing(ix, b, nq, nprobe, st, QTILE_Q, QTILE_V);
   if (e != hipSuccess) return e;
-  // list scan first pass on the quantised vectors
-  TileQArgs u{};
-  u.Qq = (const uint8_t *)Qq;
-  u.ldqq = ldqq;
-  u.qscale = qscale;
-  u.d_dot = d_s;
-  u.vec = (const uint8_t *)qs.vec;
-  u.vscale = qs.scale;
-  u.d_pad = ix->d_pad;
-  u.poff = ix->poff;
-  u.len = ix->len;
-  u.nlist = ix->nlist;
-  u.tile_off = b.tile_off;
-  u.bkt_off = b.bkt_off;
-  u.cnt = b.cnt;
-  u.work = b.work;
-  u.bucket = b.bucket;
-  u.pair_div = nprobe;
-  u.pair_base = b.pair_base;
-  u.out = b.D;
-  {
-    KernelTimer tm("tile_q_scan", st);
-    const int qgrid = (int)(b.max_items > 0 ? std::min<int64_t>(PERSIST_WG, round_up(std::max<int64_t>(8, b.max_items), 8))
-                                            : PERSIST_WG);
-    if (fmt == 1)
-      hipLaunchKernelGGL((k_tile_q_scan<1, QTILE_Q, QTILE_V>), dim3(qgrid), dim3(256), 0, st, u);
-    else
-      hipLaunchKernelGGL((k_tile_q_scan<2, QTILE_Q, QTILE_V>), dim3(qgrid), dim3(256), 0, st, u);
-  }
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  SelArgs r{};
-  r.mode = SEL_QUANT;
+  if ((e = launch_q_scan(ix, fmt, b, Qq, ldqq, qscale, nprobe, d_s, st)) != hipSuccess) return e;
+  SelArgs r{};  r.mode = SEL_QUANT;
   r.D = b.D;
   r.seg_off = b.seg_off;
   r.K2 = rerank_k;
@@ -4315,6 +4780,57 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
     const size_t smem = sel_caps(r, SEG_LDS_CAP);
     KernelTimer tm("select_q_scan", st);
     launch_select(r, nq, smem, b.redo ? b.redo + 1 : nullptr, b.redo ? b.redo + 2 : nullptr, st);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_filtered_search(const adanns_index *ix, int32_t fmt, const SearchBufs &b,
+                                  const void *Qq, int64_t ldqq, const float *qscale, int64_t nq,
+                                  int32_t d_c, int32_t d_s, int32_t nprobe, int32_t k,
+                                  float *dist, int64_t *ids, int32_t *user_probes,
+                                  hipStream_t st) {
+  const QuantStore &qs = ix->quant[fmt];
+  // the FP32 coarse step, exactly as adanns_search runs it
+  hipError_t e = launch_coarse(ix, b, nq, d_c, nprobe, user_probes, st);
+  if (e != hipSuccess) return e;
+  if ((e = launch_bucketing(ix, b, nq, nprobe, st, QTILE_Q, QTILE_V)) != hipSuccess) return e;
+  if ((e = launch_q_scan(ix, fmt, b, Qq, ldqq, qscale, nprobe, d_s, st)) != hipSuccess) return e;
+  SelArgs r{};
+  r.mode = SEL_QUANT;
+  r.D = b.D;
+  r.seg_off = b.seg_off;
+  r.K2 = k;
+  r.K1 = k;
+  r.kout = k;
+  r.stageB = 1;
+  r.Qs = b.Qs;
+  r.ldqs = b.ldqs;
+  r.d_dot = d_s;
+  r.d_B = d_s;
+  r.vec = ix->vec;
+  r.rows = ix->rows;
+  r.d_pad = ix->d_pad;
+  r.poff = ix->poff;
+  r.rowid = ix->rowid;
+  r.probes = b.probes;
+  r.nprobe = nprobe;
+  r.pair_base = b.pair_base;
+  r.qfmt = fmt;
+  r.qvec = qs.vec;
+  r.qscale = qs.scale;
+  r.qd_pad = ix->d_pad;
+  r.qQ = Qq;
+  r.qQscale = qscale;
+  r.ldqq = ldqq;
+  r.qerr = qs.emax;
+  r.qrerr = qs.rerr;
+  r.xmax2 = ix->xmax2;
+  r.out_dist = dist;
+  r.out_ids = ids;
+  {
+    KernelTimer tm("select_filtered", st);
+    if (nq > 0)
+      hipLaunchKernelGGL(k_select_exact_filtered, dim3((unsigned)nq), dim3(256), 0, st, r);
   }
   return hipGetLastError();
 }

@@ -224,6 +224,25 @@ class IvfIndex:
                                           _stream(stream)))
         return (dist, ids, probes) if return_probes else (dist, ids)
 
+    def search_filtered(self, Q, d_c: int, d_s: int, nprobe: int, k: int, fmt: str,
+                        return_probes=False, stream=None, out=None):
+        """adanns_search_filtered: adanns_search's result from a quantised first
+        pass. Returns (dist, ids[, probes])."""
+        Qd = Q if (isinstance(Q, torch.Tensor) and Q.is_cuda and Q.dtype == torch.float32
+                   and Q.stride(1) == 1) else _dev_f32(Q, "cuda")
+        nq = Qd.shape[0]
+        if out is None:
+            dist = torch.empty((nq, k), dtype=torch.float32, device=Qd.device)
+            ids = torch.empty((nq, k), dtype=torch.int64, device=Qd.device)
+        else:
+            dist, ids = out
+        probes = torch.empty((nq, nprobe), dtype=torch.int32, device=Qd.device) if return_probes else None
+        check(lib.adanns_search_filtered(self._h, Qd.data_ptr(), nq,
+                                         Qd.stride(0) if nq else Qd.shape[1], d_c, d_s, nprobe,
+                                         k, self.FORMATS[fmt], dist.data_ptr(), ids.data_ptr(),
+                                         _ptr(probes), _stream(stream)))
+        return (dist, ids, probes) if return_probes else (dist, ids)
+
     def quantized(self, fmt: str):
         """The low-precision copy in id order: (values [n, d], scales [n])."""
         dt = np.uint16 if fmt == "bf16" else np.uint8

@@ -116,3 +116,17 @@ def test_fullwidth_pq_rerank(wide, lib):
         check.compare_knn(Q[qi], X, cands[j], dist[qi], gid[qi], rd[j], ri[j], D, report=rep,
                           tag=f"q{qi}")
     assert rep.ok, rep.problems
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+def test_fullwidth_filtered_equals_search(wide, lib, fmt):
+    """The FP32 search's result from a quantised first pass: bit for bit the
+    plain search's at the full width (every query of the batch)."""
+    X, Q, C32, off, ids, index = wide
+    index.set_precision(fmt)
+    Qd = torch.from_numpy(Q).cuda()
+    a = index.search(Qd, D_C, D, NPROBE, K, return_probes=True)
+    b = index.search_filtered(Qd, D_C, D, NPROBE, K, fmt, return_probes=True)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)

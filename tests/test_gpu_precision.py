@@ -124,3 +124,67 @@ def test_precision_parity_wide(prec_wide, fmt, d_s):
         check.compare_knn(Q[qi], X, shortlists[j], dist[qi], gid[qi], rd[j], ri[j], d_s,
                           report=rep, tag=f"q{qi}")
     assert rep.ok, rep.problems
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+@pytest.mark.parametrize("d_c,d_s,nprobe,k", [(16, 64, 4, 10), (12, 40, 3, 7), (16, 64, 32, 100),
+                                              (16, 48, 1, 1)])
+def test_filtered_equals_search(prec, fmt, d_c, d_s, nprobe, k):
+    """adanns_search_filtered returns adanns_search's result bit for bit."""
+    w, X, Q, C32, off, ids, index = prec
+    Qd = torch.from_numpy(Q).cuda()
+    a = index.search(Qd, d_c, d_s, nprobe, k, return_probes=True)
+    b = index.search_filtered(Qd, d_c, d_s, nprobe, k, fmt, return_probes=True)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("fmt,nprobe,k", [("fp8", 32, 100), ("bf16", 32, 100), ("fp8", 8, 10)])
+def test_filtered_stats(prec, lib, fmt, nprobe, k):
+    """The filter's counters: every query measures at least min(k, L) and at
+    most L candidates exactly (L its candidates), and the result still equals
+    adanns_search's."""
+    w, X, Q, C32, off, ids, index = prec
+    Qd = torch.from_numpy(Q).cuda()
+    a = index.search(Qd, w.d_c, w.d_s, nprobe, k, return_probes=True)
+    lib.filtered_stats(reset=True)
+    b = index.search_filtered(Qd, w.d_c, w.d_s, nprobe, k, fmt, return_probes=True)
+    measured, windowed = lib.filtered_stats(reset=True)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    lens = np.diff(off)
+    L = lens[a[2].cpu().numpy()].sum(axis=1)
+    print(f"{fmt} nprobe={nprobe} k={k}: measured {measured} ({measured / len(Q):.1f}/query, "
+          f"candidates {L.mean():.0f}/query), windowed {windowed}")
+    assert np.minimum(L, k).sum() <= measured <= L.sum()
+    assert 0 <= windowed <= len(Q)
+
+
+def test_filtered_ties_and_windows(lib, small_data):
+    """Ties the filter cannot split: 600 copies of one row at the same
+    distance from the queries (set 1 outgrows the slots and is taken in
+    position order), and queries whose bound band outgrows the slots (taken
+    in windows of the lower bound). The result equals adanns_search's."""
+    w, X0, Q0 = small_data
+    X = X0[:6000].copy()
+    X[:600] = X0[0]
+    Q = np.concatenate([X0[:1] + 0.01 * Q0[:4], Q0[4:40]]).astype(np.float32)
+    C32, a, off, ids = oracle_index(X, 16, w.d_c, 4, w.seed)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    try:
+        Qd = torch.from_numpy(Q).cuda()
+        for fmt in ("bf16", "fp8"):
+            index.set_precision(fmt)
+            for nprobe, k in ((4, 10), (16, 128)):
+                r = index.search(Qd, w.d_c, w.d_s, nprobe, k, return_probes=True)
+                lib.filtered_stats(reset=True)
+                f = index.search_filtered(Qd, w.d_c, w.d_s, nprobe, k, fmt, return_probes=True)
+                measured, windowed = lib.filtered_stats(reset=True)
+                torch.cuda.synchronize()
+                print(f"{fmt} nprobe={nprobe} k={k}: measured {measured}, windowed {windowed}")
+                for x, y in zip(r, f):
+                    assert torch.equal(x, y)
+    finally:
+        index.free()
