@@ -1146,38 +1146,16 @@ __device__ FpBound wave_fp_bound(const SelArgs &a, int64_t q, int lane) {
     fb.c2 = 4.f * 0x1p-24f * fb.qn;
     fb.kind = 2;
   } else if (a.mode == SEL_QUANT || a.mode == SEL_COARSE_QUANT) {
-    // lane l takes coordinates 4l + 256u .. +3 (16-byte query loads, eight
-    // in flight; the staged rows are padded past d to a multiple of 4)
-    const float *qrow = a.Qs + q * a.ldqs;
-    const float qs = a.qfmt == 1 ? 1.f : ldg(a.qQscale + q);
+    const float ADANNS_GLOBAL_AS *qrow = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
     float qq = 0.f, ee = 0.f;
-    for (int d0 = 4 * lane; d0 < d; d0 += 256 * 8) {
-      float4 xv[8];
-      uint2 hv[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int dim = d0 + 256 * u;
-        const int64_t qi = q * a.ldqq + dim;
-        xv[u] = dim < d ? ldg4(qrow + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
-        if (dim >= d) hv[u] = make_uint2(0u, 0u);
-        else if (a.qfmt == 1) hv[u] = *(const uint2 *)((const uint16_t *)a.qQ + qi);
-        else hv[u] = make_uint2(*(const uint32_t *)((const uint8_t *)a.qQ + qi), 0u);
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int dim = d0 + 256 * u + e;
-          if (dim < d) {
-            const uint32_t w = e < 2 ? hv[u].x : hv[u].y;
-            const float qh = a.qfmt == 1
-                                 ? __uint_as_float((e & 1 ? w >> 16 : w & 0xffffu) << 16)
-                                 : qs * e4m3_to_float((uint8_t)(hv[u].x >> (8 * e)));
-            const float df = f4(xv[u], e) - qh;
-            qq = fmaf(qh, qh, qq);
-            ee = fmaf(df, df, ee);
-          }
-        }
+    for (int dim = lane; dim < d; dim += 64) {
+      const int64_t qi = q * a.ldqq + dim;
+      const float qh = a.qfmt == 1
+                           ? bf16_to_float(ldg((const uint16_t *)a.qQ + qi))
+                           : ldg(a.qQscale + q) * e4m3_to_float(ldg((const uint8_t *)a.qQ + qi));
+      const float df = qrow[dim] - qh;
+      qq = fmaf(qh, qh, qq);
+      ee = fmaf(df, df, ee);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -1192,19 +1170,9 @@ __device__ FpBound wave_fp_bound(const SelArgs &a, int64_t q, int lane) {
       fb.kind = 1;
     }
   } else if (a.xmax2 != nullptr) {  // FP32 first pass
-    const float *qrow = a.Qs + q * a.ldqs;
+    const float ADANNS_GLOBAL_AS *qrow = (const float ADANNS_GLOBAL_AS *)(a.Qs + q * a.ldqs);
     float qq = 0.f;
-    for (int d0 = 4 * lane; d0 < d; d0 += 256 * 8) {
-      float4 xv[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        xv[u] = d0 + 256 * u < d ? ldg4(qrow + d0 + 256 * u) : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (d0 + 256 * u + e < d) qq = fmaf(f4(xv[u], e), f4(xv[u], e), qq);
-    }
+    for (int dim = lane; dim < d; dim += 64) qq = fmaf(qrow[dim], qrow[dim], qq);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) qq += __shfl_xor(qq, o);
     const float X2 = ldg(a.xmax2), X = sqrtf(X2), qn = sqrtf(qq);
@@ -1212,6 +1180,62 @@ __device__ FpBound wave_fp_bound(const SelArgs &a, int64_t q, int lane) {
     fb.kind = 1;
   }
   if (!(fb.B <= __FLT_MAX__) || !(fb.qn <= __FLT_MAX__)) fb.kind = 0;  // overflowed
+  return fb;
+}
+
+// wave_fp_bound for the quantised modes with the query's coordinates read
+// as 16-byte pieces, eight in flight per lane (the same bound; the sums'
+// order differs, which their 1.001 margins cover). For the kernels whose
+// registers allow it.
+__device__ __forceinline__ FpBound wave_fp_bound_quant_vec(const SelArgs &a, int64_t q, int lane) {
+  FpBound fb{0, 0.f, 0.f, 0.f, 0.f, -1.f, 0.f};
+  const int d = a.d_dot;
+  // lane l takes coordinates 4l + 256u .. +3 (16-byte query loads, eight
+  // in flight; the staged rows are padded past d to a multiple of 4)
+  const float *qrow = a.Qs + q * a.ldqs;
+  const float qs = a.qfmt == 1 ? 1.f : ldg(a.qQscale + q);
+  float qq = 0.f, ee = 0.f;
+  for (int d0 = 4 * lane; d0 < d; d0 += 256 * 8) {
+    float4 xv[8];
+    uint2 hv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int dim = d0 + 256 * u;
+      const int64_t qi = q * a.ldqq + dim;
+      xv[u] = dim < d ? ldg4(qrow + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+      if (dim >= d) hv[u] = make_uint2(0u, 0u);
+      else if (a.qfmt == 1) hv[u] = *(const uint2 *)((const uint16_t *)a.qQ + qi);
+      else hv[u] = make_uint2(*(const uint32_t *)((const uint8_t *)a.qQ + qi), 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int dim = d0 + 256 * u + e;
+        if (dim < d) {
+          const uint32_t w = e < 2 ? hv[u].x : hv[u].y;
+          const float qh = a.qfmt == 1
+                               ? __uint_as_float((e & 1 ? w >> 16 : w & 0xffffu) << 16)
+                               : qs * e4m3_to_float((uint8_t)(hv[u].x >> (8 * e)));
+          const float df = f4(xv[u], e) - qh;
+          qq = fmaf(qh, qh, qq);
+          ee = fmaf(df, df, ee);
+        }
+      }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    qq += __shfl_xor(qq, o);
+    ee += __shfl_xor(ee, o);
+  }
+  fb.eq = sqrtf(ee);
+  fb.qq = qq;
+  if (a.qerr != nullptr && a.xmax2 != nullptr) {
+    const float X = (sqrtf(ldg(a.xmax2)) + ldg(a.qerr)) * 1.001f, qn = sqrtf(qq) * 1.001f;
+    fb.B = 4.f * (float)(d + 2) * 0x1p-24f * (X * X + 2.f * qn * X);
+    fb.kind = 1;
+  }
+  if (!(fb.B <= __FLT_MAX__)) fb.kind = 0;  // overflowed
   return fb;
 }
 
@@ -2025,7 +2049,7 @@ __global__ __launch_bounds__(256) void k_select_qrerank(SelArgs a) {
 constexpr int FLT_NPT = 256;
 constexpr int FLT_LIST = 1024;  // candidates listed for the bound test
 
-__global__ __launch_bounds__(256) void k_select_exact_filtered(SelArgs a) {
+__device__ __forceinline__ void filtered_block(const SelArgs &a, const int64_t q) {
   __shared__ uint32_t hist[QRR_BINS];
   __shared__ int32_t s_lpos[FLT_LIST];
   __shared__ float s_lf[FLT_LIST];
@@ -2037,8 +2061,7 @@ __global__ __launch_bounds__(256) void k_select_exact_filtered(SelArgs a) {
   __shared__ FpBound s_fb;
   __shared__ uint32_t s_kmin, s_kmax;
   __shared__ int s_cnt, s_bk, s_c1, s_nl;
-  __shared__ float s_U, s_t;
-  const int64_t q = blockIdx.x;
+  __shared__ float s_t;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
   const int kout = a.kout, np = a.nprobe;
   const int64_t seg0 = a.seg_off[q], L = a.seg_off[q + 1] - seg0;
@@ -2046,7 +2069,7 @@ __global__ __launch_bounds__(256) void k_select_exact_filtered(SelArgs a) {
   const int64_t ldo = a.ldo ? a.ldo : a.kout;
   const bool tab = np <= FLT_NPT;
   if (wv == 0) {
-    const FpBound fb = wave_fp_bound(a, q, lane);
+    const FpBound fb = wave_fp_bound_quant_vec(a, q, lane);
     if (lane == 0) s_fb = fb;
   }
   if (tid == 0) {
@@ -2428,6 +2451,20 @@ __global__ __launch_bounds__(256) void k_select_exact_filtered(SelArgs a) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_select_exact_filtered(SelArgs a) {
+  filtered_block(a, blockIdx.x);
+}
+
+// The queries the one-wave selection handed over (a.redo_cnt / a.redo_list),
+// one workgroup each, striding over the list.
+__global__ __launch_bounds__(256) void k_select_exact_filtered_redo(SelArgs a) {
+  const int32_t n = *(volatile const int32_t *)a.redo_cnt;
+  for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    filtered_block(a, a.redo_list[i]);
+    __syncthreads();  // the next query reuses the LDS
+  }
+}
+
 // The same selection and measures for one query on one wave, without LDS
 // or barriers, when K1 <= 64 (see k_select_wave below for the list
 // mechanics). Results equal select_body's.
@@ -2782,6 +2819,175 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
       a.out_ids[q * ldo + lane] = has ? myid : -1;
     }
   }
+}
+
+// adanns_search_filtered's selection with one wave per query (kout +
+// WAVE_MARGIN <= WSEL_K): the WSEL_K smallest first-pass values as a sorted
+// list over the lanes (as k_select_wave); the first kout of them measured
+// exactly in FP32, U their largest (an upper bound on the k-th nearest's
+// distance); then the others whose lower bound
+// sqrt(f - B + |q^|^2) - |q - q^| - |x - x^| reaches sqrt(U) measured too, and
+// the kout nearest of all measured returned. If the list's last value can
+// still reach sqrt(U) with the largest row error, candidates beyond the list
+// might too: the query goes to the workgroup kernel (a.redo_cnt /
+// a.redo_list). The exact measure accumulates each lane's coordinates in the
+// order of measureB, so the distances equal adanns_search's bit for bit.
+__global__ __launch_bounds__(256, 3) void k_select_filtered_wave(SelArgs a, int64_t nq) {
+  const int lane = threadIdx.x & 63;
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= nq) return;  // whole waves leave; nothing synchronises the block
+  const int kout = a.kout;
+  const int64_t ldo = a.ldo ? a.ldo : a.kout;
+  const int64_t seg0 = a.seg_off[q], L = a.seg_off[q + 1] - seg0;
+  const float ADANNS_GLOBAL_AS *sg = (const float ADANNS_GLOBAL_AS *)(a.D + seg0);
+  constexpr int K1 = WSEL_K;
+  // 1. the K1 smallest (key, position) composites, sorted over the lanes
+  // (batches of 64 U values, the next loading while one is merged;
+  // positions past the segment re-read its last value)
+  uint64_t best = ~0ull, thr = ~0ull;
+  constexpr int U = 16;
+  auto load = [&](float (&v)[U], int64_t base) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = sg[min64(base + 64 * u + lane, L - 1)];
+  };
+  auto merge = [&](const float (&v)[U], int64_t base) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + 64 * u + lane;
+      const uint64_t comp = i < L ? ((uint64_t)order_key(v[u]) << 32) | (uint64_t)i : ~0ull;
+      uint64_t mask = __ballot(comp < thr);
+      while (mask) {
+        const int b = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const uint64_t x = readlane64(comp, b);
+        if (x < thr) {
+          const uint64_t up = shfl_up64(best, 1);
+          if (!(best < x)) best = (lane == 0 || up < x) ? x : up;
+          thr = readlane64(best, K1 - 1);
+        }
+      }
+    }
+  };
+  if (L > 0) {
+    float va[U], vb[U];
+    load(va, 0);
+    for (int64_t base = 0;; base += 128 * U) {
+      load(vb, base + 64 * U);
+      merge(va, base);
+      if (base + 64 * U >= L) break;
+      load(va, base + 128 * U);
+      merge(vb, base + 64 * U);
+      if (base + 128 * U >= L) break;
+    }
+  }
+  const int ncand = (int)min64(L, (int64_t)K1);
+  const FpBound fb = wave_fp_bound_quant_vec(a, q, lane);
+  if (L > K1 && fb.kind != 1) {  // no bound: every candidate, in the workgroup kernel
+    if (lane == 0) push_redo(a.redo_cnt, a.redo_list, q + a.redo_q0);
+    return;
+  }
+  // 2. where each candidate lives (lane j < ncand holds candidate j)
+  int64_t my_id = INT64_MAX, my_row = 0, my_npad = 0;
+  const float *my_base = nullptr;
+  if (lane < ncand) {
+    const CandLoc c = locate(a, false, q, seg0, (int64_t)(uint32_t)best);
+    my_id = c.id;
+    my_row = c.row;
+    my_npad = a.rows ? 1 : c.npad;
+    my_base = a.rows ? a.rows + c.row * a.d_pad : a.vec + c.p0 * a.d_pad + (c.row - c.p0) * SLAB;
+  }
+  // 3. exact FP32 measures of the lanes in a mask, two candidates at a time,
+  // lane l taking coordinates 4l + 256u + e in that order, 1024 per pass
+  const int d = a.d_B;
+  const float *qrow = a.Qs + q * a.ldqs;
+  float myS = __builtin_inff(), myC = 0.f;
+  int nmeas = 0;
+  auto measure_mask = [&](uint64_t mask) {
+    nmeas += __popcll(mask);
+    while (mask) {
+      const int c0 = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      int c1 = c0;
+      if (mask) {
+        c1 = __builtin_ctzll(mask);
+        mask &= mask - 1;
+      }
+      const float *xp[2] = {(const float *)readlane64((uint64_t)my_base, c0),
+                            (const float *)readlane64((uint64_t)my_base, c1)};
+      const int64_t np[2] = {(int64_t)readlane64((uint64_t)my_npad, c0),
+                             (int64_t)readlane64((uint64_t)my_npad, c1)};
+      float S[2] = {0.f, 0.f}, C[2] = {0.f, 0.f};
+      constexpr int PP = 4;
+      for (int d0 = 4 * lane; d0 < d; d0 += 256 * PP) {
+        float4 qv[PP], xv[2][PP];
+#pragma unroll
+        for (int u = 0; u < PP; ++u) {
+          const int dim = d0 + 256 * u;
+          qv[u] = dim < d ? ldg4(qrow + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+          for (int u = 0; u < PP; ++u) {
+            const int dim = d0 + 256 * u;
+            xv[gi][u] = dim < d ? ldg4(xp[gi] + (int64_t)(dim / SLAB) * np[gi] * SLAB + dim % SLAB)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+        for (int u = 0; u < PP; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (d0 + 256 * u + e < d)
+#pragma unroll
+              for (int gi = 0; gi < 2; ++gi)
+                acc_sq_diff(f4(qv[u], e), f4(xv[gi][u], e), S[gi], C[gi]);
+      }
+      wave_reduce_pair(S[0], C[0]);
+      wave_reduce_pair(S[1], C[1]);
+      if (lane == c0) {
+        myS = S[0];
+        myC = C[0];
+      }
+      if (lane == c1 && c1 != c0) {
+        myS = S[1];
+        myC = C[1];
+      }
+    }
+  };
+  const uint64_t lanes_lt = [&](int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }(
+      L > K1 ? kout : ncand);
+  measure_mask(lanes_lt & __ballot(lane < ncand));
+  if (L > K1) {
+    // U: the largest of the kout measured; the bound test for the rest
+    float u = lane < kout ? (myS + myC) * (1.f + 0x1p-20f) : 0.f;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) u = fmaxf(u, __shfl_xor(u, o));
+    const float sU = sqrtf(u);
+    const float B = fb.B;
+    const float qlo = fb.qq * (1.f - 4.f * (float)(a.d_dot + 2) * 0x1p-24f);
+    const float eq = fb.eq * 1.001f;
+    const float reach = sU + eq + ldg(a.qerr) * 1.001f;
+    const float flim = reach * reach * 1.001f + B - qlo;
+    if (comp_value(readlane64(best, K1 - 1)) <= flim) {  // not certified within the list
+      if (lane == 0) push_redo(a.redo_cnt, a.redo_list, q + a.redo_q0);
+      return;
+    }
+    const float f = comp_value(best);
+    bool need = false;
+    if (lane >= kout && f <= flim) {
+      const float lo = sqrtf(fmaxf(f - B + qlo, 0.f)) - eq - ldg(a.qrerr + my_row) * 1.001f;
+      need = lo <= sU;
+    }
+    measure_mask(__ballot(need));
+  }
+  int64_t gp = 0;
+  bitonic_lanes(myS, myC, my_id, gp, lane);
+  if (lane < kout) {
+    const bool has = lane < nmeas;
+    a.out_dist[q * ldo + lane] = has ? myS : __builtin_inff();
+    a.out_ids[q * ldo + lane] = has ? my_id : -1;
+  }
+  if (lane == 0) atomicAdd(&g_sel_stats[2], (unsigned long long)nmeas);
 }
 
 // COARSE: the coarse step's selection (m.coarse set), else the scan's; two
@@ -4829,8 +5035,19 @@ hipError_t launch_filtered_search(const adanns_index *ix, int32_t fmt, const Sea
   r.out_ids = ids;
   {
     KernelTimer tm("select_filtered", st);
-    if (nq > 0)
+    if (nq > 0 && fmt == 1 && k + WAVE_MARGIN <= WSEL_K && b.redo != nullptr) {
+      // BF16: one wave per query; the queries it cannot certify within its
+      // list go to the workgroup kernel. (e4m3's bound band outgrows the
+      // list for most queries at d_s 2048: the workgroup kernel directly.)
+      r.redo_cnt = b.redo + 1;
+      r.redo_list = b.redo + 2;
+      r.redo_q0 = 0;
+      hipLaunchKernelGGL(k_select_filtered_wave, dim3((unsigned)cdiv(nq, 4)), dim3(256), 0, st, r,
+                         nq);
+      hipLaunchKernelGGL(k_select_exact_filtered_redo, dim3(redo_grid(nq)), dim3(256), 0, st, r);
+    } else if (nq > 0) {
       hipLaunchKernelGGL(k_select_exact_filtered, dim3((unsigned)nq), dim3(256), 0, st, r);
+    }
   }
   return hipGetLastError();
 }
