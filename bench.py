@@ -77,17 +77,33 @@ def parse():
     ap.add_argument("--row-copy", action="store_true",
                     help="add the row-major copy of the vectors that the exact re-measures read")
     ap.add_argument("--rerank", type=int, default=256, help="precision form shortlist")
+    ap.add_argument("--widths", default=None,
+                    help="sweep form: comma-separated d_c values (default: the whole grid)")
+    ap.add_argument("--probes", default=None,
+                    help="sweep form: comma-separated nprobe values (default: the whole grid)")
     ap.add_argument("--pq-rotation", default="opq", choices=["opq", "random"],
                     help="IVF-PQ forms: learned OPQ rotation or a seeded random one")
     return ap.parse_args()
 
 
+SCAN_SOURCE_END = b"// ---- per-query selection and exact re-measurement"
+
+
 def kernel_source_digest() -> str:
+    """Digest of the FP32 tile kernels' source: internal.h and kernels.hip up
+    to the start of the selection code (the tile kernels and every helper
+    they use are defined above it), so that changes elsewhere keep the
+    committed traffic figures valid."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "internal.h"):
-        with open(os.path.join(ROOT, "paper_2305_19435_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2305_19435_amd", "csrc", "internal.h"), "rb") as fh:
+        h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2305_19435_amd", "csrc", "kernels.hip"), "rb") as fh:
+        src = fh.read()
+    cut = src.find(SCAN_SOURCE_END)
+    if cut < 0:
+        raise RuntimeError("kernels.hip: the selection-code marker is missing")
+    h.update(src[:cut])
     return h.hexdigest()[:16]
 
 

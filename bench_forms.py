@@ -461,8 +461,10 @@ def sweep_form(args, lib, torch, log):
     n_train = min(n, 64 * nlist)
     tr = synth.subsample_rows(n, n_train, w.seed)
     init = synth.init_rows(n_train, nlist, w.seed)
-    widths = [8, 16, 32, 64, 128, 256, 512, 1024, 2048]
-    probes = [1, 2, 4, 8, 16, 32, 64]
+    widths = ([int(v) for v in args.widths.split(",")] if args.widths
+              else [8, 16, 32, 64, 128, 256, 512, 1024, 2048])
+    probes = ([int(v) for v in args.probes.split(",")] if args.probes
+              else [1, 2, 4, 8, 16, 32, 64])
     truth = None
     grid = {}
     shapes = {}
