@@ -29,12 +29,15 @@ def _timed(torch, fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def _kernel_ms(lib, names):
+def _kernel_ms(lib, names, calls=None):
+    """Kernel times since the last reset: per search when ``calls`` (the
+    searches timed) is given, since a search split into query chunks
+    launches each kernel once per chunk; else per launch."""
     out = {}
     for n in names:
         c, ms = lib.timing_read(n)
         if c:
-            out[n] = round(ms / c, 4)
+            out[n] = round(ms / (calls or c), 4)
     return out
 
 
@@ -78,9 +81,9 @@ def precision_form(args, lib, torch, log):
     lib.timing_reset()
     lib.timing_enable(True)
     t = _timed(torch, lambda: index.search(Qd, d_c, w.d_s, nprobe, k), args.steps, args.warmup)
+    kern32 = _kernel_ms(lib, ["tile_dist_scan", "select_scan"], args.steps + args.warmup)
     _, ids32 = index.search(Qs_d, d_c, w.d_s, nprobe, k)
-    res["fp32"] = {"qps": nq / t, "ms_per_step": t * 1e3,
-                   "kernels_ms": _kernel_ms(lib, ["tile_dist_scan", "select_scan"])}
+    res["fp32"] = {"qps": nq / t, "ms_per_step": t * 1e3, "kernels_ms": kern32}
     gpu_ids = {"fp32": ids32.cpu().numpy()}
     reranks = sorted({args.rerank, 32}, reverse=True)
     for fmt0 in ("bf16", "fp8"):
@@ -92,10 +95,11 @@ def precision_form(args, lib, torch, log):
             t = _timed(torch, lambda: index.search_precision(Qd, d_c, w.d_s, nprobe, k, fmt0, R),
                        args.steps, args.warmup)
             resel, uncert = lib.selection_stats(reset=True)
+            kq = _kernel_ms(lib, ["tile_q_coarse", "select_q_coarse", "tile_q_scan",
+                                  "select_q_scan"], args.steps + args.warmup)
             dd, ii = index.search_precision(Qs_d, d_c, w.d_s, nprobe, k, fmt0, R)
             res[fmt] = {"qps": nq / t, "ms_per_step": t * 1e3, "rerank": R,
-                        "kernels_ms": _kernel_ms(lib, ["tile_q_coarse", "select_q_coarse",
-                                                       "tile_q_scan", "select_q_scan"]),
+                        "kernels_ms": kq,
                         "reselected_per_step": resel / (args.steps + args.warmup),
                         "uncertified": uncert}
             gpu_ids[fmt] = ii.cpu().numpy()
@@ -297,7 +301,8 @@ def pq_form(args, lib, torch, log):
             lib.timing_reset()
             t = _timed(torch, lambda: index.search_pq(Qd, w.d_c, nprobe, M, 10), args.steps,
                        args.warmup)
-            kern = _kernel_ms(lib, ["pq_rotate", "pq_lut", "adc_scan", "select_adc"])
+            kern = _kernel_ms(lib, ["pq_rotate", "pq_lut", "adc_scan", "select_adc"],
+                              args.steps + args.warmup)
             # ADC scan algorithmic bytes: every probed list's codes once per
             # (query, probe), plus each query's table once
             off, _ = index.lists()
@@ -497,7 +502,8 @@ def sweep_form(args, lib, torch, log):
             t = _timed(torch, lambda: index.search(Qd, dc, d_s, npb, k, out=(dist, ids)),
                        max(2, args.steps // 2), 1)
             lib.timing_enable(False)
-            kern = _kernel_ms(lib, ["tile_dist_coarse", "tile_dist_scan", "select_scan"])
+            kern = _kernel_ms(lib, ["tile_dist_coarse", "tile_dist_scan", "select_scan"],
+                              max(2, args.steps // 2) + 1)
             got = ids.cpu().numpy()
             hits = sum(len(set(a.tolist()) & set(b.tolist())) for a, b in zip(got, truth))
             coarse_tf = (2.0 * nq * nlist * dc / (kern["tile_dist_coarse"] * 1e-3) / 1e12
@@ -559,6 +565,16 @@ def latency_form(args, lib, torch, log):
             e1.record()
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
+        # per-kernel times of the same search (separate runs: the library's
+        # events add to the whole-search time)
+        lib.timing_reset()
+        lib.timing_enable(True)
+        for _ in range(10):
+            index.search(Qd, w.d_c, w.d_s, w.nprobe, w.k, out=(dist, ids))
+        torch.cuda.synchronize()
+        lib.timing_enable(False)
+        kern = _kernel_ms(lib, ["stage_queries", "tile_dist_coarse", "select_coarse", "bucketing",
+                                "tile_dist_scan", "select_scan", "select_redo"], 10)
         # the same search as one replayed hipGraph (batching form, one
         # configuration): launch overheads leave the host's path
         gb = lib.Batch([(index, nq, w.d_c, w.d_s, w.nprobe, w.k)], ldq=w.d, ldk=w.k)
@@ -585,7 +601,13 @@ def latency_form(args, lib, torch, log):
                            "graph_p99_ms": round(float(np.percentile(gms, 99)), 4),
                            "distinct_lists": int(len(lists)),
                            "hbm_floor_ms": round(floor_bytes / (HBM_PEAK_GBS * 1e9) * 1e3, 4),
-                           "hbm_floor_frac": round(floor_bytes / (HBM_PEAK_GBS * 1e9) / (p50 * 1e-3), 4)}
+                           "hbm_floor_frac": round(floor_bytes / (HBM_PEAK_GBS * 1e9) / (p50 * 1e-3), 4),
+                           "kernels_ms": kern,
+                           "scan_hbm_gbs": (round(floor_bytes / (kern["tile_dist_scan"] * 1e-3) / 1e9, 1)
+                                            if "tile_dist_scan" in kern else None),
+                           "scan_hbm_frac": (round(floor_bytes / (kern["tile_dist_scan"] * 1e-3) / 1e9
+                                                   / HBM_PEAK_GBS, 4)
+                                             if "tile_dist_scan" in kern else None)}
         log(f"nq={nq}: p50 {p50:.3f} ms, p99 {p99:.3f} ms")
     index.free()
     out = {"metric": "p50/p99 latency of one FP32 search per batch size", "value": res["nq=1"]["p50_ms"],
