@@ -468,7 +468,7 @@ adanns_status adanns_batch_run_graph(adanns_batch *batch, const float *Q, float 
  * (64, 128) and persistent grid. Results do not depend on the shape. Until
  * set or autotuned, a batch (and adanns_search) uses the autotune cache's
  * shape for its key, else 64 x 128 tiles when probed lists meet at least 32
- * queries on average, else 64 x 64. */
+ * queries on average, else 32 x 64. */
 adanns_status adanns_batch_set_shape(adanns_batch *batch, int32_t tq, int32_t tv, int32_t grid);
 
 /* Autotuner: times every (tq, tv, grid) candidate on this batch (one warm-up and

@@ -161,6 +161,13 @@ def test_batch_invalid(lib, setup):
         lib.Batch([(ix, 5, 17, 64, 4, 10)], ldq=128)       # d_c above d_c_build
     with pytest.raises(lib.AdannsError):
         lib.Batch([(ix, 5, 16, 64, 4, 10)], ldq=32)        # ldq too small
+    b = lib.Batch([(ix, 5, 16, 64, 4, 10)], ldq=128)
+    for tq, tv in ((8, 64), (48, 64), (64, 256), (64, 32)):  # no such tile
+        with pytest.raises(lib.AdannsError):
+            b.set_shape(tq, 1024, tv)
+    with pytest.raises(lib.AdannsError):
+        b.set_shape(64, 4, 64)                             # grid below 8
+    b.free()
 
 
 def test_all_shapes_ragged_prefixes_parity(lib, setup):
