@@ -188,3 +188,25 @@ def test_filtered_ties_and_windows(lib, small_data):
                     assert torch.equal(x, y)
     finally:
         index.free()
+
+
+def test_filtered_many_probes(lib, small_data):
+    """More probes than the workgroup kernel's LDS probe table holds (256):
+    candidates are located through global memory. k = 100 takes the
+    workgroup kernel directly; k = 10 the one-wave selection first."""
+    w, X0, Q0 = small_data
+    X, Q = X0[:6000], Q0[:24]
+    C32, a, off, ids = oracle_index(X, 320, w.d_c, 3, w.seed)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    try:
+        Qd = torch.from_numpy(Q).cuda()
+        for fmt in ("bf16", "fp8"):
+            index.set_precision(fmt)
+            for nprobe, k in ((300, 100), (300, 10), (260, 1)):
+                r = index.search(Qd, w.d_c, w.d_s, nprobe, k, return_probes=True)
+                f = index.search_filtered(Qd, w.d_c, w.d_s, nprobe, k, fmt, return_probes=True)
+                torch.cuda.synchronize()
+                for x, y in zip(r, f):
+                    assert torch.equal(x, y), (fmt, nprobe, k)
+    finally:
+        index.free()
