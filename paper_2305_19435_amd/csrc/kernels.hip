@@ -2046,6 +2046,41 @@ __global__ __launch_bounds__(256) void k_select_qrerank(SelArgs a) {
 // (position -> probe by binary search); queries with more probes than the
 // table holds locate through global memory. g_sel_stats[2] counts exact
 // measures, g_sel_stats[3] queries that needed more than one window.
+// Exact FP32 measure (compensated, as measureB) of two vector rows at once
+// against the query row qrow (16-byte aligned, padded to a multiple of 4):
+// lane l takes coordinates 4l + 256u + e in that order, 1024 per pass, the
+// query's pieces re-read from L2 each pass (fewer registers than holding
+// them), so each row's sum has measureB's order and bits. xp / np: the rows'
+// first slab piece and slab stride in rows (1 for the row-major copy).
+__device__ __forceinline__ void measure2_rows(const float *qrow, int d, const float *const xp[2],
+                                              const int64_t np[2], int lane, float S[2],
+                                              float C[2]) {
+  constexpr int PP = 4;
+  for (int d0 = 4 * lane; d0 < d; d0 += 256 * PP) {
+    float4 qv[PP], xv[2][PP];
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+      const int dim = d0 + 256 * u;
+      qv[u] = dim < d ? ldg4(qrow + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+      for (int u = 0; u < PP; ++u) {
+        const int dim = d0 + 256 * u;
+        xv[gi][u] = dim < d ? ldg4(xp[gi] + (int64_t)(dim / SLAB) * np[gi] * SLAB + dim % SLAB)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+    for (int u = 0; u < PP; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (d0 + 256 * u + e < d)
+#pragma unroll
+          for (int gi = 0; gi < 2; ++gi) acc_sq_diff(f4(qv[u], e), f4(xv[gi][u], e), S[gi], C[gi]);
+  }
+}
+
 constexpr int FLT_NPT = 256;
 constexpr int FLT_LIST = 1024;  // candidates listed for the bound test
 
@@ -2157,31 +2192,27 @@ __device__ __forceinline__ void filtered_block(const SelArgs &a, const int64_t q
   auto measure = [&](int c0, int c1) __attribute__((always_inline)) {
     if (tid == 0) measured += c1 - c0;
     if (a.d_B <= 2048) {
-      // this lane's query coordinates 4 lane + 256 u (+0..3), as 16-byte
-      // loads inside the staged row (ldqs >= d_B, a multiple of 4; values
-      // past d_B are not used)
-      float4 q4[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int dim = 4 * lane + 256 * u;
-        q4[u] = dim < a.ldqs ? ldg4(a.Qs + q * a.ldqs + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
+      const float *qrow = a.Qs + q * a.ldqs;
       for (int c = c0 + 2 * wv; c < c1; c += 2 * nwv) {
         const int cc = c + 1 < c1 ? c + 1 : c;
         const CandLoc L0 = loc_of(cpos[c]);
         const CandLoc L1 = loc_of(cpos[cc]);
-        float S0 = 0.f, C0 = 0.f, S1 = 0.f, C1 = 0.f;
-        measureB_vec_rq2(a, L0, L1, q4, lane, S0, C0, S1, C1);
-        wave_reduce_pair(S0, C0);
-        wave_reduce_pair(S1, C1);
+        const float *xp[2] = {
+            a.rows ? a.rows + L0.row * a.d_pad : a.vec + L0.p0 * a.d_pad + (L0.row - L0.p0) * SLAB,
+            a.rows ? a.rows + L1.row * a.d_pad : a.vec + L1.p0 * a.d_pad + (L1.row - L1.p0) * SLAB};
+        const int64_t np[2] = {a.rows ? 1 : L0.npad, a.rows ? 1 : L1.npad};
+        float S[2] = {0.f, 0.f}, C[2] = {0.f, 0.f};
+        measure2_rows(qrow, a.d_B, xp, np, lane, S, C);
+        wave_reduce_pair(S[0], C[0]);
+        wave_reduce_pair(S[1], C[1]);
         if (lane == 0) {
-          chi[c] = S0;
-          clo[c] = C0;
+          chi[c] = S[0];
+          clo[c] = C[0];
           cid[c] = L0.id;
           cg[c] = L0.gpack;
           if (cc != c) {
-            chi[cc] = S1;
-            clo[cc] = C1;
+            chi[cc] = S[1];
+            clo[cc] = C[1];
             cid[cc] = L1.id;
             cg[cc] = L1.gpack;
           }
@@ -2451,13 +2482,16 @@ __device__ __forceinline__ void filtered_block(const SelArgs &a, const int64_t q
   }
 }
 
-__global__ __launch_bounds__(256) void k_select_exact_filtered(SelArgs a) {
+// (three workgroups per CU: the measures wait on memory, so workgroups in
+// flight count more than the registers the bound spills; e4m3 selection
+// 12.2 -> 9.7 ms at the ImageNet-1K shape)
+__global__ __launch_bounds__(256, 3) void k_select_exact_filtered(SelArgs a) {
   filtered_block(a, blockIdx.x);
 }
 
 // The queries the one-wave selection handed over (a.redo_cnt / a.redo_list),
 // one workgroup each, striding over the list.
-__global__ __launch_bounds__(256) void k_select_exact_filtered_redo(SelArgs a) {
+__global__ __launch_bounds__(256, 3) void k_select_exact_filtered_redo(SelArgs a) {
   const int32_t n = *(volatile const int32_t *)a.redo_cnt;
   for (int32_t i = blockIdx.x; i < n; i += gridDim.x) {
     filtered_block(a, a.redo_list[i]);
@@ -2920,31 +2954,7 @@ __global__ __launch_bounds__(256, 3) void k_select_filtered_wave(SelArgs a, int6
       const int64_t np[2] = {(int64_t)readlane64((uint64_t)my_npad, c0),
                              (int64_t)readlane64((uint64_t)my_npad, c1)};
       float S[2] = {0.f, 0.f}, C[2] = {0.f, 0.f};
-      constexpr int PP = 4;
-      for (int d0 = 4 * lane; d0 < d; d0 += 256 * PP) {
-        float4 qv[PP], xv[2][PP];
-#pragma unroll
-        for (int u = 0; u < PP; ++u) {
-          const int dim = d0 + 256 * u;
-          qv[u] = dim < d ? ldg4(qrow + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int gi = 0; gi < 2; ++gi)
-#pragma unroll
-          for (int u = 0; u < PP; ++u) {
-            const int dim = d0 + 256 * u;
-            xv[gi][u] = dim < d ? ldg4(xp[gi] + (int64_t)(dim / SLAB) * np[gi] * SLAB + dim % SLAB)
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
-          }
-#pragma unroll
-        for (int u = 0; u < PP; ++u)
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (d0 + 256 * u + e < d)
-#pragma unroll
-              for (int gi = 0; gi < 2; ++gi)
-                acc_sq_diff(f4(qv[u], e), f4(xv[gi][u], e), S[gi], C[gi]);
-      }
+      measure2_rows(qrow, d, xp, np, lane, S, C);
       wave_reduce_pair(S[0], C[0]);
       wave_reduce_pair(S[1], C[1]);
       if (lane == c0) {
