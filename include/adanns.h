@@ -347,7 +347,9 @@ adanns_status adanns_search_precision(const adanns_index *index, const float *Q,
  * exact measure is the one adanns_search uses, so dist, ids and probes equal
  * adanns_search's bit for bit. Needs adanns_set_precision(fmt) first;
  * ldq >= d (queries are quantised over all d coordinates); 1 <= k <= 128.
- * Other arguments and conventions as adanns_search.
+ * Other arguments and conventions as adanns_search. Errors: ADANNS_EINVAL
+ * (arguments out of range, fmt not 1 or 2, no copy in fmt), ADANNS_ENOMEM
+ * (search scratch), ADANNS_EHIP.
  */
 adanns_status adanns_search_filtered(const adanns_index *index, const float *Q, int64_t nq,
                                      int64_t ldq, int32_t d_c, int32_t d_s, int32_t nprobe,
