@@ -429,6 +429,13 @@ adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t d_c, in
       for (int64_t j = 0; j < nt; ++j) J += h_mind[j];
       objective[it] = J;
     }
+    // the host indexes its arrays by these: a cluster outside [0, nlist)
+    // (non-finite rows or centroids leave the coarse step without an order)
+    // is an error, not an index
+    for (int64_t j = 0; j < nt; ++j)
+      ADANNS_REQUIRE(h_asg[j] >= 0 && h_asg[j] < nlist,
+                     "k-means: row %lld assigned to cluster %d outside [0, %d) (non-finite data?)",
+                     (long long)j, h_asg[j], nlist);
     // stable counting sort of the training rows by cluster
     std::fill(h_off.begin(), h_off.end(), 0);
     for (int64_t j = 0; j < nt; ++j) h_off[h_asg[j] + 1]++;
@@ -466,6 +473,10 @@ adanns_status kmeans_gpu(const Mat &X, int64_t n, int32_t nlist, int32_t d_c, in
   }
   ADANNS_HIP(hipMemcpyAsync(assign_all.data(), asg, n * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   ADANNS_HIP(hipStreamSynchronize(st));
+  for (int64_t j = 0; j < n; ++j)
+    ADANNS_REQUIRE(assign_all[j] >= 0 && assign_all[j] < nlist,
+                   "k-means: row %lld assigned to cluster %d outside [0, %d) (non-finite data?)",
+                   (long long)j, assign_all[j], nlist);
   if (objective) {
     double J = 0.0;
     if (train_rows)
