@@ -131,6 +131,40 @@ def test_precision_band_overflow(lib):
         index.free()
 
 
+@pytest.mark.parametrize("per,k", [(48, 5), (200, 60)])
+def test_filtered_band_overflow(lib, per, k):
+    """Exact search with a quantised first pass on offset rows: the rows'
+    quantisation errors (~0.1 for BF16, several units for e4m3 at norm 100)
+    put every near row of a query, and for e4m3 the near rows of the other
+    queries as well, inside the band of the k-th, so the one-wave list
+    cannot certify and the workgroup kernel takes the band in position rounds
+    and lower-bound windows. The result must equal adanns_search's bit for
+    bit and the FP64 oracle's."""
+    d, nq, nlist = 64, 16, 4
+    X, Q = offset_rows(4 + per, d, nq, per)
+    C32, a, off, ids = oracle_index(X, nlist, 16, 10, 7)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    try:
+        Qd = torch.from_numpy(Q).cuda()
+        ref = index.search(Qd, 16, d, nlist, k, return_probes=True)
+        torch.cuda.synchronize()
+        dist, gid, probes = (t.cpu().numpy() for t in ref)
+        rep = check_search(X, Q, C32, off, ids, 16, d, nlist, k, dist, gid, got_p=probes)
+        assert rep.ok, rep.problems
+        for fmt in ("bf16", "fp8"):
+            index.set_precision(fmt)
+            lib.filtered_stats(reset=True)
+            got = index.search_filtered(Qd, 16, d, nlist, k, fmt, return_probes=True)
+            measured, windowed = lib.filtered_stats(reset=True)
+            torch.cuda.synchronize()
+            print(f"{fmt} per={per} k={k}: measured {measured}, windowed {windowed}")
+            for x, y in zip(ref, got):
+                assert torch.equal(x, y), fmt
+            assert measured >= nq * min(per, 2 * k)
+    finally:
+        index.free()
+
+
 @pytest.mark.parametrize("rerank", [0, 8])
 def test_pq_identical_codes(lib, small_data, rerank):
     """48 copies of one row next to query 0 share their codes, so their ADC
