@@ -3827,21 +3827,65 @@ __global__ __launch_bounds__(256) void k_tile_dist_q(TileQArgs a) {
   }
 }
 
-// LDS-DMA form of the precision form's scan tile (TQ x TV, TQ, TV >= 64),
+// LDS-DMA form of the precision form's scan tile (TQ x TV = 128 x 64),
 // built like tile_compute_dma: every stage holds 128 bytes of each operand
 // row (SC = 64 BF16 or 128 e4m3 coordinates, KS slabs), copied straight into
 // LDS by 16-byte global_load_lds_dwordx4 with chunk c of row r at position
-// c ^ f(r); two stages, one barrier per stage; four waves in a 2 x 2 grid,
-// each (TQ/2) x (TV/2) in 16x16x32 MFMA blocks. Lane l reads, per k-step of
-// 32 coordinates, the 8 values at coordinates 8 (l >> 4) .. of row l & 15,
-// for both operands. Quantised norms are summed from the decoded B fragments.
-// Coordinates past d_dot are zeroed in LDS on the last stage (both
-// operands); copies that would start past a row's stored width re-read an
-// earlier piece of it, which is zeroed too.
-constexpr int QTILE_Q = 128, QTILE_V = 128;  // precision-form scan tile
+// c ^ f(r); four waves in a 2 x 2 grid, each (TQ/2) x (TV/2) in 16x16x32
+// MFMA blocks. Lane l reads, per k-step of 32 coordinates, the 8 values at
+// coordinates 8 (l >> 4) .. of row l & 15, for both operands. Quantised
+// norms are summed from the decoded B fragments. Coordinates past d_dot are
+// zeroed in LDS on the last stage (both operands); copies that would start
+// past a row's stored width re-read an earlier piece of it, which is zeroed
+// too.
+// The copies run in a ring of three stages, two ahead of the one being
+// read: the scan waits on copy latency (its MFMA work per stage is short), so
+// bytes in flight set its pace. The barrier that hands a stage over waits
+// for LDS work only, and the fragment reads are inline-asm ds_read groups
+// that wait for their own results: LDS reads that the compiler sees make it
+// wait for every copy still in flight (it cannot tell the stage being read
+// from the stages being filled), which would drain the ring at every stage.
+constexpr int QTILE_Q = 128, QTILE_V = 64;  // precision-form scan tile
+
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+// LDS address of p, as ds_read takes it
+__device__ __forceinline__ uint32_t lds_off(const uint8_t *p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint8_t *)p;
+}
+// Four A-operand reads at la and two B-operand reads at lb, rows 16 apart
+// (2048 bytes), 16 bytes each; one group that waits for its own results.
+__device__ __forceinline__ void lds_frags_b128(uint32_t la, uint32_t lb, v4i32 (&ra)[4],
+                                               v4i32 (&rb)[2]) {
+  asm volatile(
+      "ds_read_b128 %0, %6\n"
+      "ds_read_b128 %1, %6 offset:2048\n"
+      "ds_read_b128 %2, %6 offset:4096\n"
+      "ds_read_b128 %3, %6 offset:6144\n"
+      "ds_read_b128 %4, %7\n"
+      "ds_read_b128 %5, %7 offset:2048\n"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(ra[0]), "=&v"(ra[1]), "=&v"(ra[2]), "=&v"(ra[3]), "=&v"(rb[0]), "=&v"(rb[1])
+      : "v"(la), "v"(lb));
+}
+// The same with 8-byte reads.
+__device__ __forceinline__ void lds_frags_b64(uint32_t la, uint32_t lb, long (&ra)[4],
+                                              long (&rb)[2]) {
+  asm volatile(
+      "ds_read_b64 %0, %6\n"
+      "ds_read_b64 %1, %6 offset:2048\n"
+      "ds_read_b64 %2, %6 offset:4096\n"
+      "ds_read_b64 %3, %6 offset:6144\n"
+      "ds_read_b64 %4, %7\n"
+      "ds_read_b64 %5, %7 offset:2048\n"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(ra[0]), "=&v"(ra[1]), "=&v"(ra[2]), "=&v"(ra[3]), "=&v"(rb[0]), "=&v"(rb[1])
+      : "v"(la), "v"(lb));
+}
 
 template <int FMT, int TQ, int TV>
 __global__ __launch_bounds__(256, 2) void k_tile_q_scan(TileQArgs a) {
+  static_assert(TQ == 128 && TV == 64, "fragment reads written for 128 x 64 tiles");
+  constexpr int NST = 3;  // stages in the copy ring (3 x 24 KB at 128 x 64)
   constexpr int EB = FMT == 1 ? 2 : 1;
   constexpr int KS = 128 / (SLAB * EB);    // slabs per stage
   constexpr int SC = KS * SLAB;            // coordinates per stage
@@ -3850,8 +3894,8 @@ __global__ __launch_bounds__(256, 2) void k_tile_q_scan(TileQArgs a) {
   constexpr int NA = TQ / 32, NBV = TV / 32;
   constexpr int NB16 = TQ / 32, NC16 = TV / 32;
   constexpr int NKS = SC / 32;             // MFMA k-steps per stage
-  __shared__ __attribute__((aligned(16))) uint8_t A0[TQ * 128], A1[TQ * 128];
-  __shared__ __attribute__((aligned(16))) uint8_t B0[TV * 128], B1[TV * 128];
+  __shared__ __attribute__((aligned(16))) uint8_t Ar[NST][TQ * 128];
+  __shared__ __attribute__((aligned(16))) uint8_t Br[NST][TV * 128];
   __shared__ int64_t rbase[TQ];
   __shared__ int32_t rq[TQ];
   __shared__ float rsc[TQ], csc[TV], cn[TV];
@@ -3972,14 +4016,17 @@ __global__ __launch_bounds__(256, 2) void k_tile_q_scan(TileQArgs a) {
         const int ch = FMT == 1 ? 4 * ks + g16 : 2 * ks + (g16 >> 1);
         const int inner = FMT == 1 ? 0 : (g16 & 1) * 8;
         const int off = ((ch ^ sw16) << 4) + inner;
+        const uint32_t la = lds_off(A + (rbw + r16) * 128 + off);
+        const uint32_t lb = lds_off(B + (cbw + r16) * 128 + off);
         if constexpr (FMT == 1) {
+          v4i32 ra[NB16], rb[NC16];
+          lds_frags_b128(la, lb, ra, rb);
           bf16x8 af[NB16], bfv[NC16];
 #pragma unroll
-          for (int i = 0; i < NB16; ++i)
-            af[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)&A[(rbw + i * 16 + r16) * 128 + off]);
+          for (int i = 0; i < NB16; ++i) af[i] = __builtin_bit_cast(bf16x8, ra[i]);
 #pragma unroll
           for (int j = 0; j < NC16; ++j) {
-            const uint4 x = *(const uint4 *)&B[(cbw + j * 16 + r16) * 128 + off];
+            const uint4 x = __builtin_bit_cast(uint4, rb[j]);
             bfv[j] = __builtin_bit_cast(bf16x8, x);
             const uint32_t wd[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
@@ -3995,11 +4042,9 @@ __global__ __launch_bounds__(256, 2) void k_tile_q_scan(TileQArgs a) {
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfv[j], acc[i][j], 0, 0, 0);
         } else {
           long af[NB16], bfv[NC16];
-#pragma unroll
-          for (int i = 0; i < NB16; ++i) af[i] = *(const long *)&A[(rbw + i * 16 + r16) * 128 + off];
+          lds_frags_b64(la, lb, af, bfv);
 #pragma unroll
           for (int j = 0; j < NC16; ++j) {
-            bfv[j] = *(const long *)&B[(cbw + j * 16 + r16) * 128 + off];
             const int lo32 = (int)(uint32_t)bfv[j], hi32 = (int)(uint32_t)((uint64_t)bfv[j] >> 32);
             const float v[8] = {
                 __builtin_amdgcn_cvt_f32_fp8(lo32, 0), __builtin_amdgcn_cvt_f32_fp8(lo32, 1),
@@ -4018,21 +4063,21 @@ __global__ __launch_bounds__(256, 2) void k_tile_q_scan(TileQArgs a) {
       }
     };
     __builtin_amdgcn_s_waitcnt(vm_wait_imm(0));  // the previous item's stores first
-    issue(0, A0, B0);
-    int s = 0;
-    auto step = [&](auto J) -> bool {
-      constexpr int j = decltype(J)::value;
-      uint8_t *A = j == 0 ? A0 : A1, *B = j == 0 ? B0 : B1;
-      __builtin_amdgcn_s_waitcnt(vm_wait_imm(0));  // this wave's copies of stage s landed
-      __syncthreads();  // stage s is in buffer j; every wave is done with 1 - j
-      if (s + 1 < nstage) issue(s + 1, j == 0 ? A1 : A0, j == 0 ? B1 : B0);
-      if (a.d_dot - s * SC < SC) clip(A, B, a.d_dot - s * SC);
-      if (active) compute(A, B);
-      return ++s >= nstage;
-    };
-    for (;;) {
-      if (step(ic<0>{})) break;
-      if (step(ic<1>{})) break;
+    constexpr int NCOPY = NA + NBV;  // copies per lane and stage
+    for (int p = 0; p < NST - 1 && p < nstage; ++p) issue(p, Ar[p], Br[p]);
+    for (int s = 0; s < nstage; ++s) {
+      const int j = s % NST;
+      // this wave's copies of stage s have landed; those of stage s + 1 (issued
+      // after them, and counted in order) may still be in flight
+      if (s + 1 < nstage) __builtin_amdgcn_s_waitcnt(vm_wait_imm(NCOPY));
+      else __builtin_amdgcn_s_waitcnt(vm_wait_imm(0));
+      // LDS-only barrier: stage s has landed for every wave, and every wave's
+      // reads of stage s - 1 (whose buffer is refilled next) have returned
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0), other counters free
+      __builtin_amdgcn_s_barrier();
+      if (s + NST - 1 < nstage) issue(s + NST - 1, Ar[(s + NST - 1) % NST], Br[(s + NST - 1) % NST]);
+      if (a.d_dot - s * SC < SC) clip(Ar[j], Br[j], a.d_dot - s * SC);
+      if (active) compute(Ar[j], Br[j]);
     }
     // norms: the four lane groups of a column hold its coordinate ranges
 #pragma unroll
