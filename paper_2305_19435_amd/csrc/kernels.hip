@@ -2667,6 +2667,32 @@ __device__ __forceinline__ void bitonic_lanes(float &S, float &C, int64_t &id, i
   }
 }
 
+// Admission cap for a one-wave list of the K1 smallest (key, position)
+// composites, from its first batch v (values at positions base + 64 u + lane,
+// those at L or beyond ignored): the K1-th smallest of the lanes' minima is
+// at least the K1-th smallest value of all L (K1 distinct candidates lie at or
+// under it), so values above it never enter the list, and equal keys are
+// admitted at every position. ~0 when fewer than K1 lanes hold a value.
+template <int U>
+__device__ __forceinline__ uint64_t admit_cap(const float (&v)[U], int64_t base, int64_t L,
+                                              int lane, int K1) {
+  uint32_t mk = 0xFFFFFFFFu;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (base + 64 * u + lane < L) mk = min(mk, order_key(v[u]));
+  // bitonic sort of the 64 lane minima, ascending over the lanes
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t o = (uint32_t)__shfl_xor((int)mk, j);
+      const bool up = (lane & k) == 0, lower = (lane & j) == 0;
+      mk = (lower == up) ? min(mk, o) : max(mk, o);
+    }
+  const uint32_t t = (uint32_t)__builtin_amdgcn_readlane((int)mk, K1 - 1);
+  return t == 0xFFFFFFFFu ? ~0ull : ((uint64_t)t << 32) | 0xFFFFFFFFull;
+}
+
 __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
   const bool coarse = a.mode == SEL_COARSE || a.mode == SEL_COARSE_QUANT;
   const int64_t ldo = a.ldo ? a.ldo : a.kout;
@@ -2881,7 +2907,7 @@ __global__ __launch_bounds__(256, 3) void k_select_filtered_wave(SelArgs a, int6
   // 1. the K1 smallest (key, position) composites, sorted over the lanes
   // (batches of 64 U values, the next loading while one is merged;
   // positions past the segment re-read its last value)
-  uint64_t best = ~0ull, thr = ~0ull;
+  uint64_t best = ~0ull, thr = ~0ull, cap = ~0ull;
   constexpr int U = 16;
   auto load = [&](float (&v)[U], int64_t base) {
 #pragma unroll
@@ -2900,7 +2926,8 @@ __global__ __launch_bounds__(256, 3) void k_select_filtered_wave(SelArgs a, int6
         if (x < thr) {
           const uint64_t up = shfl_up64(best, 1);
           if (!(best < x)) best = (lane == 0 || up < x) ? x : up;
-          thr = readlane64(best, K1 - 1);
+          const uint64_t kth = readlane64(best, K1 - 1);
+          thr = kth < cap ? kth : cap;
         }
       }
     }
@@ -2910,6 +2937,7 @@ __global__ __launch_bounds__(256, 3) void k_select_filtered_wave(SelArgs a, int6
     load(va, 0);
     for (int64_t base = 0;; base += 128 * U) {
       load(vb, base + 64 * U);
+      if (base == 0) thr = cap = admit_cap(va, 0, L, lane, K1);
       merge(va, base);
       if (base + 64 * U >= L) break;
       load(va, base + 128 * U);
@@ -3040,7 +3068,7 @@ __global__ __launch_bounds__(256, WIDE ? 2 : 3) void k_select_wave(SelMultiArgs 
 
   // 1. the K1 smallest (key, position) composites, sorted over lanes
   const float ADANNS_GLOBAL_AS *sg = (const float ADANNS_GLOBAL_AS *)seg;
-  uint64_t best = ~0ull, thr = ~0ull;
+  uint64_t best = ~0ull, thr = ~0ull, cap = ~0ull;
   constexpr int U = !COARSE && WIDE ? 32 : 16;  // loads in flight per lane and batch
   // scan: batches of 64 U values, the next batch loading while one is merged
   // (positions past the segment re-read its last value, so that the loads
@@ -3062,7 +3090,8 @@ __global__ __launch_bounds__(256, WIDE ? 2 : 3) void k_select_wave(SelMultiArgs 
         if (x < thr) {
           const uint64_t up = shfl_up64(best, 1);
           if (!(best < x)) best = (lane == 0 || up < x) ? x : up;
-          thr = readlane64(best, K1 - 1);
+          const uint64_t kth = readlane64(best, K1 - 1);
+          thr = kth < cap ? kth : cap;
         }
       }
     }
@@ -3077,6 +3106,7 @@ __global__ __launch_bounds__(256, WIDE ? 2 : 3) void k_select_wave(SelMultiArgs 
         const int64_t i = base + 64 * u + lane;
         v[u] = i < L ? sg[i] : 0.f;
       }
+      if (base == 0) thr = cap = admit_cap(v, 0, L, lane, K1);
       merge(v, base);
     }
   } else if (L > 0) {
@@ -3086,6 +3116,7 @@ __global__ __launch_bounds__(256, WIDE ? 2 : 3) void k_select_wave(SelMultiArgs 
     // last value, and the wait counts stay exact on every path)
     for (int64_t base = 0;; base += 128 * U) {
       load(vb, base + 64 * U);
+      if (base == 0) thr = cap = admit_cap(va, 0, L, lane, K1);
       merge(va, base);
       if (base + 64 * U >= L) break;
       load(va, base + 128 * U);
