@@ -721,6 +721,9 @@ struct SelArgs {
   int32_t *redo_cnt;
   int32_t *redo_list;
   int64_t redo_q0;         // added to a query's index in redo_list
+  // k_select_filtered_wave: > 0 also certifies that every result lies in the
+  // shortlist of this many nearest candidates by exact quantised distance
+  int32_t shortlist;
 };
 
 // Process-wide selection counters (per device): [0] queries handed to the
@@ -3021,8 +3024,30 @@ __global__ __launch_bounds__(256, 3) void k_select_filtered_wave(SelArgs a, int6
     }
     measure_mask(__ballot(need));
   }
-  int64_t gp = 0;
+  // (each lane's first-pass value rides along with its measure)
+  int64_t gp = (int64_t)__float_as_uint(comp_value(best));
   bitonic_lanes(myS, myC, my_id, gp, lane);
+  if (a.shortlist > 0 && L > a.shortlist) {
+    // The precision form's result: the FP32 k nearest of the shortlist S (the
+    // a.shortlist nearest candidates by exact quantised distance). If every
+    // result above lies in S, it is that result too (S holds all candidates'
+    // k nearest). A candidate y ahead of result x in S's order has
+    // f_y <= f_x + 2B (B bounds each first-pass value's error), so x is in S
+    // when at most a.shortlist candidates have f <= T = max_x f_x + 2B; all
+    // of them are in the list when its last entry lies above T.
+    float T = -__builtin_inff();
+    if (lane < kout && lane < nmeas) T = __uint_as_float((uint32_t)gp);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) T = fmaxf(T, __shfl_xor(T, o));
+    T += 2.f * fb.B * 1.001f;
+    T += fabsf(T) * 0x1p-20f;
+    const bool inlist = L <= K1 || comp_value(readlane64(best, K1 - 1)) > T;
+    const int nle = __popcll(__ballot(lane < ncand && comp_value(best) <= T));
+    if (fb.kind != 1 || !(T <= __FLT_MAX__) || !inlist || nle > a.shortlist) {
+      if (lane == 0) push_redo(a.redo_cnt, a.redo_list, q + a.redo_q0);
+      return;
+    }
+  }
   if (lane < kout) {
     const bool has = lane < nmeas;
     a.out_dist[q * ldo + lane] = has ? myS : __builtin_inff();
@@ -5074,7 +5099,26 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
   {
     const size_t smem = sel_caps(r, SEG_LDS_CAP);
     KernelTimer tm("select_q_scan", st);
-    launch_select(r, nq, smem, b.redo ? b.redo + 1 : nullptr, b.redo ? b.redo + 2 : nullptr, st);
+    if (nq > 0 && fmt == 1 && k + WAVE_MARGIN <= WSEL_K && b.redo != nullptr) {
+      // BF16: the exact search's one-wave selection (FP32 k nearest of all
+      // candidates, per-row quantisation bound), certified to return only
+      // shortlist members, which makes it the shortlist's k nearest; the
+      // queries it cannot certify go to the general re-selection launch
+      SelArgs w = r;
+      w.shortlist = rerank_k;
+      w.redo_cnt = b.redo + 1;
+      w.redo_list = b.redo + 2;
+      w.redo_q0 = 0;
+      hipLaunchKernelGGL(k_select_filtered_wave, dim3((unsigned)cdiv(nq, 4)), dim3(256), 0, st, w,
+                         nq);
+      w.shortlist = 0;
+      w.kcap = redo_kcap();
+      w.lcap = seg_cap(w.kcap, SEG_LDS_CAP);
+      hipLaunchKernelGGL(k_select_refine_redo, dim3(redo_grid(nq)), dim3(512),
+                         sel_smem_bytes(w.lcap, w.kcap), st, w);
+    } else {
+      launch_select(r, nq, smem, b.redo ? b.redo + 1 : nullptr, b.redo ? b.redo + 2 : nullptr, st);
+    }
   }
   return hipGetLastError();
 }
