@@ -2696,7 +2696,7 @@ __device__ __forceinline__ uint64_t admit_cap(const float (&v)[U], int64_t base,
   return t == 0xFFFFFFFFu ? ~0ull : ((uint64_t)t << 32) | 0xFFFFFFFFull;
 }
 
-__device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
+__device__ __forceinline__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
   const bool coarse = a.mode == SEL_COARSE || a.mode == SEL_COARSE_QUANT;
   const int64_t ldo = a.ldo ? a.ldo : a.kout;
   const float *seg;
@@ -2716,7 +2716,7 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
   const int kv = a.stageB ? a.K2 : a.kout;
   const int K1 = max(a.K1, min(WSEL_K, kv + WAVE_MARGIN));
   const float ADANNS_GLOBAL_AS *sg = (const float ADANNS_GLOBAL_AS *)seg;
-  uint64_t best = ~0ull, thr = ~0ull;
+  uint64_t best = ~0ull, thr = ~0ull, cap = ~0ull;
   constexpr int U = 16;
   for (int64_t base = 0; base < L; base += 64 * U) {
     float v[U];
@@ -2725,6 +2725,7 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
       const int64_t i = base + 64 * u + lane;
       v[u] = i < L ? sg[i] : 0.f;
     }
+    if (base == 0) thr = cap = admit_cap(v, 0, L, lane, K1);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = base + 64 * u + lane;
@@ -2737,7 +2738,8 @@ __device__ void wave_select(const SelArgs &a, const int64_t q, const int lane) {
         if (x < thr) {
           const uint64_t up = shfl_up64(best, 1);
           if (!(best < x)) best = (lane == 0 || up < x) ? x : up;
-          thr = readlane64(best, K1 - 1);
+          const uint64_t kth = readlane64(best, K1 - 1);
+          thr = kth < cap ? kth : cap;
         }
       }
     }

@@ -65,6 +65,51 @@ def test_precision_parity(prec, fmt, d_c, d_s, nprobe, k, rerank, margin):
     assert rep.ok, rep.problems
 
 
+@pytest.mark.parametrize("fmt", ["bf16", "fp8"])
+@pytest.mark.parametrize("rerank,k", [(1, 1), (2, 2), (4, 1)])
+def test_precision_shortlist_excludes_fp32_nearest(lib, small_data, fmt, rerank, k):
+    """Pairs of rows at distances 0.05 and 0.05 (1 + 2e-4) from each query:
+    the quantised first pass orders many pairs against their FP32 order, so
+    with a shortlist this short its FP32 re-rank returns the row that is not
+    the FP32 nearest (the oracle's result for 9 of 24 queries at rerank 1).
+    The library must return the shortlist's result, not the exact search's."""
+    w, X0, Q0 = small_data
+    rng = np.random.default_rng(7)
+    nq = 24
+    Q = Q0[:nq].astype(np.float64)
+    rows = [X0[:4000].astype(np.float64)]
+    for i in range(nq):
+        u = rng.standard_normal((2, Q.shape[1]))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        rows.append(Q[i] + (0.05 * np.array([1.0, 1.0 + 2e-4]))[:, None] * u)
+    X = np.concatenate(rows).astype(np.float32)
+    Q = Q.astype(np.float32)
+    d = X.shape[1]
+    C32, a, off, ids = oracle_index(X, 16, w.d_c, 4, w.seed)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    try:
+        index.set_precision(fmt)
+        Qd = torch.from_numpy(Q).cuda()
+        dist, gid, probes = index.search_precision(Qd, w.d_c, d, 16, k, fmt, rerank, 0,
+                                                   return_probes=True)
+        _, eid = index.search(Qd, w.d_c, d, 16, k)
+        torch.cuda.synchronize()
+        dist, gid, probes = dist.cpu().numpy(), gid.cpu().numpy(), probes.cpu().numpy()
+        rd, ri, rp, shortlists = precision.precision_search64(
+            X, Q, C32.astype(np.float64), off, ids, w.d_c, d, 16, k, fmt, rerank, 0,
+            return_shortlist=True)
+        assert np.array_equal(np.sort(probes, 1), np.sort(rp, 1))
+        rep = check.Report()
+        for qi in range(nq):
+            check.compare_knn(Q[qi], X, shortlists[qi], dist[qi], gid[qi], rd[qi], ri[qi], d,
+                              report=rep, tag=f"q{qi}")
+        assert rep.ok, rep.problems
+        if rerank == 1:
+            assert (gid[:, 0] != eid.cpu().numpy()[:, 0]).sum() >= 1
+    finally:
+        index.free()
+
+
 def test_precision_requires_copy(lib, small_data):
     w, X, Q = small_data
     C32, a, off, ids = oracle_index(X[:2000], 8, w.d_c, 3, w.seed)
