@@ -1090,6 +1090,49 @@ __device__ __forceinline__ void measureB(const SelArgs &a, bool coarse, const Ca
   }
 }
 
+// G centroid candidates at once, their loads in flight together, each in the
+// order of its single measure: measure1's quantised coarse case (STAGE 0)
+// or measureB's centroid case (STAGE 1). Same bits as one at a time.
+template <int G, int STAGE, class QP>
+__device__ __forceinline__ void measure_cent_g(const SelArgs &a, int64_t q, const CandLoc *L,
+                                               QP qrow, int lane, float *S, float *C) {
+  if constexpr (STAGE == 0) {
+    const int d = a.d_dot;
+    const float qs = a.qfmt == 2 ? ldg(a.qQscale + q) : 1.f;
+    float xs[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) xs[g] = a.qfmt == 2 ? ldg(a.qscale + L[g].row) : 1.f;
+    for (int dim = lane; dim < d; dim += 64) {
+      float qh, ql, xh[G], xl[G];
+      quant_value(a.qfmt, a.qQ, q * a.ldqq + dim, qs, qh, ql);
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        quant_value(a.qfmt, a.qvec,
+                    ((int64_t)(dim / SLAB) * a.qnpad + L[g].row) * SLAB + (dim % SLAB), xs[g],
+                    xh[g], xl[g]);
+#pragma unroll
+      for (int g = 0; g < G; ++g) acc_sq_diff2(qh, ql - xl[g], xh[g], S[g], C[g]);
+    }
+  } else {
+    const int d = a.d_B;
+    const float *x[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) x[g] = a.cent + L[g].row * a.ld_cent;
+    for (int d0 = lane; d0 < d; d0 += 64 * 8) {
+      float xv[G][8];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[g][u] = d0 + 64 * u < d ? ldg(x[g] + d0 + 64 * u) : 0.f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (d0 + 64 * u < d)
+#pragma unroll
+          for (int g = 0; g < G; ++g) acc_sq_diff(qrow[d0 + 64 * u], xv[g][u], S[g], C[g]);
+    }
+  }
+}
+
 // measureB's vector case (d_B <= 2048) with this lane's query coordinates
 // 4l + 256u .. 4l + 256u + 3 already in registers (q4[u]); the same order of
 // accumulation, so the same bits.
@@ -2803,6 +2846,23 @@ __device__ __forceinline__ void wave_select(const SelArgs &a, const int64_t q, c
         myC = C[1];
       }
     }
+  } else if (a.mode == SEL_COARSE_QUANT) {
+    // four centroids at a time (duplicates of the last one discarded)
+    for (int cc = 0; cc < ncand; cc += 4) {
+      CandLoc Lp[4];
+#pragma unroll
+      for (int g = 0; g < 4; ++g) Lp[g] = cand(cc + g < ncand ? cc + g : ncand - 1);
+      float S[4] = {0.f, 0.f, 0.f, 0.f}, C[4] = {0.f, 0.f, 0.f, 0.f};
+      measure_cent_g<4, 0>(a, q, Lp, qglob, lane, S, C);
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        wave_reduce_pair(S[g], C[g]);
+        if (lane == cc + g && cc + g < ncand) {
+          myS = S[g];
+          myC = C[g];
+        }
+      }
+    }
   } else {
     for (int cc = 0; cc < ncand; ++cc) {
       const CandLoc Lc = cand(cc);
@@ -2857,17 +2917,37 @@ __device__ __forceinline__ void wave_select(const SelArgs &a, const int64_t q, c
         q4[u] = make_float4(v[0], v[1], v[2], v[3]);
       }
     }
-    for (int cc = 0; cc < nres; ++cc) {
-      const int64_t gp = (int64_t)readlane64((uint64_t)mygp, cc);
-      float S = 0.f, C = 0.f;
-      if (rq)
-        measureB_vec_rq(a, locate_packed(a, false, gp), q4, lane, S, C);
-      else
-        measureB(a, coarse, locate_packed(a, coarse, gp), qglob, lane, S, C);
-      wave_reduce_pair(S, C);
-      if (lane == cc) {
-        myS = S;
-        myC = C;
+    if (coarse) {  // four centroids at a time, as the first measure
+      for (int cc = 0; cc < nres; cc += 4) {
+        CandLoc Lp[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          Lp[g] = locate_packed(a, true, (int64_t)readlane64((uint64_t)mygp,
+                                                            cc + g < nres ? cc + g : nres - 1));
+        float S[4] = {0.f, 0.f, 0.f, 0.f}, C[4] = {0.f, 0.f, 0.f, 0.f};
+        measure_cent_g<4, 1>(a, q, Lp, qglob, lane, S, C);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          wave_reduce_pair(S[g], C[g]);
+          if (lane == cc + g && cc + g < nres) {
+            myS = S[g];
+            myC = C[g];
+          }
+        }
+      }
+    } else {
+      for (int cc = 0; cc < nres; ++cc) {
+        const int64_t gp = (int64_t)readlane64((uint64_t)mygp, cc);
+        float S = 0.f, C = 0.f;
+        if (rq)
+          measureB_vec_rq(a, locate_packed(a, false, gp), q4, lane, S, C);
+        else
+          measureB(a, false, locate_packed(a, false, gp), qglob, lane, S, C);
+        wave_reduce_pair(S, C);
+        if (lane == cc) {
+          myS = S;
+          myC = C;
+        }
       }
     }
     bitonic_lanes(myS, myC, myid, mygp, lane);
