@@ -205,6 +205,37 @@ def test_pq_identical_codes(lib, small_data, rerank):
         index.free()
 
 
+def test_exact_ties_take_smallest_ids(lib, small_data):
+    """150 copies of one row next to query 0: their first-pass values and
+    exact distances tie, the tie outgrows the one-wave lists and their
+    admission cap equals the tied value. Every search path must return the
+    k copies with the smallest ids (ties by id), as the oracle orders them."""
+    w, X0, Q = small_data
+    X0 = X0[:3000]
+    dup = np.repeat((Q[0] + np.float32(1e-3)).astype(np.float32)[None, :], 150, axis=0)
+    X = np.concatenate([X0[:1000], dup, X0[1000:]])
+    nlist, k = 8, 5
+    C32, a, off, ids = oracle_index(X, nlist, w.d_c, 6, 3)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    try:
+        Qd = torch.from_numpy(Q[:8]).cuda()
+        want = np.arange(1000, 1000 + k)
+        dist, gid, probes = _search(index, Q[:8], w.d_c, w.d, nlist, k)
+        rep = check_search(X, Q[:8], C32, off, ids, w.d_c, w.d, nlist, k, dist, gid, got_p=probes)
+        assert rep.ok, rep.problems
+        assert np.array_equal(gid[0], want), gid[0]
+        for fmt in ("bf16", "fp8"):
+            index.set_precision(fmt)
+            f = index.search_filtered(Qd, w.d_c, w.d, nlist, k, fmt)
+            p = index.search_precision(Qd, w.d_c, w.d, nlist, k, fmt, 8, 0)
+            torch.cuda.synchronize()
+            assert np.array_equal(f[1].cpu().numpy()[0], want), (fmt, f[1][0])
+            assert torch.equal(f[0][0], torch.from_numpy(dist[0]).cuda()), fmt
+            assert np.array_equal(p[1].cpu().numpy()[0], want), (fmt, p[1][0])
+    finally:
+        index.free()
+
+
 def test_certified_results_unchanged_when_band_is_narrow(lib, small_data):
     """On ordinary data no query needs re-selection and the counters stay 0."""
     w, X, Q = small_data
