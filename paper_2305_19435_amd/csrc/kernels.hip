@@ -3599,9 +3599,14 @@ __global__ __launch_bounds__(256) void k_pq_lut(const float *__restrict__ qh, in
 // list; each row sums the M table entries its codes pick (in code order
 // m = 0..M-1). 1024 threads share one table, so that a CU holds enough waves
 // to hide the table reads' latency. The next list's location is loaded while
-// the current one is scanned.
+// the current one is scanned. MM > 0: M = MM, a multiple of 16, and each
+// row's codes are loaded whole (all its 16-byte pieces in flight together)
+// before its look-ups: loaded one piece at a time between look-ups, the
+// rows' cache lines were evicted and fetched again (1.33x the algorithmic
+// bytes at M = 64). MM = 0: any M (a multiple of 4) given at run time.
 constexpr int ADC_THREADS = 1024;
-__global__ __launch_bounds__(ADC_THREADS) void k_adc_scan(const float *__restrict__ lut, int32_t M,
+template <int MM>
+__global__ __launch_bounds__(ADC_THREADS) void k_adc_scan(const float *__restrict__ lut, int32_t M_,
                                                           const uint8_t *__restrict__ codes,
                                                           const int32_t *__restrict__ probes,
                                                           int32_t nprobe, int32_t G,
@@ -3609,6 +3614,8 @@ __global__ __launch_bounds__(ADC_THREADS) void k_adc_scan(const float *__restric
                                                           const int32_t *__restrict__ len,
                                                           const int64_t *__restrict__ pair_base,
                                                           float *__restrict__ D) {
+  static_assert(MM % 16 == 0 && MM <= 64, "whole-row loads for M = 16, 32, 48, 64");
+  const int M = MM > 0 ? MM : M_;
   extern __shared__ float tab[];  // [M][256]
   const int gpq = (nprobe + G - 1) / G;
   const int64_t q = blockIdx.x / gpq;
@@ -3634,7 +3641,25 @@ __global__ __launch_bounds__(ADC_THREADS) void k_adc_scan(const float *__restric
     if (j + 1 < j1) where(j + 1, n2, cb2, out2);
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
       float acc = 0.f;
-      if ((M & 15) == 0) {  // 16 codes per load (rows are 16-byte aligned)
+      if constexpr (MM > 0) {
+        constexpr int NW = MM / 16;
+        const uint4 *row = (const uint4 *)(cbase + (int64_t)r * MM);
+        uint4 c16[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) c16[w] = row[w];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const uint32_t wd[4] = {c16[w].x, c16[w].y, c16[w].z, c16[w].w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int m = w * 16 + e * 4;
+            acc += tab[(m + 0) * 256 + (wd[e] & 0xff)];
+            acc += tab[(m + 1) * 256 + ((wd[e] >> 8) & 0xff)];
+            acc += tab[(m + 2) * 256 + ((wd[e] >> 16) & 0xff)];
+            acc += tab[(m + 3) * 256 + (wd[e] >> 24)];
+          }
+        }
+      } else if ((M & 15) == 0) {  // 16 codes per load (rows are 16-byte aligned)
         const uint4 *row = (const uint4 *)(cbase + (int64_t)r * M);
         for (int w = 0; w < (M >> 4); ++w) {
           const uint4 c16 = row[w];
@@ -5319,9 +5344,21 @@ hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const Sea
     // lists per workgroup: as many as keep about 512 workgroups in flight
     const int32_t G = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nprobe, nq * nprobe / 512));
     if (nq > 0)
-      hipLaunchKernelGGL(k_adc_scan, dim3((unsigned)(nq * cdiv(nprobe, G))), dim3(ADC_THREADS),
-                         pq.M * 256 * sizeof(float), st, lut, pq.M, pq.codes, b.probes, nprobe, G,
-                         ix->poff, ix->len, b.pair_base, b.D);
+    {
+      const dim3 grid((unsigned)(nq * cdiv(nprobe, G)));
+      const size_t tb = pq.M * 256 * sizeof(float);
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(ADC_THREADS), tb, st, lut, pq.M, pq.codes, b.probes,
+                           nprobe, G, ix->poff, ix->len, b.pair_base, b.D);
+      };
+      switch (pq.M) {
+        case 16: go(k_adc_scan<16>); break;
+        case 32: go(k_adc_scan<32>); break;
+        case 48: go(k_adc_scan<48>); break;
+        case 64: go(k_adc_scan<64>); break;
+        default: go(k_adc_scan<0>);
+      }
+    }
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
