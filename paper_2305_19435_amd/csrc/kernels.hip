@@ -3614,7 +3614,7 @@ __global__ __launch_bounds__(ADC_THREADS) void k_adc_scan(const float *__restric
                                                           const int32_t *__restrict__ len,
                                                           const int64_t *__restrict__ pair_base,
                                                           float *__restrict__ D) {
-  static_assert(MM % 16 == 0 && MM <= 64, "whole-row loads for M = 16, 32, 48, 64");
+  static_assert(MM % 16 == 0 && MM <= 64, "whole-row loads for M = 16, 32, 64");
   const int M = MM > 0 ? MM : M_;
   extern __shared__ float tab[];  // [M][256]
   const int gpq = (nprobe + G - 1) / G;
@@ -5354,7 +5354,6 @@ hipError_t launch_pq_search(const adanns_index *ix, const PqCodec &pq, const Sea
       switch (pq.M) {
         case 16: go(k_adc_scan<16>); break;
         case 32: go(k_adc_scan<32>); break;
-        case 48: go(k_adc_scan<48>); break;
         case 64: go(k_adc_scan<64>); break;
         default: go(k_adc_scan<0>);
       }

@@ -24,7 +24,7 @@ def pq_small(lib, small_data):
     C32, a, off, ids = oracle_index(X, w.nlist, w.d_c, 10, w.seed)
     index = lib.IvfIndex.import_ivf(X, C32, a)
     codecs = {}
-    for M, opq in ((16, True), (8, False)):
+    for M, opq in ((16, True), (8, False), (32, False), (64, False)):
         R32, cb32, codes = make_codec(X, M, w.d, opq, w.seed + M)
         index.pq_import(M, w.d, R32 if opq else None, cb32, codes)
         codecs[M] = (R32, cb32, codes)
@@ -33,7 +33,8 @@ def pq_small(lib, small_data):
 
 
 @pytest.mark.parametrize("M,nprobe,k,rerank", [(16, 4, 10, 0), (8, 4, 10, 0), (16, 4, 10, 40),
-                                               (16, 32, 5, 0), (8, 2, 50, 60)])
+                                               (16, 32, 5, 0), (8, 2, 50, 60), (32, 4, 10, 0),
+                                               (64, 8, 10, 0), (64, 4, 10, 40)])
 def test_pq_parity(pq_small, M, nprobe, k, rerank):
     w, X, Q, C32, off, ids, index, codecs = pq_small
     R32, cb32, codes = codecs[M]
