@@ -1104,6 +1104,20 @@ adanns_status adanns_index_add_row_copy(adanns_index *ix, void *stream) {
   return ADANNS_OK;
 }
 
+// Query rows for the FP32 steps: read in place when they are 16-byte aligned
+// and cover the zero-padded staging width (the kernels read 16-byte pieces up
+// to the 32-coordinate slab that holds the last coordinate they use and mask
+// what lies past it), else staged into zero-padded rows.
+static hipError_t stage_or_in_place(SearchBufs &b, const float *Q, int64_t nq, int64_t ldq,
+                                    int32_t dq, hipStream_t st) {
+  if (ldq % 4 == 0 && ((uintptr_t)Q & 15) == 0 && ldq >= b.ldqs) {
+    b.Qs = const_cast<float *>(Q);
+    b.ldqs = ldq;
+    return hipSuccess;
+  }
+  return launch_stage_queries(Q, nq, ldq, dq, b.Qs, b.ldqs, st);
+}
+
 adanns_status adanns_search_precision(const adanns_index *cix, const float *Q, int64_t nq,
                                       int64_t ldq, int32_t d_c, int32_t d_s, int32_t nprobe,
                                       int32_t k, int32_t fmt, int32_t rerank_k,
@@ -1164,7 +1178,7 @@ adanns_status adanns_search_precision(const adanns_index *cix, const float *Q, i
   Carver c{(char *)base, total, 0};
   void *Qq = c.take<uint8_t>((size_t)nq * ix->d_pad * eb);
   float *qscale = c.take<float>((size_t)nq);
-  ADANNS_HIP(launch_stage_queries(Q, nq, ldq, dq, b.Qs, b.ldqs, st));
+  ADANNS_HIP(stage_or_in_place(b, Q, nq, ldq, dq, st));
   ADANNS_HIP(launch_quantize_queries(Q, nq, ldq, ix->d, fmt, Qq, ix->d_pad, qscale, st));
   ADANNS_HIP(launch_precision_search(ix, fmt, b, Qq, ix->d_pad, qscale, nq, d_c, d_s, nprobe, k,
                                      rerank_k, coarse_margin, dist, ids, probes, st));
@@ -1225,7 +1239,7 @@ adanns_status adanns_search_filtered(const adanns_index *cix, const float *Q, in
   Carver c{(char *)base, total, 0};
   void *Qq = c.take<uint8_t>((size_t)nq * ix->d_pad * eb);
   float *qscale = c.take<float>((size_t)nq);
-  ADANNS_HIP(launch_stage_queries(Q, nq, ldq, dq, b.Qs, b.ldqs, st));
+  ADANNS_HIP(stage_or_in_place(b, Q, nq, ldq, dq, st));
   ADANNS_HIP(launch_quantize_queries(Q, nq, ldq, ix->d, fmt, Qq, ix->d_pad, qscale, st));
   ADANNS_HIP(launch_filtered_search(ix, fmt, b, Qq, ix->d_pad, qscale, nq, d_c, d_s, nprobe, k,
                                     dist, ids, probes, st));

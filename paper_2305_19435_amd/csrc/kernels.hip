@@ -3767,9 +3767,41 @@ __global__ __launch_bounds__(256) void k_quant_rows(const float *__restrict__ Q,
   const int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (q >= nq) return;
   const float *row = Q + q * ldq;
+  // Rows that are 16-byte aligned and at least ldo wide (ldo a multiple of 8):
+  // eight coordinates per lane and step, 16-byte loads, four steps in flight
+  // (values past d_used are written as zero, the same per coordinate as
+  // below); other rows one coordinate per lane and step.
+  const bool vec = ((uintptr_t)Q & 15) == 0 && ldq % 4 == 0 && ldq >= ldo && ldo % 8 == 0;
   if (fmt == 1) {
     uint16_t *o = (uint16_t *)out + q * ldo;
-    for (int dim = lane; dim < ldo; dim += 64) o[dim] = dim < d_used ? bf16_rne(row[dim]) : 0;
+    if (vec) {
+      for (int c0 = 8 * lane; c0 < ldo; c0 += 512 * 4) {
+        float4 v[4][2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int dim = c0 + 512 * u + 4 * h;
+            v[u][h] = dim < ldo ? *(const float4 *)(row + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+          }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int dim = c0 + 512 * u;
+          if (dim >= ldo) break;
+          uint32_t w[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const float x0 = f4(v[u][t >> 1], 2 * (t & 1)), x1 = f4(v[u][t >> 1], 2 * (t & 1) + 1);
+            const uint32_t b0 = dim + 2 * t < d_used ? bf16_rne(x0) : 0u;
+            const uint32_t b1 = dim + 2 * t + 1 < d_used ? bf16_rne(x1) : 0u;
+            w[t] = b0 | (b1 << 16);
+          }
+          *(uint4 *)(o + dim) = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+      }
+    } else {
+      for (int dim = lane; dim < ldo; dim += 64) o[dim] = dim < d_used ? bf16_rne(row[dim]) : 0;
+    }
     if (lane == 0 && scale) scale[q] = 1.f;
     return;
   }
