@@ -3805,14 +3805,56 @@ __global__ __launch_bounds__(256) void k_quant_rows(const float *__restrict__ Q,
     if (lane == 0 && scale) scale[q] = 1.f;
     return;
   }
+  uint8_t *o = (uint8_t *)out + q * ldo;
   float amax = 0.f;
-  for (int dim = lane; dim < d_used; dim += 64) amax = fmaxf(amax, fabsf(row[dim]));
+  if (vec) {
+    for (int c0 = 8 * lane; c0 < ldo; c0 += 512 * 4) {
+      float4 v[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int dim = c0 + 512 * u + 4 * h;
+          v[u][h] = dim < ldo ? *(const float4 *)(row + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (c0 + 512 * u + t < d_used) amax = fmaxf(amax, fabsf(f4(v[u][t >> 2], t & 3)));
+    }
+  } else {
+    for (int dim = lane; dim < d_used; dim += 64) amax = fmaxf(amax, fabsf(row[dim]));
+  }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
   const float inv = amax > 0.f ? 448.f / amax : 0.f;
   if (lane == 0) scale[q] = amax / 448.f;
-  uint8_t *o = (uint8_t *)out + q * ldo;
-  for (int dim = lane; dim < ldo; dim += 64) o[dim] = dim < d_used ? e4m3_encode(row[dim] * inv) : 0;
+  if (vec) {
+    for (int c0 = 8 * lane; c0 < ldo; c0 += 512 * 4) {
+      float4 v[4][2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int dim = c0 + 512 * u + 4 * h;
+          v[u][h] = dim < ldo ? *(const float4 *)(row + dim) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int dim = c0 + 512 * u;
+        if (dim >= ldo) break;
+        uint32_t w[2] = {0u, 0u};
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (dim + t < d_used)
+            w[t >> 2] |= (uint32_t)e4m3_encode(f4(v[u][t >> 2], t & 3) * inv) << (8 * (t & 3));
+        *(uint2 *)(o + dim) = make_uint2(w[0], w[1]);
+      }
+    }
+  } else {
+    for (int dim = lane; dim < ldo; dim += 64) o[dim] = dim < d_used ? e4m3_encode(row[dim] * inv) : 0;
+  }
 }
 
 __device__ __forceinline__ float qdecode(int FMT, uint32_t bits) {
