@@ -2518,6 +2518,48 @@ __device__ __forceinline__ void filtered_block(const SelArgs &a, const int64_t q
     }
     got = have;
   }
+  if (a.shortlist > 0 && L > a.shortlist) {
+    // The precision form's result (the FP32 k nearest of the shortlist S, the
+    // a.shortlist nearest candidates by exact quantised distance): the result
+    // above is also S's when it lies in S (as k_select_filtered_wave argues).
+    // A candidate ahead of result x in S's order has f <= f_x + 2B, so x is
+    // in S when at most a.shortlist candidates have f <= T = max_x f_x + 2B.
+    // Otherwise the query is handed over.
+    // the results' own first-pass values (located through their list and row)
+    __syncthreads();
+    if (tid == 0) {
+      s_cnt = 0;
+      s_kmax = 0u;
+    }
+    __syncthreads();
+    if (tid < kout && tid < got) {
+      const int64_t gp = cg[tid];
+      const int32_t h = (int32_t)(gp >> 32);
+      const int64_t r = gp & 0xffffffffll;
+      int64_t pos = -1;
+      for (int p = 0; p < np && pos < 0; ++p) {
+        const int32_t hp = tab ? t_h[p] : ldg(a.probes + q * np + p);
+        if (hp == h) pos = (tab ? t_start[p] : ldg(a.pair_base + q * np + p) - seg0) + r;
+      }
+      atomicMax(&s_kmax, pos >= 0 ? order_key(src[pos]) : 0xffffffffu);
+    }
+    __syncthreads();
+    float T = __builtin_inff();
+    if (fb.kind == 1 && got >= kout && s_kmax != 0xffffffffu) {
+      T = comp_value((uint64_t)s_kmax << 32) + 2.f * B * 1.001f;
+      T += fabsf(T) * 0x1p-20f;
+    }
+    if (T <= __FLT_MAX__) {
+      int c = 0;
+      each_fast([&](int64_t, float f) { c += f <= T ? 1 : 0; });
+      if (c) atomicAdd(&s_cnt, c);
+    }
+    __syncthreads();
+    if (!(T <= __FLT_MAX__) || s_cnt > a.shortlist) {
+      if (tid == 0) push_redo(a.redo_cnt, a.redo_list, q + a.redo_q0);
+      return;
+    }
+  }
   for (int j = tid; j < kout; j += blockDim.x) {
     a.out_dist[q * ldo + j] = j < got ? chi[j] : __builtin_inff();
     a.out_ids[q * ldo + j] = j < got ? cid[j] : -1;
@@ -5292,6 +5334,20 @@ hipError_t launch_precision_search(const adanns_index *ix, int32_t fmt, const Se
       w.redo_q0 = 0;
       hipLaunchKernelGGL(k_select_filtered_wave, dim3((unsigned)cdiv(nq, 4)), dim3(256), 0, st, w,
                          nq);
+      w.shortlist = 0;
+      w.kcap = redo_kcap();
+      w.lcap = seg_cap(w.kcap, SEG_LDS_CAP);
+      hipLaunchKernelGGL(k_select_refine_redo, dim3(redo_grid(nq)), dim3(512),
+                         sel_smem_bytes(w.lcap, w.kcap), st, w);
+    } else if (nq > 0 && fmt == 2 && r.K1 > WSEL_K && k <= 128 && b.redo != nullptr) {
+      // e4m3, deep shortlist: the exact search's workgroup selection, with the
+      // same shortlist certificate; the rest to the general re-selection
+      SelArgs w = r;
+      w.shortlist = rerank_k;
+      w.redo_cnt = b.redo + 1;
+      w.redo_list = b.redo + 2;
+      w.redo_q0 = 0;
+      hipLaunchKernelGGL(k_select_exact_filtered, dim3((unsigned)nq), dim3(256), 0, st, w);
       w.shortlist = 0;
       w.kcap = redo_kcap();
       w.lcap = seg_cap(w.kcap, SEG_LDS_CAP);

@@ -131,6 +131,40 @@ def test_precision_band_overflow(lib):
         index.free()
 
 
+@pytest.mark.parametrize("fmt,rerank", [("fp8", 64), ("fp8", 256), ("bf16", 64)])
+def test_precision_deep_shortlist_overflow(lib, fmt, rerank):
+    """Precision form with a shortlist longer than the one-wave lists
+    (rerank 64 and 256) on offset rows with 300 near rows per query: the
+    near rows' first-pass values are too close for the shortlist boundary to
+    be decided from them, so the results must come from the shortlist's
+    exact boundary (queries handed over by the shortlist certificate)."""
+    d, nq, per, nlist, k = 64, 12, 300, 4, 5
+    X, Q = offset_rows(91 + rerank, d, nq, per)
+    C32, a, off, ids = oracle_index(X, nlist, 16, 10, 7)
+    index = lib.IvfIndex.import_ivf(X, C32, a)
+    try:
+        index.set_precision(fmt)
+        lib.selection_stats(reset=True)
+        dist, gid, probes = index.search_precision(torch.from_numpy(Q).cuda(), 16, d, nlist, k,
+                                                   fmt, rerank, 0, return_probes=True)
+        torch.cuda.synchronize()
+        resel, uncert = lib.selection_stats(reset=True)
+        dist, gid, probes = dist.cpu().numpy(), gid.cpu().numpy(), probes.cpu().numpy()
+        rd, ri, rp, shortlists = precision.precision_search64(
+            X, Q, C32.astype(np.float64), off, ids, 16, d, nlist, k, fmt, rerank, 0,
+            return_shortlist=True)
+        assert np.array_equal(np.sort(probes, 1), np.sort(rp, 1))
+        rep = check.Report()
+        for qi in range(nq):
+            check.compare_knn(Q[qi], X, shortlists[qi], dist[qi], gid[qi], rd[qi], ri[qi], d,
+                              report=rep, tag=f"{fmt} q{qi}")
+        assert rep.ok, rep.problems
+        print(f"{fmt} rerank={rerank}: re-selected {resel}, uncertified {uncert}")
+        assert uncert == 0
+    finally:
+        index.free()
+
+
 @pytest.mark.parametrize("per,k", [(48, 5), (200, 60)])
 def test_filtered_band_overflow(lib, per, k):
     """Exact search with a quantised first pass on offset rows: the rows'
